@@ -1,0 +1,75 @@
+"""The workloads: named, seeded problems of the sizes the method is measured on.
+
+The paper measures on scanned meshes and point clouds (data smoothing,
+(M + alpha S) x = M y); those datasets are not available, so these seeded
+synthetic surfaces of the same size range and the same system class stand in
+for them.
+"""
+import numpy as np
+
+from .meshes import (icosphere, torus_grid, flat_grid, bumpy_sphere_points, edges_from_faces,
+                     knn_edges, mean_edge_length, radial_noise, gaussian_jitter)
+from .operators import cotan_laplacian, lumped_mass, gaussian_knn_laplacian, assemble, Problem
+from .rng import uniform
+
+
+def _mesh_problem(name, pts, faces, alpha, seed):
+    edges = edges_from_faces(faces)
+    off, diag = cotan_laplacian(pts, faces)
+    mass = lumped_mass(pts, faces)
+    indptr, indices, data = assemble(off, diag, mass, alpha, edges)
+    y = uniform(seed, "rhs", pts.shape[0], -1.0, 1.0)
+    return Problem(name, np.ascontiguousarray(pts), edges, indptr, indices, data, mass * y)
+
+
+def config_icosphere(subdivisions=5, seed=0, noise=0.01, alpha=1e-3):
+    """Icosphere (5 subdivisions: 10,242 vertices), radial noise +-1%, (M + 1e-3 L) x = M b."""
+    pts, faces = icosphere(subdivisions)
+    pts = radial_noise(pts, seed, noise)
+    return _mesh_problem(f"icosphere{subdivisions}", pts, faces, alpha, seed)
+
+
+def config_torus(nu=1024, nv=1024, seed=0, alpha=1e-3, jitter=0.1):
+    """Torus R=1, r=0.4 on an nu x nv grid, Gaussian jitter sigma = 0.1 * mean edge length."""
+    pts, faces = torus_grid(nu, nv)
+    sigma = jitter * mean_edge_length(pts, edges_from_faces(faces))
+    pts = gaussian_jitter(pts, seed, sigma)
+    return _mesh_problem(f"torus{nu}x{nv}", pts, faces, alpha, seed)
+
+
+def config_bumpy_sphere(n=2_000_000, k=8, seed=0, alpha=1e-2):
+    """Bumpy-sphere point cloud, symmetrised kNN graph, Gaussian graph Laplacian, (M + 1e-2 L)."""
+    pts = bumpy_sphere_points(n, seed)
+    edges, _, kd = knn_edges(pts, k)
+    off, diag, mass = gaussian_knn_laplacian(pts, edges, kd)
+    indptr, indices, data = assemble(off, diag, mass, alpha, edges)
+    y = uniform(seed, "rhs", n, -1.0, 1.0)
+    return Problem(f"bumpysphere{n}k{k}", pts, edges, indptr, indices, data, mass * y)
+
+
+def small_icosphere(subdivisions=3, seed=0):
+    return config_icosphere(subdivisions, seed)
+
+
+def small_torus(nu=48, nv=40, seed=0):
+    return config_torus(nu, nv, seed)
+
+
+def small_flat_grid(nx=24, ny=20, seed=0, jitter=0.2, alpha=1e-3):
+    """Planar jittered grid (z stays exactly 0)."""
+    pts, faces = flat_grid(nx, ny)
+    j = uniform(seed, "jitter", 2 * pts.shape[0], -jitter, jitter).reshape(-1, 2)
+    pts = pts.copy()
+    pts[:, :2] += j
+    return _mesh_problem(f"flat{nx}x{ny}", pts, faces, alpha, seed)
+
+
+def small_pointcloud(n=4000, k=8, seed=0):
+    return config_bumpy_sphere(n, k, seed)
+
+
+CONFIGS = {
+    "icosphere5": config_icosphere,
+    "torus1024": config_torus,
+    "bumpysphere2m": config_bumpy_sphere,
+}
