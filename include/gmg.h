@@ -1,0 +1,164 @@
+/*
+ * gmg.h - C ABI of the MI355X (gfx950) Gravo MG setup + solve library.
+ *
+ * Method: Wiersma, Nasikun, Eisemann & Hildebrandt, "A Fast Geometric
+ * Multigrid Method for Curved Surfaces" (SIGGRAPH 2023).  The library builds
+ * the multigrid hierarchy of Sec. 4 (sampling, graph Voronoi cells,
+ * Voronoi-neighbour triangles, barycentric prolongation) and the Galerkin
+ * operators of Alg. 1, then solves A x = b with the V-cycle of Alg. 2.
+ *
+ * Conventions for every call:
+ *  - Arrays named *_dev are device pointers on the current HIP device; arrays
+ *    named *_host are host pointers.  Indices are int32, values float64.
+ *  - `stream` is a hipStream_t passed as void*; NULL means the default stream.
+ *    All device work is enqueued on it.
+ *  - Return value: GMG_OK (0), GMG_NOT_CONVERGED (+1, a warning), or a
+ *    negative error code.  gmg_last_error() gives a message for the calling
+ *    thread's last failure.
+ *  - Levels are numbered from 0 (the input points, the paper's level 1) to
+ *    num_levels - 1 (the coarsest level, solved directly).
+ */
+#ifndef GMG_H
+#define GMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum gmg_status {
+  GMG_OK = 0,
+  GMG_NOT_CONVERGED = 1,      /* max_iters reached; x holds the last iterate */
+  GMG_INVALID_ARGUMENT = -1,  /* null pointer, bad size, out-of-range/unsorted index, non-finite value */
+  GMG_OUT_OF_MEMORY = -2,
+  GMG_DEVICE_ERROR = -3,      /* a HIP runtime failure */
+  GMG_NOT_SPD = -4,           /* non-positive diagonal at some level or non-positive Cholesky pivot */
+  GMG_DEGENERATE = -5         /* coarsening stalled with a coarsest level too large to factor densely */
+};
+
+typedef struct gmg_handle_s* gmg_handle;
+
+/* Options of the hierarchy construction and V-cycle.  struct_size must equal
+ * sizeof(gmg_options); gmg_default_options() fills the paper's settings. */
+typedef struct gmg_options {
+  int32_t struct_size;
+  double coarsening_ratio;       /* phi of Eq. (1): keep about phi of the points per level (1/8) */
+  int32_t min_coarse_points;     /* coarsen while a level has more points than this (1000, Sec. 4.2) */
+  int32_t max_levels;            /* upper bound on the number of levels (32) */
+  int32_t nu_pre, nu_post;       /* Gauss-Seidel sweeps before/after the coarse correction (2, 2; Sec. 5.1) */
+  int32_t shift_coarse_points;   /* 1: move coarse points to their Voronoi-cell mean (Sec. 4.4) */
+  int32_t sample_order;          /* 0: hashed sweep order (default), 1: input index order (Sec. 4.2) */
+  uint64_t seed;                 /* seed of the hashed sweep and colouring orders */
+} gmg_options;
+
+typedef struct gmg_solve_info {
+  int32_t iterations;            /* V-cycles performed */
+  int32_t converged;             /* 1 if ||b - A x|| <= tol ||b|| */
+  double rel_residual;           /* ||b - A x||_2 / ||b||_2 after the last V-cycle */
+} gmg_solve_info;
+
+/* Fills *o with the defaults listed above.  Returns GMG_INVALID_ARGUMENT if o is NULL. */
+int gmg_default_options(gmg_options* o);
+
+/*
+ * Builds the hierarchy (Sec. 4 and Alg. 1): levels are coarsened while they
+ * have more than min_coarse_points points; every level gets its prolongation
+ * P_l (at most 3 entries per row), its Galerkin operator A_{l+1} = P_l^T A_l
+ * P_l and a Gauss-Seidel colouring; the coarsest level gets a dense Cholesky
+ * factorisation.
+ *
+ *  n            number of points (> 0)
+ *  points_dev   n x 3 row-major float64 positions
+ *  m            number of input edges (>= 0)
+ *  edges_dev    m x 2 int32 point pairs; any order, duplicates and self loops allowed
+ *  A_rowptr_dev, A_col_dev, A_val_dev, A_nnz
+ *               the n x n system matrix in CSR: rowptr[0] = 0, rowptr[n] = A_nnz,
+ *               strictly ascending columns per row, symmetric pattern that
+ *               contains the diagonal, finite values, positive diagonal
+ *  opt          options (NULL: defaults)
+ *  stream       hipStream_t; the call returns after the stream has finished the build
+ *  out          receives the handle (NULL on error)
+ *
+ * The library copies what it keeps; the caller may free the inputs on return.
+ * The handle owns all device memory of the hierarchy until gmg_free().
+ * Errors: GMG_INVALID_ARGUMENT, GMG_NOT_SPD, GMG_DEGENERATE, GMG_OUT_OF_MEMORY,
+ * GMG_DEVICE_ERROR.
+ */
+int gmg_build_hierarchy(int64_t n, const double* points_dev, int64_t m, const int32_t* edges_dev,
+                        const int32_t* A_rowptr_dev, const int32_t* A_col_dev,
+                        const double* A_val_dev, int64_t A_nnz, const gmg_options* opt,
+                        void* stream, gmg_handle* out);
+
+/*
+ * Solves A x = b (Alg. 1): repeats V-cycles (Alg. 2) from the initial guess
+ * in x_dev until ||b - A x||_2 <= tol ||b||_2 or max_iters cycles were run.
+ *
+ *  b_dev, x_dev       float64 device vectors of length n (x_dev: in = initial guess, out = solution)
+ *  tol                relative tolerance (>= 0)
+ *  max_iters          maximum number of V-cycles (>= 1)
+ *  info               optional host struct receiving iterations / converged / rel_residual
+ *  residual_history   optional host array of max_iters doubles: relative residual after each cycle
+ *
+ * If b = 0 the solution x = 0 is returned after 0 cycles.  Synchronises the
+ * stream once per V-cycle (convergence test).  One solve at a time per handle.
+ * Returns GMG_OK, GMG_NOT_CONVERGED, GMG_INVALID_ARGUMENT or GMG_DEVICE_ERROR.
+ */
+int gmg_solve(gmg_handle h, const double* b_dev, double* x_dev, double tol, int32_t max_iters,
+              void* stream, gmg_solve_info* info, double* residual_history);
+
+/* Releases the handle and its device memory.  NULL is ignored. */
+void gmg_free(gmg_handle h);
+
+/* Static text for a status code. */
+const char* gmg_status_string(int status);
+
+/* Message of the calling thread's last failing call ("" if none). */
+const char* gmg_last_error(void);
+
+/* Number of levels of the hierarchy. */
+int gmg_num_levels(gmg_handle h, int32_t* levels);
+
+/*
+ * Sizes of level l, written to sizes_host[0..7]:
+ *  0 points n_l, 1 undirected edges of E_l, 2 nnz(A_l), 3 nnz(P_l) (0 on the
+ *  coarsest level), 4 colours, 5 rows of P_l that used the inverse-distance
+ *  fallback, 6 coarse points sampled from this level (0 on the coarsest),
+ *  7 entries of the symmetric edge CSR (2 x edges).
+ */
+int gmg_level_sizes(gmg_handle h, int32_t level, int64_t* sizes_host);
+
+/* Export codes of gmg_export_level (element type and count for level l). */
+enum gmg_export_what {
+  GMG_EXPORT_POSITIONS = 0,    /* double[n*3] points of the level */
+  GMG_EXPORT_EDGE_ROWPTR = 1,  /* int32[n+1] symmetric edge CSR */
+  GMG_EXPORT_EDGE_COL = 2,     /* int32[2m] neighbours, ascending per row */
+  GMG_EXPORT_EDGE_W = 3,       /* double[2m] Euclidean edge lengths */
+  GMG_EXPORT_SCALARS = 4,      /* double[2] mean edge length e_hat and sampling radius r */
+  GMG_EXPORT_SAMPLES = 5,      /* int32[n_{l+1}] points kept as coarse points, ascending */
+  GMG_EXPORT_LABELS = 6,       /* int32[n] coarse point (Voronoi cell) of each point */
+  GMG_EXPORT_DIST = 7,         /* double[n] graph distance to the cell's coarse point */
+  GMG_EXPORT_P_COL = 8,        /* int32[3n] prolongation columns, row-major, unused = -1 */
+  GMG_EXPORT_P_VAL = 9,        /* double[3n] prolongation weights, unused = 0 */
+  GMG_EXPORT_P_CNT = 10,       /* int32[n] entries per row of P_l */
+  GMG_EXPORT_TRI = 11,         /* int32[2n] chosen triangle (j, k) with apex label(p); -1 = fallback */
+  GMG_EXPORT_A_ROWPTR = 12,    /* int32[n+1] CSR of A_l */
+  GMG_EXPORT_A_COL = 13,       /* int32[nnz] */
+  GMG_EXPORT_A_VAL = 14,       /* double[nnz] */
+  GMG_EXPORT_COLORS = 15,      /* int32[n] Gauss-Seidel colour of each row */
+  GMG_EXPORT_CHOL = 16         /* double[n*n] row-major lower Cholesky factor (coarsest level only) */
+};
+
+/*
+ * Copies one array of level l to host memory (inspection and testing).
+ * `bytes` must equal the array's size exactly; otherwise GMG_INVALID_ARGUMENT.
+ * Arrays a level does not have (e.g. LABELS on the coarsest level) have size 0.
+ */
+int gmg_export_level(gmg_handle h, int32_t level, int32_t what, void* host_dst, int64_t bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GMG_H */

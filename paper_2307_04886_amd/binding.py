@@ -1,0 +1,207 @@
+"""ctypes binding of libgmg.so (argument marshalling only).
+
+The names follow include/gmg.h: gmg_build_hierarchy, gmg_solve, gmg_free,
+gmg_num_levels, gmg_level_sizes, gmg_export_level.  Inputs are torch tensors
+on the current HIP device; nothing here computes any part of the method, and
+a missing library raises instead of falling back to anything else.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgmg.so")
+
+STATUS = {0: "OK", 1: "NOT_CONVERGED", -1: "INVALID_ARGUMENT", -2: "OUT_OF_MEMORY",
+          -3: "DEVICE_ERROR", -4: "NOT_SPD", -5: "DEGENERATE"}
+
+# export code -> (name, dtype); sizes come from gmg_level_sizes
+EXPORTS = {
+    "positions": (0, np.float64), "edge_rowptr": (1, np.int32), "edge_col": (2, np.int32),
+    "edge_w": (3, np.float64), "scalars": (4, np.float64), "samples": (5, np.int32),
+    "labels": (6, np.int32), "dist": (7, np.float64), "p_col": (8, np.int32), "p_val": (9, np.float64),
+    "p_cnt": (10, np.int32), "tri": (11, np.int32), "a_rowptr": (12, np.int32), "a_col": (13, np.int32),
+    "a_val": (14, np.float64), "colors": (15, np.int32), "chol": (16, np.float64),
+}
+
+# Symbols the library exports (checked on load).
+SYMBOLS = ["gmg_default_options", "gmg_build_hierarchy", "gmg_solve", "gmg_free", "gmg_status_string",
+           "gmg_last_error", "gmg_num_levels", "gmg_level_sizes", "gmg_export_level"]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_int32), ("coarsening_ratio", ctypes.c_double),
+                ("min_coarse_points", ctypes.c_int32), ("max_levels", ctypes.c_int32),
+                ("nu_pre", ctypes.c_int32), ("nu_post", ctypes.c_int32),
+                ("shift_coarse_points", ctypes.c_int32), ("sample_order", ctypes.c_int32),
+                ("seed", ctypes.c_uint64)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("rel_residual", ctypes.c_double)]
+
+
+class GMGError(RuntimeError):
+    def __init__(self, status, msg=""):
+        super().__init__(f"gmg status {status} ({STATUS.get(status, '?')}): {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def library():
+    """Loads libgmg.so (built by paper_2307_04886_amd/build.py); raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_2307_04886_amd/build.py`")
+    L = ctypes.CDLL(LIB_PATH)
+    P, I32, I64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    L.gmg_default_options.argtypes = [ctypes.POINTER(Options)]
+    L.gmg_build_hierarchy.argtypes = [I64, P, I64, P, P, P, P, I64, ctypes.POINTER(Options), P,
+                                      ctypes.POINTER(P)]
+    L.gmg_solve.argtypes = [P, P, P, ctypes.c_double, I32, P, ctypes.POINTER(SolveInfo), P]
+    L.gmg_free.argtypes = [P]
+    L.gmg_free.restype = None
+    L.gmg_status_string.argtypes = [ctypes.c_int]
+    L.gmg_status_string.restype = ctypes.c_char_p
+    L.gmg_last_error.argtypes = []
+    L.gmg_last_error.restype = ctypes.c_char_p
+    L.gmg_num_levels.argtypes = [P, ctypes.POINTER(I32)]
+    L.gmg_level_sizes.argtypes = [P, I32, P]
+    L.gmg_export_level.argtypes = [P, I32, I32, P, I64]
+    _lib = L
+    return L
+
+
+def default_options(**kw):
+    o = Options()
+    library().gmg_default_options(ctypes.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def _err(status):
+    return GMGError(status, library().gmg_last_error().decode())
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dev(t, dtype, shape=None, name=""):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {shape}, got {tuple(t.shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Hierarchy:
+    """A multigrid hierarchy owned by the library (gmg_build_hierarchy ... gmg_free)."""
+
+    def __init__(self, handle, n):
+        self._h = handle
+        self.n = n
+
+    def __del__(self):
+        self.free()
+
+    def free(self):
+        h = getattr(self, "_h", None)
+        if h:
+            library().gmg_free(h)
+            self._h = None
+
+    @property
+    def num_levels(self):
+        v = ctypes.c_int32()
+        st = library().gmg_num_levels(self._h, ctypes.byref(v))
+        if st:
+            raise _err(st)
+        return v.value
+
+    def sizes(self, level):
+        s = np.zeros(8, dtype=np.int64)
+        st = library().gmg_level_sizes(self._h, level, s.ctypes.data_as(ctypes.c_void_p))
+        if st:
+            raise _err(st)
+        return dict(n=int(s[0]), m=int(s[1]), nnzA=int(s[2]), nnzP=int(s[3]), colors=int(s[4]),
+                    fallback=int(s[5]), samples=int(s[6]), nnzE=int(s[7]))
+
+    def export(self, level, what):
+        code, dt = EXPORTS[what]
+        s = self.sizes(level)
+        n, has = s["n"], s["n"] if s["samples"] else 0
+        count = {
+            "positions": 3 * n, "edge_rowptr": n + 1, "edge_col": s["nnzE"],
+            "edge_w": s["nnzE"], "scalars": 2, "samples": s["samples"], "labels": has, "dist": has,
+            "p_col": 3 * has, "p_val": 3 * has, "p_cnt": has, "tri": 2 * has, "a_rowptr": n + 1,
+            "a_col": s["nnzA"], "a_val": s["nnzA"], "colors": n if s["colors"] else 0, "chol": n * n,
+        }[what]
+        out = np.zeros(count, dtype=dt)
+        st = library().gmg_export_level(self._h, level, code, out.ctypes.data_as(ctypes.c_void_p),
+                                        out.nbytes)
+        if st:
+            raise _err(st)
+        shapes = {"positions": (n, 3), "p_col": (has, 3), "p_val": (has, 3), "tri": (has, 2),
+                  "chol": (n, n)}
+        return out.reshape(shapes[what]) if what in shapes else out
+
+    def solve(self, b, x=None, tol=1e-8, max_iters=100, stream=None, history=False):
+        """Solves A x = b by V-cycles (in place on x if given).  Returns (x, SolveInfo, status[, hist])."""
+        import torch
+        pb = _dev(b, torch.float64, (self.n,), "b")
+        if x is None:
+            x = torch.zeros_like(b)
+        px = _dev(x, torch.float64, (self.n,), "x")
+        info = SolveInfo()
+        hist = np.zeros(max_iters, dtype=np.float64)
+        st = library().gmg_solve(self._h, pb, px, float(tol), int(max_iters), _stream_ptr(stream),
+                                 ctypes.byref(info), hist.ctypes.data_as(ctypes.c_void_p))
+        if st < 0:
+            raise _err(st)
+        if history:
+            return x, info, st, hist[:info.iterations]
+        return x, info, st
+
+
+def build_hierarchy(points, edges, rowptr, col, val, options=None, stream=None):
+    """gmg_build_hierarchy on torch tensors: points (n,3) f64, edges (m,2) int32, A as CSR
+    (rowptr int32 (n+1), col int32, val f64).  All on the current HIP device."""
+    import torch
+    n = int(points.shape[0])
+    m = int(edges.shape[0])
+    nnz = int(col.shape[0])
+    args = [_dev(points, torch.float64, (n, 3), "points"), _dev(edges, torch.int32, (m, 2), "edges"),
+            _dev(rowptr, torch.int32, (n + 1,), "rowptr"), _dev(col, torch.int32, (nnz,), "col"),
+            _dev(val, torch.float64, (nnz,), "val")]
+    opt = options if options is not None else default_options()
+    h = ctypes.c_void_p()
+    st = library().gmg_build_hierarchy(n, args[0], m, args[1], args[2], args[3], args[4], nnz,
+                                       ctypes.byref(opt), _stream_ptr(stream), ctypes.byref(h))
+    if st:
+        raise _err(st)
+    return Hierarchy(h, n)
+
+
+def from_problem(prob, options=None, device="cuda"):
+    """Uploads a synthetic problem (numpy arrays) and builds its hierarchy."""
+    import torch
+    t = dict(points=torch.from_numpy(prob.points).to(device), edges=torch.from_numpy(prob.edges).to(device),
+             rowptr=torch.from_numpy(prob.indptr).to(device), col=torch.from_numpy(prob.indices).to(device),
+             val=torch.from_numpy(prob.data).to(device))
+    return build_hierarchy(options=options, **t), t

@@ -1,0 +1,433 @@
+// C ABI of the library (include/gmg.h): argument checks, the level loop of
+// the hierarchy construction (Sec. 4, Alg. 1), the V-cycle driver (Alg. 1,
+// Alg. 2) and the inspection exports.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+
+#include "gmg_internal.hpp"
+
+namespace gmg {
+
+namespace {
+thread_local std::string g_last_error;
+std::mutex g_pool_mutex;
+bool g_pool_ready[64] = {};
+
+// Keep freed stream-ordered allocations cached in the device's default pool,
+// so that repeated builds do not return memory to the driver.
+void ensure_pool(int dev) {
+  std::lock_guard<std::mutex> lock(g_pool_mutex);
+  if (dev < 0 || dev >= 64 || g_pool_ready[dev]) return;
+  hipMemPool_t pool;
+  if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+    uint64_t thr = UINT64_MAX;
+    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+  }
+  g_pool_ready[dev] = true;
+}
+
+double* pinned_scratch() {
+  static thread_local double* p = nullptr;
+  if (!p) check_hip(hipHostMalloc((void**)&p, 64, hipHostMallocDefault), "pinned host buffer");
+  return p;
+}
+}  // namespace
+
+void set_error(const std::string& m) { g_last_error = m; }
+
+void check_hip(hipError_t e, const char* what) {
+  if (e == hipSuccess) return;
+  (void)hipGetLastError();
+  int st = (e == hipErrorOutOfMemory) ? GMG_OUT_OF_MEMORY : GMG_DEVICE_ERROR;
+  throw Error{st, std::string(what) + ": " + hipGetErrorString(e)};
+}
+
+void* dalloc(Handle& h, size_t bytes) {
+  void* p = nullptr;
+  check_hip(hipMallocAsync(&p, std::max<size_t>(bytes, 256), h.stream), "device allocation");
+  h.allocs.push_back(p);
+  return p;
+}
+
+void* talloc(hipStream_t s, size_t bytes) {
+  void* p = nullptr;
+  check_hip(hipMallocAsync(&p, std::max<size_t>(bytes, 256), s), "device allocation");
+  return p;
+}
+
+void tfree(hipStream_t s, void* p) {
+  if (p) (void)hipFreeAsync(p, s);
+}
+
+void sync(hipStream_t s, const char* what) {
+  check_hip(hipGetLastError(), what);
+  check_hip(hipStreamSynchronize(s), what);
+}
+
+int64_t read_i64(Handle& h, const void* dev_ptr, int bytes) {
+  double* buf = pinned_scratch();
+  check_hip(hipMemcpyAsync(buf, dev_ptr, bytes, hipMemcpyDeviceToHost, h.stream), "device-to-host copy");
+  sync(h.stream, "device-to-host copy");
+  if (bytes == 4) {
+    int32_t v;
+    std::memcpy(&v, buf, 4);
+    return v;
+  }
+  int64_t v;
+  std::memcpy(&v, buf, 8);
+  return v;
+}
+
+void check_flags(Handle& h, const char* phase) {
+  int32_t f = (int32_t)read_i64(h, h.flags, 4);
+  if (f & F_INVALID) throw Error{GMG_INVALID_ARGUMENT, std::string(phase) + ": invalid input"};
+  if (f & F_NOT_SPD) throw Error{GMG_NOT_SPD, std::string(phase) + ": non-positive diagonal or pivot"};
+  if (f & F_OVERFLOW) throw Error{GMG_DEVICE_ERROR, std::string(phase) + ": a coarse row is too dense"};
+}
+
+namespace {
+
+template <typename H>
+void release(H* h) {
+  if (!h) return;
+  for (void* p : h->allocs) (void)hipFreeAsync(p, h->stream);
+  (void)hipStreamSynchronize(h->stream);
+  delete h;
+}
+
+bool options_ok(const gmg_options& o) {
+  return o.struct_size == (int32_t)sizeof(gmg_options) && o.coarsening_ratio > 0.0 &&
+         o.coarsening_ratio < 1.0 && o.min_coarse_points >= 1 && o.max_levels >= 1 && o.nu_pre >= 0 &&
+         o.nu_post >= 0 && (o.sample_order == 0 || o.sample_order == 1);
+}
+
+struct PT {
+  int32_t* rp = nullptr;
+  int32_t* col = nullptr;
+  double* val = nullptr;
+};
+
+void build(Handle& h, int64_t n, const double* points, int64_t m, const int32_t* edges, const int32_t* arp,
+           const int32_t* acol, const double* aval, int64_t nnz) {
+  hipStream_t s = h.stream;
+  const gmg_options& o = h.opt;
+  const double rho = std::cbrt(1.0 / o.coarsening_ratio);
+  h.flags = (int32_t*)dalloc(h, 64 * 4);
+  h.rounds = (int32_t*)dalloc(h, kMaxRounds * 4);
+  h.red = (double*)dalloc(h, (kNormBlocks + 8) * 8);
+  check_hip(hipMemsetAsync(h.flags, 0, 64 * 4, s), "memset");
+
+  h.L.emplace_back();
+  {
+    Level& lv = h.L[0];
+    lv.n = n;
+    lv.X = (double*)dalloc(h, (size_t)n * 3 * 8);
+    check_hip(hipMemcpyAsync(lv.X, points, (size_t)n * 3 * 8, hipMemcpyDeviceToDevice, s), "copy points");
+    validate_points(lv.X, n, h.flags, s);
+    edges_to_csr(h, lv, edges, m);
+    lv.arp = (int32_t*)dalloc(h, (size_t)(n + 1) * 4);
+    lv.acol = (int32_t*)dalloc(h, (size_t)nnz * 4);
+    lv.aval = (double*)dalloc(h, (size_t)nnz * 8);
+    lv.nnzA = nnz;
+    check_hip(hipMemcpyAsync(lv.arp, arp, (size_t)(n + 1) * 4, hipMemcpyDeviceToDevice, s), "copy A");
+    check_hip(hipMemcpyAsync(lv.acol, acol, (size_t)nnz * 4, hipMemcpyDeviceToDevice, s), "copy A");
+    check_hip(hipMemcpyAsync(lv.aval, aval, (size_t)nnz * 8, hipMemcpyDeviceToDevice, s), "copy A");
+    validate_matrix(lv.arp, lv.acol, lv.aval, n, nnz, h.flags, s);
+    check_flags(h, "input");
+    lv.scal = (double*)dalloc(h, 16);
+    check_hip(hipMemsetAsync(lv.scal, 0, 16, s), "memset");
+  }
+
+  std::vector<PT> pts;
+  // Sec. 4.2: coarsen while a level has more than min_coarse_points points.
+  while (h.L.back().n > o.min_coarse_points && (int)h.L.size() < o.max_levels) {
+    const int l = (int)h.L.size() - 1;
+    Level nx;
+    {
+      Level& lv = h.L[l];
+      lv.ew = (double*)dalloc(h, (size_t)(lv.nnzE + 1) * 8);
+      edge_weights(lv, s);
+      mean_edge(h, lv, rho);
+      lv.sampled = true;
+      int64_t nc = sample_lfmis(h, lv, l);
+      if (nc == lv.n) {                       // no progress: this level becomes the coarsest
+        tfree(s, lv.status);
+        lv.status = nullptr;
+        break;
+      }
+      voronoi(h, lv);
+      int32_t *cptr = nullptr, *cmem = nullptr;
+      cells_and_shift(h, lv, nx, o.shift_coarse_points != 0, &cptr, &cmem);
+      coarse_edges(h, lv, nx, cptr, cmem);
+      tfree(s, cptr);
+      tfree(s, cmem);
+      prolongation(h, lv, nx);
+      PT pt;
+      transpose_p(h, lv, nx.n, &pt.rp, &pt.col, &pt.val);
+      galerkin(h, lv, nx, pt.rp, pt.col, pt.val);
+      check_flags(h, "Galerkin operator");
+      pts.push_back(pt);
+      nx.scal = (double*)dalloc(h, 16);
+      check_hip(hipMemsetAsync(nx.scal, 0, 16, s), "memset");
+    }
+    h.L.push_back(nx);
+  }
+  Level& last = h.L.back();
+  if (!last.ew && last.nnzE > 0) {
+    last.ew = (double*)dalloc(h, (size_t)last.nnzE * 8);
+    edge_weights(last, s);
+  }
+  last.nc = 0;                                // the coarsest level keeps no coarsening products
+  last.samples = nullptr;
+  last.label = nullptr;
+  last.dist = nullptr;
+  if (last.n > kMaxDenseCoarse) throw Error{GMG_DEGENERATE, "coarsening stalled above the dense-solve limit"};
+  const int nl = (int)h.L.size();
+  for (int l = 0; l + 1 < nl; ++l) colouring(h, h.L[l], l);
+  solve_layout(h, h.L[nl - 1], nullptr, nullptr, nullptr, nullptr);
+  for (int l = nl - 2; l >= 0; --l)
+    solve_layout(h, h.L[l], &h.L[l + 1], pts[l].rp, pts[l].col, pts[l].val);
+  for (auto& pt : pts) {
+    tfree(s, pt.rp);
+    tfree(s, pt.col);
+    tfree(s, pt.val);
+  }
+  coarse_factor(h, last);
+  sync(s, "build");
+}
+
+void vcycle(Handle& h, size_t l, hipStream_t s) {
+  Level& lv = h.L[l];
+  if (l + 1 == h.L.size()) {
+    coarse_solve(h, lv, s);
+    return;
+  }
+  Level& nx = h.L[l + 1];
+  for (int k = 0; k < h.opt.nu_pre; ++k) gs_sweep(lv, s);
+  residual(lv, s);
+  restrict_to(lv, nx, s);
+  fill_f64(nx.x, 0.0, nx.n, s);
+  vcycle(h, l + 1, s);
+  prolong_correct(lv, nx, s);
+  for (int k = 0; k < h.opt.nu_post; ++k) gs_sweep(lv, s);
+}
+
+const char* status_text(int st) {
+  switch (st) {
+    case GMG_OK: return "ok";
+    case GMG_NOT_CONVERGED: return "not converged";
+    case GMG_INVALID_ARGUMENT: return "invalid argument";
+    case GMG_OUT_OF_MEMORY: return "out of memory";
+    case GMG_DEVICE_ERROR: return "device error";
+    case GMG_NOT_SPD: return "matrix not symmetric positive definite";
+    case GMG_DEGENERATE: return "degenerate coarsening";
+    default: return "unknown status";
+  }
+}
+
+}  // namespace
+}  // namespace gmg
+
+using namespace gmg;
+
+// The opaque handle of the C ABI is the library's hierarchy object.
+struct gmg_handle_s : public gmg::Handle {};
+
+extern "C" {
+
+int gmg_default_options(gmg_options* o) {
+  if (!o) return GMG_INVALID_ARGUMENT;
+  std::memset(o, 0, sizeof(*o));
+  o->struct_size = (int32_t)sizeof(gmg_options);
+  o->coarsening_ratio = 1.0 / 8.0;
+  o->min_coarse_points = 1000;
+  o->max_levels = 32;
+  o->nu_pre = 2;
+  o->nu_post = 2;
+  o->shift_coarse_points = 1;
+  o->sample_order = 0;
+  o->seed = 0;
+  return GMG_OK;
+}
+
+int gmg_build_hierarchy(int64_t n, const double* points_dev, int64_t m, const int32_t* edges_dev,
+                        const int32_t* A_rowptr_dev, const int32_t* A_col_dev, const double* A_val_dev,
+                        int64_t A_nnz, const gmg_options* opt, void* stream, gmg_handle* out) {
+  set_error("");
+  if (!out) {
+    set_error("out is NULL");
+    return GMG_INVALID_ARGUMENT;
+  }
+  *out = nullptr;
+  if (n <= 0 || n > INT32_MAX - 1 || m < 0 || m > INT32_MAX / 2 || A_nnz < n || A_nnz > INT32_MAX - 1 ||
+      !points_dev || (m > 0 && !edges_dev) || !A_rowptr_dev || !A_col_dev || !A_val_dev) {
+    set_error("invalid sizes or null pointers");
+    return GMG_INVALID_ARGUMENT;
+  }
+  gmg_handle_s* h = new gmg_handle_s();
+  h->stream = (hipStream_t)stream;
+  if (opt) h->opt = *opt; else gmg_default_options(&h->opt);
+  if (!options_ok(h->opt)) {
+    delete h;
+    set_error("invalid options");
+    return GMG_INVALID_ARGUMENT;
+  }
+  try {
+    check_hip(hipGetDevice(&h->device), "hipGetDevice");
+    ensure_pool(h->device);
+    build(*h, n, points_dev, m, edges_dev, A_rowptr_dev, A_col_dev, A_val_dev, A_nnz);
+  } catch (const Error& e) {
+    set_error(e.msg);
+    release(h);
+    return e.status;
+  }
+  *out = h;
+  return GMG_OK;
+}
+
+int gmg_solve(gmg_handle hh, const double* b_dev, double* x_dev, double tol, int32_t max_iters, void* stream,
+              gmg_solve_info* info, double* residual_history) {
+  set_error("");
+  Handle* h = hh;
+  if (!h || !b_dev || !x_dev || max_iters < 1 || !(tol >= 0.0)) {
+    set_error("invalid solve arguments");
+    return GMG_INVALID_ARGUMENT;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  hipStream_t saved = h->stream;
+  h->stream = s;                               // synchronous reads below use the solve stream
+  int status = GMG_OK;
+  try {
+    Level& l0 = h->L[0];
+    const int64_t n = l0.n;
+    double* red = h->red;
+    double* hs = pinned_scratch();
+    check_hip(hipMemsetAsync(h->flags, 0, 4, s), "memset");
+    check_finite(b_dev, n, h->flags, s);
+    check_finite(x_dev, n, h->flags, s);
+    norm2_partials(b_dev, n, red, s);
+    finish_norm(red, red + kNormBlocks, s);
+    const double nb = [&] {
+      check_hip(hipMemcpyAsync(hs, red + kNormBlocks, 8, hipMemcpyDeviceToHost, s), "copy");
+      sync(s, "norm of b");
+      return hs[0];
+    }();
+    if ((int32_t)read_i64(*h, h->flags, 4) & F_INVALID) throw Error{GMG_INVALID_ARGUMENT, "non-finite b or x"};
+    if (info) {
+      info->iterations = 0;
+      info->converged = 0;
+      info->rel_residual = 0.0;
+    }
+    if (nb == 0.0) {
+      fill_f64(x_dev, 0.0, n, s);
+      sync(s, "solve");
+      if (info) info->converged = 1;
+      h->stream = saved;
+      return GMG_OK;
+    }
+    permute_in(l0.perm, b_dev, l0.b, n, s);
+    permute_in(l0.perm, x_dev, l0.x, n, s);
+    status = GMG_NOT_CONVERGED;
+    double rel = 0.0;
+    int32_t it = 0;
+    while (it < max_iters) {
+      vcycle(*h, 0, s);
+      residual_norm(l0, red, s);
+      finish_norm(red, red + kNormBlocks, s);
+      check_hip(hipMemcpyAsync(hs, red + kNormBlocks, 8, hipMemcpyDeviceToHost, s), "copy");
+      sync(s, "V-cycle");
+      ++it;
+      rel = hs[0] / nb;
+      if (residual_history) residual_history[it - 1] = rel;
+      if (rel <= tol) {
+        status = GMG_OK;
+        break;
+      }
+    }
+    permute_out(l0.perm, l0.x, x_dev, n, s);
+    sync(s, "solve");
+    if (info) {
+      info->iterations = it;
+      info->converged = status == GMG_OK;
+      info->rel_residual = rel;
+    }
+  } catch (const Error& e) {
+    set_error(e.msg);
+    status = e.status;
+  }
+  h->stream = saved;
+  return status;
+}
+
+void gmg_free(gmg_handle h) { release(h); }
+
+const char* gmg_status_string(int status) { return status_text(status); }
+
+const char* gmg_last_error(void) { return g_last_error.c_str(); }
+
+int gmg_num_levels(gmg_handle h, int32_t* levels) {
+  if (!h || !levels) return GMG_INVALID_ARGUMENT;
+  *levels = (int32_t)h->L.size();
+  return GMG_OK;
+}
+
+int gmg_level_sizes(gmg_handle h, int32_t l, int64_t* sz) {
+  if (!h || !sz || l < 0 || l >= (int32_t)h->L.size()) return GMG_INVALID_ARGUMENT;
+  const Level& lv = h->L[l];
+  sz[0] = lv.n;
+  sz[1] = lv.nnzE / 2;
+  sz[2] = lv.nnzA;
+  sz[3] = lv.nc ? lv.nnzP : 0;
+  sz[4] = lv.color ? lv.ncolors : 0;
+  sz[5] = lv.nc ? lv.fallback : 0;
+  sz[6] = lv.nc;
+  sz[7] = lv.nnzE;
+  return GMG_OK;
+}
+
+int gmg_export_level(gmg_handle h, int32_t l, int32_t what, void* dst, int64_t bytes) {
+  set_error("");
+  if (!h || l < 0 || l >= (int32_t)h->L.size() || (!dst && bytes)) return GMG_INVALID_ARGUMENT;
+  const Level& lv = h->L[l];
+  const bool coarse = l + 1 == (int32_t)h->L.size();
+  const int64_t n = lv.n, has = lv.nc ? n : 0;
+  const void* src = nullptr;
+  int64_t nb = 0;
+  switch (what) {
+    case GMG_EXPORT_POSITIONS: src = lv.X; nb = 24 * n; break;
+    case GMG_EXPORT_EDGE_ROWPTR: src = lv.erp; nb = 4 * (n + 1); break;
+    case GMG_EXPORT_EDGE_COL: src = lv.ecol; nb = 4 * lv.nnzE; break;
+    case GMG_EXPORT_EDGE_W: src = lv.ew; nb = lv.ew ? 8 * lv.nnzE : 0; break;
+    case GMG_EXPORT_SCALARS: src = lv.scal; nb = 16; break;
+    case GMG_EXPORT_SAMPLES: src = lv.samples; nb = 4 * lv.nc; break;
+    case GMG_EXPORT_LABELS: src = lv.label; nb = 4 * has; break;
+    case GMG_EXPORT_DIST: src = lv.dist; nb = 8 * has; break;
+    case GMG_EXPORT_P_COL: src = lv.pcol; nb = 12 * has; break;
+    case GMG_EXPORT_P_VAL: src = lv.pval; nb = 24 * has; break;
+    case GMG_EXPORT_P_CNT: src = lv.pcnt; nb = 4 * has; break;
+    case GMG_EXPORT_TRI: src = lv.tri; nb = 8 * has; break;
+    case GMG_EXPORT_A_ROWPTR: src = lv.arp; nb = 4 * (n + 1); break;
+    case GMG_EXPORT_A_COL: src = lv.acol; nb = 4 * lv.nnzA; break;
+    case GMG_EXPORT_A_VAL: src = lv.aval; nb = 8 * lv.nnzA; break;
+    case GMG_EXPORT_COLORS: src = lv.color; nb = lv.color ? 4 * n : 0; break;
+    case GMG_EXPORT_CHOL:
+      if (!coarse) return GMG_INVALID_ARGUMENT;
+      src = h->chol; nb = 8 * n * n; break;
+    default: return GMG_INVALID_ARGUMENT;
+  }
+  if (bytes != nb) {
+    set_error("export size mismatch");
+    return GMG_INVALID_ARGUMENT;
+  }
+  if (nb == 0) return GMG_OK;
+  hipError_t e = hipMemcpy(dst, src, (size_t)nb, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) {
+    set_error(hipGetErrorString(e));
+    return GMG_DEVICE_ERROR;
+  }
+  return GMG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,188 @@
+// Internal declarations of the MI355X Gravo MG library: device helpers shared
+// by the kernels, the hierarchy data layout in HBM and the host launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/gmg.h"
+
+namespace gmg {
+
+constexpr int kBlock = 256;          // threads per block of the streaming kernels
+constexpr int kWave = 64;            // CDNA wavefront
+constexpr int kSlice = 64;           // rows per SELL slice = one wavefront
+constexpr double kDegenerateTau = 1e-12;
+constexpr int64_t kMaxDenseCoarse = 4096;
+constexpr uint64_t kColorSalt = 0xC2B2AE3D27D4EB4FULL;
+constexpr int kRoundBatch = 8;       // rounds launched between host checks of a frontier loop
+constexpr int kMaxRounds = 4096;
+
+// Device error flags (bit set in Handle::flags[0]).
+enum : int { F_INVALID = 1, F_NOT_SPD = 2, F_OVERFLOW = 4 };
+
+// ------------------------------------------------------------------ device helpers
+// SplitMix64 finaliser (Steele, Lea & Flood 2014), the hashed sweep/colour order key.
+__host__ __device__ inline uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+struct V3 { double x, y, z; };
+__device__ inline V3 ld3(const double* X, int64_t i) { return {X[3 * i], X[3 * i + 1], X[3 * i + 2]}; }
+__device__ inline V3 sub3(V3 a, V3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+// Fixed association order ((x + y) + z); the library is built with -ffp-contract=off.
+__device__ inline double dot3(V3 a, V3 b) { return (a.x * b.x + a.y * b.y) + a.z * b.z; }
+__device__ inline V3 cross3(V3 a, V3 b) {
+  return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+
+template <typename T>
+__device__ inline T wave_sum(T v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+inline int blocks_for(int64_t n, int per_block = kBlock) {
+  int64_t b = (n + per_block - 1) / per_block;
+  return (int)(b < 1 ? 1 : b);
+}
+
+// ------------------------------------------------------------------ hierarchy layout
+// One level.  "Original" arrays use the level's own point numbering (what the
+// method defines and what is exported); the solve arrays use the colour-sorted
+// numbering new = iperm[old] in which every colour class is a contiguous row
+// range, so that a Gauss-Seidel colour sweep streams contiguous memory.
+struct Level {
+  int64_t n = 0;
+  double* X = nullptr;                  // n x 3 AoS positions
+  int32_t* erp = nullptr;               // edge CSR (symmetric, sorted, no loops)
+  int32_t* ecol = nullptr;
+  double* ew = nullptr;                 // edge lengths per CSR entry
+  int64_t nnzE = 0;
+  double* scal = nullptr;               // device [e_hat, r]
+  bool sampled = false;                 // sampling ran on this level
+  // coarsening products (levels that are not the coarsest)
+  int64_t nc = 0;                       // coarse points taken from this level
+  int32_t* samples = nullptr;           // [nc] fine index of each coarse point
+  int32_t* label = nullptr;             // [n]
+  double* dist = nullptr;               // [n]
+  uint8_t* status = nullptr;            // [n] sweep status, alive from sampling to the Voronoi step
+  int32_t* pcol = nullptr;              // [3n] ELL-3, unused -1
+  double* pval = nullptr;               // [3n] unused 0
+  int32_t* pcnt = nullptr;              // [n]
+  int32_t* tri = nullptr;               // [2n]
+  int64_t nnzP = 0, fallback = 0;
+  // operator A_l (original numbering)
+  int32_t* arp = nullptr;
+  int32_t* acol = nullptr;
+  double* aval = nullptr;
+  int64_t nnzA = 0;
+  // Gauss-Seidel colouring
+  int32_t* color = nullptr;
+  int32_t ncolors = 0;
+  std::vector<int32_t> color_ptr;       // host: rows [color_ptr[c], color_ptr[c+1]) in new numbering
+  // solve layout (new numbering)
+  int32_t* perm = nullptr;              // perm[new] = old
+  int32_t* iperm = nullptr;             // iperm[old] = new
+  int32_t* s_ptr = nullptr;             // SELL-64: slice s entries start at s_ptr[s]
+  int32_t* s_col = nullptr;             //   entry t of row r: s_ptr[r/64] + t*64 + r%64
+  double* s_val = nullptr;
+  int32_t* s_len = nullptr;             //   row lengths
+  double* diag = nullptr;
+  int32_t* q_col = nullptr;             // P in new numbering, SoA ELL-3: [3][n] (coarse new ids)
+  double* q_val = nullptr;
+  int32_t* q_cnt = nullptr;
+  int32_t* t_rp = nullptr;              // P^T in new numbering: rows = coarse new ids,
+  int32_t* t_col = nullptr;             //   entries ascending in the original fine index
+  double* t_val = nullptr;
+  double* x = nullptr;                  // work vectors
+  double* b = nullptr;
+  double* r = nullptr;
+};
+
+struct Handle {
+  int device = 0;
+  hipStream_t stream = nullptr;         // build stream (frees are ordered on it)
+  gmg_options opt{};
+  std::vector<Level> L;
+  int64_t ncoarse = 0;
+  double* chol = nullptr;               // dense lower factor of the coarsest A
+  double* cinv = nullptr;               // dense inverse of the coarsest A (row-major)
+  int32_t* flags = nullptr;             // device error flags and counters
+  int32_t* rounds = nullptr;            // device per-round counters of frontier loops
+  double* red = nullptr;                // reduction partials
+  double* host_scal = nullptr;          // pinned host staging
+  std::vector<void*> allocs;
+};
+
+// ------------------------------------------------------------------ host utilities
+struct Error {
+  int status;
+  std::string msg;
+};
+
+void set_error(const std::string& m);
+void check_hip(hipError_t e, const char* what);           // throws Error
+void* dalloc(Handle& h, size_t bytes);                      // owned by the handle
+void* talloc(hipStream_t s, size_t bytes);                  // temporary (stream-ordered)
+void tfree(hipStream_t s, void* p);
+void sync(hipStream_t s, const char* what);
+int64_t read_i64(Handle& h, const void* dev_ptr, int bytes); // D2H of a 4- or 8-byte scalar (syncs)
+void check_flags(Handle& h, const char* phase);             // throws on device error flags
+
+// ------------------------------------------------------------------ launchers (prims.hip)
+// out[0..n] = exclusive prefix sum of in[0..n-1]; out[n] = total.  Returns nothing; total stays on device.
+void scan_i32(const int32_t* in, int32_t* out, int64_t n, hipStream_t s);
+void fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
+void fill_f64(double* p, double v, int64_t n, hipStream_t s);
+void iota_i32(int32_t* p, int64_t n, hipStream_t s);
+void segment_sort_unique(int32_t* keys, const int32_t* ptr, int32_t* cnt_out, int64_t nseg,
+                         hipStream_t s);
+void compact_segments(const int32_t* src, const int32_t* src_ptr, const int32_t* dst_ptr,
+                      int32_t* dst, int64_t nseg, hipStream_t s);
+
+// ------------------------------------------------------------------ launchers (setup_graph.hip)
+void validate_points(const double* X, int64_t n, int32_t* flags, hipStream_t s);
+void edges_to_csr(Handle& h, Level& lv, const int32_t* edges, int64_t m);
+void validate_matrix(const int32_t* rp, const int32_t* col, const double* val, int64_t n,
+                     int64_t nnz, int32_t* flags, hipStream_t s);
+void edge_weights(Level& lv, hipStream_t s);
+void mean_edge(Handle& h, Level& lv, double rho);
+int64_t sample_lfmis(Handle& h, Level& lv, int level);     // returns number of coarse points
+void voronoi(Handle& h, Level& lv);
+void cells_and_shift(Handle& h, Level& lv, Level& nx, bool shift, int32_t** cell_ptr,
+                     int32_t** cell_mem);
+void coarse_edges(Handle& h, Level& lv, Level& nx, const int32_t* cell_ptr, const int32_t* cell_mem);
+
+// ------------------------------------------------------------------ launchers (setup_prolong.hip)
+void prolongation(Handle& h, Level& lv, Level& nx);
+void transpose_p(Handle& h, Level& lv, int64_t nc, int32_t** t_rp, int32_t** t_col, double** t_val);
+void galerkin(Handle& h, Level& lv, Level& nx, const int32_t* t_rp, const int32_t* t_col,
+              const double* t_val);
+
+// ------------------------------------------------------------------ launchers (setup_solve.hip)
+void colouring(Handle& h, Level& lv, int level);
+void solve_layout(Handle& h, Level& lv, const Level* nx, const int32_t* t_rp, const int32_t* t_col,
+                  const double* t_val);
+void coarse_factor(Handle& h, Level& lv);
+
+// ------------------------------------------------------------------ launchers (solve.hip)
+void gs_sweep(const Level& lv, hipStream_t s);
+void residual(const Level& lv, hipStream_t s);
+void restrict_to(const Level& lv, Level& nx, hipStream_t s);
+void prolong_correct(Level& lv, const Level& nx, hipStream_t s);
+void coarse_solve(Handle& h, Level& lv, hipStream_t s);
+void permute_in(const int32_t* perm, const double* src, double* dst, int64_t n, hipStream_t s);
+void permute_out(const int32_t* perm, const double* src, double* dst, int64_t n, hipStream_t s);
+void norm2_partials(const double* v, int64_t n, double* partials, hipStream_t s);
+void residual_norm(const Level& lv, double* partials, hipStream_t s);
+void finish_norm(const double* partials, double* out, hipStream_t s);
+void check_finite(const double* v, int64_t n, int32_t* flag, hipStream_t s);
+constexpr int kNormBlocks = 1024;
+
+}  // namespace gmg

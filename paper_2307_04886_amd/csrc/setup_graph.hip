@@ -1,0 +1,497 @@
+// Hierarchy construction, graph part (Sec. 4.1-4.3): input canonicalisation,
+// edge lengths and the sampling radius (Eq. 1), the greedy sampling sweep as a
+// lexicographically-first maximal independent set, graph Voronoi cells by
+// parallel Bellman-Ford, coarse positions (cell means) and Voronoi-neighbour
+// edges.
+//
+// Every floating-point decision repeats the exact IEEE binary64 operation
+// sequence of the method's definition (no contraction: built with
+// -ffp-contract=off), so samples, labels and coarse edges are reproducible bit
+// for bit by any correct implementation.
+#include "gmg_internal.hpp"
+
+namespace gmg {
+
+namespace {
+
+// ------------------------------------------------------------------ validation
+__global__ void k_validate_points(const double* X, int64_t n3, int32_t* flags) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n3 && !isfinite(X[i])) atomicOr(flags, F_INVALID);
+}
+
+__global__ void k_edge_degree(const int32_t* edges, int64_t m, int64_t n, int32_t* deg, int32_t* flags) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m) return;
+  int32_t u = edges[2 * e], v = edges[2 * e + 1];
+  if (u < 0 || v < 0 || u >= n || v >= n) {
+    atomicOr(flags, F_INVALID);
+    return;
+  }
+  if (u == v) return;
+  atomicAdd(&deg[u], 1);
+  atomicAdd(&deg[v], 1);
+}
+
+__global__ void k_edge_scatter(const int32_t* edges, int64_t m, int64_t n, const int32_t* ptr,
+                               int32_t* cur, int32_t* out) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m) return;
+  int32_t u = edges[2 * e], v = edges[2 * e + 1];
+  if (u < 0 || v < 0 || u >= n || v >= n || u == v) return;
+  out[ptr[u] + atomicAdd(&cur[u], 1)] = v;
+  out[ptr[v] + atomicAdd(&cur[v], 1)] = u;
+}
+
+// Row i of the system matrix: valid offsets, strictly ascending in-range
+// columns, finite values, diagonal present and positive, symmetric pattern.
+__global__ void k_validate_matrix(const int32_t* rp, const int32_t* col, const double* val, int64_t n,
+                                  int64_t nnz, int32_t* flags) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0 && (rp[0] != 0 || rp[n] != nnz)) atomicOr(flags, F_INVALID);
+  if (i >= n) return;
+  int32_t b = rp[i], e = rp[i + 1];
+  if (b < 0 || e < b || e > nnz) {
+    atomicOr(flags, F_INVALID);
+    return;
+  }
+  bool diag = false;
+  for (int32_t k = b; k < e; ++k) {
+    int32_t j = col[k];
+    if (j < 0 || j >= n || (k > b && j <= col[k - 1]) || !isfinite(val[k])) {
+      atomicOr(flags, F_INVALID);
+      return;
+    }
+    if (j == i) {
+      diag = true;
+      if (!(val[k] > 0.0)) atomicOr(flags, F_NOT_SPD);
+    }
+    int32_t jb = rp[j], je = rp[j + 1];
+    if (jb < 0 || je < jb || je > nnz) {
+      atomicOr(flags, F_INVALID);
+      return;
+    }
+    int32_t lo = jb, hi = je;                     // binary search for i in row j
+    while (lo < hi) {
+      int32_t mid = (lo + hi) >> 1;
+      if (col[mid] < i) lo = mid + 1; else hi = mid;
+    }
+    if (lo >= je || col[lo] != i) {
+      atomicOr(flags, F_INVALID);
+      return;
+    }
+  }
+  if (!diag) atomicOr(flags, F_INVALID);
+}
+
+// ------------------------------------------------------------------ edge lengths, Eq. (1)
+__global__ void k_edge_weights(const double* X, const int32_t* rp, const int32_t* col, int64_t n,
+                               double* w) {
+  int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= n) return;
+  V3 pu = ld3(X, u);
+  for (int32_t e = rp[u]; e < rp[u + 1]; ++e) {
+    V3 d = sub3(pu, ld3(X, col[e]));
+    w[e] = sqrt(dot3(d, d));
+  }
+}
+
+// Longest undirected edge, as the bit pattern of a non-negative double
+// (ordered like the value), combined with an unsigned 64-bit atomic max.
+__global__ void k_edge_max(const int32_t* rp, const int32_t* col, const double* w, int64_t n,
+                           unsigned long long* maxbits) {
+  int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long m = 0;
+  if (u < n)
+    for (int32_t e = rp[u]; e < rp[u + 1]; ++e)
+      if (u < col[e]) {
+        unsigned long long b = (unsigned long long)__double_as_longlong(w[e]);
+        m = b > m ? b : m;
+      }
+  for (int o = 32; o > 0; o >>= 1) {
+    unsigned long long t = __shfl_xor(m, o, 64);
+    m = t > m ? t : m;
+  }
+  if ((threadIdx.x & 63) == 0 && m) atomicMax(maxbits, m);
+}
+
+__device__ inline int fixed_point_shift(double M, int64_t cnt) {
+  int ex = 0;
+  frexp(M, &ex);
+  int lg = 0;
+  while ((int64_t(1) << lg) < cnt) ++lg;
+  return 62 - ex - lg;
+}
+
+// Exact, order-independent sum of the undirected edge lengths in 64-bit fixed
+// point: with the longest edge M < 2^e, each length scaled by 2^F,
+// F = 62 - e - ceil(log2 m), rounds to an integer below 2^(62 - ceil log2 m).
+__global__ void k_edge_fixsum(const int32_t* rp, const int32_t* col, const double* w, int64_t n,
+                              int64_t cnt, const unsigned long long* maxbits, unsigned long long* sum) {
+  double M = __longlong_as_double((long long)*maxbits);
+  if (M == 0.0) return;
+  int F = fixed_point_shift(M, cnt);
+  int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  long long s = 0;
+  if (u < n)
+    for (int32_t e = rp[u]; e < rp[u + 1]; ++e)
+      if (u < col[e]) s += (long long)rint(ldexp(w[e], F));
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0 && s) atomicAdd(sum, (unsigned long long)s);
+}
+
+__global__ void k_edge_mean_finish(const unsigned long long* maxbits, const unsigned long long* sum,
+                                   int64_t cnt, double rho, double* scal) {
+  double M = __longlong_as_double((long long)*maxbits);
+  if (cnt == 0 || M == 0.0) {
+    scal[0] = 0.0;
+    scal[1] = 0.0;
+    return;
+  }
+  int F = fixed_point_shift(M, cnt);
+  double ehat = ldexp((double)(long long)*sum, -F) / (double)cnt;
+  scal[0] = ehat;
+  scal[1] = rho * ehat;
+}
+
+// ------------------------------------------------------------------ sampling (Sec. 4.2)
+// Sweep order key (hashed or index); ties by index.
+struct SweepKey {
+  uint64_t base;
+  bool by_index;
+  __device__ uint64_t operator()(int32_t v) const { return by_index ? 0ull : mix64(base ^ (uint64_t)v); }
+};
+
+__device__ inline bool key_less(uint64_t ka, int32_t a, uint64_t kb, int32_t b) {
+  return ka < kb || (ka == kb && a < b);
+}
+
+// One round of the parallel greedy sweep.  An undecided point joins the
+// sample set when every point in conflict with it (within path length r over
+// at most two edges) that comes earlier in the sweep order is already
+// excluded; it is excluded as soon as one of them is a sample.  Decisions are
+// final, so statuses are updated in place; the result equals the sequential
+// sweep's for any interleaving.
+__global__ void __launch_bounds__(kBlock) k_lfmis_round(const int32_t* rp, const int32_t* col,
+                                                        const double* w, int64_t n, const double* scal,
+                                                        SweepKey key, uint8_t* status, int32_t* rounds,
+                                                        int k) {
+  if (k > 0 && rounds[k - 1] == 0) return;
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool undecided = false;
+  if (p < n && status[p] == 0) {
+    const double r = scal[1];
+    const uint64_t kp = key((int32_t)p);
+    bool blocked = false, out = false;
+    for (int32_t e = rp[p]; e < rp[p + 1] && !out; ++e) {
+      int32_t m = col[e];
+      double wpm = w[e];
+      if (wpm <= r && key_less(key(m), m, kp, (int32_t)p)) {
+        uint8_t s = __atomic_load_n(&status[m], __ATOMIC_RELAXED);
+        if (s == 1) out = true; else if (s == 0) blocked = true;
+      }
+      for (int32_t f = rp[m]; f < rp[m + 1] && !out; ++f) {
+        int32_t q = col[f];
+        if (q != p && wpm + w[f] <= r && key_less(key(q), q, kp, (int32_t)p)) {
+          uint8_t s = __atomic_load_n(&status[q], __ATOMIC_RELAXED);
+          if (s == 1) out = true; else if (s == 0) blocked = true;
+        }
+      }
+    }
+    if (out) status[p] = 2;
+    else if (!blocked) status[p] = 1;
+    else undecided = true;
+  }
+  unsigned long long b = __ballot(undecided);
+  if ((threadIdx.x & 63) == 0 && b) atomicAdd(&rounds[k], __popcll(b));
+}
+
+__global__ void k_seed_flags(const uint8_t* status, int64_t n, int32_t* f) {
+  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < n) f[v] = status[v] == 1 ? 1 : 0;
+}
+
+__global__ void k_collect_samples(const uint8_t* status, const int32_t* ids, int64_t n, int32_t* samples) {
+  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < n && status[v] == 1) samples[ids[v]] = (int32_t)v;
+}
+
+// ------------------------------------------------------------------ graph Voronoi (Sec. 4.3)
+__global__ void k_voronoi_init(const uint8_t* status, const int32_t* ids, int64_t n, double* d, int32_t* lab) {
+  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  bool seed = status[v] == 1;
+  d[v] = seed ? 0.0 : INFINITY;
+  lab[v] = seed ? ids[v] : -1;
+}
+
+// One Jacobi Bellman-Ford round over (distance, coarse id) pairs compared
+// lexicographically: a point takes the smallest (d(u) + w_uv, label(u)) over
+// its neighbours.  From +inf this converges to the multi-source shortest-path
+// labelling with ties going to the smaller coarse id (same fixed point as a
+// multi-source Dijkstra with lexicographic keys).
+__global__ void __launch_bounds__(kBlock) k_voronoi_round(const int32_t* rp, const int32_t* col,
+                                                          const double* w, const uint8_t* status,
+                                                          int64_t n, const double* dA, const int32_t* lA,
+                                                          double* dB, int32_t* lB, int32_t* rounds, int k) {
+  if (k > 0 && rounds[k - 1] == 0) return;
+  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool changed = false;
+  if (v < n) {
+    double bd = dA[v];
+    int32_t bl = lA[v];
+    if (status[v] != 1) {
+      for (int32_t e = rp[v]; e < rp[v + 1]; ++e) {
+        int32_t u = col[e];
+        int32_t lu = lA[u];
+        if (lu < 0) continue;
+        double c = dA[u] + w[e];
+        if (c < bd || (c == bd && lu < bl)) {
+          bd = c;
+          bl = lu;
+        }
+      }
+      changed = (bd != dA[v]) || (bl != lA[v]);
+    }
+    dB[v] = bd;
+    lB[v] = bl;
+  }
+  unsigned long long b = __ballot(changed);
+  if ((threadIdx.x & 63) == 0 && b) atomicAdd(&rounds[k], __popcll(b));
+}
+
+// ------------------------------------------------------------------ cells, shift (Sec. 4.4)
+__global__ void k_count_labels(const int32_t* lab, int64_t n, int32_t* cnt) {
+  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < n) atomicAdd(&cnt[lab[v]], 1);
+}
+
+__global__ void k_scatter_labels(const int32_t* lab, int64_t n, const int32_t* ptr, int32_t* cur, int32_t* mem) {
+  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < n) {
+    int32_t I = lab[v];
+    mem[ptr[I] + atomicAdd(&cur[I], 1)] = (int32_t)v;
+  }
+}
+
+// Coarse point I = mean of its cell's points, summed in ascending fine index
+// from 0.0 (or the sample's own position without the shift).
+__global__ void k_cell_mean(const double* X, const int32_t* ptr, const int32_t* mem, const int32_t* samples,
+                            int64_t nc, int shift, double* Xc) {
+  int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= nc) return;
+  if (!shift) {
+    int64_t s = samples[I];
+    Xc[3 * I] = X[3 * s];
+    Xc[3 * I + 1] = X[3 * s + 1];
+    Xc[3 * I + 2] = X[3 * s + 2];
+    return;
+  }
+  double sx = 0.0, sy = 0.0, sz = 0.0;
+  int32_t b = ptr[I], e = ptr[I + 1];
+  for (int32_t k = b; k < e; ++k) {
+    int64_t i = mem[k];
+    sx = sx + X[3 * i];
+    sy = sy + X[3 * i + 1];
+    sz = sz + X[3 * i + 2];
+  }
+  double c = (double)(e - b);
+  Xc[3 * I] = sx / c;
+  Xc[3 * I + 1] = sy / c;
+  Xc[3 * I + 2] = sz / c;
+}
+
+// ------------------------------------------------------------------ Voronoi-neighbour edges (Sec. 4.3)
+__global__ void k_cell_degree(const int32_t* ptr, const int32_t* mem, const int32_t* rp, int64_t nc,
+                              int32_t* cdeg) {
+  int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= nc) return;
+  int32_t s = 0;
+  for (int32_t k = ptr[I]; k < ptr[I + 1]; ++k) s += rp[mem[k] + 1] - rp[mem[k]];
+  cdeg[I] = s;
+}
+
+// The distinct cells J != I reached by an edge from cell I, kept sorted in
+// this cell's slot range of `tmp` by insertion.
+__global__ void k_cell_neighbours(const int32_t* ptr, const int32_t* mem, const int32_t* rp,
+                                  const int32_t* col, const int32_t* lab, const int32_t* cptr,
+                                  int64_t nc, int32_t* tmp, int32_t* ucnt) {
+  int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= nc) return;
+  int32_t* out = tmp + cptr[I];
+  int32_t u = 0;
+  for (int32_t k = ptr[I]; k < ptr[I + 1]; ++k) {
+    int32_t a = mem[k];
+    for (int32_t e = rp[a]; e < rp[a + 1]; ++e) {
+      int32_t J = lab[col[e]];
+      if (J == (int32_t)I) continue;
+      int32_t lo = 0, hi = u;
+      while (lo < hi) {
+        int32_t mid = (lo + hi) >> 1;
+        if (out[mid] < J) lo = mid + 1; else hi = mid;
+      }
+      if (lo < u && out[lo] == J) continue;
+      for (int32_t t = u; t > lo; --t) out[t] = out[t - 1];
+      out[lo] = J;
+      ++u;
+    }
+  }
+  ucnt[I] = u;
+}
+
+}  // namespace
+
+void validate_points(const double* X, int64_t n, int32_t* flags, hipStream_t s) {
+  k_validate_points<<<blocks_for(3 * n), kBlock, 0, s>>>(X, 3 * n, flags);
+}
+
+void edges_to_csr(Handle& h, Level& lv, const int32_t* edges, int64_t m) {
+  hipStream_t s = h.stream;
+  int64_t n = lv.n;
+  int32_t* deg = (int32_t*)talloc(s, (size_t)(n + 1) * 4);
+  int32_t* tptr = (int32_t*)talloc(s, (size_t)(n + 1) * 4);
+  int32_t* cur = (int32_t*)talloc(s, (size_t)(n + 1) * 4);
+  int32_t* tmp = (int32_t*)talloc(s, (size_t)(2 * m + 1) * 4);
+  check_hip(hipMemsetAsync(deg, 0, (size_t)(n + 1) * 4, s), "memset");
+  check_hip(hipMemsetAsync(cur, 0, (size_t)(n + 1) * 4, s), "memset");
+  if (m > 0) k_edge_degree<<<blocks_for(m), kBlock, 0, s>>>(edges, m, n, deg, h.flags);
+  scan_i32(deg, tptr, n, s);
+  if (m > 0) k_edge_scatter<<<blocks_for(m), kBlock, 0, s>>>(edges, m, n, tptr, cur, tmp);
+  segment_sort_unique(tmp, tptr, deg, n, s);
+  lv.erp = (int32_t*)dalloc(h, (size_t)(n + 1) * 4);
+  scan_i32(deg, lv.erp, n, s);
+  lv.nnzE = read_i64(h, lv.erp + n, 4);
+  check_flags(h, "edge array");
+  lv.ecol = (int32_t*)dalloc(h, (size_t)(lv.nnzE + 1) * 4);
+  compact_segments(tmp, tptr, lv.erp, lv.ecol, n, s);
+  tfree(s, deg);
+  tfree(s, tptr);
+  tfree(s, cur);
+  tfree(s, tmp);
+}
+
+void validate_matrix(const int32_t* rp, const int32_t* col, const double* val, int64_t n, int64_t nnz,
+                     int32_t* flags, hipStream_t s) {
+  k_validate_matrix<<<blocks_for(n), kBlock, 0, s>>>(rp, col, val, n, nnz, flags);
+}
+
+void edge_weights(Level& lv, hipStream_t s) {
+  k_edge_weights<<<blocks_for(lv.n), kBlock, 0, s>>>(lv.X, lv.erp, lv.ecol, lv.n, lv.ew);
+}
+
+void mean_edge(Handle& h, Level& lv, double rho) {
+  hipStream_t s = h.stream;
+  unsigned long long* acc = (unsigned long long*)talloc(s, 16);
+  check_hip(hipMemsetAsync(acc, 0, 16, s), "memset");
+  int64_t cnt = lv.nnzE / 2;
+  k_edge_max<<<blocks_for(lv.n), kBlock, 0, s>>>(lv.erp, lv.ecol, lv.ew, lv.n, acc);
+  k_edge_fixsum<<<blocks_for(lv.n), kBlock, 0, s>>>(lv.erp, lv.ecol, lv.ew, lv.n, cnt, acc, acc + 1);
+  k_edge_mean_finish<<<1, 1, 0, s>>>(acc, acc + 1, cnt, rho, lv.scal);
+  tfree(s, acc);
+}
+
+// Runs sweep rounds until every point is decided; returns the number of
+// coarse points and fills lv.samples (ascending fine index = coarse id order).
+int64_t sample_lfmis(Handle& h, Level& lv, int level) {
+  hipStream_t s = h.stream;
+  int64_t n = lv.n;
+  uint8_t* status = (uint8_t*)talloc(s, (size_t)n);
+  check_hip(hipMemsetAsync(status, 0, (size_t)n, s), "memset");
+  check_hip(hipMemsetAsync(h.rounds, 0, kMaxRounds * 4, s), "memset");
+  SweepKey key{h.opt.seed ^ ((uint64_t)level << 32), h.opt.sample_order == 1};
+  int k = 0;
+  for (;;) {
+    for (int t = 0; t < kRoundBatch; ++t, ++k)
+      k_lfmis_round<<<blocks_for(n), kBlock, 0, s>>>(lv.erp, lv.ecol, lv.ew, n, lv.scal, key, status,
+                                                     h.rounds, k);
+    if (read_i64(h, h.rounds + (k - 1), 4) == 0) break;
+    if (k + kRoundBatch > kMaxRounds) throw Error{GMG_DEVICE_ERROR, "sampling did not terminate"};
+  }
+  int32_t* f = (int32_t*)talloc(s, (size_t)(n + 1) * 4);
+  int32_t* ids = (int32_t*)talloc(s, (size_t)(n + 1) * 4);
+  k_seed_flags<<<blocks_for(n), kBlock, 0, s>>>(status, n, f);
+  scan_i32(f, ids, n, s);
+  int64_t nc = read_i64(h, ids + n, 4);
+  lv.nc = nc;
+  lv.samples = (int32_t*)dalloc(h, (size_t)(nc + 1) * 4);
+  k_collect_samples<<<blocks_for(n), kBlock, 0, s>>>(status, ids, n, lv.samples);
+  lv.label = (int32_t*)dalloc(h, (size_t)n * 4);
+  lv.dist = (double*)dalloc(h, (size_t)n * 8);
+  k_voronoi_init<<<blocks_for(n), kBlock, 0, s>>>(status, ids, n, lv.dist, lv.label);
+  lv.status = status;                            // released by voronoi()
+  tfree(s, f);
+  tfree(s, ids);
+  return nc;
+}
+
+void voronoi(Handle& h, Level& lv) {
+  hipStream_t s = h.stream;
+  int64_t n = lv.n;
+  uint8_t* status = lv.status;
+  lv.status = nullptr;
+  double* dB = (double*)talloc(s, (size_t)n * 8);
+  int32_t* lB = (int32_t*)talloc(s, (size_t)n * 4);
+  check_hip(hipMemsetAsync(h.rounds, 0, kMaxRounds * 4, s), "memset");
+  int k = 0;
+  for (;;) {
+    for (int t = 0; t < kRoundBatch; ++t, ++k) {
+      const double* dA = (k % 2 == 0) ? lv.dist : dB;
+      const int32_t* lA = (k % 2 == 0) ? lv.label : lB;
+      double* dO = (k % 2 == 0) ? dB : lv.dist;
+      int32_t* lO = (k % 2 == 0) ? lB : lv.label;
+      k_voronoi_round<<<blocks_for(n), kBlock, 0, s>>>(lv.erp, lv.ecol, lv.ew, status, n, dA, lA, dO, lO,
+                                                       h.rounds, k);
+    }
+    if (read_i64(h, h.rounds + (k - 1), 4) == 0) break;
+    if (k + kRoundBatch > kMaxRounds) throw Error{GMG_DEVICE_ERROR, "Voronoi rounds did not terminate"};
+  }
+  // The first round without changes copied its input unchanged, so both
+  // buffers hold the fixed point; lv.dist / lv.label are final.
+  tfree(s, dB);
+  tfree(s, lB);
+  tfree(s, status);
+}
+
+void cells_and_shift(Handle& h, Level& lv, Level& nx, bool shift, int32_t** cell_ptr, int32_t** cell_mem) {
+  hipStream_t s = h.stream;
+  int64_t n = lv.n, nc = lv.nc;
+  int32_t* cnt = (int32_t*)talloc(s, (size_t)(nc + 1) * 4);
+  int32_t* cur = (int32_t*)talloc(s, (size_t)(nc + 1) * 4);
+  int32_t* ptr = (int32_t*)talloc(s, (size_t)(nc + 1) * 4);
+  int32_t* mem = (int32_t*)talloc(s, (size_t)n * 4);
+  check_hip(hipMemsetAsync(cnt, 0, (size_t)(nc + 1) * 4, s), "memset");
+  check_hip(hipMemsetAsync(cur, 0, (size_t)(nc + 1) * 4, s), "memset");
+  k_count_labels<<<blocks_for(n), kBlock, 0, s>>>(lv.label, n, cnt);
+  scan_i32(cnt, ptr, nc, s);
+  k_scatter_labels<<<blocks_for(n), kBlock, 0, s>>>(lv.label, n, ptr, cur, mem);
+  segment_sort_unique(mem, ptr, cnt, nc, s);     // members ascending (they are distinct)
+  nx.n = nc;
+  nx.X = (double*)dalloc(h, (size_t)nc * 3 * 8);
+  k_cell_mean<<<blocks_for(nc), kBlock, 0, s>>>(lv.X, ptr, mem, lv.samples, nc, shift ? 1 : 0, nx.X);
+  tfree(s, cnt);
+  tfree(s, cur);
+  *cell_ptr = ptr;
+  *cell_mem = mem;
+}
+
+void coarse_edges(Handle& h, Level& lv, Level& nx, const int32_t* cell_ptr, const int32_t* cell_mem) {
+  hipStream_t s = h.stream;
+  int64_t nc = nx.n;
+  int32_t* cdeg = (int32_t*)talloc(s, (size_t)(nc + 1) * 4);
+  int32_t* cptr = (int32_t*)talloc(s, (size_t)(nc + 1) * 4);
+  int32_t* tmp = (int32_t*)talloc(s, (size_t)(lv.nnzE + 1) * 4);
+  k_cell_degree<<<blocks_for(nc), kBlock, 0, s>>>(cell_ptr, cell_mem, lv.erp, nc, cdeg);
+  scan_i32(cdeg, cptr, nc, s);
+  k_cell_neighbours<<<blocks_for(nc), kBlock, 0, s>>>(cell_ptr, cell_mem, lv.erp, lv.ecol, lv.label, cptr,
+                                                      nc, tmp, cdeg);
+  nx.erp = (int32_t*)dalloc(h, (size_t)(nc + 1) * 4);
+  scan_i32(cdeg, nx.erp, nc, s);
+  nx.nnzE = read_i64(h, nx.erp + nc, 4);
+  nx.ecol = (int32_t*)dalloc(h, (size_t)(nx.nnzE + 1) * 4);
+  compact_segments(tmp, cptr, nx.erp, nx.ecol, nc, s);
+  tfree(s, cdeg);
+  tfree(s, cptr);
+  tfree(s, tmp);
+}
+
+}  // namespace gmg

@@ -1,0 +1,251 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle.
+
+Discrete outputs (samples, labels, coarse edges, triangle choices, P pattern,
+A patterns, colours) must match bit for bit; so must every value produced
+by a fixed operation sequence (positions, edge lengths, e_hat, Voronoi
+distances, P weights).  A_l values and the Cholesky factor are compared to
+1e-12 of their scale; the solve must reach the same V-cycle count and
+residual history (1e-10 relative) as the oracle.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.conftest import problem
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def gmg():
+    import paper_2307_04886_amd as g
+    g.library()
+    return g
+
+
+def both(prob, **opt):
+    g = gmg()
+    from paper_2307_04886_amd.binding import from_problem
+    o_orc = oracle.default_options(**opt)
+    o_gpu = g.default_options(**opt)
+    orc = oracle.Hierarchy.from_problem(prob, o_orc)
+    gpu, tensors = from_problem(prob, o_gpu)
+    return orc, gpu
+
+
+BITWISE = ["positions", "edge_rowptr", "edge_col", "edge_w", "scalars", "samples", "labels", "dist",
+           "p_col", "p_val", "p_cnt", "tri", "a_rowptr", "a_col", "colors"]
+ORC_CODE = {"positions": oracle.POSITIONS, "edge_rowptr": oracle.EDGE_ROWPTR, "edge_col": oracle.EDGE_COL,
+            "edge_w": oracle.EDGE_W, "scalars": oracle.SCALARS, "samples": oracle.SAMPLES,
+            "labels": oracle.LABELS, "dist": oracle.DIST, "p_col": oracle.P_COL, "p_val": oracle.P_VAL,
+            "p_cnt": oracle.P_CNT, "tri": oracle.TRI, "a_rowptr": oracle.A_ROWPTR, "a_col": oracle.A_COL,
+            "a_val": oracle.A_VAL, "colors": oracle.COLORS, "chol": oracle.CHOL}
+
+
+def compare_hierarchies(orc, gpu, name=""):
+    assert gpu.num_levels == orc.num_levels, (gpu.num_levels, orc.num_levels)
+    for l in range(orc.num_levels):
+        so, sg = orc.sizes(l), gpu.sizes(l)
+        assert so == sg, (name, l, so, sg)
+        for what in BITWISE:
+            a = orc.export(l, ORC_CODE[what]).reshape(-1)
+            b = gpu.export(l, what).reshape(-1)
+            assert a.shape == b.shape, (name, l, what, a.shape, b.shape)
+            if a.dtype == np.float64:
+                same = np.array_equal(a.view(np.int64), b.view(np.int64))
+            else:
+                same = np.array_equal(a, b)
+            if not same:
+                bad = np.nonzero(a != b)[0]
+                raise AssertionError(f"{name} level {l} {what}: {bad.size} of {a.size} differ, "
+                                     f"first {bad[:5]} oracle {a[bad[:5]]} gpu {b[bad[:5]]}")
+        # A_l values: same pattern, values to 1e-12 of the entry scale
+        av_o = orc.export(l, oracle.A_VAL)
+        av_g = gpu.export(l, "a_val")
+        scale = np.abs(av_o).max()
+        assert np.all(np.abs(av_o - av_g) <= 1e-12 * scale), (name, l)
+    L = orc.num_levels - 1
+    co, cg = orc.chol(), gpu.export(L, "chol")
+    assert np.all(np.abs(co - cg) <= 1e-12 * np.abs(co).max()), name
+
+
+def compare_solves(orc, gpu, prob, tol=1e-8, max_iters=200):
+    x_o, it_o, hist_o, st_o = orc.solve(prob.rhs, tol=tol, max_iters=max_iters)
+    b = torch.from_numpy(prob.rhs).cuda()
+    x_g, info, st_g, hist_g = gpu.solve(b, tol=tol, max_iters=max_iters, history=True)
+    torch.cuda.synchronize()
+    x_g = x_g.cpu().numpy()
+    near = abs(hist_o[-1] - tol) <= 1e-12 or (it_o > 1 and abs(hist_o[-2] - tol) <= 1e-12)
+    assert info.iterations == it_o or (near and abs(info.iterations - it_o) == 1), (info.iterations, it_o)
+    k = min(it_o, info.iterations)
+    # b - A x cancels to about 1e-16 |b|, so a relative residual carries that absolute error
+    assert np.all(np.abs(hist_g[:k] - hist_o[:k]) <= 1e-10 * hist_o[:k] + 1e-13), (hist_g[:k], hist_o[:k])
+    assert st_g == st_o
+    A = prob.matrix()
+    res = np.linalg.norm(prob.rhs - A @ x_g) / np.linalg.norm(prob.rhs)
+    assert res <= tol * (1 + 1e-9)
+    assert abs(res - info.rel_residual) <= 1e-9 * res
+    err = np.linalg.norm(x_g - x_o) / np.linalg.norm(x_o)
+    assert err <= 1e-9, err
+    return info.iterations, err
+
+
+SMALL = [("ico3", 100), ("ico4", 100), ("ico5", 1000), ("torus48", 100), ("torus96", 200), ("flat", 100),
+         ("pc4k", 200), ("pc20k", 500)]
+
+
+@pytest.mark.parametrize("name,minc", SMALL)
+def test_hierarchy_bitwise_small(name, minc):
+    _say(f"[gpu] hierarchy parity {name} min_coarse={minc}")
+    prob = problem(name)
+    orc, gpu = both(prob, min_coarse_points=minc)
+    compare_hierarchies(orc, gpu, name)
+
+
+@pytest.mark.parametrize("name,minc", SMALL)
+def test_solve_parity_small(name, minc):
+    _say(f"[gpu] solve parity {name}")
+    prob = problem(name)
+    orc, gpu = both(prob, min_coarse_points=minc)
+    compare_solves(orc, gpu, prob)
+
+
+@pytest.mark.parametrize("opt", [dict(sample_order=1), dict(shift_coarse_points=0), dict(seed=12345),
+                                 dict(coarsening_ratio=0.25), dict(nu_pre=1, nu_post=3)])
+def test_option_variants(opt):
+    _say(f"[gpu] options {opt}")
+    prob = problem("torus96")
+    orc, gpu = both(prob, min_coarse_points=200, **opt)
+    compare_hierarchies(orc, gpu, str(opt))
+    compare_solves(orc, gpu, prob)
+
+
+def test_config_icosphere_full():
+    _say("[gpu] icosphere 5 subdivisions, full pipeline")
+    prob = problem("ico5")
+    orc, gpu = both(prob)
+    compare_hierarchies(orc, gpu, "ico5")
+    it, err = compare_solves(orc, gpu, prob)
+    _say(f"[gpu] ico5 V-cycles {it} |x_gpu - x_orc| / |x_orc| = {err:.2e}")
+
+
+def test_config_torus_full():
+    _say("[gpu] torus 1024x1024, full pipeline (bench launch configuration)")
+    prob = problem("torus1024")
+    orc, gpu = both(prob)
+    compare_hierarchies(orc, gpu, "torus1024")
+    it, err = compare_solves(orc, gpu, prob)
+    _say(f"[gpu] torus1024 V-cycles {it} |x_gpu - x_orc| / |x_orc| = {err:.2e}")
+
+
+def test_determinism():
+    _say("[gpu] determinism")
+    prob = problem("torus96")
+    g = gmg()
+    from paper_2307_04886_amd.binding import from_problem
+    h1, _ = from_problem(prob, g.default_options(min_coarse_points=200))
+    h2, _ = from_problem(prob, g.default_options(min_coarse_points=200))
+    for l in range(h1.num_levels):
+        for what in BITWISE + ["a_val"]:
+            assert np.array_equal(h1.export(l, what), h2.export(l, what))
+    b = torch.from_numpy(prob.rhs).cuda()
+    x1 = h1.solve(b)[0].cpu().numpy()
+    x2 = h1.solve(b)[0].cpu().numpy()
+    assert np.array_equal(x1, x2)
+
+
+def test_edge_cases():
+    _say("[gpu] edge cases")
+    g = gmg()
+    from paper_2307_04886_amd.binding import build_hierarchy
+    prob = problem("ico3")
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    # duplicate edges, reversed edges and self loops in the input are canonicalised
+    e = np.concatenate([prob.edges, prob.edges[:, ::-1], np.stack([np.arange(5)] * 2, 1)]).astype(np.int32)
+    o = dict(min_coarse_points=100)
+    h = build_hierarchy(dev(prob.points), dev(e), dev(prob.indptr), dev(prob.indices), dev(prob.data),
+                        g.default_options(**o))
+    ho = oracle.Hierarchy(prob.points, e, prob.indptr, prob.indices, prob.data, oracle.default_options(**o))
+    compare_hierarchies(ho, h, "messy edges")
+    # no edges at all: every point is its own sample, the input level is solved directly
+    n = prob.n
+    rp = np.arange(n + 1, dtype=np.int32)
+    ci = np.arange(n, dtype=np.int32)
+    va = np.linspace(1.0, 2.0, n)
+    h = build_hierarchy(dev(prob.points), dev(np.zeros((0, 2), np.int32)), dev(rp), dev(ci), dev(va),
+                        g.default_options(**o))
+    assert h.num_levels == 1
+    b = torch.from_numpy(np.ones(n)).cuda()
+    x, info, st = h.solve(b)
+    assert st == 0 and info.iterations == 1
+    assert np.allclose(x.cpu().numpy(), 1.0 / va, rtol=1e-14)
+    # a single point
+    h = build_hierarchy(dev(np.zeros((1, 3))), dev(np.zeros((0, 2), np.int32)), dev(np.array([0, 1], np.int32)),
+                        dev(np.array([0], np.int32)), dev(np.array([4.0])), g.default_options())
+    x, info, st = h.solve(torch.tensor([2.0], dtype=torch.float64).cuda())
+    assert st == 0 and abs(x.item() - 0.5) < 1e-15
+    # zero right-hand side
+    from paper_2307_04886_amd.binding import from_problem
+    hh, _ = from_problem(prob, g.default_options(**o))
+    x, info, st = hh.solve(torch.zeros(n, dtype=torch.float64).cuda())
+    assert st == 0 and info.iterations == 0 and not x.abs().sum().item()
+    # iteration cap
+    x, info, st = hh.solve(torch.from_numpy(prob.rhs).cuda(), max_iters=1, tol=1e-14)
+    assert st == 1 and info.iterations == 1
+
+
+def test_error_paths():
+    _say("[gpu] error paths")
+    g = gmg()
+    from paper_2307_04886_amd.binding import build_hierarchy
+    prob = problem("ico3")
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    args = lambda **kw: [dev(kw.get(k, v)) for k, v in
+                         [("points", prob.points), ("edges", prob.edges), ("rowptr", prob.indptr),
+                          ("col", prob.indices), ("val", prob.data)]]
+    pts = prob.points.copy()
+    pts[7, 2] = np.nan
+    with pytest.raises(g.GMGError) as e:
+        build_hierarchy(*args(points=pts))
+    assert e.value.status == -1
+    bad = prob.edges.copy()
+    bad[3, 1] = prob.n + 5
+    with pytest.raises(g.GMGError) as e:
+        build_hierarchy(*args(edges=bad))
+    assert e.value.status == -1
+    ci = prob.indices.copy()
+    ci[prob.indptr[4]], ci[prob.indptr[4] + 1] = ci[prob.indptr[4] + 1], ci[prob.indptr[4]]
+    with pytest.raises(g.GMGError) as e:
+        build_hierarchy(*args(col=ci))
+    assert e.value.status == -1
+    va = prob.data.copy()
+    row = 9
+    va[prob.indptr[row]:prob.indptr[row + 1]][prob.indices[prob.indptr[row]:prob.indptr[row + 1]] == row] = -1.0
+    with pytest.raises(g.GMGError) as e:
+        build_hierarchy(*args(val=va))
+    assert e.value.status == -4
+    # indefinite matrix with a positive diagonal: the dense factorisation fails
+    import scipy.sparse as sp
+    M = prob.matrix()
+    off = M - sp.diags(M.diagonal())
+    Lp = off - sp.diags(np.asarray(off.sum(axis=1)).ravel())
+    A = (Lp - 0.05 * Lp.diagonal().min() * sp.eye(prob.n)).tocsr()
+    A.sort_indices()
+    with pytest.raises(g.GMGError) as e:
+        build_hierarchy(*args(rowptr=A.indptr.astype(np.int32), col=A.indices.astype(np.int32), val=A.data))
+    assert e.value.status == -4
+    h = build_hierarchy(*args())
+    b = torch.from_numpy(prob.rhs).cuda()
+    b[3] = float("inf")
+    with pytest.raises(g.GMGError) as e:
+        h.solve(b)
+    assert e.value.status == -1
