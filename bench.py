@@ -19,6 +19,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 
+KERNEL_NAMES = {"gs_finest": "k_gs_color_fine (one colour of a Gauss-Seidel sweep, level 0)",
+                "residual_finest": "k_residual_norm (residual + norm partials, level 0)"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -27,6 +31,8 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--size", type=int, default=1024, help="torus grid size (default 1024)")
+    ap.add_argument("--timer", default="gs_finest", choices=["gs_finest", "residual_finest", "none"],
+                    help="kernel class timed with HIP events for the roofline entry")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the method's single-mesh "
@@ -38,7 +44,7 @@ def main():
 
     import synth
     import paper_2307_04886_amd as g
-    from paper_2307_04886_amd.binding import build_hierarchy, default_options
+    from paper_2307_04886_amd.binding import build_hierarchy, default_options, timer_start, timer_stop
 
     g.library()
     dev = torch.device("cuda", 0)
@@ -69,10 +75,13 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    if args.timer != "none":
+        timer_start(args.timer, expected_launches=2000 * args.steps)
     t0 = time.perf_counter()
     infos = [step() for _ in range(args.steps)]
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    k_ms, k_launches, k_bytes = timer_stop() if args.timer != "none" else (float("nan"), 0, 0.0)
     info, levels = infos[-1]
     ms = 1e3 * dt / args.steps
 
@@ -92,7 +101,11 @@ def main():
         "config": {"workload": f"torus {args.size}x{args.size} jittered, cotan (M + 1e-3 L) x = M b",
                    "points": prob.n, "edges": prob.m, "nnz_A": prob.nnz, "levels": levels,
                    "v_cycles": info.iterations, "rel_residual": info.rel_residual, "tol": args.tol},
-        "roofline": None,
+        "roofline": None if args.timer == "none" else {"bound": "hbm", "kernel": KERNEL_NAMES[args.timer],
+                     "achieved": k_bytes / (k_ms * 1e-3) / 1e9, "peak": 8000.0, "unit": "GB/s",
+                     "frac": k_bytes / (k_ms * 1e-3) / 1e9 / 8000.0, "traffic": None,
+                     "launches": k_launches, "avg_launch_us": 1e3 * k_ms / max(k_launches, 1),
+                     "bytes_per_launch": k_bytes / max(k_launches, 1)},
         "cpu_baseline": None,
     }
 

@@ -157,6 +157,23 @@ enum gmg_export_what {
  */
 int gmg_export_level(gmg_handle h, int32_t level, int32_t what, void* host_dst, int64_t bytes);
 
+/*
+ * Measurement support (not part of the method).  Times every launch of one
+ * kernel class with a pair of HIP events recorded on the stream that kernel is
+ * launched on, and accumulates the algorithmic bytes of those launches
+ * (12 bytes per matrix entry read, 28 per row: right-hand side, diagonal,
+ * row length, result).  Process-wide: one timing session at a time.
+ *
+ *  kernel              GMG_TIMER_GS_FINEST: one colour of a Gauss-Seidel sweep on level 0;
+ *                      GMG_TIMER_RESIDUAL_FINEST: residual + norm partials on level 0
+ *  expected_launches   events to pre-create (more are created on demand)
+ * gmg_timer_stop waits for the recorded events and returns the summed kernel
+ * time in milliseconds, the number of timed launches and their bytes.
+ */
+enum gmg_timer_kernel { GMG_TIMER_GS_FINEST = 0, GMG_TIMER_RESIDUAL_FINEST = 1 };
+int gmg_timer_start(int32_t kernel, int32_t expected_launches);
+int gmg_timer_stop(double* total_ms, int64_t* launches, double* bytes);
+
 #ifdef __cplusplus
 }
 #endif

@@ -27,7 +27,11 @@ EXPORTS = {
 
 # Symbols the library exports (checked on load).
 SYMBOLS = ["gmg_default_options", "gmg_build_hierarchy", "gmg_solve", "gmg_free", "gmg_status_string",
-           "gmg_last_error", "gmg_num_levels", "gmg_level_sizes", "gmg_export_level"]
+           "gmg_last_error", "gmg_num_levels", "gmg_level_sizes", "gmg_export_level", "gmg_timer_start",
+           "gmg_timer_stop"]
+
+# kernel classes of gmg_timer_start
+TIMER_KERNELS = {"gs_finest": 0, "residual_finest": 1}
 
 
 class Options(ctypes.Structure):
@@ -74,8 +78,27 @@ def library():
     L.gmg_num_levels.argtypes = [P, ctypes.POINTER(I32)]
     L.gmg_level_sizes.argtypes = [P, I32, P]
     L.gmg_export_level.argtypes = [P, I32, I32, P, I64]
+    L.gmg_timer_start.argtypes = [I32, I32]
+    L.gmg_timer_stop.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64),
+                                 ctypes.POINTER(ctypes.c_double)]
     _lib = L
     return L
+
+
+def timer_start(kernel, expected_launches=0):
+    """gmg_timer_start: time every launch of one kernel class with HIP events (measurement only)."""
+    st = library().gmg_timer_start(TIMER_KERNELS[kernel], int(expected_launches))
+    if st:
+        raise _err(st)
+
+
+def timer_stop():
+    """gmg_timer_stop -> (total kernel ms, launches, algorithmic bytes)."""
+    ms, n, by = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
+    st = library().gmg_timer_stop(ctypes.byref(ms), ctypes.byref(n), ctypes.byref(by))
+    if st:
+        raise _err(st)
+    return ms.value, n.value, by.value
 
 
 def default_options(**kw):

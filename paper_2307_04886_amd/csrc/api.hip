@@ -2,7 +2,10 @@
 // the hierarchy construction (Sec. 4, Alg. 1), the V-cycle driver (Alg. 1,
 // Alg. 2) and the inspection exports.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 
@@ -28,12 +31,42 @@ void ensure_pool(int dev) {
   g_pool_ready[dev] = true;
 }
 
+constexpr size_t kStaging = 1 << 16;
+
 double* pinned_scratch() {
   static thread_local double* p = nullptr;
-  if (!p) check_hip(hipHostMalloc((void**)&p, 64, hipHostMallocDefault), "pinned host buffer");
+  if (!p) check_hip(hipHostMalloc((void**)&p, kStaging, hipHostMallocDefault), "pinned host buffer");
   return p;
 }
 }  // namespace
+
+void* pinned_staging(size_t bytes) {
+  if (bytes > kStaging / 2) throw Error{GMG_DEVICE_ERROR, "staging buffer too small"};
+  return (char*)pinned_scratch() + kStaging / 2;      // second half: bulk staging
+}
+
+void read_scalars(Handle& h, const ScalarRead* items, int count) {
+  char* buf = (char*)pinned_scratch();
+  for (int k = 0; k < count; ++k)
+    check_hip(hipMemcpyAsync(buf + 8 * k, items[k].src, items[k].bytes, hipMemcpyDeviceToHost, h.stream),
+              "device-to-host copy");
+  sync(h.stream, "device-to-host copy");
+  for (int k = 0; k < count; ++k) {
+    if (items[k].bytes == 4) {
+      int32_t v;
+      std::memcpy(&v, buf + 8 * k, 4);
+      *items[k].dst = v;
+    } else {
+      std::memcpy(items[k].dst, buf + 8 * k, 8);
+    }
+  }
+}
+
+void throw_flags(int32_t f, const char* phase) {
+  if (f & F_INVALID) throw Error{GMG_INVALID_ARGUMENT, std::string(phase) + ": invalid input"};
+  if (f & F_NOT_SPD) throw Error{GMG_NOT_SPD, std::string(phase) + ": non-positive diagonal or pivot"};
+  if (f & F_OVERFLOW) throw Error{GMG_DEVICE_ERROR, std::string(phase) + ": a coarse row is too dense"};
+}
 
 void set_error(const std::string& m) { g_last_error = m; }
 
@@ -80,11 +113,36 @@ int64_t read_i64(Handle& h, const void* dev_ptr, int bytes) {
   return v;
 }
 
-void check_flags(Handle& h, const char* phase) {
-  int32_t f = (int32_t)read_i64(h, h.flags, 4);
-  if (f & F_INVALID) throw Error{GMG_INVALID_ARGUMENT, std::string(phase) + ": invalid input"};
-  if (f & F_NOT_SPD) throw Error{GMG_NOT_SPD, std::string(phase) + ": non-positive diagonal or pivot"};
-  if (f & F_OVERFLOW) throw Error{GMG_DEVICE_ERROR, std::string(phase) + ": a coarse row is too dense"};
+void check_flags(Handle& h, const char* phase) { throw_flags((int32_t)read_i64(h, h.flags, 4), phase); }
+
+// ------------------------------------------------------------------ kernel timer
+int KernelTimer::active = -1;
+
+namespace {
+std::vector<hipEvent_t> g_ev;        // pairs (start, stop)
+size_t g_ev_used = 0;
+double g_bytes = 0.0;
+int64_t g_launches = 0;
+}  // namespace
+
+KernelTimer::Scope::Scope(int kind, hipStream_t s, double bytes) : stream(s) {
+  if (active != kind) return;
+  if (g_ev_used + 2 > g_ev.size()) {
+    for (int k = 0; k < 256; ++k) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return;
+      g_ev.push_back(e);
+    }
+  }
+  (void)hipEventRecord(g_ev[g_ev_used], s);
+  stop = g_ev[g_ev_used + 1];
+  g_ev_used += 2;
+  g_bytes += bytes;
+  g_launches += 1;
+}
+
+KernelTimer::Scope::~Scope() {
+  if (stop) (void)hipEventRecord(stop, stream);
 }
 
 namespace {
@@ -92,6 +150,9 @@ namespace {
 template <typename H>
 void release(H* h) {
   if (!h) return;
+  if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
+  if (h->graph) (void)hipGraphDestroy(h->graph);
+  if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   for (void* p : h->allocs) (void)hipFreeAsync(p, h->stream);
   (void)hipStreamSynchronize(h->stream);
   delete h;
@@ -114,6 +175,17 @@ void build(Handle& h, int64_t n, const double* points, int64_t m, const int32_t*
   hipStream_t s = h.stream;
   const gmg_options& o = h.opt;
   const double rho = std::cbrt(1.0 / o.coarsening_ratio);
+  // GMG_PROFILE_BUILD=1: synchronise after every phase and print host wall times (diagnostics)
+  const bool prof = std::getenv("GMG_PROFILE_BUILD") != nullptr;
+  const auto t_start = std::chrono::steady_clock::now();
+  double t_last = 0.0;
+  auto mark = [&](const char* what, int level) {
+    if (!prof) return;
+    sync(s, what);
+    double t = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    std::fprintf(stderr, "[gmg build] level %d %-22s %8.3f ms (+%.3f)\n", level, what, t, t - t_last);
+    t_last = t;
+  };
   h.flags = (int32_t*)dalloc(h, 64 * 4);
   h.rounds = (int32_t*)dalloc(h, kMaxRounds * 4);
   h.red = (double*)dalloc(h, (kNormBlocks + 8) * 8);
@@ -138,6 +210,9 @@ void build(Handle& h, int64_t n, const double* points, int64_t m, const int32_t*
     check_flags(h, "input");
     lv.scal = (double*)dalloc(h, 16);
     check_hip(hipMemsetAsync(lv.scal, 0, 16, s), "memset");
+    lv.stats = (unsigned long long*)dalloc(h, 16);
+    check_hip(hipMemsetAsync(lv.stats, 0, 16, s), "memset");
+    mark("input", 0);
   }
 
   std::vector<PT> pts;
@@ -147,36 +222,43 @@ void build(Handle& h, int64_t n, const double* points, int64_t m, const int32_t*
     Level nx;
     {
       Level& lv = h.L[l];
-      lv.ew = (double*)dalloc(h, (size_t)(lv.nnzE + 1) * 8);
+      lv.ew = (double*)dalloc(h, (size_t)(lv.nnzE_cap + 1) * 8);
       edge_weights(lv, s);
       mean_edge(h, lv, rho);
-      lv.sampled = true;
+      mark("edge lengths", l);
       int64_t nc = sample_lfmis(h, lv, l);
+      mark("sampling", l);
       if (nc == lv.n) {                       // no progress: this level becomes the coarsest
         tfree(s, lv.status);
         lv.status = nullptr;
         break;
       }
       voronoi(h, lv);
+      mark("voronoi", l);
       int32_t *cptr = nullptr, *cmem = nullptr;
       cells_and_shift(h, lv, nx, o.shift_coarse_points != 0, &cptr, &cmem);
       coarse_edges(h, lv, nx, cptr, cmem);
       tfree(s, cptr);
       tfree(s, cmem);
+      mark("cells, coarse edges", l);
       prolongation(h, lv, nx);
+      mark("prolongation", l);
       PT pt;
       transpose_p(h, lv, nx.n, &pt.rp, &pt.col, &pt.val);
+      mark("transpose", l);
       galerkin(h, lv, nx, pt.rp, pt.col, pt.val);
-      check_flags(h, "Galerkin operator");
+      mark("galerkin", l);
       pts.push_back(pt);
       nx.scal = (double*)dalloc(h, 16);
       check_hip(hipMemsetAsync(nx.scal, 0, 16, s), "memset");
+      nx.stats = (unsigned long long*)dalloc(h, 16);
+      check_hip(hipMemsetAsync(nx.stats, 0, 16, s), "memset");
     }
     h.L.push_back(nx);
   }
   Level& last = h.L.back();
-  if (!last.ew && last.nnzE > 0) {
-    last.ew = (double*)dalloc(h, (size_t)last.nnzE * 8);
+  if (!last.ew) {
+    last.ew = (double*)dalloc(h, (size_t)(last.nnzE_cap + 1) * 8);
     edge_weights(last, s);
   }
   last.nc = 0;                                // the coarsest level keeps no coarsening products
@@ -185,33 +267,160 @@ void build(Handle& h, int64_t n, const double* points, int64_t m, const int32_t*
   last.dist = nullptr;
   if (last.n > kMaxDenseCoarse) throw Error{GMG_DEGENERATE, "coarsening stalled above the dense-solve limit"};
   const int nl = (int)h.L.size();
-  for (int l = 0; l + 1 < nl; ++l) colouring(h, h.L[l], l);
+  for (int l = 0; l + 1 < nl; ++l) {
+    colouring(h, h.L[l], l);
+    mark("colouring", l);
+  }
   solve_layout(h, h.L[nl - 1], nullptr, nullptr, nullptr, nullptr);
-  for (int l = nl - 2; l >= 0; --l)
+  for (int l = nl - 2; l >= 0; --l) {
     solve_layout(h, h.L[l], &h.L[l + 1], pts[l].rp, pts[l].col, pts[l].val);
+    mark("solve layout", l);
+  }
   for (auto& pt : pts) {
     tfree(s, pt.rp);
     tfree(s, pt.col);
     tfree(s, pt.val);
   }
   coarse_factor(h, last);
+  mark("coarse factor", nl - 1);
+  // deferred sizes and statistics, with the error flags, in one synchronisation
+  {
+    std::vector<ScalarRead> rd;
+    std::vector<int64_t> vals(1 + 3 * nl);
+    rd.push_back({h.flags, 4, &vals[0]});
+    for (int l = 0; l < nl; ++l) {
+      rd.push_back({h.L[l].erp + h.L[l].n, 4, &vals[1 + 3 * l]});
+      rd.push_back({h.L[l].stats, 8, &vals[2 + 3 * l]});
+      rd.push_back({h.L[l].stats + 1, 8, &vals[3 + 3 * l]});
+    }
+    read_scalars(h, rd.data(), (int)rd.size());
+    throw_flags((int32_t)vals[0], "build");
+    for (int l = 0; l < nl; ++l) {
+      h.L[l].nnzE = vals[1 + 3 * l];
+      h.L[l].fallback = vals[2 + 3 * l];
+      h.L[l].nnzP = vals[3 + 3 * l];
+    }
+  }
+  // levels with few rows run their part of the V-cycle in one workgroup
+  h.tail_start = nl - 1;
+  while (h.tail_start > 0 && h.L[h.tail_start - 1].n <= kTailRows && nl - (h.tail_start - 1) <= kMaxTail)
+    --h.tail_start;
+  h.tail.nlev = nl - h.tail_start;
+  h.tail.nu_pre = o.nu_pre;
+  h.tail.nu_post = o.nu_post;
+  h.tail.cinv = h.cinv;
+  h.tail.lanes = 4;
+  h.tail.lds_doubles = 0;
+  for (int l = h.tail_start; l < nl; ++l) {
+    const LevelView& v = h.L[l].view;
+    h.tail.lv[l - h.tail_start] = v;
+    if (l + 1 < nl) h.tail.lanes = std::max({h.tail.lanes, v.ra, v.rt});
+    if (h.tail.lds_doubles + v.n <= kTailLdsDoubles) {
+      h.tail.lds_off[l - h.tail_start] = h.tail.lds_doubles;
+      h.tail.lds_doubles += (int32_t)v.n;
+    } else {
+      h.tail.lds_off[l - h.tail_start] = -1;
+    }
+  }
   sync(s, "build");
 }
 
+// MGI(x, b, l) of Alg. 2: pre-relax, restrict the residual, recurse from a
+// zero guess, prolong and correct the pre-relaxed iterate, post-relax.
 void vcycle(Handle& h, size_t l, hipStream_t s) {
   Level& lv = h.L[l];
-  if (l + 1 == h.L.size()) {
-    coarse_solve(h, lv, s);
+  if ((int)l == h.tail_start) {
+    if (h.tail.nlev == 1) coarse_solve(h, lv, s); else tail_vcycle(h, s);
     return;
   }
   Level& nx = h.L[l + 1];
-  for (int k = 0; k < h.opt.nu_pre; ++k) gs_sweep(lv, s);
-  residual(lv, s);
+  for (int k = 0; k < h.opt.nu_pre; ++k) gs_sweep(lv, s, l == 0);
+  residual(lv, s, l == 0);
   restrict_to(lv, nx, s);
   fill_f64(nx.x, 0.0, nx.n, s);
   vcycle(h, l + 1, s);
   prolong_correct(lv, nx, s);
-  for (int k = 0; k < h.opt.nu_post; ++k) gs_sweep(lv, s);
+  for (int k = 0; k < h.opt.nu_post; ++k) gs_sweep(lv, s, l == 0);
+}
+
+// The part of the level-0 V-cycle between pre- and post-smoothing.
+void cycle_inner(Handle& h, hipStream_t s) {
+  Level& l0 = h.L[0];
+  Level& l1 = h.L[1];
+  residual(l0, s, true);
+  restrict_to(l0, l1, s);
+  fill_f64(l1.x, 0.0, l1.n, s);
+  vcycle(h, 1, s);
+  prolong_correct(l0, l1, s);
+}
+
+// One iteration of the solve: a V-cycle and the convergence residual norm.
+// Graph mode 0 replays all of it; when a level-0 kernel class is being timed
+// with events (which cannot be read back from inside a graph), that class is
+// launched directly around the replayed remainder (modes 1 and 2).
+void run_iteration(Handle& h, hipStream_t s) {
+  Level& l0 = h.L[0];
+  const bool graph = h.graph_exec != nullptr;
+  if (graph && h.graph_mode == 0) {
+    check_hip(hipGraphLaunch(h.graph_exec, s), "graph launch");
+    return;
+  }
+  if (graph && h.graph_mode == 1) {
+    for (int k = 0; k < h.opt.nu_pre; ++k) gs_sweep(l0, s, true);
+    check_hip(hipGraphLaunch(h.graph_exec, s), "graph launch");
+    for (int k = 0; k < h.opt.nu_post; ++k) gs_sweep(l0, s, true);
+  } else if (graph && h.graph_mode == 2) {
+    check_hip(hipGraphLaunch(h.graph_exec, s), "graph launch");
+  } else {
+    vcycle(h, 0, s);
+  }
+  residual_norm(l0, h.red, s);
+  finish_norm(h.red, h.red + kNormBlocks, s);
+}
+
+// Captures the iteration into a graph (one launch instead of ~100) on a
+// private stream; it is replayed on the caller's stream.  Any failure leaves
+// the handle on direct launches.
+void capture_cycle(Handle& h) {
+  if (h.graph_exec || h.graph_failed) return;
+  if (std::getenv("GMG_DISABLE_GRAPHS")) {
+    h.graph_failed = true;
+    return;
+  }
+  if (!h.cap_stream && hipStreamCreateWithFlags(&h.cap_stream, hipStreamNonBlocking) != hipSuccess) {
+    h.graph_failed = true;
+    (void)hipGetLastError();
+    return;
+  }
+  Level& l0 = h.L[0];
+  const bool multi = h.L.size() > 1 && h.tail_start > 0;
+  h.graph_mode = 0;
+  if (multi && KernelTimer::active == KernelTimer::GS_FINEST) h.graph_mode = 1;
+  if (KernelTimer::active == KernelTimer::RESIDUAL_FINEST) h.graph_mode = 2;
+  const int saved = KernelTimer::active;
+  KernelTimer::active = -1;                    // no event records inside the capture
+  bool ok = hipStreamBeginCapture(h.cap_stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+  if (ok) {
+    if (h.graph_mode == 1) {
+      cycle_inner(h, h.cap_stream);
+    } else {
+      vcycle(h, 0, h.cap_stream);
+      if (h.graph_mode == 0) {
+        residual_norm(l0, h.red, h.cap_stream);
+        finish_norm(h.red, h.red + kNormBlocks, h.cap_stream);
+      }
+    }
+    ok = hipStreamEndCapture(h.cap_stream, &h.graph) == hipSuccess && h.graph;
+  }
+  KernelTimer::active = saved;
+  if (ok) ok = hipGraphInstantiate(&h.graph_exec, h.graph, nullptr, nullptr, 0) == hipSuccess;
+  if (!ok) {
+    (void)hipGetLastError();
+    if (h.graph) (void)hipGraphDestroy(h.graph);
+    h.graph = nullptr;
+    h.graph_exec = nullptr;
+    h.graph_failed = true;
+  }
 }
 
 const char* status_text(int st) {
@@ -332,10 +541,9 @@ int gmg_solve(gmg_handle hh, const double* b_dev, double* x_dev, double tol, int
     status = GMG_NOT_CONVERGED;
     double rel = 0.0;
     int32_t it = 0;
+    capture_cycle(*h);
     while (it < max_iters) {
-      vcycle(*h, 0, s);
-      residual_norm(l0, red, s);
-      finish_norm(red, red + kNormBlocks, s);
+      run_iteration(*h, s);
       check_hip(hipMemcpyAsync(hs, red + kNormBlocks, 8, hipMemcpyDeviceToHost, s), "copy");
       sync(s, "V-cycle");
       ++it;
@@ -362,6 +570,35 @@ int gmg_solve(gmg_handle hh, const double* b_dev, double* x_dev, double tol, int
 }
 
 void gmg_free(gmg_handle h) { release(h); }
+
+int gmg_timer_start(int32_t kernel, int32_t expected_launches) {
+  if (kernel < 0 || kernel >= KernelTimer::KINDS || expected_launches < 0) return GMG_INVALID_ARGUMENT;
+  g_ev_used = 0;
+  g_bytes = 0.0;
+  g_launches = 0;
+  while ((int64_t)g_ev.size() < 2 * (int64_t)expected_launches) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return GMG_DEVICE_ERROR;
+    g_ev.push_back(e);
+  }
+  KernelTimer::active = kernel;
+  return GMG_OK;
+}
+
+int gmg_timer_stop(double* total_ms, int64_t* launches, double* bytes) {
+  KernelTimer::active = -1;
+  double ms = 0.0;
+  for (size_t k = 0; k + 1 < g_ev_used + 1 && k < g_ev_used; k += 2) {
+    if (hipEventSynchronize(g_ev[k + 1]) != hipSuccess) return GMG_DEVICE_ERROR;
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, g_ev[k], g_ev[k + 1]) != hipSuccess) return GMG_DEVICE_ERROR;
+    ms += t;
+  }
+  if (total_ms) *total_ms = ms;
+  if (launches) *launches = g_launches;
+  if (bytes) *bytes = g_bytes;
+  return GMG_OK;
+}
 
 const char* gmg_status_string(int status) { return status_text(status); }
 

@@ -47,12 +47,69 @@ __device__ inline T wave_sum(T v) {
   return v;
 }
 
+// Appends v to out[] (counter *cnt) for the lanes where pred holds, with one
+// atomic per wavefront.  Every lane of the wavefront must call it.
+__device__ inline void wave_append(bool pred, int32_t v, int32_t* out, int32_t* cnt) {
+  const unsigned long long m = __ballot(pred);
+  if (!m) return;
+  const int lane = threadIdx.x & 63;
+  const int leader = __ffsll((long long)m) - 1;
+  int32_t base = 0;
+  if (lane == leader) base = atomicAdd(cnt, (int32_t)__popcll(m));
+  base = __shfl(base, leader, 64);
+  if (pred) out[base + __popcll(m & ((1ull << lane) - 1ull))] = v;
+}
+
+constexpr int kRoundGrid = 1024;     // blocks of a worklist round (grid-stride)
+
 inline int blocks_for(int64_t n, int per_block = kBlock) {
   int64_t b = (n + per_block - 1) / per_block;
   return (int)(b < 1 ? 1 : b);
 }
 
 // ------------------------------------------------------------------ hierarchy layout
+constexpr int kTailThreads = 1024;   // one workgroup runs the V-cycle below kTailRows
+constexpr int64_t kTailRows = 4096;
+constexpr int kMaxTail = 8;
+constexpr int kLaneEntries = 8;      // entries per lane per pass of a lane-parallel row
+
+// A matrix in SELL-64: entry t of row r at ptr[r/64] + 64 t + r%64.
+struct SellView {
+  const int32_t* ptr = nullptr;
+  const int32_t* col = nullptr;
+  const double* val = nullptr;
+  const int32_t* len = nullptr;
+};
+
+// What the V-cycle kernels need of one level (device pointers, new numbering).
+struct LevelView {
+  int32_t n = 0;
+  int32_t ncolors = 0;
+  const int32_t* cptr = nullptr;        // device colour ranges [ncolors + 1]
+  SellView A;                           // A_l
+  SellView T;                           // P_l^T (rows: coarse points)
+  int32_t ra = 1, rt = 1;               // lanes per row for A_l / P_l^T (power of two)
+  int32_t maxa = 0, maxt = 0;           // longest row of A_l / P_l^T
+  const double* diag = nullptr;
+  const int32_t* q_col = nullptr;       // P_l, SoA ELL-3 [3][n]
+  const double* q_val = nullptr;
+  const int32_t* q_cnt = nullptr;
+  double* x = nullptr;
+  double* b = nullptr;
+  double* r = nullptr;
+};
+
+struct TailDesc {
+  int32_t nlev = 0;                     // tail levels, the last one is the coarsest
+  int32_t nu_pre = 0, nu_post = 0;
+  int32_t lanes = 4;                    // lanes per row (max over the tail levels)
+  int32_t lds_doubles = 0;              // LDS holding the tail levels' iterates
+  int32_t lds_off[kMaxTail] = {};       // offset of level l's x in LDS, or -1 (global)
+  const double* cinv = nullptr;
+  LevelView lv[kMaxTail];
+};
+constexpr int32_t kTailLdsDoubles = 12 * 1024;   // 96 KB
+
 // One level.  "Original" arrays use the level's own point numbering (what the
 // method defines and what is exported); the solve arrays use the colour-sorted
 // numbering new = iperm[old] in which every colour class is a contiguous row
@@ -63,9 +120,10 @@ struct Level {
   int32_t* erp = nullptr;               // edge CSR (symmetric, sorted, no loops)
   int32_t* ecol = nullptr;
   double* ew = nullptr;                 // edge lengths per CSR entry
-  int64_t nnzE = 0;
+  int64_t nnzE = 0;                     // exact once the build has finished
+  int64_t nnzE_cap = 0;                 // allocation bound for the edge arrays
   double* scal = nullptr;               // device [e_hat, r]
-  bool sampled = false;                 // sampling ran on this level
+  unsigned long long* stats = nullptr;  // device [fallback rows, nnz(P)], read at the end of the build
   // coarsening products (levels that are not the coarsest)
   int64_t nc = 0;                       // coarse points taken from this level
   int32_t* samples = nullptr;           // [nc] fine index of each coarse point
@@ -86,23 +144,16 @@ struct Level {
   int32_t* color = nullptr;
   int32_t ncolors = 0;
   std::vector<int32_t> color_ptr;       // host: rows [color_ptr[c], color_ptr[c+1]) in new numbering
+  std::vector<double> color_bytes;      // algorithmic bytes of one colour's sweep
+  double residual_bytes = 0;            // algorithmic bytes of one residual
   // solve layout (new numbering)
   int32_t* perm = nullptr;              // perm[new] = old
   int32_t* iperm = nullptr;             // iperm[old] = new
-  int32_t* s_ptr = nullptr;             // SELL-64: slice s entries start at s_ptr[s]
-  int32_t* s_col = nullptr;             //   entry t of row r: s_ptr[r/64] + t*64 + r%64
-  double* s_val = nullptr;
-  int32_t* s_len = nullptr;             //   row lengths
   double* diag = nullptr;
-  int32_t* q_col = nullptr;             // P in new numbering, SoA ELL-3: [3][n] (coarse new ids)
-  double* q_val = nullptr;
-  int32_t* q_cnt = nullptr;
-  int32_t* t_rp = nullptr;              // P^T in new numbering: rows = coarse new ids,
-  int32_t* t_col = nullptr;             //   entries ascending in the original fine index
-  double* t_val = nullptr;
   double* x = nullptr;                  // work vectors
   double* b = nullptr;
   double* r = nullptr;
+  LevelView view;
 };
 
 struct Handle {
@@ -116,8 +167,28 @@ struct Handle {
   int32_t* flags = nullptr;             // device error flags and counters
   int32_t* rounds = nullptr;            // device per-round counters of frontier loops
   double* red = nullptr;                // reduction partials
-  double* host_scal = nullptr;          // pinned host staging
+  int tail_start = -1;                  // first level solved by the single-workgroup tail kernel
+  TailDesc tail;
+  // one V-cycle plus the convergence residual, captured once and replayed
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  bool graph_failed = false;
+  int graph_mode = 0;                   // 0 whole cycle, 1 without level-0 smoothing, 2 without residual
   std::vector<void*> allocs;
+};
+
+// Per-kernel timing with HIP events on the launch stream (measurement only;
+// inactive unless gmg_timer_start was called).
+struct KernelTimer {
+  enum Kind { GS_FINEST = 0, RESIDUAL_FINEST = 1, KINDS = 2 };
+  static int active;
+  struct Scope {
+    hipEvent_t stop = nullptr;
+    hipStream_t stream = nullptr;
+    Scope(int kind, hipStream_t s, double bytes);
+    ~Scope();
+  };
 };
 
 // ------------------------------------------------------------------ host utilities
@@ -134,6 +205,15 @@ void tfree(hipStream_t s, void* p);
 void sync(hipStream_t s, const char* what);
 int64_t read_i64(Handle& h, const void* dev_ptr, int bytes); // D2H of a 4- or 8-byte scalar (syncs)
 void check_flags(Handle& h, const char* phase);             // throws on device error flags
+void throw_flags(int32_t f, const char* phase);             // throws if f has error bits
+// Several device scalars (4 or 8 bytes each) copied to the host with one synchronisation.
+struct ScalarRead {
+  const void* src;
+  int bytes;
+  int64_t* dst;
+};
+void read_scalars(Handle& h, const ScalarRead* items, int count);
+void* pinned_staging(size_t bytes);                         // per-thread pinned host buffer
 
 // ------------------------------------------------------------------ launchers (prims.hip)
 // out[0..n] = exclusive prefix sum of in[0..n-1]; out[n] = total.  Returns nothing; total stays on device.
@@ -172,11 +252,12 @@ void solve_layout(Handle& h, Level& lv, const Level* nx, const int32_t* t_rp, co
 void coarse_factor(Handle& h, Level& lv);
 
 // ------------------------------------------------------------------ launchers (solve.hip)
-void gs_sweep(const Level& lv, hipStream_t s);
-void residual(const Level& lv, hipStream_t s);
+void gs_sweep(const Level& lv, hipStream_t s, bool finest);
+void residual(const Level& lv, hipStream_t s, bool finest);
 void restrict_to(const Level& lv, Level& nx, hipStream_t s);
 void prolong_correct(Level& lv, const Level& nx, hipStream_t s);
 void coarse_solve(Handle& h, Level& lv, hipStream_t s);
+void tail_vcycle(Handle& h, hipStream_t s);
 void permute_in(const int32_t* perm, const double* src, double* dst, int64_t n, hipStream_t s);
 void permute_out(const int32_t* perm, const double* src, double* dst, int64_t n, hipStream_t s);
 void norm2_partials(const double* v, int64_t n, double* partials, hipStream_t s);

@@ -8,6 +8,8 @@
 // sequence of the method's definition (no contraction: built with
 // -ffp-contract=off), so samples, labels and coarse edges are reproducible bit
 // for bit by any correct implementation.
+#include <algorithm>
+
 #include "gmg_internal.hpp"
 
 namespace gmg {
@@ -127,7 +129,8 @@ __device__ inline int fixed_point_shift(double M, int64_t cnt) {
 // point: with the longest edge M < 2^e, each length scaled by 2^F,
 // F = 62 - e - ceil(log2 m), rounds to an integer below 2^(62 - ceil log2 m).
 __global__ void k_edge_fixsum(const int32_t* rp, const int32_t* col, const double* w, int64_t n,
-                              int64_t cnt, const unsigned long long* maxbits, unsigned long long* sum) {
+                              const unsigned long long* maxbits, unsigned long long* sum) {
+  const int64_t cnt = rp[n] / 2;
   double M = __longlong_as_double((long long)*maxbits);
   if (M == 0.0) return;
   int F = fixed_point_shift(M, cnt);
@@ -141,7 +144,8 @@ __global__ void k_edge_fixsum(const int32_t* rp, const int32_t* col, const doubl
 }
 
 __global__ void k_edge_mean_finish(const unsigned long long* maxbits, const unsigned long long* sum,
-                                   int64_t cnt, double rho, double* scal) {
+                                   const int32_t* total, double rho, double* scal) {
+  const int64_t cnt = *total / 2;     // undirected edges
   double M = __longlong_as_double((long long)*maxbits);
   if (cnt == 0 || M == 0.0) {
     scal[0] = 0.0;
@@ -171,39 +175,45 @@ __device__ inline bool key_less(uint64_t ka, int32_t a, uint64_t kb, int32_t b) 
 // at most two edges) that comes earlier in the sweep order is already
 // excluded; it is excluded as soon as one of them is a sample.  Decisions are
 // final, so statuses are updated in place; the result equals the sequential
-// sweep's for any interleaving.
-__global__ void __launch_bounds__(kBlock) k_lfmis_round(const int32_t* rp, const int32_t* col,
-                                                        const double* w, int64_t n, const double* scal,
-                                                        SweepKey key, uint8_t* status, int32_t* rounds,
-                                                        int k) {
-  if (k > 0 && rounds[k - 1] == 0) return;
-  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  bool undecided = false;
-  if (p < n && status[p] == 0) {
-    const double r = scal[1];
-    const uint64_t kp = key((int32_t)p);
-    bool blocked = false, out = false;
-    for (int32_t e = rp[p]; e < rp[p + 1] && !out; ++e) {
-      int32_t m = col[e];
-      double wpm = w[e];
-      if (wpm <= r && key_less(key(m), m, kp, (int32_t)p)) {
-        uint8_t s = __atomic_load_n(&status[m], __ATOMIC_RELAXED);
+// sweep's for any interleaving.  Round 0 visits every point; later rounds
+// visit the worklist of points still undecided after the previous round.
+__device__ inline bool lfmis_attempt(const int32_t* rp, const int32_t* col, const double* w, double r,
+                                     const SweepKey& key, uint8_t* status, int32_t p) {
+  const uint64_t kp = key(p);
+  bool blocked = false, out = false;
+  for (int32_t e = rp[p]; e < rp[p + 1] && !out; ++e) {
+    int32_t m = col[e];
+    double wpm = w[e];
+    if (wpm <= r && key_less(key(m), m, kp, p)) {
+      uint8_t s = __atomic_load_n(&status[m], __ATOMIC_RELAXED);
+      if (s == 1) out = true; else if (s == 0) blocked = true;
+    }
+    for (int32_t f = rp[m]; f < rp[m + 1] && !out; ++f) {
+      int32_t q = col[f];
+      if (q != p && wpm + w[f] <= r && key_less(key(q), q, kp, p)) {
+        uint8_t s = __atomic_load_n(&status[q], __ATOMIC_RELAXED);
         if (s == 1) out = true; else if (s == 0) blocked = true;
       }
-      for (int32_t f = rp[m]; f < rp[m + 1] && !out; ++f) {
-        int32_t q = col[f];
-        if (q != p && wpm + w[f] <= r && key_less(key(q), q, kp, (int32_t)p)) {
-          uint8_t s = __atomic_load_n(&status[q], __ATOMIC_RELAXED);
-          if (s == 1) out = true; else if (s == 0) blocked = true;
-        }
-      }
     }
-    if (out) status[p] = 2;
-    else if (!blocked) status[p] = 1;
-    else undecided = true;
   }
-  unsigned long long b = __ballot(undecided);
-  if ((threadIdx.x & 63) == 0 && b) atomicAdd(&rounds[k], __popcll(b));
+  if (out) status[p] = 2;
+  else if (!blocked) status[p] = 1;
+  return !out && blocked;
+}
+
+__global__ void __launch_bounds__(kBlock) k_lfmis_round(const int32_t* rp, const int32_t* col,
+                                                        const double* w, int64_t n, const double* scal,
+                                                        SweepKey key, uint8_t* status, const int32_t* wl_in,
+                                                        int32_t* wl_out, int32_t* rounds, int k) {
+  const int64_t count = k == 0 ? n : rounds[k - 1];
+  const double r = scal[1];
+  for (int64_t base = (int64_t)blockIdx.x * kBlock; base < count; base += (int64_t)gridDim.x * kBlock) {
+    const int64_t i = base + threadIdx.x;
+    const bool act = i < count;
+    const int32_t p = act ? (k == 0 ? (int32_t)i : wl_in[i]) : 0;
+    const bool pend = act && lfmis_attempt(rp, col, w, r, key, status, p);
+    wave_append(pend, p, wl_out, &rounds[k]);
+  }
 }
 
 __global__ void k_seed_flags(const uint8_t* status, int64_t n, int32_t* f) {
@@ -360,8 +370,13 @@ void edges_to_csr(Handle& h, Level& lv, const int32_t* edges, int64_t m) {
   segment_sort_unique(tmp, tptr, deg, n, s);
   lv.erp = (int32_t*)dalloc(h, (size_t)(n + 1) * 4);
   scan_i32(deg, lv.erp, n, s);
-  lv.nnzE = read_i64(h, lv.erp + n, 4);
-  check_flags(h, "edge array");
+  {
+    int64_t f = 0;
+    ScalarRead rd[2] = {{lv.erp + n, 4, &lv.nnzE}, {h.flags, 4, &f}};
+    read_scalars(h, rd, 2);
+    throw_flags((int32_t)f, "edge array");
+  }
+  lv.nnzE_cap = lv.nnzE;
   lv.ecol = (int32_t*)dalloc(h, (size_t)(lv.nnzE + 1) * 4);
   compact_segments(tmp, tptr, lv.erp, lv.ecol, n, s);
   tfree(s, deg);
@@ -383,10 +398,9 @@ void mean_edge(Handle& h, Level& lv, double rho) {
   hipStream_t s = h.stream;
   unsigned long long* acc = (unsigned long long*)talloc(s, 16);
   check_hip(hipMemsetAsync(acc, 0, 16, s), "memset");
-  int64_t cnt = lv.nnzE / 2;
   k_edge_max<<<blocks_for(lv.n), kBlock, 0, s>>>(lv.erp, lv.ecol, lv.ew, lv.n, acc);
-  k_edge_fixsum<<<blocks_for(lv.n), kBlock, 0, s>>>(lv.erp, lv.ecol, lv.ew, lv.n, cnt, acc, acc + 1);
-  k_edge_mean_finish<<<1, 1, 0, s>>>(acc, acc + 1, cnt, rho, lv.scal);
+  k_edge_fixsum<<<blocks_for(lv.n), kBlock, 0, s>>>(lv.erp, lv.ecol, lv.ew, lv.n, acc, acc + 1);
+  k_edge_mean_finish<<<1, 1, 0, s>>>(acc, acc + 1, lv.erp + lv.n, rho, lv.scal);
   tfree(s, acc);
 }
 
@@ -399,19 +413,26 @@ int64_t sample_lfmis(Handle& h, Level& lv, int level) {
   check_hip(hipMemsetAsync(status, 0, (size_t)n, s), "memset");
   check_hip(hipMemsetAsync(h.rounds, 0, kMaxRounds * 4, s), "memset");
   SweepKey key{h.opt.seed ^ ((uint64_t)level << 32), h.opt.sample_order == 1};
-  int k = 0;
-  for (;;) {
-    for (int t = 0; t < kRoundBatch; ++t, ++k)
-      k_lfmis_round<<<blocks_for(n), kBlock, 0, s>>>(lv.erp, lv.ecol, lv.ew, n, lv.scal, key, status,
-                                                     h.rounds, k);
-    if (read_i64(h, h.rounds + (k - 1), 4) == 0) break;
-    if (k + kRoundBatch > kMaxRounds) throw Error{GMG_DEVICE_ERROR, "sampling did not terminate"};
-  }
+  int32_t* wl = (int32_t*)talloc(s, (size_t)2 * n * 4);
+  const int grid = std::min(blocks_for(n), kRoundGrid);
   int32_t* f = (int32_t*)talloc(s, (size_t)(n + 1) * 4);
   int32_t* ids = (int32_t*)talloc(s, (size_t)(n + 1) * 4);
-  k_seed_flags<<<blocks_for(n), kBlock, 0, s>>>(status, n, f);
-  scan_i32(f, ids, n, s);
-  int64_t nc = read_i64(h, ids + n, 4);
+  int k = 0;
+  int64_t nc = 0;
+  for (;;) {
+    for (int t = 0; t < kRoundBatch; ++t, ++k)
+      k_lfmis_round<<<grid, kBlock, 0, s>>>(lv.erp, lv.ecol, lv.ew, n, lv.scal, key, status,
+                                            wl + ((k + 1) % 2) * n, wl + (k % 2) * n, h.rounds, k);
+    // coarse ids, valid if this batch finished the sweep (read together with the round count)
+    k_seed_flags<<<blocks_for(n), kBlock, 0, s>>>(status, n, f);
+    scan_i32(f, ids, n, s);
+    int64_t left = 0;
+    ScalarRead rd[2] = {{h.rounds + (k - 1), 4, &left}, {ids + n, 4, &nc}};
+    read_scalars(h, rd, 2);
+    if (left == 0) break;
+    if (k + kRoundBatch > kMaxRounds) throw Error{GMG_DEVICE_ERROR, "sampling did not terminate"};
+  }
+  tfree(s, wl);
   lv.nc = nc;
   lv.samples = (int32_t*)dalloc(h, (size_t)(nc + 1) * 4);
   k_collect_samples<<<blocks_for(n), kBlock, 0, s>>>(status, ids, n, lv.samples);
@@ -479,15 +500,16 @@ void coarse_edges(Handle& h, Level& lv, Level& nx, const int32_t* cell_ptr, cons
   int64_t nc = nx.n;
   int32_t* cdeg = (int32_t*)talloc(s, (size_t)(nc + 1) * 4);
   int32_t* cptr = (int32_t*)talloc(s, (size_t)(nc + 1) * 4);
-  int32_t* tmp = (int32_t*)talloc(s, (size_t)(lv.nnzE + 1) * 4);
+  int32_t* tmp = (int32_t*)talloc(s, (size_t)(lv.nnzE_cap + 1) * 4);
   k_cell_degree<<<blocks_for(nc), kBlock, 0, s>>>(cell_ptr, cell_mem, lv.erp, nc, cdeg);
   scan_i32(cdeg, cptr, nc, s);
   k_cell_neighbours<<<blocks_for(nc), kBlock, 0, s>>>(cell_ptr, cell_mem, lv.erp, lv.ecol, lv.label, cptr,
                                                       nc, tmp, cdeg);
   nx.erp = (int32_t*)dalloc(h, (size_t)(nc + 1) * 4);
   scan_i32(cdeg, nx.erp, nc, s);
-  nx.nnzE = read_i64(h, nx.erp + nc, 4);
-  nx.ecol = (int32_t*)dalloc(h, (size_t)(nx.nnzE + 1) * 4);
+  // every coarse edge entry comes from a distinct fine edge entry: nnz(E_{l+1}) <= nnz(E_l)
+  nx.nnzE_cap = lv.nnzE_cap;
+  nx.ecol = (int32_t*)dalloc(h, (size_t)(nx.nnzE_cap + 1) * 4);
   compact_segments(tmp, cptr, nx.erp, nx.ecol, nc, s);
   tfree(s, cdeg);
   tfree(s, cptr);

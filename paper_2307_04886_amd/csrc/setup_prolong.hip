@@ -172,6 +172,8 @@ __global__ void __launch_bounds__(kBlock) k_project(const double* X, const int32
 }
 
 // ------------------------------------------------------------------ P^T
+__global__ void k_store_total(const int32_t* total, unsigned long long* out) { *out = (unsigned long long)*total; }
+
 __global__ void k_count_cols(const int32_t* pcol, const int32_t* pcnt, int64_t n, int32_t* cnt) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -190,22 +192,46 @@ __global__ void k_scatter_cols(const int32_t* pcol, const double* pval, const in
   }
 }
 
-// Rows of P^T sorted by fine index (insertion sort on (index, value) pairs).
-__global__ void k_sort_pairs(const int32_t* ptr, int32_t* col, double* val, int64_t nrow) {
-  int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// Rows of P^T sorted by fine index: one wavefront per row, a bitonic sort of
+// (index, value) pairs across the 64 lanes; longer rows (rare) fall back to
+// an insertion sort by the first lane.
+__global__ void __launch_bounds__(kBlock) k_sort_pairs(const int32_t* ptr, int32_t* col, double* val,
+                                                       int64_t nrow) {
+  const int64_t I = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+  const int lane = threadIdx.x & (kWave - 1);
   if (I >= nrow) return;
-  int32_t b = ptr[I], e = ptr[I + 1];
-  for (int32_t i = b + 1; i < e; ++i) {
-    int32_t c = col[i];
-    double v = val[i];
-    int32_t j = i - 1;
-    while (j >= b && col[j] > c) {
-      col[j + 1] = col[j];
-      val[j + 1] = val[j];
-      --j;
+  const int32_t b = ptr[I], e = ptr[I + 1], len = e - b;
+  if (len <= kWave) {
+    int32_t key = lane < len ? col[b + lane] : INT32_MAX;
+    double v = lane < len ? val[b + lane] : 0.0;
+    for (int k = 2; k <= kWave; k <<= 1)
+      for (int j = k >> 1; j > 0; j >>= 1) {
+        const int32_t ok = __shfl_xor(key, j, kWave);
+        const double ov = __shfl_xor(v, j, kWave);
+        const bool up = (lane & k) == 0, lower = (lane & j) == 0;
+        const bool take = lower ? (up ? ok < key : ok > key) : (up ? ok > key : ok < key);
+        if (take) {
+          key = ok;
+          v = ov;
+        }
+      }
+    if (lane < len) {
+      col[b + lane] = key;
+      val[b + lane] = v;
     }
-    col[j + 1] = c;
-    val[j + 1] = v;
+  } else if (lane == 0) {
+    for (int32_t i = b + 1; i < e; ++i) {
+      int32_t c = col[i];
+      double w = val[i];
+      int32_t j = i - 1;
+      while (j >= b && col[j] > c) {
+        col[j + 1] = col[j];
+        val[j + 1] = val[j];
+        --j;
+      }
+      col[j + 1] = c;
+      val[j + 1] = w;
+    }
   }
 }
 
@@ -213,107 +239,219 @@ __global__ void k_sort_pairs(const int32_t* ptr, int32_t* col, double* val, int6
 // One wavefront per coarse row I.  The terms of row I are
 //   (P[i,I] * A[i,j]) * P[j,J]  for i in row I of P^T (ascending), j in row i
 // of A (CSR order), J in row j of P (column order).
+// The (i, j) pairs of a row are enumerated 64 at a time (one per lane, after
+// a wavefront prefix sum over the row lengths), so a row's dependent loads
+// are issued for 64 pairs at once.
 // Symbolic pass: the distinct J go into an LDS hash set.  Numeric pass: the
-// sorted distinct J are handed one per lane; every lane walks the whole term
-// list in the order above and adds the terms of its own column, so each
-// entry is summed in exactly the order of the definition's row accumulation.
-constexpr int kHash = 1024;
+// terms are staged in LDS in definition order, and the lane that owns output
+// column J adds the staged terms of J in that order, so each entry is summed
+// exactly like the definition's row accumulation.
 
+// Inclusive scan of one int per lane over a wavefront.
+__device__ inline int wave_incl_scan(int v) {
+  const int lane = threadIdx.x & (kWave - 1);
+  for (int o = 1; o < kWave; o <<= 1) {
+    int t = __shfl_up(v, o, kWave);
+    if (lane >= o) v += t;
+  }
+  return v;
+}
+
+template <int HS>
 __device__ inline bool hash_insert(int32_t* keys, int32_t J) {
-  uint32_t h = ((uint32_t)J * 2654435761u) & (kHash - 1);
-  for (int probe = 0; probe < kHash; ++probe) {
+  uint32_t h = ((uint32_t)J * 2654435761u) & (HS - 1);
+  for (int probe = 0; probe < HS; ++probe) {
     int32_t old = atomicCAS(&keys[h], -1, J);
     if (old == -1 || old == J) return true;
-    h = (h + 1) & (kHash - 1);
+    h = (h + 1) & (HS - 1);
   }
   return false;
 }
 
-__device__ inline bool hash_fill_row(int32_t I, const int32_t* trp, const int32_t* tcol, const int32_t* arp,
-                                     const int32_t* acol, const int32_t* pcol, const int32_t* pcnt,
-                                     int32_t* keys) {
+struct PairChunk {
+  int32_t pre[kWave];                  // exclusive prefix of A-row lengths over a chunk of P^T entries
+  int32_t rb[kWave];                   // first A entry of that row
+  double piI[kWave];                   // P[i, I]
+};
+
+// Loads P^T entries [q0, q0 + 64) of row I and returns the number of (i, j) pairs.
+__device__ inline int load_pairs(int32_t q0, int32_t qe, const int32_t* tcol, const double* tval,
+                                 const int32_t* arp, PairChunk& pc) {
   const int lane = threadIdx.x;
-  for (int s = lane; s < kHash; s += kWave) keys[s] = -1;
+  const int32_t q = q0 + lane;
+  const bool on = q < qe;
+  const int32_t i = on ? tcol[q] : 0;
+  const int32_t rb = on ? arp[i] : 0;
+  const int32_t rl = on ? arp[i + 1] - rb : 0;
+  const int incl = wave_incl_scan(rl);
+  pc.pre[lane] = incl - rl;
+  pc.rb[lane] = rb;
+  pc.piI[lane] = on ? tval[q] : 0.0;
+  __syncthreads();
+  return __shfl(incl, kWave - 1, kWave);
+}
+
+// Pair p of the chunk -> (P^T entry index within the chunk, A entry index)
+__device__ inline void locate_pair(const PairChunk& pc, int p, int& src, int32_t& e) {
+  int lo = 0, hi = kWave;                           // last src with pre[src] <= p
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (pc.pre[mid] <= p) lo = mid; else hi = mid;
+  }
+  src = lo;
+  e = pc.rb[lo] + (p - pc.pre[lo]);
+}
+
+template <int HS>
+__global__ void __launch_bounds__(kWave) k_galerkin_count(const int32_t* trp, const int32_t* tcol,
+                                                          const double* tval, const int32_t* arp,
+                                                          const int32_t* acol, const int32_t* pcol,
+                                                          const int32_t* pcnt, int64_t nc, int32_t* rowcnt,
+                                                          int32_t* flags) {
+  __shared__ int32_t keys[HS];
+  __shared__ PairChunk pc;
+  const int32_t I = blockIdx.x;
+  if (I >= nc) return;
+  const int lane = threadIdx.x;
+  for (int s = lane; s < HS; s += kWave) keys[s] = -1;
   __syncthreads();
   bool ok = true;
-  for (int32_t q = trp[I]; q < trp[I + 1]; ++q) {
-    int32_t i = tcol[q];
-    for (int32_t e = arp[i] + lane; e < arp[i + 1]; e += kWave) {
-      int32_t j = acol[e];
-      for (int t = 0; t < pcnt[j]; ++t) ok &= hash_insert(keys, pcol[3 * j + t]);
+  for (int32_t q0 = trp[I]; q0 < trp[I + 1]; q0 += kWave) {
+    const int tot = load_pairs(q0, trp[I + 1], tcol, tval, arp, pc);
+    for (int p0 = 0; p0 < tot; p0 += kWave) {
+      const int p = p0 + lane;
+      if (p < tot) {
+        int src;
+        int32_t e;
+        locate_pair(pc, p, src, e);
+        const int32_t j = acol[e];
+        const int c = pcnt[j];
+        for (int t = 0; t < c; ++t) ok &= hash_insert<HS>(keys, pcol[3 * j + t]);
+      }
     }
+    __syncthreads();
   }
-  __syncthreads();
-  return ok;
-}
-
-__global__ void __launch_bounds__(kWave) k_galerkin_count(const int32_t* trp, const int32_t* tcol,
-                                                          const int32_t* arp, const int32_t* acol,
-                                                          const int32_t* pcol, const int32_t* pcnt,
-                                                          int64_t nc, int32_t* rowcnt, int32_t* flags) {
-  __shared__ int32_t keys[kHash];
-  int32_t I = blockIdx.x;
-  if (I >= nc) return;
-  bool ok = hash_fill_row(I, trp, tcol, arp, acol, pcol, pcnt, keys);
   int c = 0;
-  for (int s = threadIdx.x; s < kHash; s += kWave) c += keys[s] >= 0;
+  for (int s = lane; s < HS; s += kWave) c += keys[s] >= 0;
   c = wave_sum(c);
-  if (!ok || c > kHash * 3 / 4) { if (threadIdx.x == 0) atomicOr(flags, F_OVERFLOW); }
-  if (threadIdx.x == 0) rowcnt[I] = c;
+  bool bad = __ballot(!ok) != 0;
+  if (lane == 0) {
+    rowcnt[I] = c;
+    if (bad || c > HS * 3 / 4) atomicOr(flags, F_OVERFLOW);
+  }
 }
 
+template <int HS>
 __global__ void __launch_bounds__(kWave) k_galerkin_fill(const int32_t* trp, const int32_t* tcol,
                                                          const double* tval, const int32_t* arp,
                                                          const int32_t* acol, const double* aval,
                                                          const int32_t* pcol, const double* pval,
                                                          const int32_t* pcnt, int64_t nc, const int32_t* crp,
                                                          int32_t* ccol, double* cval, int32_t* flags) {
-  __shared__ int32_t keys[kHash];
-  __shared__ int32_t list[kHash];
-  __shared__ int32_t sorted[kHash];
+  constexpr int kT = HS;               // terms staged at a time
+  __shared__ int32_t keys[HS];
+  __shared__ int32_t sorted[HS * 3 / 4];
+  __shared__ double accum[HS * 3 / 4];
+  __shared__ int32_t termJ[kT];
+  __shared__ double termV[kT];
+  __shared__ PairChunk pc;
   __shared__ int32_t nlist;
-  int32_t I = blockIdx.x;
+  const int32_t I = blockIdx.x;
   if (I >= nc) return;
   const int lane = threadIdx.x;
-  hash_fill_row(I, trp, tcol, arp, acol, pcol, pcnt, keys);
+  // distinct columns (the symbolic pass guaranteed they fit)
+  for (int s = lane; s < HS; s += kWave) keys[s] = -1;
   if (lane == 0) nlist = 0;
   __syncthreads();
-  for (int s = lane; s < kHash; s += kWave)
-    if (keys[s] >= 0) list[atomicAdd(&nlist, 1)] = keys[s];
+  for (int32_t q0 = trp[I]; q0 < trp[I + 1]; q0 += kWave) {
+    const int tot = load_pairs(q0, trp[I + 1], tcol, tval, arp, pc);
+    for (int p0 = 0; p0 < tot; p0 += kWave) {
+      const int p = p0 + lane;
+      if (p < tot) {
+        int src;
+        int32_t e;
+        locate_pair(pc, p, src, e);
+        const int32_t j = acol[e];
+        for (int t = 0; t < pcnt[j]; ++t) hash_insert<HS>(keys, pcol[3 * j + t]);
+      }
+    }
+    __syncthreads();
+  }
+  for (int s = lane; s < HS; s += kWave)
+    if (keys[s] >= 0) termJ[atomicAdd(&nlist, 1)] = keys[s];      // termJ used as scratch here
   __syncthreads();
   const int k = nlist;
   for (int a = lane; a < k; a += kWave) {
-    int32_t key = list[a];
+    int32_t key = termJ[a];
     int rank = 0;
-    for (int b = 0; b < k; ++b) rank += list[b] < key;
+    for (int b = 0; b < k; ++b) rank += termJ[b] < key;
     sorted[rank] = key;
+    accum[rank] = 0.0;
   }
   __syncthreads();
+  int base = 0;
+  auto flush = [&]() {
+    __syncthreads();
+    for (int o = lane; o < k; o += kWave) {
+      const int32_t J = sorted[o];
+      double acc = accum[o];
+      for (int t = 0; t < base; ++t)
+        if (termJ[t] == J) acc = acc + termV[t];
+      accum[o] = acc;
+    }
+    __syncthreads();
+    base = 0;
+  };
+  for (int32_t q0 = trp[I]; q0 < trp[I + 1]; q0 += kWave) {
+    const int tot = load_pairs(q0, trp[I + 1], tcol, tval, arp, pc);
+    for (int p0 = 0; p0 < tot; p0 += kWave) {
+      const int p = p0 + lane;
+      const bool on = p < tot;
+      int src = 0;
+      int32_t e = 0, j = 0;
+      int c = 0;
+      double t1 = 0.0;
+      if (on) {
+        locate_pair(pc, p, src, e);
+        j = acol[e];
+        c = pcnt[j];
+        t1 = pc.piI[src] * aval[e];
+      }
+      const int incl = wave_incl_scan(c);
+      const int total = __shfl(incl, kWave - 1, kWave);
+      if (base + total > kT) flush();
+      if (on) {
+        const int pos = base + incl - c;
+        for (int t = 0; t < c; ++t) {
+          termJ[pos + t] = pcol[3 * j + t];
+          termV[pos + t] = t1 * pval[3 * j + t];
+        }
+      }
+      base += total;
+    }
+    __syncthreads();
+  }
+  flush();
   const int32_t out = crp[I];
   bool diag_ok = false;
-  for (int c0 = 0; c0 < k; c0 += kWave) {
-    const bool mine = c0 + lane < k;
-    const int32_t myJ = mine ? sorted[c0 + lane] : -1;
-    double acc = 0.0;
-    for (int32_t q = trp[I]; q < trp[I + 1]; ++q) {
-      const int32_t i = tcol[q];
-      const double piI = tval[q];
-      for (int32_t e = arp[i]; e < arp[i + 1]; ++e) {
-        const int32_t j = acol[e];
-        const double t1 = piI * aval[e];
-        for (int t = 0; t < pcnt[j]; ++t)
-          if (pcol[3 * j + t] == myJ) acc = acc + t1 * pval[3 * j + t];
-      }
-    }
-    if (mine) {
-      ccol[out + c0 + lane] = myJ;
-      cval[out + c0 + lane] = acc;
-      if (myJ == I && acc > 0.0) diag_ok = true;
-    }
+  for (int o = lane; o < k; o += kWave) {
+    ccol[out + o] = sorted[o];
+    cval[out + o] = accum[o];
+    if (sorted[o] == I && accum[o] > 0.0) diag_ok = true;
   }
   // a missing or non-positive diagonal makes Gauss-Seidel divide by zero
-  unsigned long long b = __ballot(diag_ok);
-  if (lane == 0 && b == 0) atomicOr(flags, F_NOT_SPD);
+  unsigned long long bal = __ballot(diag_ok);
+  if (lane == 0 && bal == 0) atomicOr(flags, F_NOT_SPD);
+}
+
+__global__ void k_max_i32(const int32_t* v, int64_t n, int32_t* out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int32_t m = i < n ? v[i] : 0;
+  for (int o = 32; o > 0; o >>= 1) {
+    int32_t t = __shfl_xor(m, o, 64);
+    m = t > m ? t : m;
+  }
+  if ((threadIdx.x & 63) == 0 && m) atomicMax(out, m);
 }
 
 }  // namespace
@@ -325,12 +463,8 @@ void prolongation(Handle& h, Level& lv, Level& nx) {
   lv.pval = (double*)dalloc(h, (size_t)3 * n * 8);
   lv.pcnt = (int32_t*)dalloc(h, (size_t)n * 4);
   lv.tri = (int32_t*)dalloc(h, (size_t)2 * n * 4);
-  unsigned long long* fb = (unsigned long long*)talloc(s, 8);
-  check_hip(hipMemsetAsync(fb, 0, 8, s), "memset");
   k_project<<<blocks_for(n), kBlock, 0, s>>>(lv.X, lv.label, n, nx.X, nx.erp, nx.ecol, lv.pcol, lv.pval,
-                                             lv.pcnt, lv.tri, fb);
-  lv.fallback = read_i64(h, fb, 8);
-  tfree(s, fb);
+                                             lv.pcnt, lv.tri, lv.stats);
 }
 
 void transpose_p(Handle& h, Level& lv, int64_t nc, int32_t** t_rp, int32_t** t_col, double** t_val) {
@@ -343,11 +477,11 @@ void transpose_p(Handle& h, Level& lv, int64_t nc, int32_t** t_rp, int32_t** t_c
   check_hip(hipMemsetAsync(cur, 0, (size_t)(nc + 1) * 4, s), "memset");
   k_count_cols<<<blocks_for(n), kBlock, 0, s>>>(lv.pcol, lv.pcnt, n, cnt);
   scan_i32(cnt, rp, nc, s);
-  lv.nnzP = read_i64(h, rp + nc, 4);
-  int32_t* col = (int32_t*)talloc(s, (size_t)(lv.nnzP + 1) * 4);
-  double* val = (double*)talloc(s, (size_t)(lv.nnzP + 1) * 8);
+  k_store_total<<<1, 1, 0, s>>>(rp + nc, lv.stats + 1);      // nnz(P), read at the end of the build
+  int32_t* col = (int32_t*)talloc(s, (size_t)(3 * n + 1) * 4);   // nnz(P) <= 3n
+  double* val = (double*)talloc(s, (size_t)(3 * n + 1) * 8);
   k_scatter_cols<<<blocks_for(n), kBlock, 0, s>>>(lv.pcol, lv.pval, lv.pcnt, n, rp, cur, col, val);
-  k_sort_pairs<<<blocks_for(nc), kBlock, 0, s>>>(rp, col, val, nc);
+  k_sort_pairs<<<blocks_for(nc, kBlock / kWave), kBlock, 0, s>>>(rp, col, val, nc);
   tfree(s, cnt);
   tfree(s, cur);
   *t_rp = rp;
@@ -360,17 +494,28 @@ void galerkin(Handle& h, Level& lv, Level& nx, const int32_t* t_rp, const int32_
   hipStream_t s = h.stream;
   int64_t nc = nx.n;
   int32_t* cnt = (int32_t*)talloc(s, (size_t)(nc + 1) * 4);
+  int32_t* mx = (int32_t*)talloc(s, 4);
+  check_hip(hipMemsetAsync(mx, 0, 4, s), "memset");
   nx.arp = (int32_t*)dalloc(h, (size_t)(nc + 1) * 4);
-  k_galerkin_count<<<(int)nc, kWave, 0, s>>>(t_rp, t_col, lv.arp, lv.acol, lv.pcol, lv.pcnt, nc, cnt,
-                                            h.flags);
+  k_galerkin_count<1024><<<(int)nc, kWave, 0, s>>>(t_rp, t_col, t_val, lv.arp, lv.acol, lv.pcol, lv.pcnt, nc,
+                                                  cnt, h.flags);
+  k_max_i32<<<blocks_for(nc), kBlock, 0, s>>>(cnt, nc, mx);
   scan_i32(cnt, nx.arp, nc, s);
-  nx.nnzA = read_i64(h, nx.arp + nc, 4);
-  check_flags(h, "Galerkin pattern");
+  int64_t maxrow = 0, f = 0;
+  ScalarRead rd[3] = {{nx.arp + nc, 4, &nx.nnzA}, {mx, 4, &maxrow}, {h.flags, 4, &f}};
+  read_scalars(h, rd, 3);
+  throw_flags((int32_t)f, "Galerkin operator");
   nx.acol = (int32_t*)dalloc(h, (size_t)(nx.nnzA + 1) * 4);
   nx.aval = (double*)dalloc(h, (size_t)(nx.nnzA + 1) * 8);
-  k_galerkin_fill<<<(int)nc, kWave, 0, s>>>(t_rp, t_col, t_val, lv.arp, lv.acol, lv.aval, lv.pcol, lv.pval,
-                                           lv.pcnt, nc, nx.arp, nx.acol, nx.aval, h.flags);
+  // a smaller LDS footprint (more resident wavefronts) when every row fits
+  if (maxrow <= 256 * 3 / 4)
+    k_galerkin_fill<256><<<(int)nc, kWave, 0, s>>>(t_rp, t_col, t_val, lv.arp, lv.acol, lv.aval, lv.pcol,
+                                                   lv.pval, lv.pcnt, nc, nx.arp, nx.acol, nx.aval, h.flags);
+  else
+    k_galerkin_fill<1024><<<(int)nc, kWave, 0, s>>>(t_rp, t_col, t_val, lv.arp, lv.acol, lv.aval, lv.pcol,
+                                                    lv.pval, lv.pcnt, nc, nx.arp, nx.acol, nx.aval, h.flags);
   tfree(s, cnt);
+  tfree(s, mx);
 }
 
 }  // namespace gmg

@@ -2,6 +2,8 @@
 // colour-sorted solve layout (SELL-64 matrix, SoA prolongation, restriction
 // rows), and the dense factorisation of the coarsest operator (Alg. 2 solves
 // the coarsest level directly).
+#include <algorithm>
+
 #include "gmg_internal.hpp"
 
 namespace gmg {
@@ -18,47 +20,61 @@ struct ColorKey {
   __device__ uint64_t operator()(int32_t v) const { return mix64(base ^ (uint64_t)v); }
 };
 
-__global__ void __launch_bounds__(kBlock) k_color_round(const int32_t* rp, const int32_t* col, int64_t n,
-                                                        ColorKey key, int32_t* color, int32_t* ncol,
-                                                        int32_t* rounds, int k) {
-  if (k > 0 && rounds[k - 1] == 0) return;
-  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  bool pending = false;
-  if (v < n && color[v] < 0) {
-    const uint64_t kv = key((int32_t)v);
-    uint64_t mask = 0;
-    bool blocked = false, high = false;
-    for (int32_t e = rp[v]; e < rp[v + 1]; ++e) {
-      int32_t u = col[e];
-      if (u == v) continue;
-      uint64_t ku = key(u);
-      if (!(ku < kv || (ku == kv && u < v))) continue;
-      int32_t cu = __atomic_load_n(&color[u], __ATOMIC_RELAXED);
-      if (cu < 0) { blocked = true; break; }
-      if (cu < 64) mask |= 1ull << cu; else high = true;
-    }
-    if (blocked) {
-      pending = true;
-    } else {
-      int32_t c = (~mask) ? __builtin_ctzll(~mask) : 64;
-      if (c == 64 && high) {
-        for (;; ++c) {                              // rare: every colour below 64 is taken
-          bool used = false;
-          for (int32_t e = rp[v]; e < rp[v + 1] && !used; ++e) {
-            int32_t u = col[e];
-            if (u == v) continue;
-            uint64_t ku = key(u);
-            if ((ku < kv || (ku == kv && u < v)) && color[u] == c) used = true;
-          }
-          if (!used) break;
-        }
+// Returns 0 if v must wait for a lower-key neighbour, else colours v and
+// returns its colour + 1.
+__device__ inline int32_t color_attempt(const int32_t* rp, const int32_t* col, const ColorKey& key,
+                                        int32_t* color, int32_t v) {
+  const uint64_t kv = key(v);
+  uint64_t mask = 0;
+  bool high = false;
+  for (int32_t e = rp[v]; e < rp[v + 1]; ++e) {
+    int32_t u = col[e];
+    if (u == v) continue;
+    uint64_t ku = key(u);
+    if (!(ku < kv || (ku == kv && u < v))) continue;
+    int32_t cu = __atomic_load_n(&color[u], __ATOMIC_RELAXED);
+    if (cu < 0) return 0;
+    if (cu < 64) mask |= 1ull << cu; else high = true;
+  }
+  int32_t c = (~mask) ? __builtin_ctzll(~mask) : 64;
+  if (c == 64 && high) {
+    for (;; ++c) {                              // rare: every colour below 64 is taken
+      bool used = false;
+      for (int32_t e = rp[v]; e < rp[v + 1] && !used; ++e) {
+        int32_t u = col[e];
+        if (u == v) continue;
+        uint64_t ku = key(u);
+        if ((ku < kv || (ku == kv && u < v)) && color[u] == c) used = true;
       }
-      color[v] = c;
-      atomicMax(ncol, c + 1);
+      if (!used) break;
     }
   }
-  unsigned long long b = __ballot(pending);
-  if ((threadIdx.x & 63) == 0 && b) atomicAdd(&rounds[k], __popcll(b));
+  color[v] = c;
+  return c + 1;
+}
+
+// One Jones-Plassmann round; round 0 visits every row, later rounds the
+// worklist of rows still waiting after the previous round.
+__global__ void __launch_bounds__(kBlock) k_color_round(const int32_t* rp, const int32_t* col, int64_t n,
+                                                        ColorKey key, int32_t* color, int32_t* ncol,
+                                                        const int32_t* wl_in, int32_t* wl_out, int32_t* rounds,
+                                                        int k) {
+  const int64_t count = k == 0 ? n : rounds[k - 1];
+  int32_t newc = 0;
+  for (int64_t base = (int64_t)blockIdx.x * kBlock; base < count; base += (int64_t)gridDim.x * kBlock) {
+    const int64_t i = base + threadIdx.x;
+    const bool act = i < count;
+    const int32_t v = act ? (k == 0 ? (int32_t)i : wl_in[i]) : 0;
+    int32_t got = 0;
+    if (act) got = color_attempt(rp, col, key, color, v);
+    newc = got > newc ? got : newc;
+    wave_append(act && got == 0, v, wl_out, &rounds[k]);
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    int32_t t = __shfl_xor(newc, o, 64);
+    newc = t > newc ? t : newc;
+  }
+  if ((threadIdx.x & 63) == 0 && newc) atomicMax(ncol, newc);
 }
 
 // ------------------------------------------------------------------ stable colour partition
@@ -95,10 +111,15 @@ __global__ void k_color_ptr(const int32_t* off, int nb, int nc, int32_t* cptr) {
   if (c <= nc) cptr[c] = off[(int64_t)c * nb];
 }
 
-// ------------------------------------------------------------------ SELL-64 matrix
-__global__ void k_row_len(const int32_t* perm, const int32_t* arp, int64_t n, int32_t* len) {
+// ------------------------------------------------------------------ SELL-64 matrices
+// Row r of the result is source row perm[r] (or r) of a CSR matrix; columns
+// are renumbered through cmap (or kept); entries keep their CSR order, so
+// every row sum adds its terms in the same order as the source row.
+__global__ void k_row_len(const int32_t* perm, const int32_t* rp, int64_t n, int32_t* len) {
   int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r < n) len[r] = arp[perm[r] + 1] - arp[perm[r]];
+  if (r >= n) return;
+  int32_t src = perm ? perm[r] : (int32_t)r;
+  len[r] = rp[src + 1] - rp[src];
 }
 
 __global__ void k_slice_width(const int32_t* len, int64_t n, int64_t ns, int32_t* wsz) {
@@ -109,29 +130,43 @@ __global__ void k_slice_width(const int32_t* len, int64_t n, int64_t ns, int32_t
   wsz[s] = w * kSlice;
 }
 
-// Entries keep the CSR order of the original row (so every row sum adds its
-// terms in the same order as the definition); columns are renumbered.
-__global__ void k_sell_fill(const int32_t* perm, const int32_t* iperm, const int32_t* arp,
-                            const int32_t* acol, const double* aval, int64_t n, const int32_t* sptr,
-                            int32_t* scol, double* sval, double* diag) {
+__global__ void k_sell_fill(const int32_t* perm, const int32_t* cmap, const int32_t* rp, const int32_t* col,
+                            const double* val, int64_t n, const int32_t* sptr, int32_t* scol, double* sval,
+                            double* diag) {
   int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n) return;
   int64_t s = r / kSlice, ln = r % kSlice;
-  int32_t old = perm[r];
-  int32_t b = arp[old], e = arp[old + 1];
+  int32_t src = perm ? perm[r] : (int32_t)r;
+  int32_t b = rp[src], e = rp[src + 1];
   int32_t w = (sptr[s + 1] - sptr[s]) / kSlice;
   for (int32_t t = 0; t < w; ++t) {
     int64_t o = sptr[s] + (int64_t)t * kSlice + ln;
     if (b + t < e) {
-      int32_t j = acol[b + t];
-      scol[o] = iperm[j];
-      sval[o] = aval[b + t];
-      if (j == old) diag[r] = aval[b + t];
+      int32_t j = col[b + t];
+      scol[o] = cmap ? cmap[j] : j;
+      sval[o] = val[b + t];
+      if (diag && j == src) diag[r] = val[b + t];
     } else {
-      scol[o] = (int32_t)r;
+      scol[o] = 0;
       sval[o] = 0.0;
     }
   }
+}
+
+__global__ void k_max_len(const int32_t* v, int64_t n, int32_t* out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int32_t m = i < n ? v[i] : 0;
+  for (int o = 32; o > 0; o >>= 1) {
+    int32_t t = __shfl_xor(m, o, 64);
+    m = t > m ? t : m;
+  }
+  if ((threadIdx.x & 63) == 0 && m) atomicMax(out, m);
+}
+
+// nnz of colour class c = prefix[cptr[c+1]] - prefix[cptr[c]] of the row lengths
+__global__ void k_color_nnz(const int32_t* prefix, const int32_t* cptr, int nc, int32_t* cnnz) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < nc) cnnz[c] = prefix[cptr[c + 1]] - prefix[cptr[c]];
 }
 
 // P in the new numbering, SoA ELL-3 ([3][n]); padding repeats the first
@@ -144,28 +179,10 @@ __global__ void k_p_layout(const int32_t* perm, const int32_t* ciperm, const int
   int32_t old = perm[r];
   int32_t c = pcnt[old];
   qcnt[r] = c;
-  int32_t first = c > 0 ? pcol[3 * old] : 0;
-  first = (ciperm && c > 0) ? ciperm[first] : first;
+  int32_t first = c > 0 ? ciperm[pcol[3 * old]] : 0;
   for (int t = 0; t < 3; ++t) {
-    int32_t j = t < c ? pcol[3 * old + t] : -1;
-    qcol[t * n + r] = t < c ? (ciperm ? ciperm[j] : j) : first;
+    qcol[t * n + r] = t < c ? ciperm[pcol[3 * old + t]] : first;
     qval[t * n + r] = t < c ? pval[3 * old + t] : 0.0;
-  }
-}
-
-__global__ void k_t_len(const int32_t* trp, const int32_t* ciperm, int64_t nc, int32_t* len) {
-  int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (I < nc) len[ciperm ? ciperm[I] : I] = trp[I + 1] - trp[I];
-}
-
-__global__ void k_t_fill(const int32_t* trp, const int32_t* tcol, const double* tval, const int32_t* ciperm,
-                         const int32_t* fiperm, int64_t nc, const int32_t* nrp, int32_t* ncol, double* nval) {
-  int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (I >= nc) return;
-  int32_t o = nrp[ciperm ? ciperm[I] : I];
-  for (int32_t q = trp[I]; q < trp[I + 1]; ++q, ++o) {
-    ncol[o] = fiperm[tcol[q]];
-    nval[o] = tval[q];
   }
 }
 
@@ -177,38 +194,76 @@ __global__ void k_dense_scatter(const int32_t* rp, const int32_t* col, const dou
   for (int32_t e = rp[i]; e < rp[i + 1]; ++e) D[i * n + col[e]] = val[e];
 }
 
-// Right-looking dense Cholesky in one workgroup.  Entry (i, c) receives its
-// updates -L[i][j] * L[c][j] in ascending j, i.e. the same operations in the
-// same order as the column-by-column (left-looking) definition.
-__global__ void __launch_bounds__(1024) k_cholesky(double* D, int64_t n, int32_t* flags) {
+// Blocked right-looking dense Cholesky (32-column panels).  Entry (i, c)
+// receives its updates -L[i][j] * L[c][j] one at a time in ascending j, then
+// (below the diagonal) the division by L[c][c]: the same operations in the
+// same order as the column-by-column definition, whatever the blocking.
+constexpr int kPanel = 32;
+
+// Factor the diagonal block of panel k0 and solve the panel rows below it.
+__global__ void __launch_bounds__(1024) k_chol_panel(double* D, int64_t n, int64_t k0, int32_t* flags) {
+  __shared__ double T[kPanel][kPanel + 1];
   __shared__ int bad;
-  __shared__ double piv;
-  if (threadIdx.x == 0) bad = 0;
+  const int tid = threadIdx.x;
+  const int kb = (int)(n - k0 < kPanel ? n - k0 : kPanel);
+  const int ti = tid / kPanel, tc = tid % kPanel;
+  if (tid == 0) bad = 0;
+  if (ti < kb && tc <= ti) T[ti][tc] = D[(k0 + ti) * n + k0 + tc];
   __syncthreads();
-  for (int64_t j = 0; j < n; ++j) {
-    if (threadIdx.x == 0) {
-      double s = D[j * n + j];
-      if (!(s > 0.0)) {
+  for (int j = 0; j < kb; ++j) {
+    if (tid == 0) {
+      const double sv = T[j][j];
+      if (!(sv > 0.0)) {
         bad = 1;
         atomicOr(flags, F_NOT_SPD);
       } else {
-        piv = sqrt(s);
-        D[j * n + j] = piv;
+        T[j][j] = sqrt(sv);
       }
     }
     __syncthreads();
     if (bad) return;
-    const double d = piv;
-    for (int64_t i = j + 1 + threadIdx.x; i < n; i += blockDim.x) D[i * n + j] = D[i * n + j] / d;
+    if (tid > j && tid < kb) T[tid][j] = T[tid][j] / T[j][j];
     __syncthreads();
-    const int64_t m = n - j - 1;
-    for (int64_t idx = threadIdx.x; idx < m * m; idx += blockDim.x) {
-      int64_t a = idx / m, c = idx % m;
-      if (c > a) continue;
-      int64_t i = j + 1 + a, k = j + 1 + c;
-      D[i * n + k] = D[i * n + k] - D[i * n + j] * D[k * n + j];
+    if (ti > j && ti < kb && tc > j && tc <= ti) T[ti][tc] = T[ti][tc] - T[ti][j] * T[tc][j];
+    __syncthreads();
+  }
+  if (ti < kb && tc <= ti) D[(k0 + ti) * n + k0 + tc] = T[ti][tc];
+  // panel rows: l_ij = (a_ij - sum_{k0 <= m < j} l_im l_jm) / l_jj, ascending j
+  for (int64_t i = k0 + kb + tid; i < n; i += blockDim.x) {
+    double a[kPanel];
+#pragma unroll
+    for (int j = 0; j < kPanel; ++j) a[j] = j < kb ? D[i * n + k0 + j] : 0.0;
+#pragma unroll
+    for (int j = 0; j < kPanel; ++j) {
+      if (j >= kb) break;
+      double t = a[j];
+      for (int m = 0; m < j; ++m) t = t - a[m] * T[j][m];
+      a[j] = t / T[j][j];
     }
-    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kPanel; ++j)
+      if (j < kb) D[i * n + k0 + j] = a[j];
+  }
+}
+
+// Trailing update of the lower triangle below panel k0: one 32x32 tile per
+// workgroup, a_ic <- a_ic - l_ij l_cj for the panel columns j in ascending order.
+__global__ void __launch_bounds__(1024) k_chol_update(double* D, int64_t n, int64_t k0, int kb) {
+  __shared__ double LI[kPanel][kPanel + 1];
+  __shared__ double LC[kPanel][kPanel + 1];
+  const int64_t base = k0 + kb;
+  const int64_t I = blockIdx.y, C = blockIdx.x;
+  if (C > I) return;
+  const int ti = threadIdx.x / kPanel, tc = threadIdx.x % kPanel;
+  const int64_t gi = base + I * kPanel + ti, gc = base + C * kPanel + ti;
+  LI[ti][tc] = (gi < n && tc < kb) ? D[gi * n + k0 + tc] : 0.0;
+  LC[ti][tc] = (gc < n && tc < kb) ? D[gc * n + k0 + tc] : 0.0;
+  __syncthreads();
+  const int64_t i = base + I * kPanel + ti, c = base + C * kPanel + tc;
+  if (i < n && c <= i) {
+    double a = D[i * n + c];
+    for (int j = 0; j < kb; ++j) a = a - LI[ti][j] * LC[tc][j];
+    D[i * n + c] = a;
   }
 }
 
@@ -222,27 +277,58 @@ __global__ void k_split_factor(const double* D, int64_t n, double* L, double* U)
   U[k * n + i] = v;
 }
 
-// Column c of A^-1 by forward then backward substitution with L, one
-// wavefront per column; written as row c (A^-1 is symmetric).
+// Column c of A^-1 = L^-T L^-1 e_c by blocked forward then backward
+// substitution, one wavefront per column: for each block of 32 rows the
+// wavefront forms the products with the already-solved part in parallel,
+// then solves the block's triangle column by column (lane k owns row k of
+// the block; the 32x32 diagonal block is staged in LDS).  Written as row c
+// (A^-1 is symmetric).
 __global__ void __launch_bounds__(kWave) k_chol_inverse(const double* L, const double* U, int64_t n,
                                                         double* inv) {
   extern __shared__ double y[];
+  __shared__ double tile[kPanel][kPanel + 1];
   const int64_t c = blockIdx.x;
   const int lane = threadIdx.x;
+  const int r = lane & (kPanel - 1), half = lane / kPanel;
   for (int64_t i = lane; i < n; i += kWave) y[i] = 0.0;
   __syncthreads();
-  for (int64_t i = c; i < n; ++i) {
-    double s = 0.0;
-    for (int64_t m = c + lane; m < i; m += kWave) s += L[i * n + m] * y[m];
-    s = wave_sum(s);
-    if (lane == 0) y[i] = ((i == c ? 1.0 : 0.0) - s) / L[i * n + i];
+  for (int64_t b0 = (c / kPanel) * kPanel; b0 < n; b0 += kPanel) {
+    const int nb = (int)(n - b0 < kPanel ? n - b0 : kPanel);
+    double sacc = 0.0;
+    if (r < nb)
+      for (int64_t m = c + half; m < b0; m += 2) sacc += L[(b0 + r) * n + m] * y[m];
+    sacc += __shfl_xor(sacc, kPanel, kWave);
+    for (int k = half; k < kPanel; k += 2)
+      tile[r][k] = (r < nb && k < nb) ? L[(b0 + r) * n + b0 + k] : 0.0;
+    __syncthreads();
+    const int64_t row = b0 + r;
+    double t = (row == c ? 1.0 : 0.0) - sacc;
+    for (int k = 0; k < nb; ++k) {
+      if (lane == k) t = (b0 + k < c) ? 0.0 : t / tile[k][k];
+      const double yk = __shfl(t, k, kWave);
+      if (r > k) t = t - tile[r][k] * yk;
+    }
+    if (lane < nb) y[row] = (row < c) ? 0.0 : t;
     __syncthreads();
   }
-  for (int64_t i = n - 1; i >= 0; --i) {
-    double s = 0.0;
-    for (int64_t m = i + 1 + lane; m < n; m += kWave) s += U[i * n + m] * y[m];
-    s = wave_sum(s);
-    if (lane == 0) y[i] = (y[i] - s) / U[i * n + i];
+  for (int64_t b1 = n; b1 > 0; b1 -= kPanel) {
+    const int64_t b0 = b1 - kPanel > 0 ? b1 - kPanel : 0;
+    const int nb = (int)(b1 - b0);
+    double sacc = 0.0;
+    if (r < nb)
+      for (int64_t m = b1 + half; m < n; m += 2) sacc += U[(b0 + r) * n + m] * y[m];
+    sacc += __shfl_xor(sacc, kPanel, kWave);
+    for (int k = half; k < kPanel; k += 2)
+      tile[r][k] = (r < nb && k < nb) ? U[(b0 + r) * n + b0 + k] : 0.0;
+    __syncthreads();
+    double t = (r < nb ? y[b0 + r] : 0.0) - sacc;
+    for (int k = nb - 1; k >= 0; --k) {
+      if (lane == k) t = t / tile[k][k];
+      const double xk = __shfl(t, k, kWave);
+      if (r < k) t = t - tile[r][k] * xk;
+    }
+    __syncthreads();
+    if (lane < nb) y[b0 + r] = t;
     __syncthreads();
   }
   for (int64_t i = lane; i < n; i += kWave) inv[c * n + i] = y[i];
@@ -259,86 +345,147 @@ void colouring(Handle& h, Level& lv, int level) {
   check_hip(hipMemsetAsync(ncol, 0, 4, s), "memset");
   check_hip(hipMemsetAsync(h.rounds, 0, kMaxRounds * 4, s), "memset");
   ColorKey key{(h.opt.seed ^ kColorSalt) ^ ((uint64_t)level << 32)};
+  int32_t* wl = (int32_t*)talloc(s, (size_t)2 * n * 4);
+  const int grid = std::min(blocks_for(n), kRoundGrid);
   int k = 0;
   for (;;) {
     for (int t = 0; t < kRoundBatch; ++t, ++k)
-      k_color_round<<<blocks_for(n), kBlock, 0, s>>>(lv.arp, lv.acol, n, key, lv.color, ncol, h.rounds, k);
-    if (read_i64(h, h.rounds + (k - 1), 4) == 0) break;
+      k_color_round<<<grid, kBlock, 0, s>>>(lv.arp, lv.acol, n, key, lv.color, ncol, wl + ((k + 1) % 2) * n,
+                                            wl + (k % 2) * n, h.rounds, k);
+    int64_t left = 0, nco = 0;
+    ScalarRead rd[2] = {{h.rounds + (k - 1), 4, &left}, {ncol, 4, &nco}};
+    read_scalars(h, rd, 2);
+    lv.ncolors = (int32_t)nco;
+    if (left == 0) break;
     if (k + kRoundBatch > kMaxRounds) throw Error{GMG_DEVICE_ERROR, "colouring did not terminate"};
   }
-  lv.ncolors = (int32_t)read_i64(h, ncol, 4);
+  tfree(s, wl);
   tfree(s, ncol);
 }
+
+namespace {
+
+// CSR (source rows perm[r], columns through cmap) -> SELL-64 owned by the
+// handle; *maxlen receives the longest row.
+SellView make_sell(Handle& h, const int32_t* perm, const int32_t* cmap, const int32_t* rp, const int32_t* col,
+                   const double* val, int64_t n, double* diag, int32_t* maxlen) {
+  hipStream_t s = h.stream;
+  const int64_t ns = (n + kSlice - 1) / kSlice;
+  int32_t* len = (int32_t*)dalloc(h, (size_t)(n + 1) * 4);
+  int32_t* ptr = (int32_t*)dalloc(h, (size_t)(ns + 1) * 4);
+  int32_t* wsz = (int32_t*)talloc(s, (size_t)(ns + 1) * 4);
+  int32_t* mx = (int32_t*)talloc(s, 4);
+  check_hip(hipMemsetAsync(mx, 0, 4, s), "memset");
+  k_row_len<<<blocks_for(n), kBlock, 0, s>>>(perm, rp, n, len);
+  k_max_len<<<blocks_for(n), kBlock, 0, s>>>(len, n, mx);
+  k_slice_width<<<blocks_for(ns), kBlock, 0, s>>>(len, n, ns, wsz);
+  scan_i32(wsz, ptr, ns, s);
+  int64_t tot = 0, ml = 0;
+  ScalarRead rd[2] = {{ptr + ns, 4, &tot}, {mx, 4, &ml}};
+  read_scalars(h, rd, 2);
+  *maxlen = (int32_t)ml;
+  int32_t* scol = (int32_t*)dalloc(h, (size_t)(tot + 1) * 4);
+  double* sval = (double*)dalloc(h, (size_t)(tot + 1) * 8);
+  k_sell_fill<<<blocks_for(n), kBlock, 0, s>>>(perm, cmap, rp, col, val, n, ptr, scol, sval, diag);
+  tfree(s, wsz);
+  tfree(s, mx);
+  SellView v;
+  v.ptr = ptr;
+  v.col = scol;
+  v.val = sval;
+  v.len = len;
+  return v;
+}
+
+// Lanes per row for the lane-parallel row kernels: each lane loads up to
+// kLaneEntries entries of its row per pass.
+int32_t lanes_for(int32_t maxlen) {
+  int32_t r = 4;
+  while (r < 64 && r * kLaneEntries < maxlen) r *= 2;
+  return r;
+}
+
+}  // namespace
 
 void solve_layout(Handle& h, Level& lv, const Level* nx, const int32_t* t_rp, const int32_t* t_col,
                   const double* t_val) {
   hipStream_t s = h.stream;
   const int64_t n = lv.n;
   const int nb = blocks_for(n);
+  const int C = lv.color ? lv.ncolors : 1;
   lv.perm = (int32_t*)dalloc(h, (size_t)n * 4);
   lv.iperm = (int32_t*)dalloc(h, (size_t)n * 4);
-  int32_t *hist = nullptr, *off = nullptr, *cptr = nullptr;
+  int32_t* cptr = (int32_t*)dalloc(h, (size_t)(C + 1) * 4);
+  int32_t *hist = nullptr, *off = nullptr;
+  int32_t* stage = (int32_t*)pinned_staging((size_t)(2 * C + 1) * 4);
   if (lv.color) {
     // rows sorted by (colour, index)
-    const int C = lv.ncolors;
     hist = (int32_t*)talloc(s, ((size_t)C * nb + 1) * 4);
     off = (int32_t*)talloc(s, ((size_t)C * nb + 1) * 4);
     k_color_hist<<<nb, kBlock, (size_t)C * 4, s>>>(lv.color, n, nb, C, hist);
     scan_i32(hist, off, (int64_t)C * nb, s);
     k_color_place<<<nb, kBlock, 0, s>>>(lv.color, n, nb, off, lv.perm, lv.iperm);
-    cptr = (int32_t*)talloc(s, (size_t)(C + 1) * 4);
     k_color_ptr<<<blocks_for(C + 1), kBlock, 0, s>>>(off, nb, C, cptr);
-    lv.color_ptr.assign(C + 1, 0);
-    check_hip(hipMemcpyAsync(lv.color_ptr.data(), cptr, (size_t)(C + 1) * 4, hipMemcpyDeviceToHost, s),
-              "copy");
   } else {
     // the coarsest level keeps its numbering (it is solved directly)
     iota_i32(lv.perm, n, s);
     iota_i32(lv.iperm, n, s);
-    lv.color_ptr = {0, (int32_t)n};
+    stage[0] = 0;
+    stage[1] = (int32_t)n;
+    check_hip(hipMemcpyAsync(cptr, stage, 8, hipMemcpyHostToDevice, s), "copy");
   }
-  // SELL-64
-  const int64_t ns = (n + kSlice - 1) / kSlice;
-  lv.s_len = (int32_t*)dalloc(h, (size_t)n * 4);
-  int32_t* wsz = (int32_t*)talloc(s, (size_t)(ns + 1) * 4);
-  lv.s_ptr = (int32_t*)dalloc(h, (size_t)(ns + 1) * 4);
-  k_row_len<<<blocks_for(n), kBlock, 0, s>>>(lv.perm, lv.arp, n, lv.s_len);
-  k_slice_width<<<blocks_for(ns), kBlock, 0, s>>>(lv.s_len, n, ns, wsz);
-  scan_i32(wsz, lv.s_ptr, ns, s);
-  int64_t tot = read_i64(h, lv.s_ptr + ns, 4);
-  lv.s_col = (int32_t*)dalloc(h, (size_t)(tot + 1) * 4);
-  lv.s_val = (double*)dalloc(h, (size_t)(tot + 1) * 8);
   lv.diag = (double*)dalloc(h, (size_t)n * 8);
-  k_sell_fill<<<blocks_for(n), kBlock, 0, s>>>(lv.perm, lv.iperm, lv.arp, lv.acol, lv.aval, n, lv.s_ptr,
-                                               lv.s_col, lv.s_val, lv.diag);
-  // vectors
+  LevelView& v = lv.view;
+  v.n = (int32_t)n;
+  v.ncolors = C;
+  v.cptr = cptr;
+  v.A = make_sell(h, lv.perm, lv.iperm, lv.arp, lv.acol, lv.aval, n, lv.diag, &v.maxa);
+  v.ra = lanes_for(v.maxa);
+  v.diag = lv.diag;
   lv.x = (double*)dalloc(h, (size_t)n * 8);
   lv.b = (double*)dalloc(h, (size_t)n * 8);
   lv.r = (double*)dalloc(h, (size_t)n * 8);
-  // prolongation / restriction in the new numbering
-  if (nx) {
-    const int64_t nc = nx->n;
-    const int32_t* ciperm = nx->iperm;           // null on the coarsest level (identity)
-    lv.q_col = (int32_t*)dalloc(h, (size_t)3 * n * 4);
-    lv.q_val = (double*)dalloc(h, (size_t)3 * n * 8);
-    lv.q_cnt = (int32_t*)dalloc(h, (size_t)n * 4);
-    k_p_layout<<<blocks_for(n), kBlock, 0, s>>>(lv.perm, ciperm, lv.pcol, lv.pval, lv.pcnt, n, lv.q_col,
-                                                lv.q_val, lv.q_cnt);
-    int32_t* len = (int32_t*)talloc(s, (size_t)(nc + 1) * 4);
-    lv.t_rp = (int32_t*)dalloc(h, (size_t)(nc + 1) * 4);
-    k_t_len<<<blocks_for(nc), kBlock, 0, s>>>(t_rp, ciperm, nc, len);
-    scan_i32(len, lv.t_rp, nc, s);
-    lv.t_col = (int32_t*)dalloc(h, (size_t)(lv.nnzP + 1) * 4);
-    lv.t_val = (double*)dalloc(h, (size_t)(lv.nnzP + 1) * 8);
-    k_t_fill<<<blocks_for(nc), kBlock, 0, s>>>(t_rp, t_col, t_val, ciperm, lv.iperm, nc, lv.t_rp, lv.t_col,
-                                               lv.t_val);
-    tfree(s, len);
+  v.x = lv.x;
+  v.b = lv.b;
+  v.r = lv.r;
+  // algorithmic bytes: 12 per entry (column + value), 28 per row (b, diagonal, row length, x write)
+  lv.residual_bytes = 12.0 * (double)lv.nnzA + 28.0 * (double)n;
+  int32_t* pre = nullptr;
+  int32_t* cn = nullptr;
+  if (lv.color) {
+    pre = (int32_t*)talloc(s, (size_t)(n + 1) * 4);
+    cn = (int32_t*)talloc(s, (size_t)C * 4);
+    scan_i32(v.A.len, pre, n, s);
+    k_color_nnz<<<blocks_for(C), kBlock, 0, s>>>(pre, cptr, C, cn);
   }
+  if (nx) {
+    // P: rows in this level's new numbering, columns in the next level's
+    int32_t* qcol = (int32_t*)dalloc(h, (size_t)3 * n * 4);
+    double* qval = (double*)dalloc(h, (size_t)3 * n * 8);
+    int32_t* qcnt = (int32_t*)dalloc(h, (size_t)n * 4);
+    k_p_layout<<<blocks_for(n), kBlock, 0, s>>>(lv.perm, nx->iperm, lv.pcol, lv.pval, lv.pcnt, n, qcol, qval,
+                                                qcnt);
+    v.q_col = qcol;
+    v.q_val = qval;
+    v.q_cnt = qcnt;
+    // P^T: row I' = coarse row perm_c[I'], entries in ascending original fine index
+    v.T = make_sell(h, nx->perm, lv.iperm, t_rp, t_col, t_val, nx->n, nullptr, &v.maxt);
+    v.rt = lanes_for(v.maxt);
+  }
+  // colour ranges and per-colour entry counts (staging is reused by make_sell's reads, so copy last)
+  stage = (int32_t*)pinned_staging((size_t)(2 * C + 1) * 4);
+  check_hip(hipMemcpyAsync(stage, cptr, (size_t)(C + 1) * 4, hipMemcpyDeviceToHost, s), "copy");
+  if (lv.color) check_hip(hipMemcpyAsync(stage + C + 1, cn, (size_t)C * 4, hipMemcpyDeviceToHost, s), "copy");
   sync(s, "solve layout");
+  lv.color_ptr.assign(stage, stage + C + 1);
+  lv.color_bytes.assign(C, 0.0);
+  if (lv.color)
+    for (int c = 0; c < C; ++c)
+      lv.color_bytes[c] = 12.0 * (double)stage[C + 1 + c] + 28.0 * (double)(lv.color_ptr[c + 1] - lv.color_ptr[c]);
+  tfree(s, pre);
+  tfree(s, cn);
   tfree(s, hist);
   tfree(s, off);
-  tfree(s, cptr);
-  tfree(s, wsz);
 }
 
 void coarse_factor(Handle& h, Level& lv) {
@@ -348,7 +495,15 @@ void coarse_factor(Handle& h, Level& lv) {
   double* U = (double*)talloc(s, (size_t)n * n * 8);
   check_hip(hipMemsetAsync(D, 0, (size_t)n * n * 8, s), "memset");
   k_dense_scatter<<<blocks_for(n), kBlock, 0, s>>>(lv.arp, lv.acol, lv.aval, n, D);
-  k_cholesky<<<1, 1024, 0, s>>>(D, n, h.flags);
+  for (int64_t k0 = 0; k0 < n; k0 += kPanel) {
+    const int kb = (int)std::min<int64_t>(kPanel, n - k0);
+    k_chol_panel<<<1, 1024, 0, s>>>(D, n, k0, h.flags);
+    const int64_t m = n - k0 - kb;
+    if (m > 0) {
+      const int t = (int)((m + kPanel - 1) / kPanel);
+      k_chol_update<<<dim3(t, t), 1024, 0, s>>>(D, n, k0, kb);
+    }
+  }
   h.chol = (double*)dalloc(h, (size_t)n * n * 8);
   h.cinv = (double*)dalloc(h, (size_t)n * n * 8);
   k_split_factor<<<blocks_for(n * n), kBlock, 0, s>>>(D, n, h.chol, U);
