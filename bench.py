@@ -19,8 +19,22 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 
+# HBM bytes per launch from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE (scaled by a plain copy;
+# profiles/k_gs_color_fine_torus1024.md), valid only for the solve kernels they were taken on.
+TRAFFIC = {"gs_finest": {"bytes_per_launch": 30476802, "solve_src_sha256_16": "ae2bd73a3e8e2323"}}
+
 KERNEL_NAMES = {"gs_finest": "k_gs_color_fine (one colour of a Gauss-Seidel sweep, level 0)",
                 "residual_finest": "k_residual_norm (residual + norm partials, level 0)"}
+
+
+def traffic_for(kind):
+    import hashlib
+    rec = TRAFFIC.get(kind)
+    if rec is None:
+        return None
+    src = os.path.join(ROOT, "paper_2307_04886_amd", "csrc", "solve.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    return rec["bytes_per_launch"] if sha == rec["solve_src_sha256_16"] else None
 
 
 def main():
@@ -33,6 +47,9 @@ def main():
     ap.add_argument("--size", type=int, default=1024, help="torus grid size (default 1024)")
     ap.add_argument("--timer", default="gs_finest", choices=["gs_finest", "residual_finest", "none"],
                     help="kernel class timed with HIP events for the roofline entry")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="after the timed region, run one plain 256 MiB device copy (reference for "
+                         "hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the method's single-mesh "
@@ -102,12 +119,21 @@ def main():
                    "points": prob.n, "edges": prob.m, "nnz_A": prob.nnz, "levels": levels,
                    "v_cycles": info.iterations, "rel_residual": info.rel_residual, "tol": args.tol},
         "roofline": None if args.timer == "none" else {"bound": "hbm", "kernel": KERNEL_NAMES[args.timer],
+                     "share_of_step": k_ms * 1e-3 / dt,
                      "achieved": k_bytes / (k_ms * 1e-3) / 1e9, "peak": 8000.0, "unit": "GB/s",
-                     "frac": k_bytes / (k_ms * 1e-3) / 1e9 / 8000.0, "traffic": None,
+                     "frac": k_bytes / (k_ms * 1e-3) / 1e9 / 8000.0, "traffic": traffic_for(args.timer),
                      "launches": k_launches, "avg_launch_us": 1e3 * k_ms / max(k_launches, 1),
                      "bytes_per_launch": k_bytes / max(k_launches, 1)},
         "cpu_baseline": None,
     }
+
+    if args.calibrate_copy:
+        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device=dev)   # 256 MiB
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["calibration_copy_bytes"] = 2 * src.numel() * 8
 
     if not args.no_cpu_baseline:
         import oracle

@@ -125,7 +125,7 @@ double g_bytes = 0.0;
 int64_t g_launches = 0;
 }  // namespace
 
-KernelTimer::Scope::Scope(int kind, hipStream_t s, double bytes) : stream(s) {
+KernelTimer::Scope::Scope(int kind, double bytes) {
   if (active != kind) return;
   if (g_ev_used + 2 > g_ev.size()) {
     for (int k = 0; k < 256; ++k) {
@@ -134,15 +134,11 @@ KernelTimer::Scope::Scope(int kind, hipStream_t s, double bytes) : stream(s) {
       g_ev.push_back(e);
     }
   }
-  (void)hipEventRecord(g_ev[g_ev_used], s);
+  start = g_ev[g_ev_used];
   stop = g_ev[g_ev_used + 1];
   g_ev_used += 2;
   g_bytes += bytes;
   g_launches += 1;
-}
-
-KernelTimer::Scope::~Scope() {
-  if (stop) (void)hipEventRecord(stop, stream);
 }
 
 namespace {

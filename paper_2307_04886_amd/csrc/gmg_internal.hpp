@@ -2,6 +2,7 @@
 // by the kernels, the hierarchy data layout in HBM and the host launchers.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -180,14 +181,14 @@ struct Handle {
 
 // Per-kernel timing with HIP events on the launch stream (measurement only;
 // inactive unless gmg_timer_start was called).
+// The events are passed to hipExtLaunchKernelGGL, which has the dispatch
+// itself record them at the kernel's start and end.
 struct KernelTimer {
   enum Kind { GS_FINEST = 0, RESIDUAL_FINEST = 1, KINDS = 2 };
   static int active;
   struct Scope {
-    hipEvent_t stop = nullptr;
-    hipStream_t stream = nullptr;
-    Scope(int kind, hipStream_t s, double bytes);
-    ~Scope();
+    hipEvent_t start = nullptr, stop = nullptr;   // null unless this launch is timed
+    Scope(int kind, double bytes);
   };
 };
 

@@ -363,9 +363,10 @@ void gs_sweep(const Level& lv, hipStream_t s, bool finest) {
     int32_t r0 = lv.color_ptr[c], r1 = lv.color_ptr[c + 1];
     if (r1 <= r0) continue;
     if (finest) {
-      KernelTimer::Scope t(KernelTimer::GS_FINEST, s, lv.color_bytes[c]);
+      KernelTimer::Scope t(KernelTimer::GS_FINEST, lv.color_bytes[c]);
       int32_t span = r1 - (r0 & ~(kSlice - 1));
-      k_gs_color_fine<<<blocks_for(span), kBlock, 0, s>>>(lv.view.A, lv.diag, lv.b, lv.x, r0, r1);
+      hipExtLaunchKernelGGL(k_gs_color_fine, dim3(blocks_for(span)), dim3(kBlock), 0, s, t.start, t.stop, 0,
+                            lv.view.A, (const double*)lv.diag, (const double*)lv.b, lv.x, r0, r1);
     } else {
       dispatch_lanes<LaunchGS>(lv.view.ra, lv, r0, r1, s);
     }
@@ -406,8 +407,9 @@ void norm2_partials(const double* v, int64_t n, double* partials, hipStream_t s)
 }
 
 void residual_norm(const Level& lv, double* partials, hipStream_t s) {
-  KernelTimer::Scope t(KernelTimer::RESIDUAL_FINEST, s, lv.residual_bytes);
-  k_residual_norm<<<kNormBlocks, kBlock, 0, s>>>(lv.view.A, lv.b, lv.x, lv.r, lv.n, partials);
+  KernelTimer::Scope t(KernelTimer::RESIDUAL_FINEST, lv.residual_bytes);
+  hipExtLaunchKernelGGL(k_residual_norm, dim3(kNormBlocks), dim3(kBlock), 0, s, t.start, t.stop, 0, lv.view.A,
+                        (const double*)lv.b, (const double*)lv.x, lv.r, (int64_t)lv.n, partials);
 }
 
 void finish_norm(const double* partials, double* out, hipStream_t s) {

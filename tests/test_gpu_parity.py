@@ -147,6 +147,36 @@ def test_config_torus_full():
     _say(f"[gpu] torus1024 V-cycles {it} |x_gpu - x_orc| / |x_orc| = {err:.2e}")
 
 
+def test_golden_paths():
+    """The hand-worked path cases (exact radius, equidistant seeds) through the C ABI."""
+    import json
+    import os
+    _say("[gpu] golden path cases")
+    g = gmg()
+    from paper_2307_04886_amd.binding import build_hierarchy
+    golden = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "path_ties.json")))
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    for case in golden["cases"]:
+        n = case["n"]
+        X = np.zeros((n, 3))
+        X[:, 0] = case.get("x", np.arange(n, dtype=np.float64))
+        edges = np.array([[i, i + 1] for i in range(n - 1)], dtype=np.int32)
+        rp, ci, va = [0], [], []
+        for i in range(n):
+            for j in (i - 1, i, i + 1):
+                if 0 <= j < n:
+                    ci.append(j)
+                    va.append(2.5 if i == j else -1.0)
+            rp.append(len(ci))
+        o = g.default_options(min_coarse_points=1, max_levels=2, sample_order=1,
+                              coarsening_ratio=case["phi"])
+        h = build_hierarchy(dev(X), dev(edges), dev(np.array(rp, np.int32)), dev(np.array(ci, np.int32)),
+                            dev(np.array(va)), o)
+        assert h.export(0, "samples").tolist() == case["samples"]
+        assert h.export(0, "labels").tolist() == case["labels"]
+        assert h.export(0, "dist").tolist() == case["dist"]
+
+
 def test_determinism():
     _say("[gpu] determinism")
     prob = problem("torus96")

@@ -162,12 +162,9 @@ def test_voronoi_fixed_point_and_dijkstra(name):
         assert np.array_equal(arg[ok], lv["labels"][ok])
 
 
-def test_voronoi_ties_on_a_path():
-    """Golden: a unit path where every odd point is equidistant from two seeds."""
-    g = json.load(open(os.path.join(GOLDEN, "path_ties.json")))
-    n = g["n"]
+def path_hierarchy(n, phi, x=None):
     X = np.zeros((n, 3))
-    X[:, 0] = np.arange(n, dtype=np.float64)
+    X[:, 0] = np.arange(n, dtype=np.float64) if x is None else np.array(x, dtype=np.float64)
     edges = np.array([[i, i + 1] for i in range(n - 1)], dtype=np.int32)
     rp = [0]
     ci, va = [], []
@@ -177,14 +174,20 @@ def test_voronoi_ties_on_a_path():
                 ci.append(j)
                 va.append(2.5 if i == j else -1.0)
         rp.append(len(ci))
-    o = oracle.default_options(min_coarse_points=1, max_levels=2, sample_order=1,
-                               coarsening_ratio=g["phi"])
-    h = oracle.Hierarchy(X, edges, np.array(rp), np.array(ci), np.array(va), o)
-    lv = h.level(0)
-    assert lv["scalars"][0] == 1.0
-    assert lv["samples"].tolist() == g["samples"]
-    assert lv["labels"].tolist() == g["labels"]
-    assert lv["dist"].tolist() == g["dist"]
+    o = oracle.default_options(min_coarse_points=1, max_levels=2, sample_order=1, coarsening_ratio=phi)
+    return oracle.Hierarchy(X, edges, np.array(rp), np.array(ci), np.array(va), o)
+
+
+def test_sampling_and_voronoi_on_a_path():
+    """Golden: unit paths where points sit exactly at the radius and exactly between two seeds."""
+    g = json.load(open(os.path.join(GOLDEN, "path_ties.json")))
+    for case in g["cases"]:
+        h = path_hierarchy(case["n"], case["phi"], case.get("x"))
+        lv = h.level(0)
+        assert lv["scalars"][0] == (2.0 if "x" in case else 1.0)
+        assert lv["samples"].tolist() == case["samples"], case["derivation"]
+        assert lv["labels"].tolist() == case["labels"]
+        assert lv["dist"].tolist() == case["dist"]
 
 
 @pytest.mark.parametrize("name", SMALL)
@@ -218,6 +221,28 @@ def test_no_shift_keeps_sample_positions():
     p, h = hier("torus48", shift_coarse_points=0)
     lv, nx = h.level(0), h.level(1)
     assert np.array_equal(nx["X"], lv["X"][lv["samples"]])
+
+
+def test_equal_distance_candidates_keep_the_first():
+    """Without the shift a sample coincides with its coarse point, so every candidate triangle
+    is at distance 0: the first non-degenerate candidate in (j, k) order must be chosen and the
+    row must be the single entry {c: 1}."""
+    for name in ["torus48", "ico4", "pc4k"]:
+        p, h = hier(name, shift_coarse_points=0)
+        lv, nx = h.level(0), h.level(1)
+        Xc = nx["X"]
+        checked = 0
+        for I, s in enumerate(lv["samples"]):
+            c = lv["labels"][s]
+            assert c == I
+            good = [(j, k) for j, k in _candidate_triangles(nx, c)
+                    if brute.sin2_angle(Xc[c], Xc[j], Xc[k]) > 1e-12 * 1.01]
+            if not good:
+                continue
+            assert tuple(lv["tri"][s]) == good[0]
+            assert lv["pcnt"][s] == 1 and lv["pcol"][s, 0] == c and lv["pval"][s, 0] == 1.0
+            checked += 1
+        assert checked > 0
 
 
 def test_closest_point_golden():
