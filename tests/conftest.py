@@ -30,6 +30,7 @@ def problem(name):
             "pc4k": lambda: synth.small_pointcloud(4000),
             "pc20k": lambda: synth.small_pointcloud(20000),
             "torus1024": lambda: synth.config_torus(),
+            "bumpy2m": lambda: synth.config_bumpy_sphere(),
         }
         _PROBLEMS[name] = makers[name]()
     return _PROBLEMS[name]

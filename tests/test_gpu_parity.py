@@ -147,6 +147,32 @@ def test_config_torus_full():
     _say(f"[gpu] torus1024 V-cycles {it} |x_gpu - x_orc| / |x_orc| = {err:.2e}")
 
 
+@pytest.mark.timeout(900)
+def test_config_bumpy_sphere_full():
+    """2M-point bumpy sphere, kNN graph: the whole hierarchy bit for bit, the
+    first V-cycles against the oracle, the full solve by its true residual."""
+    _say("[gpu] bumpy sphere 2M points, kNN k=8, full pipeline")
+    prob = problem("bumpy2m")
+    orc, gpu = both(prob)
+    compare_hierarchies(orc, gpu, "bumpy2m")
+    _say("[gpu] bumpy2m hierarchy matches; first V-cycles")
+    k = 4
+    x_o, it_o, hist_o, st_o = orc.solve(prob.rhs, tol=1e-8, max_iters=k)
+    b = torch.from_numpy(prob.rhs).cuda()
+    x_g, info, st_g, hist_g = gpu.solve(b, tol=1e-8, max_iters=k, history=True)
+    assert st_o == 1 and st_g == 1 and info.iterations == it_o == k
+    assert np.all(np.abs(hist_g[:k] - hist_o[:k]) <= 1e-10 * hist_o[:k] + 1e-13), (hist_g[:k], hist_o[:k])
+    err = np.linalg.norm(x_g.cpu().numpy() - x_o) / np.linalg.norm(x_o)
+    assert err <= 1e-9, err
+    x_g, info, st_g = gpu.solve(b, tol=1e-8, max_iters=200)
+    assert st_g == 0
+    A = prob.matrix()
+    xg = x_g.cpu().numpy()
+    res = np.linalg.norm(prob.rhs - A @ xg) / np.linalg.norm(prob.rhs)
+    assert res <= 1e-8 * (1 + 1e-9) and abs(res - info.rel_residual) <= 1e-9 * res
+    _say(f"[gpu] bumpy2m V-cycles {info.iterations}, true rel. residual {res:.3e}")
+
+
 def test_golden_paths():
     """The hand-worked path cases (exact radius, equidistant seeds) through the C ABI."""
     import json
