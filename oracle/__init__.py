@@ -66,6 +66,8 @@ def lib():
         L.orc_export.argtypes = [P, ctypes.c_int32, ctypes.c_int32, P, ctypes.c_int64]
         L.orc_solve.argtypes = [P, P, P, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
                                 ctypes.POINTER(ctypes.c_int32), P]
+        L.orc_precondition.argtypes = [P, P, P, ctypes.c_int32]
+        L.orc_solve_pcg.argtypes = [P, P, P, ctypes.c_double, ctypes.c_int32, ctypes.c_int32, P, P, P]
         L.orc_closest_point.argtypes = [P, P, P, P, P]
         L.orc_degenerate.argtypes = [P, P, P]
         L.orc_mix64.argtypes = [ctypes.c_uint64]
@@ -176,6 +178,30 @@ class Hierarchy:
         if st < 0:
             raise OracleError(st)
         return x, it.value, hist[:it.value], st
+
+
+    def precondition(self, r, precision=0):
+        """z = B r: one symmetric V-cycle from zero (precision 0: double, 1: float)."""
+        r = np.ascontiguousarray(r, dtype=np.float64)
+        z = np.zeros_like(r)
+        st = lib().orc_precondition(self._h, _ptr(r), _ptr(z), precision)
+        if st < 0:
+            raise OracleError(st)
+        return z
+
+    def solve_pcg(self, b, x0=None, tol=1e-8, max_iters=100, precision=0):
+        """Double-precision CG preconditioned by the symmetric V-cycle.
+        Returns (x, iterations, recursive residual history, status, final true rel. residual)."""
+        b = np.ascontiguousarray(b, dtype=np.float64)
+        x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
+        hist = np.zeros(max_iters, dtype=np.float64)
+        it = ctypes.c_int32(0)
+        fin = ctypes.c_double(0.0)
+        st = lib().orc_solve_pcg(self._h, _ptr(b), _ptr(x), tol, max_iters, precision, ctypes.byref(it),
+                                 _ptr(hist), ctypes.byref(fin))
+        if st < 0:
+            raise OracleError(st)
+        return x, it.value, hist[:it.value], st, fin.value
 
 
 def closest_point(p, a, b, c):

@@ -28,6 +28,9 @@
 //   colouring               - Gauss-Seidel order (Sec. 3 leaves it open)
 //   cholesky                - Alg. 2: direct solve on the coarsest level
 //   solve / vcycle          - Alg. 1 and Alg. 2 (V-cycle, nu_pre/nu_post GS)
+//   vcycle_sym, solve_pcg   - the V-cycle as a symmetric CG preconditioner
+//                             (Sec. 5 compares against MG-preconditioned CG),
+//                             in double or float, inside double-precision CG
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
@@ -645,6 +648,97 @@ void vcycle(const Hier& h, size_t l, const double* b, double* x, int mode) {
   for (int s = 0; s < h.opt.nu_post; ++s) gs_sweep(lv, b, x, mode);
 }
 
+// ---------------------------------------------------------------- CG preconditioner, mixed precision
+// A V-cycle used as the preconditioner B of conjugate gradients (MG as a CG
+// preconditioner is the solver setting the paper compares against).  For B to
+// be symmetric the post-smoothing sweeps are the adjoints of the
+// pre-smoothing sweeps: pre-smoothing visits the colours in ascending order,
+// post-smoothing in descending order.  The cycle starts from x = 0 on every
+// level.  Its arithmetic runs in T (double, or float for the mixed form): the
+// values of A_l and P_l are rounded to T once per use and every product and
+// sum is one T operation in the order written.  The coarsest level is solved
+// in double with the Cholesky factor; its right-hand side is widened from T
+// and its solution rounded to T.
+template <class T>
+inline void gs_row_t(const Level& lv, int32_t i, const T* b, T* x) {
+  T s = T(0);
+  for (int32_t e = lv.arp[i]; e < lv.arp[i + 1]; ++e) {
+    int32_t j = lv.acol[e];
+    if (j != i) s = s + (T)lv.aval[e] * x[j];
+  }
+  x[i] = (b[i] - s) / (T)lv.adiag[i];
+}
+
+template <class T>
+void gs_sweep_t(const Level& lv, const T* b, T* x, bool descending) {
+  if (!descending)
+    for (int64_t t = 0; t < lv.n; ++t) gs_row_t(lv, lv.color_rows[t], b, x);
+  else
+    for (int64_t t = lv.n - 1; t >= 0; --t) gs_row_t(lv, lv.color_rows[t], b, x);
+}
+
+template <class T>
+void vcycle_sym(const Hier& h, size_t l, const T* b, T* x) {
+  const Level& lv = h.L[l];
+  for (int64_t i = 0; i < lv.n; ++i) x[i] = T(0);
+  if (l + 1 == h.L.size()) {
+    std::vector<double> bd(lv.n), xd(lv.n);
+    for (int64_t i = 0; i < lv.n; ++i) bd[i] = (double)b[i];
+    cholesky_solve(h.chol, lv.n, bd.data(), xd.data());
+    for (int64_t i = 0; i < lv.n; ++i) x[i] = (T)xd[i];
+    return;
+  }
+  for (int s = 0; s < h.opt.nu_pre; ++s) gs_sweep_t(lv, b, x, false);
+  std::vector<T> r(lv.n);
+  for (int64_t i = 0; i < lv.n; ++i) {                   // r = b - A y
+    T s = T(0);
+    for (int32_t e = lv.arp[i]; e < lv.arp[i + 1]; ++e) s = s + (T)lv.aval[e] * x[lv.acol[e]];
+    r[i] = b[i] - s;
+  }
+  const Level& cl = h.L[l + 1];
+  std::vector<T> bc(cl.n, T(0)), xc(cl.n);
+  for (int64_t i = 0; i < lv.n; ++i)                     // b_c = P^T r, ascending i
+    for (int t = 0; t < lv.pcnt[i]; ++t) {
+      int32_t I = lv.pcol[3 * i + t];
+      bc[I] = bc[I] + (T)lv.pval[3 * i + t] * r[i];
+    }
+  vcycle_sym(h, l + 1, bc.data(), xc.data());
+  for (int64_t i = 0; i < lv.n; ++i) {                   // x <- y + P x_c
+    T s = T(0);
+    for (int t = 0; t < lv.pcnt[i]; ++t) s = s + (T)lv.pval[3 * i + t] * xc[lv.pcol[3 * i + t]];
+    x[i] = x[i] + s;
+  }
+  for (int s = 0; s < h.opt.nu_post; ++s) gs_sweep_t(lv, b, x, true);
+}
+
+// z = B r.  precision 0: double throughout; 1: r is rounded to float, the
+// cycle runs in float, z is widened back.
+void precondition(const Hier& h, const double* r, double* z, int precision) {
+  const int64_t n = h.L[0].n;
+  if (precision == 0) {
+    vcycle_sym<double>(h, 0, r, z);
+    return;
+  }
+  std::vector<float> rf(n), zf(n);
+  for (int64_t i = 0; i < n; ++i) rf[i] = (float)r[i];
+  vcycle_sym<float>(h, 0, rf.data(), zf.data());
+  for (int64_t i = 0; i < n; ++i) z[i] = (double)zf[i];
+}
+
+double dotp(const double* u, const double* v, int64_t n) {
+  double s = 0.0;
+  for (int64_t i = 0; i < n; ++i) s = s + u[i] * v[i];
+  return s;
+}
+
+void matvec(const Level& lv, const double* x, double* y) {
+  for (int64_t i = 0; i < lv.n; ++i) {
+    double s = 0.0;
+    for (int32_t e = lv.arp[i]; e < lv.arp[i + 1]; ++e) s = s + lv.aval[e] * x[lv.acol[e]];
+    y[i] = s;
+  }
+}
+
 int check_options(const Options& o) {
   if (o.struct_size != (int32_t)sizeof(Options)) return INVALID_ARGUMENT;
   if (!(o.coarsening_ratio > 0.0 && o.coarsening_ratio < 1.0)) return INVALID_ARGUMENT;
@@ -786,6 +880,79 @@ int orc_solve(void* hp, const double* b, double* x, double tol, int32_t max_iter
     *iters = it;
     if (rel <= tol) return OK;
   }
+  return NOT_CONVERGED;
+}
+
+// z = B r: one symmetric V-cycle from zero (precision 0: double, 1: float).
+int orc_precondition(void* hp, const double* r, double* z, int32_t precision) {
+  Hier* h = static_cast<Hier*>(hp);
+  if (!h || !r || !z || (precision != 0 && precision != 1)) return INVALID_ARGUMENT;
+  precondition(*h, r, z, precision);
+  return OK;
+}
+
+// Conjugate gradients in double on A x = b, preconditioned by B (above),
+// flexible form (Polak-Ribiere beta, which stays a CG method when B carries
+// rounding of a lower precision):
+//   r = b - A x, z = B r, p = z, rho = r.z
+//   repeat: q = A p; alpha = rho / p.q; x += alpha p; r_old = r; r -= alpha q;
+//           stop if |r| <= tol |b| and the true residual |b - A x| agrees;
+//           z = B r; beta = (r.z - r_old.z) / rho; rho = r.z; p = z + beta p.
+// If the recursive residual passes the test and the true one does not, r is
+// replaced by the true residual and the iteration goes on.  hist[k] is the
+// recursive |r| / |b| after iteration k+1; *final_rel the true one at the end.
+int orc_solve_pcg(void* hp, const double* b, double* x, double tol, int32_t max_iters, int32_t precision,
+                  int32_t* iters, double* hist, double* final_rel) {
+  Hier* h = static_cast<Hier*>(hp);
+  if (!h || !b || !x || !iters || !final_rel || max_iters < 1 || !(tol >= 0.0) ||
+      (precision != 0 && precision != 1))
+    return INVALID_ARGUMENT;
+  const Level& l0 = h->L[0];
+  const int64_t n = l0.n;
+  for (int64_t i = 0; i < n; ++i)
+    if (!std::isfinite(b[i]) || !std::isfinite(x[i])) return INVALID_ARGUMENT;
+  *iters = 0;
+  *final_rel = 0.0;
+  const double nb = norm2(b, n);
+  if (nb == 0.0) {
+    for (int64_t i = 0; i < n; ++i) x[i] = 0.0;
+    return OK;
+  }
+  std::vector<double> r(n), r_old(n), z(n), p(n), q(n);
+  matvec(l0, x, q.data());
+  for (int64_t i = 0; i < n; ++i) r[i] = b[i] - q[i];
+  double rel = norm2(r.data(), n) / nb;
+  *final_rel = rel;
+  if (rel <= tol) return OK;
+  precondition(*h, r.data(), z.data(), precision);
+  p = z;
+  double rho = dotp(r.data(), z.data(), n);
+  for (int32_t it = 1; it <= max_iters; ++it) {
+    matvec(l0, p.data(), q.data());
+    const double pq = dotp(p.data(), q.data(), n);
+    if (!(pq > 0.0) || !(rho > 0.0)) return NOT_SPD;
+    const double alpha = rho / pq;
+    for (int64_t i = 0; i < n; ++i) x[i] = x[i] + alpha * p[i];
+    r_old = r;
+    for (int64_t i = 0; i < n; ++i) r[i] = r[i] - alpha * q[i];
+    rel = norm2(r.data(), n) / nb;
+    if (hist) hist[it - 1] = rel;
+    *iters = it;
+    if (rel <= tol) {
+      matvec(l0, x, q.data());
+      for (int64_t i = 0; i < n; ++i) r[i] = b[i] - q[i];
+      *final_rel = norm2(r.data(), n) / nb;
+      if (*final_rel <= tol) return OK;
+    }
+    precondition(*h, r.data(), z.data(), precision);
+    const double rho_new = dotp(r.data(), z.data(), n);
+    const double beta = (rho_new - dotp(r_old.data(), z.data(), n)) / rho;
+    rho = rho_new;
+    for (int64_t i = 0; i < n; ++i) p[i] = z[i] + beta * p[i];
+  }
+  matvec(l0, x, q.data());
+  for (int64_t i = 0; i < n; ++i) r[i] = b[i] - q[i];
+  *final_rel = norm2(r.data(), n) / nb;
   return NOT_CONVERGED;
 }
 
