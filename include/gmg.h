@@ -108,6 +108,52 @@ int gmg_build_hierarchy(int64_t n, const double* points_dev, int64_t m, const in
 int gmg_solve(gmg_handle h, const double* b_dev, double* x_dev, double tol, int32_t max_iters,
               void* stream, gmg_solve_info* info, double* residual_history);
 
+/* Precision of the V-cycle used as a CG preconditioner. */
+enum gmg_precision {
+  GMG_PRECISION_F64 = 0, /* the cycle in double */
+  GMG_PRECISION_F32 = 1  /* float copies of A_l, P_l and the iterates; coarsest solve in double */
+};
+
+/*
+ * Solves A x = b by conjugate gradients in double precision, preconditioned
+ * by one symmetric V-cycle per iteration: multigrid as a CG preconditioner,
+ * the solver the paper compares against in Sec. 5, with the hierarchy of
+ * Sec. 4 and the cycle of Alg. 2 (smoothing before the coarse correction
+ * visits the colours in ascending order, after it in descending order, so the
+ * cycle from a zero guess is a symmetric operator).
+ *
+ *  b_dev, x_dev       float64 device vectors of length n (x_dev: in = initial guess, out = solution)
+ *  tol                relative tolerance (>= 0) on ||b - A x||_2 / ||b||_2
+ *  max_iters          maximum number of CG iterations (>= 1)
+ *  precision          GMG_PRECISION_F64 or GMG_PRECISION_F32: arithmetic of the cycle.  The
+ *                     residual, the solution update, every dot product and the coarsest
+ *                     (dense Cholesky) solve stay in double.
+ *  info               optional: iterations, converged, and the TRUE relative residual at exit
+ *  residual_history   optional host array of max_iters doubles: the recursively updated
+ *                     relative residual after each iteration
+ *
+ * The CG form is the flexible one (Polak-Ribiere coefficient), which stays a
+ * conjugate-direction method when the float cycle carries rounding.  When the
+ * recursive residual passes the test the true residual is computed; if that
+ * one does not pass, it replaces the recursive one and the iteration goes on.
+ * Float copies of the level data are made on the first F32 call (about
+ * 4 bytes per matrix entry) and kept by the handle.  Synchronises the stream
+ * once per iteration.  One solve at a time per handle.
+ * Returns GMG_OK, GMG_NOT_CONVERGED, GMG_INVALID_ARGUMENT, GMG_NOT_SPD (non-positive
+ * curvature: A or the cycle is not positive definite), GMG_OUT_OF_MEMORY or GMG_DEVICE_ERROR.
+ */
+int gmg_solve_pcg(gmg_handle h, const double* b_dev, double* x_dev, double tol, int32_t max_iters,
+                  int32_t precision, void* stream, gmg_solve_info* info, double* residual_history);
+
+/*
+ * z = B r: one symmetric V-cycle (the CG preconditioner above) from a zero
+ * guess, in the given precision.  r_dev, z_dev: float64 device vectors of
+ * length n (may not alias).  For callers with their own Krylov method.
+ * Returns GMG_OK, GMG_INVALID_ARGUMENT (also for non-finite r), GMG_OUT_OF_MEMORY
+ * or GMG_DEVICE_ERROR; the call returns after the stream has finished.
+ */
+int gmg_precondition(gmg_handle h, const double* r_dev, double* z_dev, int32_t precision, void* stream);
+
 /* Releases the handle and its device memory.  NULL is ignored. */
 void gmg_free(gmg_handle h);
 

@@ -26,9 +26,12 @@ EXPORTS = {
 }
 
 # Symbols the library exports (checked on load).
-SYMBOLS = ["gmg_default_options", "gmg_build_hierarchy", "gmg_solve", "gmg_free", "gmg_status_string",
-           "gmg_last_error", "gmg_num_levels", "gmg_level_sizes", "gmg_export_level", "gmg_timer_start",
-           "gmg_timer_stop"]
+SYMBOLS = ["gmg_default_options", "gmg_build_hierarchy", "gmg_solve", "gmg_solve_pcg", "gmg_precondition",
+           "gmg_free", "gmg_status_string", "gmg_last_error", "gmg_num_levels", "gmg_level_sizes",
+           "gmg_export_level", "gmg_timer_start", "gmg_timer_stop"]
+
+# gmg_precision
+PRECISION = {"f64": 0, "f32": 1}
 
 # kernel classes of gmg_timer_start
 TIMER_KERNELS = {"gs_finest": 0, "residual_finest": 1}
@@ -69,6 +72,8 @@ def library():
     L.gmg_build_hierarchy.argtypes = [I64, P, I64, P, P, P, P, I64, ctypes.POINTER(Options), P,
                                       ctypes.POINTER(P)]
     L.gmg_solve.argtypes = [P, P, P, ctypes.c_double, I32, P, ctypes.POINTER(SolveInfo), P]
+    L.gmg_solve_pcg.argtypes = [P, P, P, ctypes.c_double, I32, I32, P, ctypes.POINTER(SolveInfo), P]
+    L.gmg_precondition.argtypes = [P, P, P, I32, P]
     L.gmg_free.argtypes = [P]
     L.gmg_free.restype = None
     L.gmg_status_string.argtypes = [ctypes.c_int]
@@ -200,6 +205,37 @@ class Hierarchy:
         if history:
             return x, info, st, hist[:info.iterations]
         return x, info, st
+
+    def solve_pcg(self, b, x=None, tol=1e-8, max_iters=100, precision="f64", stream=None, history=False):
+        """gmg_solve_pcg: double CG preconditioned by the symmetric V-cycle in `precision`
+        ("f64" or "f32").  Returns (x, SolveInfo, status[, recursive residual history])."""
+        import torch
+        pb = _dev(b, torch.float64, (self.n,), "b")
+        if x is None:
+            x = torch.zeros_like(b)
+        px = _dev(x, torch.float64, (self.n,), "x")
+        info = SolveInfo()
+        hist = np.zeros(max_iters, dtype=np.float64)
+        st = library().gmg_solve_pcg(self._h, pb, px, float(tol), int(max_iters), PRECISION[precision],
+                                     _stream_ptr(stream), ctypes.byref(info),
+                                     hist.ctypes.data_as(ctypes.c_void_p))
+        if st < 0:
+            raise _err(st)
+        if history:
+            return x, info, st, hist[:info.iterations]
+        return x, info, st
+
+    def precondition(self, r, z=None, precision="f64", stream=None):
+        """gmg_precondition: z = B r, one symmetric V-cycle from zero."""
+        import torch
+        pr = _dev(r, torch.float64, (self.n,), "r")
+        if z is None:
+            z = torch.empty_like(r)
+        pz = _dev(z, torch.float64, (self.n,), "z")
+        st = library().gmg_precondition(self._h, pr, pz, PRECISION[precision], _stream_ptr(stream))
+        if st:
+            raise _err(st)
+        return z
 
 
 def build_hierarchy(points, edges, rowptr, col, val, options=None, stream=None):

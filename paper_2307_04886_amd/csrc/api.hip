@@ -8,6 +8,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
+#include <type_traits>
 
 #include "gmg_internal.hpp"
 
@@ -126,7 +127,7 @@ int64_t g_launches = 0;
 }  // namespace
 
 KernelTimer::Scope::Scope(int kind, double bytes) {
-  if (active != kind) return;
+  if (kind < 0 || active != kind) return;
   if (g_ev_used + 2 > g_ev.size()) {
     for (int k = 0; k < 256; ++k) {
       hipEvent_t e;
@@ -148,6 +149,10 @@ void release(H* h) {
   if (!h) return;
   if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
   if (h->graph) (void)hipGraphDestroy(h->graph);
+  for (int p = 0; p < 2; ++p) {
+    if (h->kry.exec[p]) (void)hipGraphExecDestroy(h->kry.exec[p]);
+    if (h->kry.graph[p]) (void)hipGraphDestroy(h->kry.graph[p]);
+  }
   if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   for (void* p : h->allocs) (void)hipFreeAsync(p, h->stream);
   (void)hipStreamSynchronize(h->stream);
@@ -158,6 +163,32 @@ bool options_ok(const gmg_options& o) {
   return o.struct_size == (int32_t)sizeof(gmg_options) && o.coarsening_ratio > 0.0 &&
          o.coarsening_ratio < 1.0 && o.min_coarse_points >= 1 && o.max_levels >= 1 && o.nu_pre >= 0 &&
          o.nu_post >= 0 && (o.sample_order == 0 || o.sample_order == 1);
+}
+
+// The single-workgroup tail of a cycle: levels tail_start.. with their views,
+// iterates in LDS while they fit.
+template <class V>
+void make_tail(const Handle& h, Cycle<V>& c) {
+  const int nl = (int)h.L.size();
+  TailDescT<V>& t = c.tail;
+  t = TailDescT<V>();
+  t.nlev = nl - h.tail_start;
+  t.nu_pre = h.opt.nu_pre;
+  t.nu_post = h.opt.nu_post;
+  t.descending_post = c.symmetric ? 1 : 0;
+  t.cinv = h.cinv;
+  t.lds_elems = 0;
+  const int32_t cap = kTailLdsBytes / (int32_t)sizeof(V);
+  for (int l = h.tail_start; l < nl; ++l) {
+    const LevelViewT<V>& v = c.v[l];
+    t.lv[l - h.tail_start] = v;
+    if (t.lds_elems + v.n <= cap) {
+      t.lds_off[l - h.tail_start] = t.lds_elems;
+      t.lds_elems += (int32_t)v.n;
+    } else {
+      t.lds_off[l - h.tail_start] = -1;
+    }
+  }
 }
 
 struct PT {
@@ -301,53 +332,43 @@ void build(Handle& h, int64_t n, const double* points, int64_t m, const int32_t*
   h.tail_start = nl - 1;
   while (h.tail_start > 0 && h.L[h.tail_start - 1].n <= kTailRows && nl - (h.tail_start - 1) <= kMaxTail)
     --h.tail_start;
-  h.tail.nlev = nl - h.tail_start;
-  h.tail.nu_pre = o.nu_pre;
-  h.tail.nu_post = o.nu_post;
-  h.tail.cinv = h.cinv;
-  h.tail.lanes = 4;
-  h.tail.lds_doubles = 0;
-  for (int l = h.tail_start; l < nl; ++l) {
-    const LevelView& v = h.L[l].view;
-    h.tail.lv[l - h.tail_start] = v;
-    if (l + 1 < nl) h.tail.lanes = std::max({h.tail.lanes, v.ra, v.rt});
-    if (h.tail.lds_doubles + v.n <= kTailLdsDoubles) {
-      h.tail.lds_off[l - h.tail_start] = h.tail.lds_doubles;
-      h.tail.lds_doubles += (int32_t)v.n;
-    } else {
-      h.tail.lds_off[l - h.tail_start] = -1;
-    }
-  }
+  h.plain.v.clear();
+  for (int l = 0; l < nl; ++l) h.plain.v.push_back(h.L[l].view);
+  h.plain.symmetric = false;
+  make_tail(h, h.plain);
   sync(s, "build");
 }
 
 // MGI(x, b, l) of Alg. 2: pre-relax, restrict the residual, recurse from a
-// zero guess, prolong and correct the pre-relaxed iterate, post-relax.
-void vcycle(Handle& h, size_t l, hipStream_t s) {
-  Level& lv = h.L[l];
+// zero guess, prolong and correct the pre-relaxed iterate, post-relax.  In a
+// symmetric cycle the post-relaxation visits the colours in descending order.
+template <class V>
+void vcycle(Handle& h, const Cycle<V>& c, size_t l, hipStream_t s) {
+  const LevelViewT<V>& v = c.v[l];
   if ((int)l == h.tail_start) {
-    if (h.tail.nlev == 1) coarse_solve(h, lv, s); else tail_vcycle(h, s);
+    if (c.tail.nlev == 1) coarse_solve(h.cinv, v, s); else tail_vcycle(c.tail, s);
     return;
   }
-  Level& nx = h.L[l + 1];
-  for (int k = 0; k < h.opt.nu_pre; ++k) gs_sweep(lv, s, l == 0);
-  residual(lv, s, l == 0);
-  restrict_to(lv, nx, s);
-  fill_f64(nx.x, 0.0, nx.n, s);
-  vcycle(h, l + 1, s);
-  prolong_correct(lv, nx, s);
-  for (int k = 0; k < h.opt.nu_post; ++k) gs_sweep(lv, s, l == 0);
+  const LevelViewT<V>& cv = c.v[l + 1];
+  const Level& lv = h.L[l];
+  const bool timed = l == 0 && !c.symmetric;
+  for (int k = 0; k < h.opt.nu_pre; ++k) gs_sweep(v, lv, s, l == 0, false, timed);
+  residual(v, s, l == 0);
+  restrict_to(v, cv, s);
+  fill_zero(cv.x, cv.n, s);
+  vcycle(h, c, l + 1, s);
+  prolong_correct(v, cv, s);
+  for (int k = 0; k < h.opt.nu_post; ++k) gs_sweep(v, lv, s, l == 0, c.symmetric, timed);
 }
 
 // The part of the level-0 V-cycle between pre- and post-smoothing.
 void cycle_inner(Handle& h, hipStream_t s) {
-  Level& l0 = h.L[0];
-  Level& l1 = h.L[1];
-  residual(l0, s, true);
-  restrict_to(l0, l1, s);
-  fill_f64(l1.x, 0.0, l1.n, s);
-  vcycle(h, 1, s);
-  prolong_correct(l0, l1, s);
+  const Cycle<double>& c = h.plain;
+  residual(c.v[0], s, true);
+  restrict_to(c.v[0], c.v[1], s);
+  fill_zero(c.v[1].x, c.v[1].n, s);
+  vcycle(h, c, 1, s);
+  prolong_correct(c.v[0], c.v[1], s);
 }
 
 // One iteration of the solve: a V-cycle and the convergence residual norm.
@@ -362,15 +383,15 @@ void run_iteration(Handle& h, hipStream_t s) {
     return;
   }
   if (graph && h.graph_mode == 1) {
-    for (int k = 0; k < h.opt.nu_pre; ++k) gs_sweep(l0, s, true);
+    for (int k = 0; k < h.opt.nu_pre; ++k) gs_sweep(h.plain.v[0], l0, s, true, false, true);
     check_hip(hipGraphLaunch(h.graph_exec, s), "graph launch");
-    for (int k = 0; k < h.opt.nu_post; ++k) gs_sweep(l0, s, true);
+    for (int k = 0; k < h.opt.nu_post; ++k) gs_sweep(h.plain.v[0], l0, s, true, false, true);
   } else if (graph && h.graph_mode == 2) {
     check_hip(hipGraphLaunch(h.graph_exec, s), "graph launch");
   } else {
-    vcycle(h, 0, s);
+    vcycle(h, h.plain, 0, s);
   }
-  residual_norm(l0, h.red, s);
+  residual_norm(l0, l0.b, l0.x, l0.r, h.red, s);
   finish_norm(h.red, h.red + kNormBlocks, s);
 }
 
@@ -400,9 +421,9 @@ void capture_cycle(Handle& h) {
     if (h.graph_mode == 1) {
       cycle_inner(h, h.cap_stream);
     } else {
-      vcycle(h, 0, h.cap_stream);
+      vcycle(h, h.plain, 0, h.cap_stream);
       if (h.graph_mode == 0) {
-        residual_norm(l0, h.red, h.cap_stream);
+        residual_norm(l0, l0.b, l0.x, l0.r, h.red, h.cap_stream);
         finish_norm(h.red, h.red + kNormBlocks, h.cap_stream);
       }
     }
@@ -417,6 +438,194 @@ void capture_cycle(Handle& h) {
     h.graph_exec = nullptr;
     h.graph_failed = true;
   }
+}
+
+// ------------------------------------------------------------------ preconditioned CG
+void kry_alloc(Handle& h) {
+  Krylov& k = h.kry;
+  if (k.r) return;
+  const int64_t n = h.L[0].n;
+  k.r = (double*)dalloc(h, (size_t)n * 8);
+  k.r_old = (double*)dalloc(h, (size_t)n * 8);
+  k.p = (double*)dalloc(h, (size_t)n * 8);
+  k.q = (double*)dalloc(h, (size_t)n * 8);
+  k.z = (double*)dalloc(h, (size_t)n * 8);
+  k.part = (double*)dalloc(h, (size_t)3 * kNormBlocks * 8);
+  k.scal = (double*)dalloc(h, (size_t)KS_COUNT * 8);
+}
+
+float* to_f32_copy(Handle& h, const double* src, int64_t n, hipStream_t s) {
+  float* d = (float*)dalloc(h, (size_t)std::max<int64_t>(n, 1) * 4);
+  if (n > 0) to_f32(src, d, n, s);
+  return d;
+}
+
+// The symmetric cycle in double shares the solve's level data; only level 0
+// reads the CG residual and writes the preconditioned vector z.
+void kry_prepare(Handle& h, Cycle<double>& c) {
+  c.v = h.plain.v;
+  c.symmetric = true;
+  c.v[0].b = h.kry.r;
+  c.v[0].x = h.kry.z;
+  make_tail(h, c);
+}
+
+// The float cycle: float copies of every level's A_l, P_l^T, P_l and diagonal
+// values (same SELL / ELL-3 layout and index arrays), float iterates.
+void kry_prepare(Handle& h, Cycle<float>& c) {
+  hipStream_t s = h.stream;
+  const int nl = (int)h.L.size();
+  c.v.assign(nl, LevelViewT<float>());
+  c.symmetric = true;
+  for (int l = 0; l < nl; ++l) {
+    const LevelView& d = h.plain.v[l];
+    const Level& lv = h.L[l];
+    LevelViewT<float>& f = c.v[l];
+    f.n = d.n;
+    f.ncolors = d.ncolors;
+    f.cptr = d.cptr;
+    f.ra = d.ra;
+    f.rt = d.rt;
+    f.maxa = d.maxa;
+    f.maxt = d.maxt;
+    f.q_col = d.q_col;
+    f.q_cnt = d.q_cnt;
+    f.x = (float*)dalloc(h, (size_t)d.n * 4);
+    f.b = (float*)dalloc(h, (size_t)d.n * 4);
+    f.r = (float*)dalloc(h, (size_t)d.n * 4);
+    if (l + 1 < nl) {                        // the coarsest level only uses b and x
+      f.A = {d.A.ptr, d.A.col, to_f32_copy(h, d.A.val, lv.a_slots, s), d.A.len};
+      f.T = {d.T.ptr, d.T.col, to_f32_copy(h, d.T.val, lv.t_slots, s), d.T.len};
+      f.diag = to_f32_copy(h, d.diag, d.n, s);
+      f.q_val = to_f32_copy(h, d.q_val, (int64_t)3 * d.n, s);
+    }
+  }
+  make_tail(h, c);
+}
+
+template <class V>
+Cycle<V>& kry_cycle(Handle& h);
+template <>
+Cycle<double>& kry_cycle<double>(Handle& h) { return h.kry.c64; }
+template <>
+Cycle<float>& kry_cycle<float>(Handle& h) { return h.kry.c32; }
+
+template <class V>
+Cycle<V>& kry_ready(Handle& h) {
+  const int prec = std::is_same<V, float>::value ? 1 : 0;
+  kry_alloc(h);
+  Cycle<V>& c = kry_cycle<V>(h);
+  if (!h.kry.ready[prec]) {
+    kry_prepare(h, c);
+    h.kry.ready[prec] = true;
+  }
+  return c;
+}
+
+// z = B r: the level-0 right-hand side is the CG residual (rounded to float
+// for the float cycle), the cycle starts from zero.
+template <class V>
+void kry_precondition(Handle& h, const Cycle<V>& c, hipStream_t s) {
+  const int64_t n = h.L[0].n;
+  if (std::is_same<V, float>::value) to_f32(h.kry.r, (float*)c.v[0].b, n, s);
+  fill_zero(c.v[0].x, n, s);
+  vcycle(h, c, 0, s);
+}
+
+template <class V>
+void kry_iteration(Handle& h, const Cycle<V>& c, hipStream_t s) {
+  kry_precondition(h, c, s);
+  kry_direction<V>(h.kry, c.v[0].x, h.L[0].n, s);
+  kry_step(h.kry, h.L[0], h.L[0].x, h.flags, s);
+}
+
+template <class V>
+void kry_capture(Handle& h, const Cycle<V>& c) {
+  const int prec = std::is_same<V, float>::value ? 1 : 0;
+  Krylov& k = h.kry;
+  if (k.exec[prec] || k.graph_failed[prec]) return;
+  if (std::getenv("GMG_DISABLE_GRAPHS")) {
+    k.graph_failed[prec] = true;
+    return;
+  }
+  if (!h.cap_stream && hipStreamCreateWithFlags(&h.cap_stream, hipStreamNonBlocking) != hipSuccess) {
+    k.graph_failed[prec] = true;
+    (void)hipGetLastError();
+    return;
+  }
+  const int saved = KernelTimer::active;
+  KernelTimer::active = -1;
+  bool ok = hipStreamBeginCapture(h.cap_stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+  if (ok) {
+    kry_iteration(h, c, h.cap_stream);
+    ok = hipStreamEndCapture(h.cap_stream, &k.graph[prec]) == hipSuccess && k.graph[prec];
+  }
+  KernelTimer::active = saved;
+  if (ok) ok = hipGraphInstantiate(&k.exec[prec], k.graph[prec], nullptr, nullptr, 0) == hipSuccess;
+  if (!ok) {
+    (void)hipGetLastError();
+    if (k.graph[prec]) (void)hipGraphDestroy(k.graph[prec]);
+    k.graph[prec] = nullptr;
+    k.exec[prec] = nullptr;
+    k.graph_failed[prec] = true;
+  }
+}
+
+// True residual r = b - A x of the CG iterate into the CG residual vector;
+// returns |r|.
+double kry_true_residual(Handle& h, hipStream_t s) {
+  Level& l0 = h.L[0];
+  residual_norm(l0, l0.b, l0.x, h.kry.r, h.red, s);
+  finish_norm(h.red, h.red + kNormBlocks, s);
+  int64_t v = 0;
+  ScalarRead rd{h.red + kNormBlocks, 8, &v};
+  read_scalars(h, &rd, 1);
+  double d;
+  std::memcpy(&d, &v, 8);
+  return d;
+}
+
+template <class V>
+int pcg(Handle& h, double nb, double tol, int32_t max_iters, hipStream_t s, int32_t* iters, double* rel_out,
+        double* hist) {
+  Cycle<V>& c = kry_ready<V>(h);
+  const int prec = std::is_same<V, float>::value ? 1 : 0;
+  Krylov& k = h.kry;
+  double rel = kry_true_residual(h, s) / nb;
+  *iters = 0;
+  *rel_out = rel;
+  if (rel <= tol) return GMG_OK;
+  kry_init(k, h.L[0].n, s);
+  kry_capture(h, c);
+  int status = GMG_NOT_CONVERGED;
+  int32_t it = 0;
+  while (it < max_iters) {
+    if (k.exec[prec])
+      check_hip(hipGraphLaunch(k.exec[prec], s), "graph launch");
+    else
+      kry_iteration(h, c, s);
+    int64_t vals[2] = {0, 0};
+    ScalarRead rd[2] = {{k.scal + KS_NORM, 8, &vals[0]}, {h.flags, 4, &vals[1]}};
+    read_scalars(h, rd, 2);
+    ++it;
+    if (vals[1] & F_NOT_SPD) throw Error{GMG_NOT_SPD, "CG: non-positive curvature (A or the cycle not SPD)"};
+    double norm;
+    std::memcpy(&norm, &vals[0], 8);
+    rel = norm / nb;
+    if (hist) hist[it - 1] = rel;
+    if (rel <= tol) {
+      const double t = kry_true_residual(h, s) / nb;
+      rel = t;
+      if (t <= tol) {
+        status = GMG_OK;
+        break;
+      }
+    }
+  }
+  if (status != GMG_OK) rel = kry_true_residual(h, s) / nb;
+  *iters = it;
+  *rel_out = rel;
+  return status;
 }
 
 const char* status_text(int st) {
@@ -557,6 +766,106 @@ int gmg_solve(gmg_handle hh, const double* b_dev, double* x_dev, double tol, int
       info->converged = status == GMG_OK;
       info->rel_residual = rel;
     }
+  } catch (const Error& e) {
+    set_error(e.msg);
+    status = e.status;
+  }
+  h->stream = saved;
+  return status;
+}
+
+int gmg_solve_pcg(gmg_handle hh, const double* b_dev, double* x_dev, double tol, int32_t max_iters,
+                  int32_t precision, void* stream, gmg_solve_info* info, double* residual_history) {
+  set_error("");
+  Handle* h = hh;
+  if (!h || !b_dev || !x_dev || max_iters < 1 || !(tol >= 0.0) ||
+      (precision != GMG_PRECISION_F64 && precision != GMG_PRECISION_F32)) {
+    set_error("invalid solve arguments");
+    return GMG_INVALID_ARGUMENT;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  hipStream_t saved = h->stream;
+  h->stream = s;
+  int status = GMG_OK;
+  try {
+    Level& l0 = h->L[0];
+    const int64_t n = l0.n;
+    double* red = h->red;
+    check_hip(hipMemsetAsync(h->flags, 0, 4, s), "memset");
+    check_finite(b_dev, n, h->flags, s);
+    check_finite(x_dev, n, h->flags, s);
+    norm2_partials(b_dev, n, red, s);
+    finish_norm(red, red + kNormBlocks, s);
+    int64_t vals[2] = {0, 0};
+    ScalarRead rd[2] = {{red + kNormBlocks, 8, &vals[0]}, {h->flags, 4, &vals[1]}};
+    read_scalars(*h, rd, 2);
+    if (vals[1] & F_INVALID) throw Error{GMG_INVALID_ARGUMENT, "non-finite b or x"};
+    double nb;
+    std::memcpy(&nb, &vals[0], 8);
+    if (info) {
+      info->iterations = 0;
+      info->converged = 0;
+      info->rel_residual = 0.0;
+    }
+    if (nb == 0.0) {
+      fill_zero(x_dev, n, s);
+      sync(s, "solve");
+      if (info) info->converged = 1;
+      h->stream = saved;
+      return GMG_OK;
+    }
+    permute_in(l0.perm, b_dev, l0.b, n, s);
+    permute_in(l0.perm, x_dev, l0.x, n, s);
+    int32_t it = 0;
+    double rel = 0.0;
+    if (precision == GMG_PRECISION_F32)
+      status = pcg<float>(*h, nb, tol, max_iters, s, &it, &rel, residual_history);
+    else
+      status = pcg<double>(*h, nb, tol, max_iters, s, &it, &rel, residual_history);
+    permute_out(l0.perm, (const double*)l0.x, x_dev, n, s);
+    sync(s, "solve");
+    if (info) {
+      info->iterations = it;
+      info->converged = status == GMG_OK;
+      info->rel_residual = rel;
+    }
+  } catch (const Error& e) {
+    set_error(e.msg);
+    status = e.status;
+  }
+  h->stream = saved;
+  return status;
+}
+
+int gmg_precondition(gmg_handle hh, const double* r_dev, double* z_dev, int32_t precision, void* stream) {
+  set_error("");
+  Handle* h = hh;
+  if (!h || !r_dev || !z_dev || (precision != GMG_PRECISION_F64 && precision != GMG_PRECISION_F32)) {
+    set_error("invalid preconditioner arguments");
+    return GMG_INVALID_ARGUMENT;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  hipStream_t saved = h->stream;
+  h->stream = s;
+  int status = GMG_OK;
+  try {
+    Level& l0 = h->L[0];
+    const int64_t n = l0.n;
+    check_hip(hipMemsetAsync(h->flags, 0, 4, s), "memset");
+    check_finite(r_dev, n, h->flags, s);
+    if ((int32_t)read_i64(*h, h->flags, 4) & F_INVALID) throw Error{GMG_INVALID_ARGUMENT, "non-finite r"};
+    kry_alloc(*h);
+    permute_in(l0.perm, r_dev, h->kry.r, n, s);
+    if (precision == GMG_PRECISION_F32) {
+      Cycle<float>& c = kry_ready<float>(*h);
+      kry_precondition(*h, c, s);
+      permute_out(l0.perm, (const float*)c.v[0].x, z_dev, n, s);
+    } else {
+      Cycle<double>& c = kry_ready<double>(*h);
+      kry_precondition(*h, c, s);
+      permute_out(l0.perm, (const double*)c.v[0].x, z_dev, n, s);
+    }
+    sync(s, "preconditioner");
   } catch (const Error& e) {
     set_error(e.msg);
     status = e.status;

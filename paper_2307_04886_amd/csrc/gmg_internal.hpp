@@ -75,41 +75,57 @@ constexpr int kMaxTail = 8;
 constexpr int kLaneEntries = 8;      // entries per lane per pass of a lane-parallel row
 
 // A matrix in SELL-64: entry t of row r at ptr[r/64] + 64 t + r%64.
-struct SellView {
+template <class V>
+struct Sell {
   const int32_t* ptr = nullptr;
   const int32_t* col = nullptr;
-  const double* val = nullptr;
+  const V* val = nullptr;
   const int32_t* len = nullptr;
 };
+using SellView = Sell<double>;
 
-// What the V-cycle kernels need of one level (device pointers, new numbering).
-struct LevelView {
+// What the V-cycle kernels need of one level (device pointers, new numbering),
+// with values and vectors in V (double; float for the mixed-precision cycle).
+template <class V>
+struct LevelViewT {
   int32_t n = 0;
   int32_t ncolors = 0;
   const int32_t* cptr = nullptr;        // device colour ranges [ncolors + 1]
-  SellView A;                           // A_l
-  SellView T;                           // P_l^T (rows: coarse points)
+  Sell<V> A;                            // A_l
+  Sell<V> T;                            // P_l^T (rows: coarse points)
   int32_t ra = 1, rt = 1;               // lanes per row for A_l / P_l^T (power of two)
   int32_t maxa = 0, maxt = 0;           // longest row of A_l / P_l^T
-  const double* diag = nullptr;
+  const V* diag = nullptr;
   const int32_t* q_col = nullptr;       // P_l, SoA ELL-3 [3][n]
-  const double* q_val = nullptr;
+  const V* q_val = nullptr;
   const int32_t* q_cnt = nullptr;
-  double* x = nullptr;
-  double* b = nullptr;
-  double* r = nullptr;
+  V* x = nullptr;
+  V* b = nullptr;
+  V* r = nullptr;
 };
+using LevelView = LevelViewT<double>;
 
-struct TailDesc {
+template <class V>
+struct TailDescT {
   int32_t nlev = 0;                     // tail levels, the last one is the coarsest
   int32_t nu_pre = 0, nu_post = 0;
-  int32_t lanes = 4;                    // lanes per row (max over the tail levels)
-  int32_t lds_doubles = 0;              // LDS holding the tail levels' iterates
+  int32_t descending_post = 0;          // 1: post-smoothing visits the colours in descending order
+  int32_t lds_elems = 0;                // LDS (elements of V) holding the tail levels' iterates
   int32_t lds_off[kMaxTail] = {};       // offset of level l's x in LDS, or -1 (global)
   const double* cinv = nullptr;
-  LevelView lv[kMaxTail];
+  LevelViewT<V> lv[kMaxTail];
 };
-constexpr int32_t kTailLdsDoubles = 12 * 1024;   // 96 KB
+constexpr int32_t kTailLdsBytes = 96 * 1024;
+
+// One variant of the V-cycle: its per-level views and its tail descriptor.
+// symmetric: post-smoothing runs the colours in descending order, so that the
+// cycle from a zero guess is a symmetric operator (a CG preconditioner).
+template <class V>
+struct Cycle {
+  std::vector<LevelViewT<V>> v;
+  TailDescT<V> tail;
+  bool symmetric = false;
+};
 
 // One level.  "Original" arrays use the level's own point numbering (what the
 // method defines and what is exported); the solve arrays use the colour-sorted
@@ -154,8 +170,28 @@ struct Level {
   double* x = nullptr;                  // work vectors
   double* b = nullptr;
   double* r = nullptr;
+  int64_t a_slots = 0, t_slots = 0;     // SELL entry slots of A_l and P_l^T (with padding)
   LevelView view;
 };
+
+// Preconditioned conjugate gradients (double) around a symmetric V-cycle in
+// double or float; the level-0 vectors use the colour-sorted numbering.
+struct Krylov {
+  double* r = nullptr;
+  double* r_old = nullptr;
+  double* p = nullptr;
+  double* q = nullptr;
+  double* z = nullptr;
+  double* part = nullptr;               // 3 x kNormBlocks partial sums
+  double* scal = nullptr;               // device scalars (KS_* below)
+  bool ready[2] = {false, false};       // cycle views built, per precision
+  Cycle<double> c64;
+  Cycle<float> c32;
+  hipGraph_t graph[2] = {nullptr, nullptr};
+  hipGraphExec_t exec[2] = {nullptr, nullptr};
+  bool graph_failed[2] = {false, false};
+};
+enum : int { KS_RHO = 0, KS_BETA = 1, KS_ALPHA = 2, KS_NORM = 3, KS_COUNT = 8 };
 
 struct Handle {
   int device = 0;
@@ -169,7 +205,8 @@ struct Handle {
   int32_t* rounds = nullptr;            // device per-round counters of frontier loops
   double* red = nullptr;                // reduction partials
   int tail_start = -1;                  // first level solved by the single-workgroup tail kernel
-  TailDesc tail;
+  Cycle<double> plain;                  // the V-cycle of the solve (Alg. 2)
+  Krylov kry;
   // one V-cycle plus the convergence residual, captured once and replayed
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
@@ -253,18 +290,37 @@ void solve_layout(Handle& h, Level& lv, const Level* nx, const int32_t* t_rp, co
 void coarse_factor(Handle& h, Level& lv);
 
 // ------------------------------------------------------------------ launchers (solve.hip)
-void gs_sweep(const Level& lv, hipStream_t s, bool finest);
-void residual(const Level& lv, hipStream_t s, bool finest);
-void restrict_to(const Level& lv, Level& nx, hipStream_t s);
-void prolong_correct(Level& lv, const Level& nx, hipStream_t s);
-void coarse_solve(Handle& h, Level& lv, hipStream_t s);
-void tail_vcycle(Handle& h, hipStream_t s);
+// V-cycle phases on one level, for V = double and V = float.  gs_sweep visits
+// the colours of lv (host ranges) in ascending or descending order; `timed`
+// lets the level-0 measurement timer see the launches.
+template <class V>
+void gs_sweep(const LevelViewT<V>& v, const Level& lv, hipStream_t s, bool finest, bool descending, bool timed);
+template <class V>
+void residual(const LevelViewT<V>& v, hipStream_t s, bool finest);
+template <class V>
+void restrict_to(const LevelViewT<V>& v, const LevelViewT<V>& c, hipStream_t s);
+template <class V>
+void prolong_correct(const LevelViewT<V>& v, const LevelViewT<V>& c, hipStream_t s);
+template <class V>
+void coarse_solve(const double* cinv, const LevelViewT<V>& c, hipStream_t s);
+template <class V>
+void tail_vcycle(const TailDescT<V>& d, hipStream_t s);
+template <class V>
+void fill_zero(V* p, int64_t n, hipStream_t s);
+void to_f32(const double* src, float* dst, int64_t n, hipStream_t s);
 void permute_in(const int32_t* perm, const double* src, double* dst, int64_t n, hipStream_t s);
-void permute_out(const int32_t* perm, const double* src, double* dst, int64_t n, hipStream_t s);
+template <class V>
+void permute_out(const int32_t* perm, const V* src, double* dst, int64_t n, hipStream_t s);
 void norm2_partials(const double* v, int64_t n, double* partials, hipStream_t s);
-void residual_norm(const Level& lv, double* partials, hipStream_t s);
+void residual_norm(const Level& lv, const double* b, const double* x, double* res, double* partials,
+                   hipStream_t s);
 void finish_norm(const double* partials, double* out, hipStream_t s);
 void check_finite(const double* v, int64_t n, int32_t* flag, hipStream_t s);
+// preconditioned CG steps (level 0, double; z in V)
+void kry_init(Krylov& k, int64_t n, hipStream_t s);
+template <class V>
+void kry_direction(Krylov& k, const V* z, int64_t n, hipStream_t s);
+void kry_step(Krylov& k, const Level& l0, double* x, int32_t* flags, hipStream_t s);
 constexpr int kNormBlocks = 1024;
 
 }  // namespace gmg

@@ -1,0 +1,120 @@
+// Row sums over a SELL-64 matrix, shared by the V-cycle and Krylov kernels.
+//
+// Matrices (A_l and P_l^T) are in the colour-sorted SELL-64 layout: slice s
+// holds rows 64s..64s+63, entry t of row r at ptr[s] + 64 t + (r mod 64).
+// Every row sum adds its terms sequentially in the CSR order of the original
+// row, so each row is the same floating-point computation as in the method's
+// definition, in the value type V of the matrix and vectors.  Two forms:
+//  - one lane per row (level 0: about 7 entries, streaming, coalesced across
+//    the 64 consecutive rows of a slice), loads issued CH at a time;
+//  - R lanes per row (Galerkin levels: 15-40 entries, latency-bound): the R
+//    lanes load and multiply the row's entries in parallel and the first lane
+//    of the group adds the products in entry order (wavefront shuffles).
+#pragma once
+
+#include "gmg_internal.hpp"
+
+namespace gmg {
+
+// One lane per row: sum_t val[t] * x[col[t]] in entry order, skipping column
+// `skip`; the row's loads are issued CH at a time before any is consumed.
+template <int CH, class V>
+__device__ __forceinline__ V row_sum_seq(const Sell<V>& A, int32_t r, const V* x, int32_t skip) {
+  const int32_t base = A.ptr[r / kSlice] + (r & (kSlice - 1));
+  const int32_t len = A.len[r];
+  V acc = V(0);
+  for (int32_t t0 = 0; t0 < len; t0 += CH) {
+    int32_t j[CH];
+    V v[CH], xv[CH];
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      const bool ok = t0 + u < len;
+      j[u] = ok ? A.col[base + (t0 + u) * kSlice] : skip;
+      v[u] = ok ? A.val[base + (t0 + u) * kSlice] : V(0);
+    }
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      xv[u] = V(0);
+      if (t0 + u < len && j[u] != skip) xv[u] = x[j[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < CH; ++u)
+      if (t0 + u < len && j[u] != skip) acc = acc + v[u] * xv[u];
+  }
+  return acc;
+}
+
+// R lanes per row (R divides 64; the lanes of a group are consecutive).  All
+// lanes of the wavefront must call this (shuffles); `active` marks lanes whose
+// group has a row.  maxlen bounds every row length (uniform).  The result is
+// valid on the group's first lane.
+template <int R, class V>
+__device__ __forceinline__ V row_sumR(const Sell<V>& A, int32_t r, bool active, const V* x, int32_t skip,
+                                      int32_t maxlen) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int sub = lane & (R - 1);
+  const int lane0 = lane - sub;
+  int32_t base = 0, len = 0;
+  if (active) {
+    base = A.ptr[r / kSlice] + (r & (kSlice - 1));
+    len = A.len[r];
+  }
+  V acc = V(0);
+  for (int32_t t0 = 0; t0 < maxlen; t0 += R * kLaneEntries) {
+    int32_t j[kLaneEntries];
+    V v[kLaneEntries], p[kLaneEntries];
+    uint32_t mask = 0;
+#pragma unroll
+    for (int k = 0; k < kLaneEntries; ++k) {
+      const int32_t t = t0 + sub + R * k;
+      const bool ok = t < len;
+      j[k] = ok ? A.col[base + t * kSlice] : skip;
+      v[k] = ok ? A.val[base + t * kSlice] : V(0);
+    }
+#pragma unroll
+    for (int k = 0; k < kLaneEntries; ++k) {
+      const bool ok = (t0 + sub + R * k < len) && j[k] != skip;
+      p[k] = V(0);
+      if (ok) p[k] = v[k] * x[j[k]];
+      mask |= ok ? (1u << k) : 0u;
+    }
+    uint32_t m[R];
+#pragma unroll
+    for (int s = 0; s < R; ++s) m[s] = __shfl(mask, lane0 + s, kWave);
+#pragma unroll
+    for (int k = 0; k < kLaneEntries; ++k)
+#pragma unroll
+      for (int s = 0; s < R; ++s) {
+        const V q = __shfl(p[k], lane0 + s, kWave);
+        if ((m[s] >> k) & 1u) acc = acc + q;
+      }
+  }
+  return acc;
+}
+
+// Block-level sum in a fixed tree order (every thread of the block calls it).
+__device__ inline double block_sum(double v) {
+  __shared__ double ws[kBlock / kWave];
+  v = wave_sum(v);
+  if ((threadIdx.x & (kWave - 1)) == 0) ws[threadIdx.x / kWave] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < kBlock / kWave; ++w) t += ws[w];
+  __syncthreads();
+  return t;
+}
+
+// Calls f(std::integral_constant<int, R>) for the lane count R of a row kernel.
+template <class F>
+void with_lanes(int R, F&& f) {
+  switch (R) {
+    case 4: f(std::integral_constant<int, 4>{}); break;
+    case 8: f(std::integral_constant<int, 8>{}); break;
+    case 16: f(std::integral_constant<int, 16>{}); break;
+    case 32: f(std::integral_constant<int, 32>{}); break;
+    default: f(std::integral_constant<int, 64>{}); break;
+  }
+}
+
+}  // namespace gmg

@@ -366,9 +366,9 @@ void colouring(Handle& h, Level& lv, int level) {
 namespace {
 
 // CSR (source rows perm[r], columns through cmap) -> SELL-64 owned by the
-// handle; *maxlen receives the longest row.
+// handle; *maxlen receives the longest row, *slots the allocated entry slots.
 SellView make_sell(Handle& h, const int32_t* perm, const int32_t* cmap, const int32_t* rp, const int32_t* col,
-                   const double* val, int64_t n, double* diag, int32_t* maxlen) {
+                   const double* val, int64_t n, double* diag, int32_t* maxlen, int64_t* slots) {
   hipStream_t s = h.stream;
   const int64_t ns = (n + kSlice - 1) / kSlice;
   int32_t* len = (int32_t*)dalloc(h, (size_t)(n + 1) * 4);
@@ -384,6 +384,7 @@ SellView make_sell(Handle& h, const int32_t* perm, const int32_t* cmap, const in
   ScalarRead rd[2] = {{ptr + ns, 4, &tot}, {mx, 4, &ml}};
   read_scalars(h, rd, 2);
   *maxlen = (int32_t)ml;
+  *slots = tot + 1;
   int32_t* scol = (int32_t*)dalloc(h, (size_t)(tot + 1) * 4);
   double* sval = (double*)dalloc(h, (size_t)(tot + 1) * 8);
   k_sell_fill<<<blocks_for(n), kBlock, 0, s>>>(perm, cmap, rp, col, val, n, ptr, scol, sval, diag);
@@ -439,7 +440,7 @@ void solve_layout(Handle& h, Level& lv, const Level* nx, const int32_t* t_rp, co
   v.n = (int32_t)n;
   v.ncolors = C;
   v.cptr = cptr;
-  v.A = make_sell(h, lv.perm, lv.iperm, lv.arp, lv.acol, lv.aval, n, lv.diag, &v.maxa);
+  v.A = make_sell(h, lv.perm, lv.iperm, lv.arp, lv.acol, lv.aval, n, lv.diag, &v.maxa, &lv.a_slots);
   v.ra = lanes_for(v.maxa);
   v.diag = lv.diag;
   lv.x = (double*)dalloc(h, (size_t)n * 8);
@@ -469,7 +470,7 @@ void solve_layout(Handle& h, Level& lv, const Level* nx, const int32_t* t_rp, co
     v.q_val = qval;
     v.q_cnt = qcnt;
     // P^T: row I' = coarse row perm_c[I'], entries in ascending original fine index
-    v.T = make_sell(h, nx->perm, lv.iperm, t_rp, t_col, t_val, nx->n, nullptr, &v.maxt);
+    v.T = make_sell(h, nx->perm, lv.iperm, t_rp, t_col, t_val, nx->n, nullptr, &v.maxt, &lv.t_slots);
     v.rt = lanes_for(v.maxt);
   }
   // colour ranges and per-colour entry counts (staging is reused by make_sell's reads, so copy last)
