@@ -3,6 +3,9 @@
 A step is one whole pass of the method on one system: build the hierarchy
 (sampling, Voronoi cells, prolongation, Galerkin operators, colouring,
 coarsest factorisation) and solve to 1e-8 relative residual with V-cycles.
+The same steps are then timed with the solve done by conjugate gradients
+preconditioned with the symmetric V-cycle in double and in float (the mixed
+form), reported under "mixed_vs_fp64".
 The workload is the 1024 x 1024 jittered torus (1,048,576 points) with the
 cotan smoothing system (M + 1e-3 L) x = M b.  Inputs are resident in HBM
 before the timed region starts.
@@ -79,12 +82,15 @@ def main():
     opt = default_options()
     stream = torch.cuda.current_stream()
 
-    def step():
+    def step(form="plain"):
         h = build_hierarchy(pts, edges, rp, ci, va, opt, stream)
         x.zero_()
-        _, info, st = h.solve(b, x, tol=args.tol, max_iters=100, stream=stream)
+        if form == "plain":
+            _, info, st = h.solve(b, x, tol=args.tol, max_iters=100, stream=stream)
+        else:
+            _, info, st = h.solve_pcg(b, x, tol=args.tol, max_iters=100, precision=form[-3:], stream=stream)
         if st != 0:
-            raise RuntimeError(f"solve did not converge (status {st})")
+            raise RuntimeError(f"{form} solve did not converge (status {st})")
         levels = h.num_levels
         h.free()
         return info, levels
@@ -101,6 +107,46 @@ def main():
     k_ms, k_launches, k_bytes = timer_stop() if args.timer != "none" else (float("nan"), 0, 0.0)
     info, levels = infos[-1]
     ms = 1e3 * dt / args.steps
+    x_plain = x.cpu().numpy()
+
+    # the same workload solved by CG preconditioned with the symmetric V-cycle, in double and in
+    # float (mixed precision): whole setup + solve per step, same tolerance
+    forms = {}
+    x_forms = {}
+    for form in ("pcg_f64", "pcg_f32"):
+        for _ in range(max(1, args.warmup)):
+            step(form)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        finfos = [step(form) for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        fdt = time.perf_counter() - t1
+        fi = finfos[-1][0]
+        x_forms[form] = x.cpu().numpy()
+        forms[form] = {"value": args.steps / fdt, "ms_per_step": 1e3 * fdt / args.steps,
+                       "iterations": fi.iterations, "rel_residual": fi.rel_residual,
+                       "vs_plain_fp64": (args.steps / fdt) / (args.steps / dt)}
+
+    # setup / solve split (separate, synchronised runs outside the timed regions)
+    def split(form, reps=3):
+        su, so = [], []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            h = build_hierarchy(pts, edges, rp, ci, va, opt, stream)
+            torch.cuda.synchronize()
+            tb = time.perf_counter()
+            x.zero_()
+            if form == "plain":
+                h.solve(b, x, tol=args.tol, max_iters=100, stream=stream)
+            else:
+                h.solve_pcg(b, x, tol=args.tol, max_iters=100, precision=form[-3:], stream=stream)
+            torch.cuda.synchronize()
+            tc = time.perf_counter()
+            h.free()
+            su.append(tb - ta)
+            so.append(tc - tb)
+        return {"setup_ms": 1e3 * float(np.median(su)), "solve_ms": 1e3 * float(np.median(so))}
 
     out = {
         "metric": "setup+solve solves/s to 1e-8 rel. residual",
@@ -125,6 +171,10 @@ def main():
                      "launches": k_launches, "avg_launch_us": 1e3 * k_ms / max(k_launches, 1),
                      "bytes_per_launch": k_bytes / max(k_launches, 1)},
         "cpu_baseline": None,
+        "mixed_vs_fp64": dict(forms, note="double CG preconditioned by one symmetric V-cycle per iteration "
+                                          "(f64: cycle in double, f32: cycle in float); whole setup + solve "
+                                          "per step, same workload and tolerance"),
+        "split_ms": {"plain": split("plain"), "pcg_f32": split("pcg_f32")},
     }
 
     if args.calibrate_copy:
@@ -141,7 +191,9 @@ def main():
         orc = oracle.Hierarchy.from_problem(prob)
         xo, it, hist, st = orc.solve(prob.rhs, tol=args.tol)
         cdt = time.perf_counter() - t0
-        err = float(np.linalg.norm(x.cpu().numpy() - xo) / np.linalg.norm(xo))
+        err = float(np.linalg.norm(x_plain - xo) / np.linalg.norm(xo))
+        for form, xf in x_forms.items():
+            forms[form]["rel_error_vs_oracle_fp64"] = float(np.linalg.norm(xf - xo) / np.linalg.norm(xo))
         out["cpu_baseline"] = {"value": 1.0 / cdt, "unit": "solves/s", "cores": 1, "kind": "oracle",
                                "sample": f"one full setup+solve of the same torus workload "
                                          f"({it} V-cycles, {cdt:.1f} s, single-threaded C++)",

@@ -7,7 +7,9 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <mutex>
+#include <unordered_map>
 #include <type_traits>
 
 #include "gmg_internal.hpp"
@@ -16,20 +18,103 @@ namespace gmg {
 
 namespace {
 thread_local std::string g_last_error;
-std::mutex g_pool_mutex;
-bool g_pool_ready[64] = {};
 
-// Keep freed stream-ordered allocations cached in the device's default pool,
-// so that repeated builds do not return memory to the driver.
-void ensure_pool(int dev) {
-  std::lock_guard<std::mutex> lock(g_pool_mutex);
-  if (dev < 0 || dev >= 64 || g_pool_ready[dev]) return;
-  hipMemPool_t pool;
-  if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
-    uint64_t thr = UINT64_MAX;
-    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+// Device memory cache.  hipFreeAsync costs 0.1-0.3 ms per call on this
+// platform and a hierarchy owns a few hundred arrays, so the library keeps
+// its own per-device cache of blocks in size classes (quarter steps between
+// powers of two).  A block freed in stream order is tagged with its stream
+// and reused only on that stream until the stream has been synchronised; a
+// block of a released handle (its stream synchronised) is reusable anywhere.
+// Idle blocks beyond kCacheIdleMax are returned to the driver, and so is the
+// whole cache when an allocation fails.
+constexpr size_t kCacheIdleMax = size_t(16) << 30;
+
+struct Cache {
+  std::mutex m;
+  std::multimap<size_t, std::pair<void*, hipStream_t>> idle;  // size class -> (block, stream tag)
+  std::unordered_map<void*, size_t> live;                     // block -> size class
+  size_t idle_bytes = 0;
+};
+Cache g_cache[64];
+
+size_t size_class(size_t b) {
+  b = std::max<size_t>(b, 256);
+  size_t base = size_t(1) << (63 - __builtin_clzll((unsigned long long)b));
+  if (b == base) return base;
+  const size_t step = base / 4;
+  return (b + step - 1) / step * step;
+}
+
+Cache& cache_for_current() {
+  int dev = 0;
+  check_hip(hipGetDevice(&dev), "hipGetDevice");
+  if (dev < 0 || dev >= 64) throw Error{GMG_DEVICE_ERROR, "device index out of range"};
+  return g_cache[dev];
+}
+
+// Returns idle blocks to the driver until at most `keep` bytes stay idle
+// (the caller holds the lock; blocks tagged with a stream are synchronised first).
+void trim_locked(Cache& c, size_t keep) {
+  if (c.idle_bytes <= keep) return;
+  bool synced = false;
+  for (auto it = c.idle.end(); it != c.idle.begin() && c.idle_bytes > keep;) {
+    --it;
+    if (it->second.second && !synced) {
+      (void)hipDeviceSynchronize();
+      synced = true;
+    }
+    (void)hipFree(it->second.first);
+    c.idle_bytes -= it->first;
+    it = c.idle.erase(it);
   }
-  g_pool_ready[dev] = true;
+}
+
+void* cache_get(size_t bytes, hipStream_t s) {
+  Cache& c = cache_for_current();
+  const size_t cls = size_class(bytes);
+  std::lock_guard<std::mutex> lock(c.m);
+  auto range = c.idle.equal_range(cls);
+  for (auto it = range.first; it != range.second; ++it) {
+    if (it->second.second == nullptr || it->second.second == s) {
+      void* p = it->second.first;
+      c.idle.erase(it);
+      c.idle_bytes -= cls;
+      c.live[p] = cls;
+      return p;
+    }
+  }
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, cls);
+  if (e == hipErrorOutOfMemory) {
+    (void)hipGetLastError();
+    trim_locked(c, 0);
+    e = hipMalloc(&p, cls);
+  }
+  check_hip(e, "device allocation");
+  c.live[p] = cls;
+  return p;
+}
+
+// idle: every use of the block on the device has finished
+void cache_put(void* p, hipStream_t s, bool idle) {
+  if (!p) return;
+  Cache& c = cache_for_current();
+  std::lock_guard<std::mutex> lock(c.m);
+  auto it = c.live.find(p);
+  if (it == c.live.end()) return;
+  const size_t cls = it->second;
+  c.live.erase(it);
+  c.idle.emplace(cls, std::make_pair(p, idle ? hipStream_t(nullptr) : s));
+  c.idle_bytes += cls;
+  if (idle) trim_locked(c, kCacheIdleMax);
+}
+
+// After a synchronisation of stream s: its freed blocks become reusable anywhere.
+void cache_settle(hipStream_t s) {
+  Cache& c = cache_for_current();
+  std::lock_guard<std::mutex> lock(c.m);
+  for (auto& kv : c.idle)
+    if (kv.second.second == s) kv.second.second = nullptr;
 }
 
 constexpr size_t kStaging = 1 << 16;
@@ -79,21 +164,14 @@ void check_hip(hipError_t e, const char* what) {
 }
 
 void* dalloc(Handle& h, size_t bytes) {
-  void* p = nullptr;
-  check_hip(hipMallocAsync(&p, std::max<size_t>(bytes, 256), h.stream), "device allocation");
+  void* p = cache_get(bytes, h.stream);
   h.allocs.push_back(p);
   return p;
 }
 
-void* talloc(hipStream_t s, size_t bytes) {
-  void* p = nullptr;
-  check_hip(hipMallocAsync(&p, std::max<size_t>(bytes, 256), s), "device allocation");
-  return p;
-}
+void* talloc(hipStream_t s, size_t bytes) { return cache_get(bytes, s); }
 
-void tfree(hipStream_t s, void* p) {
-  if (p) (void)hipFreeAsync(p, s);
-}
+void tfree(hipStream_t s, void* p) { cache_put(p, s, false); }
 
 void sync(hipStream_t s, const char* what) {
   check_hip(hipGetLastError(), what);
@@ -144,18 +222,38 @@ KernelTimer::Scope::Scope(int kind, double bytes) {
 
 namespace {
 
+// GMG_PROFILE_BUILD=1: host wall time of phases outside the build (diagnostics)
+struct HostMark {
+  bool on = std::getenv("GMG_PROFILE_BUILD") != nullptr;
+  std::chrono::steady_clock::time_point t = std::chrono::steady_clock::now();
+  void operator()(const char* what) {
+    if (!on) return;
+    auto now = std::chrono::steady_clock::now();
+    std::fprintf(stderr, "[gmg] %-28s %8.3f ms\n", what, std::chrono::duration<double, std::milli>(now - t).count());
+    t = now;
+  }
+};
+
 template <typename H>
 void release(H* h) {
   if (!h) return;
+  HostMark mark;
   if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
   if (h->graph) (void)hipGraphDestroy(h->graph);
   for (int p = 0; p < 2; ++p) {
     if (h->kry.exec[p]) (void)hipGraphExecDestroy(h->kry.exec[p]);
     if (h->kry.graph[p]) (void)hipGraphDestroy(h->kry.graph[p]);
   }
+  mark("release: graphs");
   if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
-  for (void* p : h->allocs) (void)hipFreeAsync(p, h->stream);
+  mark("release: capture stream");
   (void)hipStreamSynchronize(h->stream);
+  try {
+    cache_settle(h->stream);
+    for (void* p : h->allocs) cache_put(p, h->stream, true);
+  } catch (const Error&) {
+  }
+  mark("release: memory");
   delete h;
 }
 
@@ -337,6 +435,7 @@ void build(Handle& h, int64_t n, const double* points, int64_t m, const int32_t*
   h.plain.symmetric = false;
   make_tail(h, h.plain);
   sync(s, "build");
+  cache_settle(s);
 }
 
 // MGI(x, b, l) of Alg. 2: pre-relax, restrict the residual, recurse from a
@@ -414,6 +513,7 @@ void capture_cycle(Handle& h) {
   h.graph_mode = 0;
   if (multi && KernelTimer::active == KernelTimer::GS_FINEST) h.graph_mode = 1;
   if (KernelTimer::active == KernelTimer::RESIDUAL_FINEST) h.graph_mode = 2;
+  HostMark mark;
   const int saved = KernelTimer::active;
   KernelTimer::active = -1;                    // no event records inside the capture
   bool ok = hipStreamBeginCapture(h.cap_stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
@@ -430,7 +530,9 @@ void capture_cycle(Handle& h) {
     ok = hipStreamEndCapture(h.cap_stream, &h.graph) == hipSuccess && h.graph;
   }
   KernelTimer::active = saved;
+  mark("capture: record");
   if (ok) ok = hipGraphInstantiate(&h.graph_exec, h.graph, nullptr, nullptr, 0) == hipSuccess;
+  mark("capture: instantiate");
   if (!ok) {
     (void)hipGetLastError();
     if (h.graph) (void)hipGraphDestroy(h.graph);
@@ -690,7 +792,6 @@ int gmg_build_hierarchy(int64_t n, const double* points_dev, int64_t m, const in
   }
   try {
     check_hip(hipGetDevice(&h->device), "hipGetDevice");
-    ensure_pool(h->device);
     build(*h, n, points_dev, m, edges_dev, A_rowptr_dev, A_col_dev, A_val_dev, A_nnz);
   } catch (const Error& e) {
     set_error(e.msg);
