@@ -18,29 +18,34 @@ namespace gmg {
 
 // One lane per row: sum_t val[t] * x[col[t]] in entry order, skipping column
 // `skip`; the row's loads are issued CH at a time before any is consumed.
+// Every row has at least one entry (the diagonal of A_l; the seed of a row of
+// P_l^T), so the first chunk runs unconditionally and the row length and
+// slice offset are loaded together.
 template <int CH, class V>
 __device__ __forceinline__ V row_sum_seq(const Sell<V>& A, int32_t r, const V* x, int32_t skip) {
-  const int32_t base = A.ptr[r / kSlice] + (r & (kSlice - 1));
   const int32_t len = A.len[r];
+  const int32_t base = A.ptr[r / kSlice] + (r & (kSlice - 1));
   V acc = V(0);
-  for (int32_t t0 = 0; t0 < len; t0 += CH) {
+  int32_t t0 = 0;
+  do {
     int32_t j[CH];
     V v[CH], xv[CH];
+    // Branch-free loads: positions past the row's end re-read its last entry
+    // (and its x), so that all loads of the chunk are in flight together;
+    // only entries t < len enter the sum.
 #pragma unroll
     for (int u = 0; u < CH; ++u) {
-      const bool ok = t0 + u < len;
-      j[u] = ok ? A.col[base + (t0 + u) * kSlice] : skip;
-      v[u] = ok ? A.val[base + (t0 + u) * kSlice] : V(0);
+      const int32_t o = base + min(t0 + u, len - 1) * kSlice;
+      j[u] = A.col[o];
+      v[u] = A.val[o];
     }
 #pragma unroll
-    for (int u = 0; u < CH; ++u) {
-      xv[u] = V(0);
-      if (t0 + u < len && j[u] != skip) xv[u] = x[j[u]];
-    }
+    for (int u = 0; u < CH; ++u) xv[u] = x[j[u]];
 #pragma unroll
     for (int u = 0; u < CH; ++u)
       if (t0 + u < len && j[u] != skip) acc = acc + v[u] * xv[u];
-  }
+    t0 += CH;
+  } while (t0 < len);
   return acc;
 }
 
@@ -64,18 +69,22 @@ __device__ __forceinline__ V row_sumR(const Sell<V>& A, int32_t r, bool active, 
     int32_t j[kLaneEntries];
     V v[kLaneEntries], p[kLaneEntries];
     uint32_t mask = 0;
+    // Branch-free loads, as in row_sum_seq: positions past the row's end (or
+    // of an inactive group: row 0's first entry) re-read a valid entry.
 #pragma unroll
     for (int k = 0; k < kLaneEntries; ++k) {
       const int32_t t = t0 + sub + R * k;
-      const bool ok = t < len;
-      j[k] = ok ? A.col[base + t * kSlice] : skip;
-      v[k] = ok ? A.val[base + t * kSlice] : V(0);
+      const int32_t o = base + max(min(t, len - 1), 0) * kSlice;
+      j[k] = A.col[o];
+      v[k] = A.val[o];
     }
+    V xv[kLaneEntries];
+#pragma unroll
+    for (int k = 0; k < kLaneEntries; ++k) xv[k] = x[j[k]];
 #pragma unroll
     for (int k = 0; k < kLaneEntries; ++k) {
       const bool ok = (t0 + sub + R * k < len) && j[k] != skip;
-      p[k] = V(0);
-      if (ok) p[k] = v[k] * x[j[k]];
+      p[k] = ok ? v[k] * xv[k] : V(0);
       mask |= ok ? (1u << k) : 0u;
     }
     uint32_t m[R];

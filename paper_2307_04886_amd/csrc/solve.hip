@@ -38,8 +38,9 @@ __global__ void __launch_bounds__(kBlock) k_gs_color_fine(Sell<V> A, const V* __
                                                           const V* __restrict__ b, V* x, int32_t r0, int32_t r1) {
   const int32_t r = (r0 & ~(kSlice - 1)) + (int32_t)(blockIdx.x * kBlock + threadIdx.x);
   if (r < r0 || r >= r1) return;
+  const V br = b[r], dr = diag[r];        // issued with the row's loads
   const V acc = row_sum_seq<kChunkFine>(A, r, x, r);
-  x[r] = (b[r] - acc) / diag[r];
+  x[r] = (br - acc) / dr;
 }
 
 // The same update on a Galerkin level, R lanes per row.
@@ -50,8 +51,10 @@ __global__ void __launch_bounds__(kBlock) k_gs_color(Sell<V> A, const V* __restr
   const int64_t g = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / R;
   const int32_t r = r0 + (int32_t)g;
   const bool active = r < r1;
+  const int32_t rc = active ? r : r0;     // in range for every lane: the loads need no branch
+  const V br = b[rc], dr = diag[rc];
   const V acc = row_sumR<R>(A, r, active, x, r, maxlen);
-  if (active && (threadIdx.x & (R - 1)) == 0) x[r] = (b[r] - acc) / diag[r];
+  if (active && (threadIdx.x & (R - 1)) == 0) x[r] = (br - acc) / dr;
 }
 
 // r = b - A x on level 0
