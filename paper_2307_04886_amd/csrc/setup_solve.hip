@@ -20,22 +20,35 @@ struct ColorKey {
   __device__ uint64_t operator()(int32_t v) const { return mix64(base ^ (uint64_t)v); }
 };
 
+constexpr int kColorChunk = 16;
+
 // Returns 0 if v must wait for a lower-key neighbour, else colours v and
-// returns its colour + 1.
+// returns its colour + 1.  The row is read kColorChunk entries at a time with
+// every column and neighbour-colour load in flight together (positions past
+// the row's end re-read its last entry; every row holds its diagonal).
 __device__ inline int32_t color_attempt(const int32_t* rp, const int32_t* col, const ColorKey& key,
                                         int32_t* color, int32_t v) {
   const uint64_t kv = key(v);
   uint64_t mask = 0;
-  bool high = false;
-  for (int32_t e = rp[v]; e < rp[v + 1]; ++e) {
-    int32_t u = col[e];
-    if (u == v) continue;
-    uint64_t ku = key(u);
-    if (!(ku < kv || (ku == kv && u < v))) continue;
-    int32_t cu = __atomic_load_n(&color[u], __ATOMIC_RELAXED);
-    if (cu < 0) return 0;
-    if (cu < 64) mask |= 1ull << cu; else high = true;
+  bool high = false, wait = false;
+  const int32_t b = rp[v], e = rp[v + 1];
+  for (int32_t e0 = b; e0 < e; e0 += kColorChunk) {
+    int32_t u[kColorChunk], cu[kColorChunk];
+#pragma unroll
+    for (int k = 0; k < kColorChunk; ++k) u[k] = col[min(e0 + k, e - 1)];
+#pragma unroll
+    for (int k = 0; k < kColorChunk; ++k) cu[k] = __atomic_load_n(&color[u[k]], __ATOMIC_RELAXED);
+#pragma unroll
+    for (int k = 0; k < kColorChunk; ++k) {
+      if (e0 + k >= e || u[k] == v) continue;
+      const uint64_t ku = key(u[k]);
+      if (!(ku < kv || (ku == kv && u[k] < v))) continue;
+      if (cu[k] < 0) wait = true;
+      else if (cu[k] < 64) mask |= 1ull << cu[k];
+      else high = true;
+    }
   }
+  if (wait) return 0;
   int32_t c = (~mask) ? __builtin_ctzll(~mask) : 64;
   if (c == 64 && high) {
     for (;; ++c) {                              // rare: every colour below 64 is taken
@@ -346,7 +359,7 @@ void colouring(Handle& h, Level& lv, int level) {
   check_hip(hipMemsetAsync(h.rounds, 0, kMaxRounds * 4, s), "memset");
   ColorKey key{(h.opt.seed ^ kColorSalt) ^ ((uint64_t)level << 32)};
   int32_t* wl = (int32_t*)talloc(s, (size_t)2 * n * 4);
-  const int grid = std::min(blocks_for(n), kRoundGrid);
+  const int grid = std::min(blocks_for(n), 4 * kRoundGrid);
   int k = 0;
   for (;;) {
     for (int t = 0; t < kRoundBatch; ++t, ++k)
