@@ -108,6 +108,40 @@ int gmg_build_hierarchy(int64_t n, const double* points_dev, int64_t m, const in
 int gmg_solve(gmg_handle h, const double* b_dev, double* x_dev, double tol, int32_t max_iters,
               void* stream, gmg_solve_info* info, double* residual_history);
 
+/*
+ * Replaces the values of A (same sparsity pattern as at the build) and
+ * recomputes what depends on them: the Galerkin operators A_l of every
+ * coarser level (Alg. 1), their solve layouts and the factorisation of the
+ * coarsest one.  The hierarchy itself (samples, Voronoi cells, P_l,
+ * colourings) is geometric and is kept: a geometric hierarchy only has to be
+ * rebuilt when the domain changes (Sec. 2), as in the applications whose
+ * matrix changes from solve to solve (Sec. 5.5).
+ *
+ *  A_val_dev   float64 device array of the handle's nnz(A_1) values, in the CSR order given to
+ *              gmg_build_hierarchy; finite, positive diagonal
+ *  stream      hipStream_t; returns after the stream has finished
+ *
+ * Returns GMG_OK, GMG_INVALID_ARGUMENT, GMG_NOT_SPD (non-positive diagonal or coarse
+ * pivot) or GMG_DEVICE_ERROR.  After an error the handle's operators are undefined until
+ * a successful update; gmg_free stays valid.
+ */
+int gmg_update_matrix(gmg_handle h, const double* A_val_dev, void* stream);
+
+/*
+ * out[e] = scale * u_i * v_j for every stored entry e = (i, j) of an n x n CSR
+ * pattern.  With u = lambda (the adjoint solution of A lambda = dL/dx, A
+ * symmetric), v = x and scale = -1 this is dL/dA on A's pattern for a loss L
+ * of the solution of A x = b (and dL/db = lambda).
+ *
+ *  n                  rows; rowptr_dev int32[n+1], col_dev int32[nnz] (device)
+ *  u_dev, v_dev       float64 device vectors of length n
+ *  out_dev            float64 device array of nnz values (written)
+ *  stream             hipStream_t (asynchronous; no synchronisation)
+ * Returns GMG_OK, GMG_INVALID_ARGUMENT or GMG_DEVICE_ERROR (launch failure).
+ */
+int gmg_pattern_outer(int64_t n, const int32_t* rowptr_dev, const int32_t* col_dev, const double* u_dev,
+                      const double* v_dev, double scale, double* out_dev, void* stream);
+
 /* Precision of the V-cycle used as a CG preconditioner. */
 enum gmg_precision {
   GMG_PRECISION_F64 = 0, /* the cycle in double */
@@ -116,11 +150,12 @@ enum gmg_precision {
 
 /*
  * Solves A x = b by conjugate gradients in double precision, preconditioned
- * by one symmetric V-cycle per iteration: multigrid as a CG preconditioner,
- * the solver the paper compares against in Sec. 5, with the hierarchy of
- * Sec. 4 and the cycle of Alg. 2 (smoothing before the coarse correction
- * visits the colours in ascending order, after it in descending order, so the
- * cycle from a zero guess is a symmetric operator).
+ * by one symmetric V-cycle per iteration: the method used as the
+ * preconditioner of a Krylov solver, the extension the paper names in its
+ * conclusion (Sec. 6), with the hierarchy of Sec. 4 and the cycle of Alg. 2
+ * (smoothing before the coarse correction visits the colours in ascending
+ * order, after it in descending order, so the cycle from a zero guess is a
+ * symmetric operator).
  *
  *  b_dev, x_dev       float64 device vectors of length n (x_dev: in = initial guess, out = solution)
  *  tol                relative tolerance (>= 0) on ||b - A x||_2 / ||b||_2

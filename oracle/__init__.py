@@ -204,6 +204,19 @@ class Hierarchy:
         return x, it.value, hist[:it.value], st, fin.value
 
 
+def adjoint_gradients(indptr, indices, data, x, grad_x):
+    """Gradients of a loss L(x) through the exact solve of A x = b (A given as CSR):
+    dL/db = lambda with A^T lambda = dL/dx, and dL/dA_ij = -lambda_i x_j on A's stored
+    entries.  Plain sparse direct solve (SciPy); returns (dL/db, dL/dA values in CSR order)."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+    n = len(indptr) - 1
+    A = sp.csr_matrix((data, indices, indptr), shape=(n, n))
+    lam = spla.spsolve(A.T.tocsc(), np.asarray(grad_x, dtype=np.float64))
+    rows = np.repeat(np.arange(n), np.diff(indptr))
+    return lam, -lam[rows] * np.asarray(x)[indices]
+
+
 def closest_point(p, a, b, c):
     w = np.zeros(3)
     arr = [np.ascontiguousarray(v, dtype=np.float64) for v in (p, a, b, c)]

@@ -29,7 +29,7 @@
 //   cholesky                - Alg. 2: direct solve on the coarsest level
 //   solve / vcycle          - Alg. 1 and Alg. 2 (V-cycle, nu_pre/nu_post GS)
 //   vcycle_sym, solve_pcg   - the V-cycle as a symmetric CG preconditioner
-//                             (Sec. 5 compares against MG-preconditioned CG),
+//                             (the Krylov-preconditioner use named in Sec. 6),
 //                             in double or float, inside double-precision CG
 #include <algorithm>
 #include <cmath>
@@ -649,8 +649,8 @@ void vcycle(const Hier& h, size_t l, const double* b, double* x, int mode) {
 }
 
 // ---------------------------------------------------------------- CG preconditioner, mixed precision
-// A V-cycle used as the preconditioner B of conjugate gradients (MG as a CG
-// preconditioner is the solver setting the paper compares against).  For B to
+// A V-cycle used as the preconditioner B of conjugate gradients (the paper's
+// conclusion, Sec. 6, names the method as a Krylov preconditioner).  For B to
 // be symmetric the post-smoothing sweeps are the adjoints of the
 // pre-smoothing sweeps: pre-smoothing visits the colours in ascending order,
 // post-smoothing in descending order.  The cycle starts from x = 0 on every

@@ -27,8 +27,8 @@ EXPORTS = {
 
 # Symbols the library exports (checked on load).
 SYMBOLS = ["gmg_default_options", "gmg_build_hierarchy", "gmg_solve", "gmg_solve_pcg", "gmg_precondition",
-           "gmg_free", "gmg_status_string", "gmg_last_error", "gmg_num_levels", "gmg_level_sizes",
-           "gmg_export_level", "gmg_timer_start", "gmg_timer_stop"]
+           "gmg_update_matrix", "gmg_pattern_outer", "gmg_free", "gmg_status_string", "gmg_last_error",
+           "gmg_num_levels", "gmg_level_sizes", "gmg_export_level", "gmg_timer_start", "gmg_timer_stop"]
 
 # gmg_precision
 PRECISION = {"f64": 0, "f32": 1}
@@ -74,6 +74,8 @@ def library():
     L.gmg_solve.argtypes = [P, P, P, ctypes.c_double, I32, P, ctypes.POINTER(SolveInfo), P]
     L.gmg_solve_pcg.argtypes = [P, P, P, ctypes.c_double, I32, I32, P, ctypes.POINTER(SolveInfo), P]
     L.gmg_precondition.argtypes = [P, P, P, I32, P]
+    L.gmg_update_matrix.argtypes = [P, P, P]
+    L.gmg_pattern_outer.argtypes = [I64, P, P, P, P, ctypes.c_double, P, P]
     L.gmg_free.argtypes = [P]
     L.gmg_free.restype = None
     L.gmg_status_string.argtypes = [ctypes.c_int]
@@ -141,9 +143,12 @@ def _dev(t, dtype, shape=None, name=""):
 class Hierarchy:
     """A multigrid hierarchy owned by the library (gmg_build_hierarchy ... gmg_free)."""
 
-    def __init__(self, handle, n):
+    def __init__(self, handle, n, rowptr=None, col=None):
         self._h = handle
         self.n = n
+        self.rowptr = rowptr          # A's pattern (device copies), for gradients on it
+        self.col = col
+        self.nnz = int(col.shape[0]) if col is not None else 0
 
     def __del__(self):
         self.free()
@@ -238,6 +243,32 @@ class Hierarchy:
         return z
 
 
+    def update_matrix(self, val, stream=None):
+        """gmg_update_matrix: new values of A (same pattern); Galerkin operators and the
+        coarsest factorisation are recomputed, the geometric hierarchy is kept."""
+        import torch
+        pv = _dev(val, torch.float64, (self.nnz,), "val")
+        st = library().gmg_update_matrix(self._h, pv, _stream_ptr(stream))
+        if st:
+            raise _err(st)
+
+
+def pattern_outer(rowptr, col, u, v, scale=1.0, out=None, stream=None):
+    """gmg_pattern_outer: out[e] = scale * u_i * v_j on the entries (i, j) of a CSR pattern."""
+    import torch
+    n = int(rowptr.shape[0]) - 1
+    nnz = int(col.shape[0])
+    if out is None:
+        out = torch.empty(nnz, dtype=torch.float64, device=u.device)
+    args = [_dev(rowptr, torch.int32, (n + 1,), "rowptr"), _dev(col, torch.int32, (nnz,), "col"),
+            _dev(u, torch.float64, (n,), "u"), _dev(v, torch.float64, (n,), "v")]
+    po = _dev(out, torch.float64, (nnz,), "out")
+    st = library().gmg_pattern_outer(n, args[0], args[1], args[2], args[3], float(scale), po, _stream_ptr(stream))
+    if st:
+        raise _err(st)
+    return out
+
+
 def build_hierarchy(points, edges, rowptr, col, val, options=None, stream=None):
     """gmg_build_hierarchy on torch tensors: points (n,3) f64, edges (m,2) int32, A as CSR
     (rowptr int32 (n+1), col int32, val f64).  All on the current HIP device."""
@@ -254,7 +285,7 @@ def build_hierarchy(points, edges, rowptr, col, val, options=None, stream=None):
                                        ctypes.byref(opt), _stream_ptr(stream), ctypes.byref(h))
     if st:
         raise _err(st)
-    return Hierarchy(h, n)
+    return Hierarchy(h, n, rowptr.clone(), col.clone())
 
 
 def from_problem(prob, options=None, device="cuda"):

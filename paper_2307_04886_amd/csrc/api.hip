@@ -401,11 +401,6 @@ void build(Handle& h, int64_t n, const double* points, int64_t m, const int32_t*
     solve_layout(h, h.L[l], &h.L[l + 1], pts[l].rp, pts[l].col, pts[l].val);
     mark("solve layout", l);
   }
-  for (auto& pt : pts) {
-    tfree(s, pt.rp);
-    tfree(s, pt.col);
-    tfree(s, pt.val);
-  }
   coarse_factor(h, last);
   mark("coarse factor", nl - 1);
   // deferred sizes and statistics, with the error flags, in one synchronisation
@@ -973,6 +968,59 @@ int gmg_precondition(gmg_handle hh, const double* r_dev, double* z_dev, int32_t 
   }
   h->stream = saved;
   return status;
+}
+
+int gmg_update_matrix(gmg_handle hh, const double* A_val_dev, void* stream) {
+  set_error("");
+  Handle* h = hh;
+  if (!h || !A_val_dev) {
+    set_error("invalid update arguments");
+    return GMG_INVALID_ARGUMENT;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  hipStream_t saved = h->stream;
+  h->stream = s;
+  int status = GMG_OK;
+  try {
+    const int nl = (int)h->L.size();
+    Level& l0 = h->L[0];
+    check_hip(hipMemsetAsync(h->flags, 0, 4, s), "memset");
+    validate_matrix(l0.arp, l0.acol, A_val_dev, l0.n, l0.nnzA, h->flags, s);
+    check_hip(hipMemcpyAsync(l0.aval, A_val_dev, (size_t)l0.nnzA * 8, hipMemcpyDeviceToDevice, s), "copy values");
+    for (int l = 0; l + 1 < nl; ++l) galerkin_values(*h, h->L[l], h->L[l + 1]);
+    for (int l = 0; l < nl; ++l) refresh_values(*h, h->L[l]);
+    coarse_factor(*h, h->L[nl - 1]);                 // also raises the flags of the steps above
+    if (h->kry.ready[1])
+      for (int l = 0; l + 1 < nl; ++l) {
+        const LevelView& d = h->plain.v[l];
+        LevelViewT<float>& f = h->kry.c32.v[l];
+        to_f32(d.A.val, (float*)f.A.val, h->L[l].a_slots, s);
+        to_f32(d.diag, (float*)f.diag, d.n, s);
+      }
+    sync(s, "update");
+  } catch (const Error& e) {
+    set_error(e.msg);
+    status = e.status;
+  }
+  h->stream = saved;
+  return status;
+}
+
+int gmg_pattern_outer(int64_t n, const int32_t* rowptr_dev, const int32_t* col_dev, const double* u_dev,
+                      const double* v_dev, double scale, double* out_dev, void* stream) {
+  set_error("");
+  if (n < 0 || (n > 0 && (!rowptr_dev || !col_dev || !u_dev || !v_dev || !out_dev))) {
+    set_error("invalid pattern product arguments");
+    return GMG_INVALID_ARGUMENT;
+  }
+  try {
+    if (n > 0) pattern_outer(n, rowptr_dev, col_dev, u_dev, v_dev, scale, out_dev, (hipStream_t)stream);
+    check_hip(hipGetLastError(), "pattern product");
+  } catch (const Error& e) {
+    set_error(e.msg);
+    return e.status;
+  }
+  return GMG_OK;
 }
 
 void gmg_free(gmg_handle h) { release(h); }

@@ -172,6 +172,12 @@ struct Level {
   double* r = nullptr;
   int64_t a_slots = 0, t_slots = 0;     // SELL entry slots of A_l and P_l^T (with padding)
   LevelView view;
+  // P_l^T in the original numbering (rows: coarse points, entries in ascending
+  // fine index), kept for recomputing A_{l+1} when A changes
+  int32_t* t_rp = nullptr;
+  int32_t* t_col = nullptr;
+  double* t_val = nullptr;
+  bool galerkin_wide = false;           // A_{l+1} has a row longer than the narrow fill kernel holds
 };
 
 // Preconditioned conjugate gradients (double) around a symmetric V-cycle in
@@ -282,12 +288,14 @@ void prolongation(Handle& h, Level& lv, Level& nx);
 void transpose_p(Handle& h, Level& lv, int64_t nc, int32_t** t_rp, int32_t** t_col, double** t_val);
 void galerkin(Handle& h, Level& lv, Level& nx, const int32_t* t_rp, const int32_t* t_col,
               const double* t_val);
+void galerkin_values(Handle& h, Level& lv, Level& nx);     // same pattern, values from the current A_l
 
 // ------------------------------------------------------------------ launchers (setup_solve.hip)
 void colouring(Handle& h, Level& lv, int level);
 void solve_layout(Handle& h, Level& lv, const Level* nx, const int32_t* t_rp, const int32_t* t_col,
                   const double* t_val);
 void coarse_factor(Handle& h, Level& lv);
+void refresh_values(Handle& h, Level& lv);                 // SELL values and diagonal from lv.aval
 
 // ------------------------------------------------------------------ launchers (solve.hip)
 // V-cycle phases on one level, for V = double and V = float.  gs_sweep visits
@@ -316,6 +324,8 @@ void residual_norm(const Level& lv, const double* b, const double* x, double* re
                    hipStream_t s);
 void finish_norm(const double* partials, double* out, hipStream_t s);
 void check_finite(const double* v, int64_t n, int32_t* flag, hipStream_t s);
+void pattern_outer(int64_t n, const int32_t* rp, const int32_t* col, const double* u, const double* v,
+                   double scale, double* out, hipStream_t s);
 // preconditioned CG steps (level 0, double; z in V)
 void kry_init(Krylov& k, int64_t n, hipStream_t s);
 template <class V>

@@ -1,8 +1,8 @@
 // Conjugate gradients in double on A x = b (level 0, colour-sorted
 // numbering), preconditioned by the symmetric V-cycle in double or float
-// (multigrid as a CG preconditioner, the solver setting Sec. 5 compares
-// against).  Flexible form with the Polak-Ribiere coefficient, which keeps
-// the local A-orthogonality of successive directions when the preconditioner
+// (the method as the preconditioner of a Krylov solver, the extension named
+// in the paper's conclusion, Sec. 6).  Flexible form with the Polak-Ribiere
+// coefficient, which keeps the local A-orthogonality of successive directions when the preconditioner
 // carries float rounding.  One iteration:
 //   z = B r;  beta = (r.z - r_old.z) / rho;  rho = r.z;  p = z + beta p;
 //   q = A p;  alpha = rho / p.q;  x += alpha p;  r_old = r;  r -= alpha q.
@@ -122,7 +122,23 @@ __global__ void __launch_bounds__(kBlock) k_kry_norm(const double* part, double*
   if (threadIdx.x == 0) scal[KS_NORM] = sqrt(s);
 }
 
+// out[e] = scale * u_i * v_col(e) for every entry e of row i: the gradient of a
+// loss with respect to the stored entries of A (u = adjoint, v = solution).
+__global__ void k_pattern_outer(int64_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                const double* __restrict__ u, const double* __restrict__ v, double scale,
+                                double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double ui = scale * u[i];
+  for (int32_t e = rp[i]; e < rp[i + 1]; ++e) out[e] = ui * v[col[e]];
+}
+
 }  // namespace
+
+void pattern_outer(int64_t n, const int32_t* rp, const int32_t* col, const double* u, const double* v,
+                   double scale, double* out, hipStream_t s) {
+  k_pattern_outer<<<blocks_for(n), kBlock, 0, s>>>(n, rp, col, u, v, scale, out);
+}
 
 void kry_init(Krylov& k, int64_t n, hipStream_t s) {
   k_kry_init<<<blocks_for(n), kBlock, 0, s>>>(k.p, k.r_old, n, k.scal);

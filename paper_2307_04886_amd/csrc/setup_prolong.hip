@@ -472,14 +472,14 @@ void transpose_p(Handle& h, Level& lv, int64_t nc, int32_t** t_rp, int32_t** t_c
   int64_t n = lv.n;
   int32_t* cnt = (int32_t*)talloc(s, (size_t)(nc + 1) * 4);
   int32_t* cur = (int32_t*)talloc(s, (size_t)(nc + 1) * 4);
-  int32_t* rp = (int32_t*)talloc(s, (size_t)(nc + 1) * 4);   // freed by the caller
+  int32_t* rp = (int32_t*)dalloc(h, (size_t)(nc + 1) * 4);   // kept by the handle
   check_hip(hipMemsetAsync(cnt, 0, (size_t)(nc + 1) * 4, s), "memset");
   check_hip(hipMemsetAsync(cur, 0, (size_t)(nc + 1) * 4, s), "memset");
   k_count_cols<<<blocks_for(n), kBlock, 0, s>>>(lv.pcol, lv.pcnt, n, cnt);
   scan_i32(cnt, rp, nc, s);
   k_store_total<<<1, 1, 0, s>>>(rp + nc, lv.stats + 1);      // nnz(P), read at the end of the build
-  int32_t* col = (int32_t*)talloc(s, (size_t)(3 * n + 1) * 4);   // nnz(P) <= 3n
-  double* val = (double*)talloc(s, (size_t)(3 * n + 1) * 8);
+  int32_t* col = (int32_t*)dalloc(h, (size_t)(3 * n + 1) * 4);   // nnz(P) <= 3n
+  double* val = (double*)dalloc(h, (size_t)(3 * n + 1) * 8);
   k_scatter_cols<<<blocks_for(n), kBlock, 0, s>>>(lv.pcol, lv.pval, lv.pcnt, n, rp, cur, col, val);
   k_sort_pairs<<<blocks_for(nc, kBlock / kWave), kBlock, 0, s>>>(rp, col, val, nc);
   tfree(s, cnt);
@@ -508,14 +508,26 @@ void galerkin(Handle& h, Level& lv, Level& nx, const int32_t* t_rp, const int32_
   nx.acol = (int32_t*)dalloc(h, (size_t)(nx.nnzA + 1) * 4);
   nx.aval = (double*)dalloc(h, (size_t)(nx.nnzA + 1) * 8);
   // a smaller LDS footprint (more resident wavefronts) when every row fits
-  if (maxrow <= 256 * 3 / 4)
-    k_galerkin_fill<256><<<(int)nc, kWave, 0, s>>>(t_rp, t_col, t_val, lv.arp, lv.acol, lv.aval, lv.pcol,
-                                                   lv.pval, lv.pcnt, nc, nx.arp, nx.acol, nx.aval, h.flags);
-  else
-    k_galerkin_fill<1024><<<(int)nc, kWave, 0, s>>>(t_rp, t_col, t_val, lv.arp, lv.acol, lv.aval, lv.pcol,
-                                                    lv.pval, lv.pcnt, nc, nx.arp, nx.acol, nx.aval, h.flags);
+  lv.galerkin_wide = maxrow > 256 * 3 / 4;
+  lv.t_rp = (int32_t*)t_rp;
+  lv.t_col = (int32_t*)t_col;
+  lv.t_val = (double*)t_val;
+  galerkin_values(h, lv, nx);
   tfree(s, cnt);
   tfree(s, mx);
+}
+
+// The numeric pass alone: the pattern it writes is the one already there.
+void galerkin_values(Handle& h, Level& lv, Level& nx) {
+  hipStream_t s = h.stream;
+  const int64_t nc = nx.n;
+  if (!lv.galerkin_wide)
+    k_galerkin_fill<256><<<(int)nc, kWave, 0, s>>>(lv.t_rp, lv.t_col, lv.t_val, lv.arp, lv.acol, lv.aval, lv.pcol,
+                                                   lv.pval, lv.pcnt, nc, nx.arp, nx.acol, nx.aval, h.flags);
+  else
+    k_galerkin_fill<1024><<<(int)nc, kWave, 0, s>>>(lv.t_rp, lv.t_col, lv.t_val, lv.arp, lv.acol, lv.aval,
+                                                    lv.pcol, lv.pval, lv.pcnt, nc, nx.arp, nx.acol, nx.aval,
+                                                    h.flags);
 }
 
 }  // namespace gmg

@@ -518,14 +518,21 @@ void coarse_factor(Handle& h, Level& lv) {
       k_chol_update<<<dim3(t, t), 1024, 0, s>>>(D, n, k0, kb);
     }
   }
-  h.chol = (double*)dalloc(h, (size_t)n * n * 8);
-  h.cinv = (double*)dalloc(h, (size_t)n * n * 8);
+  if (!h.chol) h.chol = (double*)dalloc(h, (size_t)n * n * 8);
+  if (!h.cinv) h.cinv = (double*)dalloc(h, (size_t)n * n * 8);
   k_split_factor<<<blocks_for(n * n), kBlock, 0, s>>>(D, n, h.chol, U);
   k_chol_inverse<<<(int)n, kWave, (size_t)n * 8, s>>>(h.chol, U, n, h.cinv);
   h.ncoarse = n;
   check_flags(h, "coarsest factorisation");
   tfree(s, D);
   tfree(s, U);
+}
+
+// New values of A_l (same pattern) into its SELL layout and diagonal.
+void refresh_values(Handle& h, Level& lv) {
+  const LevelView& v = lv.view;
+  k_sell_fill<<<blocks_for(lv.n), kBlock, 0, h.stream>>>(lv.perm, lv.iperm, lv.arp, lv.acol, lv.aval, lv.n, v.A.ptr,
+                                                         (int32_t*)v.A.col, (double*)v.A.val, lv.diag);
 }
 
 }  // namespace gmg

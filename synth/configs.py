@@ -47,6 +47,19 @@ def config_bumpy_sphere(n=2_000_000, k=8, seed=0, alpha=1e-2):
     return Problem(f"bumpysphere{n}k{k}", pts, edges, indptr, indices, data, mass * y)
 
 
+def config_adjoint(nu=707, nv=707, seed=0, alpha=1e-3):
+    """Differentiation workload: the jittered torus (707 x 707 = 499,849 vertices),
+    (M + 1e-3 L) x = M b, loss ||x - x*||^2 with target x* ~ U[-1, 1].  Returns the
+    problem, x* and a seeded choice of 32 stored entries of A and 8 entries of b
+    (indices) for finite-difference checks."""
+    prob = config_torus(nu, nv, seed, alpha)
+    target = uniform(seed, "target", prob.n, -1.0, 1.0)
+    u = uniform(seed, "entries", 40, 0.0, 1.0)
+    a_idx = np.minimum((u[:32] * prob.nnz).astype(np.int64), prob.nnz - 1)
+    b_idx = np.minimum((u[32:] * prob.n).astype(np.int64), prob.n - 1)
+    return prob, target, a_idx, b_idx
+
+
 def small_icosphere(subdivisions=3, seed=0):
     return config_icosphere(subdivisions, seed)
 
@@ -72,4 +85,5 @@ CONFIGS = {
     "icosphere5": config_icosphere,
     "torus1024": config_torus,
     "bumpysphere2m": config_bumpy_sphere,
+    "adjoint_torus707": config_adjoint,
 }
