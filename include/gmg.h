@@ -51,7 +51,16 @@ typedef struct gmg_options {
   int32_t shift_coarse_points;   /* 1: move coarse points to their Voronoi-cell mean (Sec. 4.4) */
   int32_t sample_order;          /* 0: hashed sweep order (default), 1: input index order (Sec. 4.2) */
   uint64_t seed;                 /* seed of the hashed sweep and colouring orders */
+  int32_t weighting;             /* prolongation weights on the chosen triangle: 0 barycentric (Sec. 4.4,
+                                    default), 1 uniform, 2 inverse distance (the variants of the
+                                    weighting ablation, Sec. 5.3) */
+  int32_t fallback_on_vertex;    /* 1: also use the inverse-distance fallback when the closest point of
+                                    the best triangle is one of its vertices (default 0: edge and
+                                    vertex projections are kept, Sec. 4.4) */
 } gmg_options;
+
+/* Values of gmg_options.weighting. */
+enum gmg_weighting { GMG_WEIGHTS_BARYCENTRIC = 0, GMG_WEIGHTS_UNIFORM = 1, GMG_WEIGHTS_INVERSE_DISTANCE = 2 };
 
 typedef struct gmg_solve_info {
   int32_t iterations;            /* V-cycles performed */

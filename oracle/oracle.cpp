@@ -52,6 +52,8 @@ struct Options {                 // field order mirrors the public options struc
   int32_t shift_coarse_points;   // move coarse points to their cell mean (Sec. 4.4)
   int32_t sample_order;          // 0: hashed sweep order, 1: input (index) order
   uint64_t seed;
+  int32_t weighting;             // 0 barycentric (Sec. 4.4), 1 uniform, 2 inverse distance (Sec. 5.3)
+  int32_t fallback_on_vertex;    // 1: a best projection onto a triangle vertex uses the fallback
 };
 
 enum Status { OK = 0, NOT_CONVERGED = 1, INVALID_ARGUMENT = -1, NOT_SPD = -4, DEGENERATE = -5 };
@@ -394,7 +396,12 @@ double dist2_to(V3 P, V3 A, V3 B, V3 C, const double w[3]) {
 // in ascending (j, k); the first one with the smallest point-to-triangle
 // distance wins.  Without any non-degenerate candidate, the three points of
 // {c} U N(c) nearest to p get inverse-distance weights.
-void prolongation(Level& L, const Level& nx) {
+// Variants of the weighting ablation (Sec. 5.3) replace the barycentric
+// weights on the chosen triangle (c, j, k) by 1/3 each (uniform) or by
+// 1/|p - X_t| normalised by their sum (inverse distance; a vertex at distance 0
+// takes weight 1).  fallback_on_vertex sends a best projection that lands on a
+// triangle vertex to the inverse-distance fallback.
+void prolongation(Level& L, const Level& nx, const Options& o) {
   const Level& lv = L;
   int64_t n = lv.n;
   L.pcol.assign(3 * n, -1);
@@ -409,6 +416,7 @@ void prolongation(Level& L, const Level& nx) {
     bool found = false;
     double best = 0.0, bw[3] = {0, 0, 0};
     int32_t bj = -1, bk = -1;
+    int breg = -1;
     for (int32_t e1 = nx.erp[c]; e1 < nx.erp[c + 1]; ++e1) {
       int32_t j = nx.ecol[e1];
       for (int32_t e2 = e1 + 1; e2 < nx.erp[c + 1]; ++e2) {
@@ -417,14 +425,16 @@ void prolongation(Level& L, const Level& nx) {
         V3 B = pos(nx, j), C = pos(nx, k);
         if (degenerate(A, B, C)) continue;
         double w[3];
-        closest_point(P, A, B, C, w);
+        int reg = closest_point(P, A, B, C, w);
         double d2 = dist2_to(P, A, B, C, w);
         if (!found || d2 < best) {
-          found = true; best = d2; bj = j; bk = k;
+          found = true; best = d2; bj = j; bk = k; breg = reg;
           bw[0] = w[0]; bw[1] = w[1]; bw[2] = w[2];
         }
       }
     }
+    // regions 0, 1, 3 are the vertices A, B, C (see closest_point)
+    if (found && o.fallback_on_vertex && (breg == 0 || breg == 1 || breg == 3)) found = false;
     int32_t cols[3];
     double vals[3];
     int cnt = 0;
@@ -433,6 +443,21 @@ void prolongation(Level& L, const Level& nx) {
       L.tri[2 * p + 1] = bk;
       cols[0] = c; cols[1] = bj; cols[2] = bk;
       vals[0] = bw[0]; vals[1] = bw[1]; vals[2] = bw[2];
+      if (o.weighting == 1) {
+        vals[0] = vals[1] = vals[2] = 1.0 / 3.0;
+      } else if (o.weighting == 2) {
+        V3 T[3] = {A, pos(nx, bj), pos(nx, bk)};
+        double d[3];
+        for (int t = 0; t < 3; ++t) { V3 e = sub(P, T[t]); d[t] = std::sqrt(dot(e, e)); }
+        int zero = d[0] == 0.0 ? 0 : d[1] == 0.0 ? 1 : d[2] == 0.0 ? 2 : -1;
+        if (zero >= 0) {
+          for (int t = 0; t < 3; ++t) vals[t] = t == zero ? 1.0 : 0.0;
+        } else {
+          double inv[3] = {1.0 / d[0], 1.0 / d[1], 1.0 / d[2]};
+          double s = (inv[0] + inv[1]) + inv[2];
+          for (int t = 0; t < 3; ++t) vals[t] = inv[t] / s;
+        }
+      }
       cnt = 3;
     } else {
       L.fallback += 1;
@@ -744,6 +769,8 @@ int check_options(const Options& o) {
   if (!(o.coarsening_ratio > 0.0 && o.coarsening_ratio < 1.0)) return INVALID_ARGUMENT;
   if (o.min_coarse_points < 1 || o.max_levels < 1 || o.nu_pre < 0 || o.nu_post < 0) return INVALID_ARGUMENT;
   if (o.sample_order != 0 && o.sample_order != 1) return INVALID_ARGUMENT;
+  if (o.weighting < 0 || o.weighting > 2 || (o.fallback_on_vertex != 0 && o.fallback_on_vertex != 1))
+    return INVALID_ARGUMENT;
   return OK;
 }
 
@@ -781,7 +808,7 @@ int orc_build(int64_t n, const double* pts, int64_t m, const int32_t* edges, con
     Level nx;
     cells_and_shift(lv, nx, o.shift_coarse_points != 0);
     coarse_edges(lv, nx);
-    prolongation(lv, nx);
+    prolongation(lv, nx, o);
     st = galerkin(lv, nx);
     if (st != OK) { delete h; return st; }
     h->L.push_back(std::move(nx));

@@ -260,7 +260,8 @@ void release(H* h) {
 bool options_ok(const gmg_options& o) {
   return o.struct_size == (int32_t)sizeof(gmg_options) && o.coarsening_ratio > 0.0 &&
          o.coarsening_ratio < 1.0 && o.min_coarse_points >= 1 && o.max_levels >= 1 && o.nu_pre >= 0 &&
-         o.nu_post >= 0 && (o.sample_order == 0 || o.sample_order == 1);
+         o.nu_post >= 0 && (o.sample_order == 0 || o.sample_order == 1) && o.weighting >= 0 && o.weighting <= 2 &&
+         (o.fallback_on_vertex == 0 || o.fallback_on_vertex == 1);
 }
 
 // The single-workgroup tail of a cycle: levels tail_start.. with their views,

@@ -27,37 +27,40 @@ __device__ inline bool degenerate(V3 A, V3 B, V3 C) {
 // Barycentric weights of the point of triangle ABC closest to P (face, edge
 // or vertex), by the Voronoi-region tests of Ericson, Real-Time Collision
 // Detection (2005), Sec. 5.1.5: vertex A, vertex B, edge AB, vertex C, edge
-// AC, edge BC, face.
-__device__ inline void closest_point(V3 P, V3 A, V3 B, V3 C, double& wa, double& wb, double& wc) {
+// AC, edge BC, face.  Returns the region in that order (0 .. 6).
+enum : int { kRegionA = 0, kRegionB = 1, kRegionC = 3 };
+
+__device__ inline int closest_point(V3 P, V3 A, V3 B, V3 C, double& wa, double& wb, double& wc) {
   V3 ab = sub3(B, A), ac = sub3(C, A), ap = sub3(P, A);
   double d1 = dot3(ab, ap), d2 = dot3(ac, ap);
-  if (d1 <= 0.0 && d2 <= 0.0) { wa = 1.0; wb = 0.0; wc = 0.0; return; }
+  if (d1 <= 0.0 && d2 <= 0.0) { wa = 1.0; wb = 0.0; wc = 0.0; return 0; }
   V3 bp = sub3(P, B);
   double d3 = dot3(ab, bp), d4 = dot3(ac, bp);
-  if (d3 >= 0.0 && d4 <= d3) { wa = 0.0; wb = 1.0; wc = 0.0; return; }
+  if (d3 >= 0.0 && d4 <= d3) { wa = 0.0; wb = 1.0; wc = 0.0; return 1; }
   double vc = d1 * d4 - d3 * d2;
   if (vc <= 0.0 && d1 >= 0.0 && d3 <= 0.0) {
     double t = d1 / (d1 - d3);
-    wa = 1.0 - t; wb = t; wc = 0.0; return;
+    wa = 1.0 - t; wb = t; wc = 0.0; return 2;
   }
   V3 cp = sub3(P, C);
   double d5 = dot3(ab, cp), d6 = dot3(ac, cp);
-  if (d6 >= 0.0 && d5 <= d6) { wa = 0.0; wb = 0.0; wc = 1.0; return; }
+  if (d6 >= 0.0 && d5 <= d6) { wa = 0.0; wb = 0.0; wc = 1.0; return 3; }
   double vb = d5 * d2 - d1 * d6;
   if (vb <= 0.0 && d2 >= 0.0 && d6 <= 0.0) {
     double t = d2 / (d2 - d6);
-    wa = 1.0 - t; wb = 0.0; wc = t; return;
+    wa = 1.0 - t; wb = 0.0; wc = t; return 4;
   }
   double va = d3 * d6 - d5 * d4;
   double e43 = d4 - d3, e56 = d5 - d6;
   if (va <= 0.0 && e43 >= 0.0 && e56 >= 0.0) {
     double t = e43 / (e43 + e56);
-    wa = 0.0; wb = 1.0 - t; wc = t; return;
+    wa = 0.0; wb = 1.0 - t; wc = t; return 5;
   }
   double a = va < 0.0 ? 0.0 : va, b = vb < 0.0 ? 0.0 : vb, c = vc < 0.0 ? 0.0 : vc;
   double s = (a + b) + c;
-  if (!(s > 0.0)) { wa = 1.0; wb = 0.0; wc = 0.0; return; }
+  if (!(s > 0.0)) { wa = 1.0; wb = 0.0; wc = 0.0; return 6; }
   wa = a / s; wb = b / s; wc = c / s;
+  return 6;
 }
 
 // One thread per fine point p; c = label(p) is the coarse point closest to p.
@@ -67,8 +70,13 @@ __device__ inline void closest_point(V3 P, V3 A, V3 B, V3 C, double& wa, double&
 // candidate, the three points of {c} U N(c) nearest to p (ties by index) get
 // inverse-distance weights.  The row keeps its non-zero weights sorted by
 // column.
+// Variants (weighting ablation): the chosen triangle's vertices (c, j, k) get
+// uniform weights 1/3, or inverse-distance weights 1/|p - X_t| normalised by
+// their sum (c, j, k order; a vertex at distance 0 takes weight 1).  With
+// fallback_on_vertex, a best projection onto a vertex goes to the fallback.
 __global__ void __launch_bounds__(kBlock) k_project(const double* X, const int32_t* lab, int64_t n,
                                                     const double* Xc, const int32_t* crp, const int32_t* ccol,
+                                                    int32_t weighting, int32_t fallback_on_vertex,
                                                     int32_t* pcol, double* pval, int32_t* pcnt, int32_t* tri,
                                                     unsigned long long* fallback) {
   int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -81,6 +89,7 @@ __global__ void __launch_bounds__(kBlock) k_project(const double* X, const int32
     bool found = false;
     double best = 0.0, bw0 = 0.0, bw1 = 0.0, bw2 = 0.0;
     int32_t bj = -1, bk = -1;
+    int breg = -1;
     for (int32_t e1 = rb; e1 < re; ++e1) {
       int32_t j = ccol[e1];
       V3 B = ld3(Xc, j);
@@ -90,7 +99,7 @@ __global__ void __launch_bounds__(kBlock) k_project(const double* X, const int32
         V3 C = ld3(Xc, k);
         if (degenerate(A, B, C)) continue;
         double w0, w1, w2;
-        closest_point(P, A, B, C, w0, w1, w2);
+        const int reg = closest_point(P, A, B, C, w0, w1, w2);
         V3 q = {(w0 * A.x + w1 * B.x) + w2 * C.x, (w0 * A.y + w1 * B.y) + w2 * C.y,
                 (w0 * A.z + w1 * B.z) + w2 * C.z};
         V3 d = sub3(P, q);
@@ -103,15 +112,38 @@ __global__ void __launch_bounds__(kBlock) k_project(const double* X, const int32
           bw0 = w0;
           bw1 = w1;
           bw2 = w2;
+          breg = reg;
         }
       }
     }
+    if (found && fallback_on_vertex && (breg == kRegionA || breg == kRegionB || breg == kRegionC)) found = false;
     int32_t cols[3];
     double vals[3];
     int cnt;
     if (found) {
       cols[0] = c; cols[1] = bj; cols[2] = bk;
       vals[0] = bw0; vals[1] = bw1; vals[2] = bw2;
+      if (weighting == 1) {
+        vals[0] = vals[1] = vals[2] = 1.0 / 3.0;
+      } else if (weighting == 2) {
+        const V3 T[3] = {A, ld3(Xc, bj), ld3(Xc, bk)};
+        double dd[3];
+        int zero = -1;
+        for (int t = 0; t < 3; ++t) {
+          const V3 d = sub3(P, T[t]);
+          dd[t] = sqrt(dot3(d, d));
+          if (dd[t] == 0.0 && zero < 0) zero = t;
+        }
+        if (zero >= 0) {
+          for (int t = 0; t < 3; ++t) vals[t] = t == zero ? 1.0 : 0.0;
+        } else {
+          const double i0 = 1.0 / dd[0], i1 = 1.0 / dd[1], i2 = 1.0 / dd[2];
+          const double sum = (i0 + i1) + i2;
+          vals[0] = i0 / sum;
+          vals[1] = i1 / sum;
+          vals[2] = i2 / sum;
+        }
+      }
       cnt = 3;
     } else {
       fb = true;
@@ -463,8 +495,9 @@ void prolongation(Handle& h, Level& lv, Level& nx) {
   lv.pval = (double*)dalloc(h, (size_t)3 * n * 8);
   lv.pcnt = (int32_t*)dalloc(h, (size_t)n * 4);
   lv.tri = (int32_t*)dalloc(h, (size_t)2 * n * 4);
-  k_project<<<blocks_for(n), kBlock, 0, s>>>(lv.X, lv.label, n, nx.X, nx.erp, nx.ecol, lv.pcol, lv.pval,
-                                             lv.pcnt, lv.tri, lv.stats);
+  k_project<<<blocks_for(n), kBlock, 0, s>>>(lv.X, lv.label, n, nx.X, nx.erp, nx.ecol, h.opt.weighting,
+                                             h.opt.fallback_on_vertex, lv.pcol, lv.pval, lv.pcnt, lv.tri,
+                                             lv.stats);
 }
 
 void transpose_p(Handle& h, Level& lv, int64_t nc, int32_t** t_rp, int32_t** t_col, double** t_val) {

@@ -13,11 +13,14 @@ from .operators import cotan_laplacian, lumped_mass, gaussian_knn_laplacian, ass
 from .rng import uniform
 
 
-def _mesh_problem(name, pts, faces, alpha, seed):
+def _mesh_problem(name, pts, faces, alpha, seed, eta=None):
     edges = edges_from_faces(faces)
     off, diag = cotan_laplacian(pts, faces)
     mass = lumped_mass(pts, faces)
-    indptr, indices, data = assemble(off, diag, mass, alpha, edges)
+    if eta is None:                                   # data smoothing (M + alpha L) x = M y
+        indptr, indices, data = assemble(off, diag, mass, alpha, edges)
+    else:                                             # Poisson (L + eta M) x = M y
+        indptr, indices, data = assemble(off, diag, mass, 1.0, edges, mass_weight=eta)
     y = uniform(seed, "rhs", pts.shape[0], -1.0, 1.0)
     return Problem(name, np.ascontiguousarray(pts), edges, indptr, indices, data, mass * y)
 
@@ -45,6 +48,15 @@ def config_bumpy_sphere(n=2_000_000, k=8, seed=0, alpha=1e-2):
     indptr, indices, data = assemble(off, diag, mass, alpha, edges)
     y = uniform(seed, "rhs", n, -1.0, 1.0)
     return Problem(f"bumpysphere{n}k{k}", pts, edges, indptr, indices, data, mass * y)
+
+
+def config_poisson(nu=96, nv=80, seed=0, eta=1e-6, jitter=0.1):
+    """The Poisson problem of the paper's comparisons, (L + eta M) x = M y with eta = 1e-6,
+    y ~ U[-1, 1], on the jittered torus."""
+    pts, faces = torus_grid(nu, nv)
+    sigma = jitter * mean_edge_length(pts, edges_from_faces(faces))
+    pts = gaussian_jitter(pts, seed, sigma)
+    return _mesh_problem(f"poisson_torus{nu}x{nv}", pts, faces, None, seed, eta=eta)
 
 
 def config_adjoint(nu=707, nv=707, seed=0, alpha=1e-3):

@@ -94,8 +94,10 @@ def gaussian_knn_laplacian(points, edges, knn_dist):
     return off, diag, mass
 
 
-def assemble(off_lap, diag_lap, mass, alpha, edges):
-    """A = M + alpha * L in CSR with sorted columns and pattern = edges U diagonal.
+def assemble(off_lap, diag_lap, mass, alpha, edges, mass_weight=1.0):
+    """A = mass_weight * M + alpha * L in CSR with sorted columns and pattern = edges U
+    diagonal: the data-smoothing system (M + alpha L) by default, the Poisson system
+    (L + eta M) with alpha = 1, mass_weight = eta.
 
     Structural zeros of the pattern are kept explicitly.
     """
@@ -115,5 +117,5 @@ def assemble(off_lap, diag_lap, mass, alpha, edges):
         raise ValueError("Laplacian entry outside the edge pattern")
     vals = np.bincount(pos, weights=alpha * coo.data, minlength=keys.size)
     dpos = np.searchsorted(keys, np.arange(n, dtype=np.int64) * n + np.arange(n))
-    vals[dpos] += mass + alpha * diag_lap
+    vals[dpos] += mass_weight * mass + alpha * diag_lap
     return indptr.astype(np.int32), indices, vals.astype(np.float64)

@@ -78,24 +78,29 @@ def compare_hierarchies(orc, gpu, name=""):
     assert np.all(np.abs(co - cg) <= 1e-12 * np.abs(co).max()), name
 
 
-def compare_solves(orc, gpu, prob, tol=1e-8, max_iters=200):
+def compare_solves(orc, gpu, prob, tol=1e-8, max_iters=200, x_rtol=1e-9):
     x_o, it_o, hist_o, st_o = orc.solve(prob.rhs, tol=tol, max_iters=max_iters)
     b = torch.from_numpy(prob.rhs).cuda()
     x_g, info, st_g, hist_g = gpu.solve(b, tol=tol, max_iters=max_iters, history=True)
     torch.cuda.synchronize()
     x_g = x_g.cpu().numpy()
-    near = abs(hist_o[-1] - tol) <= 1e-12 or (it_o > 1 and abs(hist_o[-2] - tol) <= 1e-12)
+    A = prob.matrix()
+    # b - A x is computed with an absolute rounding error of about u |A| |x|; two
+    # iterates that differ in their last digits (the coarsest solve is an explicit
+    # inverse on the GPU, a substitution in the oracle) carry independent such
+    # errors.  For well-conditioned systems this floor is far below 1e-13 |b|.
+    floor = 8 * 2.0 ** -53 * np.linalg.norm(abs(A) @ np.abs(x_o)) / np.linalg.norm(prob.rhs)
+    bound = 1e-10 * hist_o + floor + 1e-13
+    near = abs(hist_o[-1] - tol) <= bound[-1] or (it_o > 1 and abs(hist_o[-2] - tol) <= bound[-2])
     assert info.iterations == it_o or (near and abs(info.iterations - it_o) == 1), (info.iterations, it_o)
     k = min(it_o, info.iterations)
-    # b - A x cancels to about 1e-16 |b|, so a relative residual carries that absolute error
-    assert np.all(np.abs(hist_g[:k] - hist_o[:k]) <= 1e-10 * hist_o[:k] + 1e-13), (hist_g[:k], hist_o[:k])
+    assert np.all(np.abs(hist_g[:k] - hist_o[:k]) <= bound[:k]), (hist_g[:k], hist_o[:k], floor)
     assert st_g == st_o
-    A = prob.matrix()
     res = np.linalg.norm(prob.rhs - A @ x_g) / np.linalg.norm(prob.rhs)
-    assert res <= tol * (1 + 1e-9)
-    assert abs(res - info.rel_residual) <= 1e-9 * res
+    assert res <= tol * (1 + 1e-9) + floor
+    assert abs(res - info.rel_residual) <= 1e-9 * res + floor
     err = np.linalg.norm(x_g - x_o) / np.linalg.norm(x_o)
-    assert err <= 1e-9, err
+    assert err <= x_rtol, err
     return info.iterations, err
 
 
@@ -127,6 +132,28 @@ def test_option_variants(opt):
     orc, gpu = both(prob, min_coarse_points=200, **opt)
     compare_hierarchies(orc, gpu, str(opt))
     compare_solves(orc, gpu, prob)
+
+
+@pytest.mark.parametrize("name,opt", [("torus96", dict(weighting=1)), ("torus96", dict(weighting=2)),
+                                      ("pc20k", dict(weighting=2)), ("pc20k", dict(fallback_on_vertex=1)),
+                                      ("flat", dict(fallback_on_vertex=1, weighting=1))])
+def test_prolongation_variants(name, opt):
+    """The weighting-ablation variants and the fallback-trigger variant, bit for bit."""
+    _say(f"[gpu] prolongation variant {name} {opt}")
+    prob = problem(name)
+    orc, gpu = both(prob, min_coarse_points=200, **opt)
+    compare_hierarchies(orc, gpu, f"{name} {opt}")
+    compare_solves(orc, gpu, prob, max_iters=300)
+
+
+def test_poisson_problem():
+    """The Poisson system of the comparisons, (L + 1e-6 M) x = M y."""
+    _say("[gpu] Poisson system, torus 96 x 80")
+    prob = synth.config_poisson(96, 80)
+    orc, gpu = both(prob, min_coarse_points=200)
+    compare_hierarchies(orc, gpu, "poisson")
+    # cond(A) ~ 1/eta: both solutions are within cond * tol of the exact one, not 1e-9 of each other
+    compare_solves(orc, gpu, prob, tol=1e-8, max_iters=300, x_rtol=1e-6)
 
 
 def test_config_icosphere_full():
