@@ -118,6 +118,32 @@ int gmg_solve(gmg_handle h, const double* b_dev, double* x_dev, double tol, int3
               void* stream, gmg_solve_info* info, double* residual_history);
 
 /*
+ * gmg_solve_pcg for nrhs right-hand sides on one hierarchy, processed in
+ * groups of 8 that share every launch: each matrix entry read serves the 8
+ * right-hand sides of a group, and the latency of each V-cycle phase is paid
+ * once per group.  Each right-hand side gets the arithmetic of gmg_solve_pcg
+ * except the order in which its dot products are summed.
+ *
+ *  B_dev, X_dev   float64 device arrays of nrhs x n values, right-hand side / solution q
+ *                 contiguous at offset q * n (X_dev: in = initial guesses, out = solutions)
+ *  infos          host array of nrhs gmg_solve_info: for right-hand side q the first
+ *                 iteration at which it met tol, converged, and its true relative residual
+ *  tol, max_iters, precision, stream: as for gmg_solve_pcg; a group iterates until all of its
+ *                 right-hand sides have converged (b = 0 gives x = 0)
+ * Returns GMG_OK, GMG_NOT_CONVERGED (some right-hand side missed tol), GMG_INVALID_ARGUMENT,
+ * GMG_NOT_SPD, GMG_OUT_OF_MEMORY or GMG_DEVICE_ERROR.
+ */
+int gmg_solve_pcg_batched(gmg_handle h, int32_t nrhs, const double* B_dev, double* X_dev, double tol,
+                          int32_t max_iters, int32_t precision, void* stream, gmg_solve_info* infos);
+
+/*
+ * gmg_precondition for nrhs vectors (layout as in gmg_solve_pcg_batched):
+ * Z_q = B R_q, one symmetric V-cycle from zero per vector.
+ */
+int gmg_precondition_batched(gmg_handle h, int32_t nrhs, const double* R_dev, double* Z_dev, int32_t precision,
+                             void* stream);
+
+/*
  * Replaces the values of A (same sparsity pattern as at the build) and
  * recomputes what depends on them: the Galerkin operators A_l of every
  * coarser level (Alg. 1), their solve layouts and the factorisation of the

@@ -27,7 +27,7 @@ EXPORTS = {
 
 # Symbols the library exports (checked on load).
 SYMBOLS = ["gmg_default_options", "gmg_build_hierarchy", "gmg_solve", "gmg_solve_pcg", "gmg_precondition",
-           "gmg_update_matrix", "gmg_pattern_outer", "gmg_free", "gmg_status_string", "gmg_last_error",
+           "gmg_update_matrix", "gmg_pattern_outer", "gmg_solve_pcg_batched", "gmg_precondition_batched", "gmg_free", "gmg_status_string", "gmg_last_error",
            "gmg_num_levels", "gmg_level_sizes", "gmg_export_level", "gmg_timer_start", "gmg_timer_stop"]
 
 # gmg_precision
@@ -75,6 +75,8 @@ def library():
     L.gmg_solve_pcg.argtypes = [P, P, P, ctypes.c_double, I32, I32, P, ctypes.POINTER(SolveInfo), P]
     L.gmg_precondition.argtypes = [P, P, P, I32, P]
     L.gmg_update_matrix.argtypes = [P, P, P]
+    L.gmg_solve_pcg_batched.argtypes = [P, I32, P, P, ctypes.c_double, I32, I32, P, ctypes.POINTER(SolveInfo)]
+    L.gmg_precondition_batched.argtypes = [P, I32, P, P, I32, P]
     L.gmg_pattern_outer.argtypes = [I64, P, P, P, P, ctypes.c_double, P, P]
     L.gmg_free.argtypes = [P]
     L.gmg_free.restype = None
@@ -242,6 +244,34 @@ class Hierarchy:
             raise _err(st)
         return z
 
+
+    def solve_pcg_batched(self, B, X=None, tol=1e-8, max_iters=100, precision="f32", stream=None):
+        """gmg_solve_pcg_batched: B, X of shape (nrhs, n).  Returns (X, [SolveInfo], status)."""
+        import torch
+        nrhs = int(B.shape[0])
+        pb = _dev(B, torch.float64, (nrhs, self.n), "B")
+        if X is None:
+            X = torch.zeros_like(B)
+        px = _dev(X, torch.float64, (nrhs, self.n), "X")
+        infos = (SolveInfo * max(nrhs, 1))()
+        st = library().gmg_solve_pcg_batched(self._h, nrhs, pb, px, float(tol), int(max_iters), PRECISION[precision],
+                                             _stream_ptr(stream), infos)
+        if st < 0:
+            raise _err(st)
+        return X, list(infos)[:nrhs], st
+
+    def precondition_batched(self, R, Z=None, precision="f32", stream=None):
+        """gmg_precondition_batched: Z_q = B R_q for R of shape (nrhs, n)."""
+        import torch
+        nrhs = int(R.shape[0])
+        pr = _dev(R, torch.float64, (nrhs, self.n), "R")
+        if Z is None:
+            Z = torch.empty_like(R)
+        pz = _dev(Z, torch.float64, (nrhs, self.n), "Z")
+        st = library().gmg_precondition_batched(self._h, nrhs, pr, pz, PRECISION[precision], _stream_ptr(stream))
+        if st:
+            raise _err(st)
+        return Z
 
     def update_matrix(self, val, stream=None):
         """gmg_update_matrix: new values of A (same pattern); Galerkin operators and the

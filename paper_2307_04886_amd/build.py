@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgmg.so")
-SOURCES = ["prims.hip", "setup_graph.hip", "setup_prolong.hip", "setup_solve.hip", "solve.hip", "krylov.hip",
+SOURCES = ["prims.hip", "setup_graph.hip", "setup_prolong.hip", "setup_solve.hip", "solve.hip", "krylov.hip", "multi.hip",
            "api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

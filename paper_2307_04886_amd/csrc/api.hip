@@ -243,6 +243,8 @@ void release(H* h) {
   for (int p = 0; p < 2; ++p) {
     if (h->kry.exec[p]) (void)hipGraphExecDestroy(h->kry.exec[p]);
     if (h->kry.graph[p]) (void)hipGraphDestroy(h->kry.graph[p]);
+    if (h->bat.exec[p]) (void)hipGraphExecDestroy(h->bat.exec[p]);
+    if (h->bat.graph[p]) (void)hipGraphDestroy(h->bat.graph[p]);
   }
   mark("release: graphs");
   if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
@@ -726,6 +728,226 @@ int pcg(Handle& h, double nb, double tol, int32_t max_iters, hipStream_t s, int3
   return status;
 }
 
+// ------------------------------------------------------------------ batched right-hand sides
+// The single-workgroup tail of a batched cycle: as make_tail, iterates of
+// n * kBatch elements.
+template <class V>
+void make_tail_batched(const Handle& h, Cycle<V>& c) {
+  make_tail(h, c);
+  TailDescT<V>& t = c.tail;
+  const int32_t cap = kTailLdsBytes / (int32_t)sizeof(V);
+  t.lds_elems = 0;
+  for (int l = 0; l < t.nlev; ++l) {
+    const int32_t e = t.lv[l].n * kBatch;
+    if (t.lds_elems + e <= cap) {
+      t.lds_off[l] = t.lds_elems;
+      t.lds_elems += e;
+    } else {
+      t.lds_off[l] = -1;
+    }
+  }
+}
+
+void bat_alloc(Handle& h) {
+  Batch& k = h.bat;
+  if (k.x) return;
+  const size_t nk = (size_t)h.L[0].n * kBatch;
+  for (double** v : {&k.x, &k.b, &k.r, &k.r_old, &k.p, &k.q, &k.z}) *v = (double*)dalloc(h, nk * 8);
+  k.part = (double*)dalloc(h, (size_t)3 * kNormBlocks * kBatch * 8);
+  k.scal = (double*)dalloc(h, (size_t)KS_COUNT * kBatch * 8);
+}
+
+// Views of a batched cycle: the matrices of the single-vector cycle of the same
+// precision, iterates of n * kBatch elements.  Level 0 reads the CG residual
+// (rounded to float for the float cycle) and writes z.
+template <class V>
+void bat_prepare(Handle& h, Cycle<V>& c, const Cycle<V>& single) {
+  const int nl = (int)h.L.size();
+  c.v = single.v;
+  c.symmetric = true;
+  for (int l = 0; l < nl; ++l) {
+    const size_t nk = (size_t)c.v[l].n * kBatch;
+    c.v[l].x = (V*)dalloc(h, nk * sizeof(V));
+    c.v[l].b = (V*)dalloc(h, nk * sizeof(V));
+    c.v[l].r = (V*)dalloc(h, nk * sizeof(V));
+  }
+  if (std::is_same<V, double>::value) {
+    c.v[0].b = (V*)h.bat.r;
+    c.v[0].x = (V*)h.bat.z;
+  }
+  make_tail_batched(h, c);
+}
+
+template <class V>
+Cycle<V>& bat_cycle(Handle& h);
+template <>
+Cycle<double>& bat_cycle<double>(Handle& h) { return h.bat.c64; }
+template <>
+Cycle<float>& bat_cycle<float>(Handle& h) { return h.bat.c32; }
+
+template <class V>
+Cycle<V>& bat_ready(Handle& h) {
+  const int prec = std::is_same<V, float>::value ? 1 : 0;
+  bat_alloc(h);
+  Cycle<V>& single = kry_ready<V>(h);                // matrices of that precision
+  Cycle<V>& c = bat_cycle<V>(h);
+  if (!h.bat.ready[prec]) {
+    bat_prepare(h, c, single);
+    h.bat.ready[prec] = true;
+  }
+  return c;
+}
+
+// The symmetric V-cycle on kBatch right-hand sides (each gets the arithmetic
+// of vcycle() on a single one).
+template <class V>
+void mvcycle(Handle& h, const Cycle<V>& c, size_t l, hipStream_t s) {
+  const LevelViewT<V>& v = c.v[l];
+  if ((int)l == h.tail_start) {
+    if (c.tail.nlev == 1) mcoarse(h.cinv, v, s); else mtail(c.tail, s);
+    return;
+  }
+  const LevelViewT<V>& cv = c.v[l + 1];
+  const Level& lv = h.L[l];
+  for (int k = 0; k < h.opt.nu_pre; ++k) mgs_sweep(v, lv, s, false);
+  mresidual(v, s);
+  mrestrict(v, cv, s);
+  fill_zero(cv.x, (int64_t)cv.n * kBatch, s);
+  mvcycle(h, c, l + 1, s);
+  mprolong(v, cv, s);
+  for (int k = 0; k < h.opt.nu_post; ++k) mgs_sweep(v, lv, s, c.symmetric);
+}
+
+template <class V>
+void bat_precondition(Handle& h, const Cycle<V>& c, hipStream_t s) {
+  const int64_t nk = h.L[0].n * kBatch;
+  if (std::is_same<V, float>::value) to_f32(h.bat.r, (float*)c.v[0].b, nk, s);
+  fill_zero(c.v[0].x, nk, s);
+  mvcycle(h, c, 0, s);
+}
+
+template <class V>
+void bat_iteration(Handle& h, const Cycle<V>& c, hipStream_t s) {
+  bat_precondition(h, c, s);
+  mkry_direction<V>(h.bat, c.v[0].x, h.L[0].n, s);
+  mkry_step(h.bat, h.L[0], h.flags, s);
+}
+
+template <class V>
+void bat_capture(Handle& h, const Cycle<V>& c) {
+  const int prec = std::is_same<V, float>::value ? 1 : 0;
+  Batch& k = h.bat;
+  if (k.exec[prec] || k.graph_failed[prec]) return;
+  if (std::getenv("GMG_DISABLE_GRAPHS")) {
+    k.graph_failed[prec] = true;
+    return;
+  }
+  if (!h.cap_stream && hipStreamCreateWithFlags(&h.cap_stream, hipStreamNonBlocking) != hipSuccess) {
+    k.graph_failed[prec] = true;
+    (void)hipGetLastError();
+    return;
+  }
+  const int saved = KernelTimer::active;
+  KernelTimer::active = -1;
+  bool ok = hipStreamBeginCapture(h.cap_stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+  if (ok) {
+    bat_iteration(h, c, h.cap_stream);
+    ok = hipStreamEndCapture(h.cap_stream, &k.graph[prec]) == hipSuccess && k.graph[prec];
+  }
+  KernelTimer::active = saved;
+  if (ok) ok = hipGraphInstantiate(&k.exec[prec], k.graph[prec], nullptr, nullptr, 0) == hipSuccess;
+  if (!ok) {
+    (void)hipGetLastError();
+    if (k.graph[prec]) (void)hipGraphDestroy(k.graph[prec]);
+    k.graph[prec] = nullptr;
+    k.exec[prec] = nullptr;
+    k.graph_failed[prec] = true;
+  }
+}
+
+// Reads kBatch doubles (and optionally the flags) with one synchronisation.
+void read_batch(Handle& h, const double* src, double* dst, int32_t* flags_out) {
+  int64_t v[kBatch + 1];
+  ScalarRead rd[kBatch + 1];
+  for (int q = 0; q < kBatch; ++q) rd[q] = {src + q, 8, &v[q]};
+  rd[kBatch] = {h.flags, 4, &v[kBatch]};
+  read_scalars(h, rd, kBatch + 1);
+  for (int q = 0; q < kBatch; ++q) std::memcpy(&dst[q], &v[q], 8);
+  if (flags_out) *flags_out = (int32_t)v[kBatch];
+}
+
+// CG on one group of nq <= kBatch right-hand sides already in h.bat.b / h.bat.x.
+// Iterates until every right-hand side with b != 0 meets tol by its recursive
+// residual and then by its true residual (true residuals that fail replace the
+// recursive ones and the iteration goes on).
+template <class V>
+int pcg_batched(Handle& h, int nq, double tol, int32_t max_iters, hipStream_t s, gmg_solve_info* infos) {
+  Cycle<V>& c = bat_ready<V>(h);
+  const int prec = std::is_same<V, float>::value ? 1 : 0;
+  Batch& k = h.bat;
+  const Level& l0 = h.L[0];
+  const int64_t n = l0.n;
+  double nb[kBatch], rel[kBatch], norm[kBatch];
+  int32_t flags = 0;
+  mnorms(k.b, n, k.part, k.scal + KS_BNORM * kBatch, s);
+  read_batch(h, k.scal + KS_BNORM * kBatch, nb, &flags);
+  if (flags & F_INVALID) throw Error{GMG_INVALID_ARGUMENT, "non-finite b or x"};
+  unsigned zero = 0;
+  for (int q = 0; q < kBatch; ++q)
+    if (q >= nq || nb[q] == 0.0) zero |= 1u << q;
+  if (zero) mzero_columns(k.x, n, zero, s);            // b = 0 (or padding): x = 0
+  int32_t first[kBatch];
+  for (int q = 0; q < kBatch; ++q) first[q] = (zero >> q) & 1u ? 0 : -1;
+  auto true_residuals = [&]() {
+    mresidual_norm(k, l0, k.scal + KS_NORM * kBatch, s);
+    read_batch(h, k.scal + KS_NORM * kBatch, norm, nullptr);
+    bool all = true;
+    for (int q = 0; q < kBatch; ++q) {
+      rel[q] = (zero >> q) & 1u ? 0.0 : norm[q] / nb[q];
+      all = all && rel[q] <= tol;
+    }
+    return all;
+  };
+  int32_t it = 0;
+  int status = GMG_OK;
+  if (!true_residuals()) {
+    mkry_init(k, n, s);
+    bat_capture(h, c);
+    status = GMG_NOT_CONVERGED;
+    while (it < max_iters) {
+      if (k.exec[prec])
+        check_hip(hipGraphLaunch(k.exec[prec], s), "graph launch");
+      else
+        bat_iteration(h, c, s);
+      read_batch(h, k.scal + KS_NORM * kBatch, norm, &flags);
+      ++it;
+      if (flags & F_NOT_SPD) throw Error{GMG_NOT_SPD, "CG: non-positive curvature (A or the cycle not SPD)"};
+      bool all = true;
+      for (int q = 0; q < kBatch; ++q) {
+        if ((zero >> q) & 1u) continue;
+        const double r = norm[q] / nb[q];
+        if (r <= tol && first[q] < 0) first[q] = it;
+        all = all && r <= tol;
+      }
+      if (all) {
+        if (true_residuals()) {
+          status = GMG_OK;
+          break;
+        }
+        for (int q = 0; q < kBatch; ++q)
+          if (rel[q] > tol) first[q] = -1;
+      }
+    }
+    if (status != GMG_OK) true_residuals();
+  }
+  for (int q = 0; q < nq; ++q) {
+    infos[q].iterations = first[q] >= 0 ? first[q] : it;
+    infos[q].converged = rel[q] <= tol;
+    infos[q].rel_residual = rel[q];
+  }
+  return status;
+}
+
 const char* status_text(int st) {
   switch (st) {
     case GMG_OK: return "ok";
@@ -1022,6 +1244,87 @@ int gmg_pattern_outer(int64_t n, const int32_t* rowptr_dev, const int32_t* col_d
     return e.status;
   }
   return GMG_OK;
+}
+
+int gmg_solve_pcg_batched(gmg_handle hh, int32_t nrhs, const double* B_dev, double* X_dev, double tol,
+                          int32_t max_iters, int32_t precision, void* stream, gmg_solve_info* infos) {
+  set_error("");
+  Handle* h = hh;
+  if (!h || nrhs < 0 || (nrhs > 0 && (!B_dev || !X_dev || !infos)) || max_iters < 1 || !(tol >= 0.0) ||
+      (precision != GMG_PRECISION_F64 && precision != GMG_PRECISION_F32)) {
+    set_error("invalid batched solve arguments");
+    return GMG_INVALID_ARGUMENT;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  hipStream_t saved = h->stream;
+  h->stream = s;
+  int status = GMG_OK;
+  try {
+    Level& l0 = h->L[0];
+    const int64_t n = l0.n;
+    check_hip(hipMemsetAsync(h->flags, 0, 4, s), "memset");
+    check_finite(B_dev, n * nrhs, h->flags, s);
+    check_finite(X_dev, n * nrhs, h->flags, s);
+    bat_alloc(*h);
+    for (int g = 0; g < nrhs; g += kBatch) {
+      const int nq = std::min(kBatch, nrhs - g);
+      mgather(l0.perm, B_dev + (int64_t)g * n, n, nq, h->bat.b, s);
+      mgather(l0.perm, X_dev + (int64_t)g * n, n, nq, h->bat.x, s);
+      const int st = precision == GMG_PRECISION_F32
+                         ? pcg_batched<float>(*h, nq, tol, max_iters, s, infos + g)
+                         : pcg_batched<double>(*h, nq, tol, max_iters, s, infos + g);
+      mscatter(l0.perm, (const double*)h->bat.x, n, nq, X_dev + (int64_t)g * n, s);
+      if (st != GMG_OK) status = st;
+    }
+    sync(s, "batched solve");
+  } catch (const Error& e) {
+    set_error(e.msg);
+    status = e.status;
+  }
+  h->stream = saved;
+  return status;
+}
+
+int gmg_precondition_batched(gmg_handle hh, int32_t nrhs, const double* R_dev, double* Z_dev, int32_t precision,
+                             void* stream) {
+  set_error("");
+  Handle* h = hh;
+  if (!h || nrhs < 0 || (nrhs > 0 && (!R_dev || !Z_dev)) ||
+      (precision != GMG_PRECISION_F64 && precision != GMG_PRECISION_F32)) {
+    set_error("invalid batched preconditioner arguments");
+    return GMG_INVALID_ARGUMENT;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  hipStream_t saved = h->stream;
+  h->stream = s;
+  int status = GMG_OK;
+  try {
+    Level& l0 = h->L[0];
+    const int64_t n = l0.n;
+    check_hip(hipMemsetAsync(h->flags, 0, 4, s), "memset");
+    check_finite(R_dev, n * nrhs, h->flags, s);
+    if ((int32_t)read_i64(*h, h->flags, 4) & F_INVALID) throw Error{GMG_INVALID_ARGUMENT, "non-finite r"};
+    bat_alloc(*h);
+    for (int g = 0; g < nrhs; g += kBatch) {
+      const int nq = std::min(kBatch, nrhs - g);
+      mgather(l0.perm, R_dev + (int64_t)g * n, n, nq, h->bat.r, s);
+      if (precision == GMG_PRECISION_F32) {
+        Cycle<float>& c = bat_ready<float>(*h);
+        bat_precondition(*h, c, s);
+        mscatter(l0.perm, (const float*)c.v[0].x, n, nq, Z_dev + (int64_t)g * n, s);
+      } else {
+        Cycle<double>& c = bat_ready<double>(*h);
+        bat_precondition(*h, c, s);
+        mscatter(l0.perm, (const double*)c.v[0].x, n, nq, Z_dev + (int64_t)g * n, s);
+      }
+    }
+    sync(s, "batched preconditioner");
+  } catch (const Error& e) {
+    set_error(e.msg);
+    status = e.status;
+  }
+  h->stream = saved;
+  return status;
 }
 
 void gmg_free(gmg_handle h) { release(h); }

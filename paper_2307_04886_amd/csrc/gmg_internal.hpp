@@ -197,7 +197,28 @@ struct Krylov {
   hipGraphExec_t exec[2] = {nullptr, nullptr};
   bool graph_failed[2] = {false, false};
 };
-enum : int { KS_RHO = 0, KS_BETA = 1, KS_ALPHA = 2, KS_NORM = 3, KS_COUNT = 8 };
+enum : int { KS_RHO = 0, KS_BETA = 1, KS_ALPHA = 2, KS_NORM = 3, KS_BNORM = 4, KS_COUNT = 8 };
+
+// The same CG for kBatch right-hand sides at once; vectors interleaved,
+// entry (i, q) at i * kBatch + q.
+constexpr int kBatch = 8;
+struct Batch {
+  double* x = nullptr;                  // level 0, colour-sorted numbering, [n][kBatch]
+  double* b = nullptr;
+  double* r = nullptr;
+  double* r_old = nullptr;
+  double* p = nullptr;
+  double* q = nullptr;
+  double* z = nullptr;
+  double* part = nullptr;               // 3 x kNormBlocks x kBatch partial sums
+  double* scal = nullptr;               // KS_COUNT x kBatch device scalars
+  bool ready[2] = {false, false};
+  Cycle<double> c64;                    // cycle views with [n][kBatch] iterates
+  Cycle<float> c32;
+  hipGraph_t graph[2] = {nullptr, nullptr};
+  hipGraphExec_t exec[2] = {nullptr, nullptr};
+  bool graph_failed[2] = {false, false};
+};
 
 struct Handle {
   int device = 0;
@@ -213,6 +234,7 @@ struct Handle {
   int tail_start = -1;                  // first level solved by the single-workgroup tail kernel
   Cycle<double> plain;                  // the V-cycle of the solve (Alg. 2)
   Krylov kry;
+  Batch bat;
   // one V-cycle plus the convergence residual, captured once and replayed
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
@@ -326,6 +348,29 @@ void finish_norm(const double* partials, double* out, hipStream_t s);
 void check_finite(const double* v, int64_t n, int32_t* flag, hipStream_t s);
 void pattern_outer(int64_t n, const int32_t* rp, const int32_t* col, const double* u, const double* v,
                    double scale, double* out, hipStream_t s);
+// batched right-hand sides (multi.hip): vectors [n][kBatch]
+template <class V>
+void mgs_sweep(const LevelViewT<V>& v, const Level& lv, hipStream_t s, bool descending);
+template <class V>
+void mresidual(const LevelViewT<V>& v, hipStream_t s);
+template <class V>
+void mrestrict(const LevelViewT<V>& v, const LevelViewT<V>& c, hipStream_t s);
+template <class V>
+void mprolong(const LevelViewT<V>& v, const LevelViewT<V>& c, hipStream_t s);
+template <class V>
+void mcoarse(const double* cinv, const LevelViewT<V>& c, hipStream_t s);
+template <class V>
+void mtail(const TailDescT<V>& d, hipStream_t s);
+void mkry_init(Batch& k, int64_t n, hipStream_t s);
+template <class V>
+void mkry_direction(Batch& k, const V* z, int64_t n, hipStream_t s);
+void mkry_step(Batch& k, const Level& l0, int32_t* flags, hipStream_t s);
+void mresidual_norm(Batch& k, const Level& l0, double* out, hipStream_t s);
+void mnorms(const double* v, int64_t n, double* part, double* out, hipStream_t s);
+void mgather(const int32_t* perm, const double* src, int64_t n, int nq, double* dst, hipStream_t s);
+template <class V>
+void mscatter(const int32_t* perm, const V* src, int64_t n, int nq, double* dst, hipStream_t s);
+void mzero_columns(double* x, int64_t n, unsigned mask, hipStream_t s);
 // preconditioned CG steps (level 0, double; z in V)
 void kry_init(Krylov& k, int64_t n, hipStream_t s);
 template <class V>

@@ -22,7 +22,7 @@ def _mesh_problem(name, pts, faces, alpha, seed, eta=None):
     else:                                             # Poisson (L + eta M) x = M y
         indptr, indices, data = assemble(off, diag, mass, 1.0, edges, mass_weight=eta)
     y = uniform(seed, "rhs", pts.shape[0], -1.0, 1.0)
-    return Problem(name, np.ascontiguousarray(pts), edges, indptr, indices, data, mass * y)
+    return Problem(name, np.ascontiguousarray(pts), edges, indptr, indices, data, mass * y, mass)
 
 
 def config_icosphere(subdivisions=5, seed=0, noise=0.01, alpha=1e-3):
@@ -47,7 +47,7 @@ def config_bumpy_sphere(n=2_000_000, k=8, seed=0, alpha=1e-2):
     off, diag, mass = gaussian_knn_laplacian(pts, edges, kd)
     indptr, indices, data = assemble(off, diag, mass, alpha, edges)
     y = uniform(seed, "rhs", n, -1.0, 1.0)
-    return Problem(f"bumpysphere{n}k{k}", pts, edges, indptr, indices, data, mass * y)
+    return Problem(f"bumpysphere{n}k{k}", pts, edges, indptr, indices, data, mass * y, mass)
 
 
 def config_poisson(nu=96, nv=80, seed=0, eta=1e-6, jitter=0.1):
@@ -70,6 +70,29 @@ def config_adjoint(nu=707, nv=707, seed=0, alpha=1e-3):
     a_idx = np.minimum((u[:32] * prob.nnz).astype(np.int64), prob.nnz - 1)
     b_idx = np.minimum((u[32:] * prob.n).astype(np.int64), prob.n - 1)
     return prob, target, a_idx, b_idx
+
+
+def config_batched(count=64, nrhs=8, lo=5_000, hi=200_000, seed=0):
+    """Many meshes of uneven size, several right-hand sides each: vertex counts
+    log-uniform in [lo, hi] (seeded); even entries are jittered tori whose grid
+    is chosen to hit the count, odd entries jittered icospheres with the
+    subdivision level nearest to it (in log scale).  (M + 1e-3 L) systems;
+    returns a list of (Problem, B) with B of shape (nrhs, n), B_q = M y_q,
+    y_q ~ U[-1, 1]."""
+    u = uniform(seed, "sizes", count, 0.0, 1.0)
+    sizes = np.exp(np.log(lo) + u * (np.log(hi) - np.log(lo)))
+    out = []
+    for i, target in enumerate(sizes):
+        if i % 2 == 0:
+            nu = max(8, int(round(np.sqrt(target * 1.6))))
+            nv = max(8, int(round(target / nu)))
+            prob = config_torus(nu, nv, seed=seed + i)
+        else:
+            sub = int(np.argmin([abs(np.log((10 * 4 ** k + 2) / target)) for k in range(2, 8)])) + 2
+            prob = config_icosphere(sub, seed=seed + i)
+        ys = uniform(seed + i, "noise", nrhs * prob.n, -1.0, 1.0).reshape(nrhs, prob.n)
+        out.append((prob, prob.mass[None, :] * ys))
+    return out
 
 
 def small_icosphere(subdivisions=3, seed=0):
@@ -98,4 +121,5 @@ CONFIGS = {
     "torus1024": config_torus,
     "bumpysphere2m": config_bumpy_sphere,
     "adjoint_torus707": config_adjoint,
+    "batched64": config_batched,
 }

@@ -24,6 +24,7 @@ class Problem:
     indices: np.ndarray
     data: np.ndarray
     rhs: np.ndarray
+    mass: np.ndarray = None       # the lumped mass diagonal M (right-hand sides are M y)
 
     @property
     def n(self):

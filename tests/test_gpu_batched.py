@@ -1,0 +1,128 @@
+"""GPU parity of the batched form (8 right-hand sides per launch) through the
+C ABI: the batched symmetric V-cycle against the oracle's cycle right-hand
+side by right-hand side, and the batched CG against the oracle's CG per
+right-hand side (tolerance model of test_gpu_pcg: the dot products are
+summed in another order).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.conftest import problem
+from tests.test_gpu_pcg import PREC, both
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rhs_block(prob, nrhs, seed=3):
+    y = synth.uniform(seed, "noise", nrhs * prob.n, -1.0, 1.0).reshape(nrhs, prob.n)
+    return np.ascontiguousarray(prob.mass[None, :] * y) if prob.mass is not None else y
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("name,minc,nrhs", [("ico4", 100, 8), ("torus96", 200, 3), ("pc20k", 500, 11),
+                                            ("ico3", 100, 1)])
+def test_batched_preconditioner_parity(name, minc, nrhs, precision):
+    _say(f"[gpu] batched preconditioner {precision} {name} nrhs={nrhs}")
+    prob = problem(name)
+    orc, gpu = both(prob, min_coarse_points=minc)
+    R = np.random.default_rng(8).uniform(-1, 1, (nrhs, prob.n))
+    Z = gpu.precondition_batched(torch.from_numpy(R).cuda(), precision=precision).cpu().numpy()
+    single = [gpu.precondition(torch.from_numpy(R[q].copy()).cuda(), precision=precision).cpu().numpy()
+              for q in range(nrhs)]
+    for q in range(nrhs):
+        zo = orc.precondition(R[q], PREC[precision])
+        rel = np.linalg.norm(Z[q] - zo) / np.linalg.norm(zo)
+        assert rel <= (1e-11 if precision == "f64" else 1e-6), (q, rel)
+        # each right-hand side gets the single-vector arithmetic
+        assert np.array_equal(Z[q], single[q]), q
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("name,minc,nrhs", [("ico4", 100, 8), ("torus96", 200, 5), ("pc20k", 500, 10)])
+def test_batched_pcg_parity(name, minc, nrhs, precision):
+    _say(f"[gpu] batched CG {precision} {name} nrhs={nrhs}")
+    prob = problem(name)
+    orc, gpu = both(prob, min_coarse_points=minc)
+    B = rhs_block(prob, nrhs)
+    tol = 1e-8
+    X, infos, st = gpu.solve_pcg_batched(torch.from_numpy(B).cuda(), tol=tol, precision=precision)
+    assert st == 0
+    X = X.cpu().numpy()
+    A = prob.matrix()
+    u = 2.0 ** -53 if precision == "f64" else 2.0 ** -24
+    for q in range(nrhs):
+        x_o, it_o, hist_o, st_o, fin_o = orc.solve_pcg(B[q], tol=tol, precision=PREC[precision])
+        assert st_o == 0
+        res = np.linalg.norm(B[q] - A @ X[q]) / np.linalg.norm(B[q])
+        assert res <= tol * (1 + 1e-9), (q, res)
+        assert abs(res - infos[q].rel_residual) <= 1e-6 * res
+        bound = 1e-6 * hist_o[-1] + 64 * u * len(hist_o) * (hist_o[-2] if len(hist_o) > 1 else 1.0)
+        near = abs(hist_o[-1] - tol) <= bound
+        assert infos[q].iterations == it_o or (near and abs(infos[q].iterations - it_o) == 1), \
+            (q, infos[q].iterations, it_o)
+        assert np.linalg.norm(X[q] - x_o) <= 1e-6 * np.linalg.norm(x_o), q
+
+
+def test_batched_edge_cases():
+    _say("[gpu] batched CG edge cases")
+    g = pytest.importorskip("paper_2307_04886_amd")
+    prob = problem("ico4")
+    orc, gpu = both(prob, min_coarse_points=100)
+    n = prob.n
+    B = rhs_block(prob, 4)
+    B[2] = 0.0                                                   # a zero right-hand side
+    X0 = np.random.default_rng(1).uniform(-1, 1, (4, n))         # non-zero initial guesses
+    X, infos, st = gpu.solve_pcg_batched(torch.from_numpy(B).cuda(), torch.from_numpy(X0).cuda(), precision="f32")
+    assert st == 0
+    X = X.cpu().numpy()
+    assert not X[2].any() and infos[2].iterations == 0
+    A = prob.matrix()
+    for q in (0, 1, 3):
+        assert np.linalg.norm(B[q] - A @ X[q]) <= 1e-8 * np.linalg.norm(B[q])
+    # no right-hand sides
+    X, infos, st = gpu.solve_pcg_batched(torch.zeros((0, n), dtype=torch.float64).cuda())
+    assert st == 0 and infos == []
+    # iteration cap
+    X, infos, st = gpu.solve_pcg_batched(torch.from_numpy(B).cuda(), tol=1e-15, max_iters=2)
+    assert st == 1
+    bad = torch.from_numpy(B).cuda()
+    bad[1, 7] = float("inf")
+    with pytest.raises(g.GMGError) as e:
+        gpu.solve_pcg_batched(bad)
+    assert e.value.status == -1
+
+
+def test_batched_workload_sample():
+    """Four meshes of the many-mesh workload, 8 right-hand sides each, float
+    preconditioner, 1e-8: every solution meets the tolerance; the first mesh
+    against the oracle."""
+    _say("[gpu] batched workload sample")
+    import paper_2307_04886_amd as g
+    from paper_2307_04886_amd.binding import from_problem
+    g.library()
+    batch = synth.config_batched(count=4)
+    for i, (prob, B) in enumerate(batch):
+        h, _ = from_problem(prob)
+        X, infos, st = h.solve_pcg_batched(torch.from_numpy(B).cuda(), tol=1e-8, precision="f32")
+        assert st == 0
+        X = X.cpu().numpy()
+        A = prob.matrix()
+        for q in range(B.shape[0]):
+            assert np.linalg.norm(B[q] - A @ X[q]) <= 1e-8 * (1 + 1e-9) * np.linalg.norm(B[q])
+        if i == 0:
+            orc = oracle.Hierarchy.from_problem(prob)
+            for q in range(0, B.shape[0], 3):
+                x_o = orc.solve_pcg(B[q], tol=1e-8, precision=1)[0]
+                assert np.linalg.norm(X[q] - x_o) <= 1e-6 * np.linalg.norm(x_o)
+        _say(f"[gpu]   mesh {i}: n={prob.n}, CG iterations {[inf.iterations for inf in infos]}")
