@@ -281,12 +281,16 @@ int gmg_export_level(gmg_handle h, int32_t level, int32_t what, void* host_dst, 
  * row length, result).  Process-wide: one timing session at a time.
  *
  *  kernel              GMG_TIMER_GS_FINEST: one colour of a Gauss-Seidel sweep on level 0;
- *                      GMG_TIMER_RESIDUAL_FINEST: residual + norm partials on level 0
+ *                      GMG_TIMER_RESIDUAL_FINEST: residual + norm partials on level 0;
+ *                      GMG_TIMER_GS_GALERKIN: one colour of a sweep on a Galerkin level
+ *                      (solved by separate launches, i.e. above the single-workgroup tail)
  *  expected_launches   events to pre-create (more are created on demand)
- * gmg_timer_stop waits for the recorded events and returns the summed kernel
- * time in milliseconds, the number of timed launches and their bytes.
+ * The timed launches of a solve are issued directly instead of from its
+ * captured graph.  gmg_timer_stop waits for the recorded events and returns
+ * the summed kernel time in milliseconds, the number of timed launches and
+ * their bytes.
  */
-enum gmg_timer_kernel { GMG_TIMER_GS_FINEST = 0, GMG_TIMER_RESIDUAL_FINEST = 1 };
+enum gmg_timer_kernel { GMG_TIMER_GS_FINEST = 0, GMG_TIMER_RESIDUAL_FINEST = 1, GMG_TIMER_GS_GALERKIN = 2 };
 int gmg_timer_start(int32_t kernel, int32_t expected_launches);
 int gmg_timer_stop(double* total_ms, int64_t* launches, double* bytes);
 

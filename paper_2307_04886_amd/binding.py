@@ -34,7 +34,7 @@ SYMBOLS = ["gmg_default_options", "gmg_build_hierarchy", "gmg_solve", "gmg_solve
 PRECISION = {"f64": 0, "f32": 1}
 
 # kernel classes of gmg_timer_start
-TIMER_KERNELS = {"gs_finest": 0, "residual_finest": 1}
+TIMER_KERNELS = {"gs_finest": 0, "residual_finest": 1, "gs_galerkin": 2}
 
 
 class Options(ctypes.Structure):

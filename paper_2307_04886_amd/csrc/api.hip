@@ -448,7 +448,7 @@ void vcycle(Handle& h, const Cycle<V>& c, size_t l, hipStream_t s) {
   }
   const LevelViewT<V>& cv = c.v[l + 1];
   const Level& lv = h.L[l];
-  const bool timed = l == 0 && !c.symmetric;
+  const bool timed = !c.symmetric;            // the solve's cycle is the measured one
   for (int k = 0; k < h.opt.nu_pre; ++k) gs_sweep(v, lv, s, l == 0, false, timed);
   residual(v, s, l == 0);
   restrict_to(v, cv, s);
@@ -501,6 +501,7 @@ void capture_cycle(Handle& h) {
     h.graph_failed = true;
     return;
   }
+  if (KernelTimer::active == KernelTimer::GS_GALERKIN) return;   // those launches are inside the cycle
   if (!h.cap_stream && hipStreamCreateWithFlags(&h.cap_stream, hipStreamNonBlocking) != hipSuccess) {
     h.graph_failed = true;
     (void)hipGetLastError();

@@ -249,7 +249,7 @@ struct Handle {
 // The events are passed to hipExtLaunchKernelGGL, which has the dispatch
 // itself record them at the kernel's start and end.
 struct KernelTimer {
-  enum Kind { GS_FINEST = 0, RESIDUAL_FINEST = 1, KINDS = 2 };
+  enum Kind { GS_FINEST = 0, RESIDUAL_FINEST = 1, GS_GALERKIN = 2, KINDS = 3 };
   static int active;
   struct Scope {
     hipEvent_t start = nullptr, stop = nullptr;   // null unless this launch is timed

@@ -256,10 +256,12 @@ void gs_sweep(const LevelViewT<V>& v, const Level& lv, hipStream_t s, bool fines
       hipExtLaunchKernelGGL(k_gs_color_fine<V>, dim3(blocks_for(span)), dim3(kBlock), 0, s, t.start, t.stop, 0,
                             v.A, (const V*)v.diag, (const V*)v.b, v.x, r0, r1);
     } else {
+      KernelTimer::Scope t(timed ? (int)KernelTimer::GS_GALERKIN : -1, lv.color_bytes[c]);
       with_lanes(v.ra, [&](auto RC) {
         constexpr int R = decltype(RC)::value;
-        k_gs_color<R, V><<<blocks_for((int64_t)(r1 - r0) * R), kBlock, 0, s>>>(v.A, v.diag, v.b, v.x, r0, r1,
-                                                                                v.maxa);
+        const auto kern = k_gs_color<R, V>;
+        hipExtLaunchKernelGGL(kern, dim3(blocks_for((int64_t)(r1 - r0) * R)), dim3(kBlock), 0, s, t.start, t.stop,
+                              0, v.A, (const V*)v.diag, (const V*)v.b, v.x, r0, r1, v.maxa);
       });
     }
   }
