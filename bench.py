@@ -22,23 +22,30 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 
-# HBM bytes per launch from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE (scaled by a plain copy;
-# profiles/k_gs_color_fine_torus1024.md), valid only for the solve kernels they were taken on.
-TRAFFIC = {"gs_finest": {"bytes_per_launch": 30476802, "solve_src_sha256_16": "ae2bd73a3e8e2323"}}
+# HBM bytes per launch from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE, scaled by what the counters read
+# for a plain device copy (profiles/k_gs_color_*_torus1024.md); valid only for the kernel sources
+# they were taken on (sha256 prefix of solve.hip + rows.hpp).
+TRAFFIC = {"gs_finest": {"bytes_per_launch": 31668131, "src_sha256_16": "f72cdb1ffc1e21a9"},
+           "gs_galerkin": {"bytes_per_launch": 3549833, "src_sha256_16": "f72cdb1ffc1e21a9"}}
 
 KERNEL_NAMES = {"gs_finest": "k_gs_color_fine (one colour of a Gauss-Seidel sweep, level 0)",
                 "residual_finest": "k_residual_norm (residual + norm partials, level 0)",
                 "gs_galerkin": "k_gs_color<R> (one colour of a Gauss-Seidel sweep, Galerkin levels above the tail)"}
 
 
-def traffic_for(kind):
+def kernel_src_sha():
     import hashlib
+    h = hashlib.sha256()
+    for f in ("solve.hip", "rows.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_2307_04886_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(kind):
     rec = TRAFFIC.get(kind)
     if rec is None:
         return None
-    src = os.path.join(ROOT, "paper_2307_04886_amd", "csrc", "solve.hip")
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    return rec["bytes_per_launch"] if sha == rec["solve_src_sha256_16"] else None
+    return rec["bytes_per_launch"] if kernel_src_sha() == rec["src_sha256_16"] else None
 
 
 def main():
@@ -49,6 +56,8 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the many-mesh batched measurement")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the plain steps (and roofline passes): for profiler runs")
     ap.add_argument("--size", type=int, default=1024, help="torus grid size (default 1024)")
     ap.add_argument("--timer", default="auto", choices=["auto", "gs_finest", "gs_galerkin", "residual_finest", "none"],
                     help="kernel classes timed with HIP events for the roofline entries (auto: both Gauss-Seidel "
@@ -134,7 +143,7 @@ def main():
     # float (mixed precision): whole setup + solve per step, same tolerance
     forms = {}
     x_forms = {}
-    for form in ("pcg_f64", "pcg_f32"):
+    for form in () if args.headline_only else ("pcg_f64", "pcg_f32"):
         for _ in range(max(1, args.warmup)):
             step(form)
         torch.cuda.synchronize()
@@ -191,13 +200,13 @@ def main():
         "mixed_vs_fp64": dict(forms, note="double CG preconditioned by one symmetric V-cycle per iteration "
                                           "(f64: cycle in double, f32: cycle in float); whole setup + solve "
                                           "per step, same workload and tolerance"),
-        "split_ms": {"plain": split("plain"), "pcg_f32": split("pcg_f32")},
+        "split_ms": None if args.headline_only else {"plain": split("plain"), "pcg_f32": split("pcg_f32")},
     }
 
     # many meshes of uneven size with 8 right-hand sides each: every hierarchy built and every
     # right-hand side solved to the same tolerance; batched float-preconditioned CG on concurrent
     # streams against the plain double V-cycle solve of each right-hand side in turn
-    if not args.no_batched:
+    if not args.no_batched and not args.headline_only:
         from paper_2307_04886_amd.batch import solve_many
         batch = synth.config_batched()
         systems = []

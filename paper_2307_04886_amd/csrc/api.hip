@@ -452,7 +452,6 @@ void vcycle(Handle& h, const Cycle<V>& c, size_t l, hipStream_t s) {
   for (int k = 0; k < h.opt.nu_pre; ++k) gs_sweep(v, lv, s, l == 0, false, timed);
   residual(v, s, l == 0);
   restrict_to(v, cv, s);
-  fill_zero(cv.x, cv.n, s);
   vcycle(h, c, l + 1, s);
   prolong_correct(v, cv, s);
   for (int k = 0; k < h.opt.nu_post; ++k) gs_sweep(v, lv, s, l == 0, c.symmetric, timed);
@@ -463,7 +462,6 @@ void cycle_inner(Handle& h, hipStream_t s) {
   const Cycle<double>& c = h.plain;
   residual(c.v[0], s, true);
   restrict_to(c.v[0], c.v[1], s);
-  fill_zero(c.v[1].x, c.v[1].n, s);
   vcycle(h, c, 1, s);
   prolong_correct(c.v[0], c.v[1], s);
 }
@@ -813,7 +811,6 @@ void mvcycle(Handle& h, const Cycle<V>& c, size_t l, hipStream_t s) {
   for (int k = 0; k < h.opt.nu_pre; ++k) mgs_sweep(v, lv, s, false);
   mresidual(v, s);
   mrestrict(v, cv, s);
-  fill_zero(cv.x, (int64_t)cv.n * kBatch, s);
   mvcycle(h, c, l + 1, s);
   mprolong(v, cv, s);
   for (int k = 0; k < h.opt.nu_post; ++k) mgs_sweep(v, lv, s, c.symmetric);

@@ -67,10 +67,11 @@ __global__ void __launch_bounds__(kBlock) k_mresidual(Sell<V> A, const V* __rest
 
 template <class V>
 __global__ void __launch_bounds__(kBlock) k_mrestrict(Sell<V> T, const V* __restrict__ r, V* __restrict__ bc,
-                                                      int64_t nc) {
+                                                      V* __restrict__ xc, int64_t nc) {
   const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (t >= nc * K) return;
   bc[t] = row_sum_multi(T, (int32_t)(t / K), r, -1, (int)(t % K));
+  xc[t] = V(0);                                   // the coarse iterate starts from zero
 }
 
 template <class V>
@@ -402,7 +403,7 @@ void mresidual(const LevelViewT<V>& v, hipStream_t s) {
 
 template <class V>
 void mrestrict(const LevelViewT<V>& v, const LevelViewT<V>& c, hipStream_t s) {
-  k_mrestrict<V><<<blocks_for((int64_t)c.n * K), kBlock, 0, s>>>(v.T, v.r, c.b, c.n);
+  k_mrestrict<V><<<blocks_for((int64_t)c.n * K), kBlock, 0, s>>>(v.T, v.r, c.b, c.x, c.n);
 }
 
 template <class V>

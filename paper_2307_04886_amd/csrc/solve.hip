@@ -108,14 +108,18 @@ __global__ void __launch_bounds__(kBlock) k_finish_norm(const double* partials, 
   if (threadIdx.x == 0) *out = sqrt(t);
 }
 
-// b_c[I] = sum over row I of P^T (ascending original fine index) of P[i,I] r_i
+// b_c[I] = sum over row I of P^T (ascending original fine index) of P[i,I] r_i,
+// and the coarse iterate starts from zero: x_c[I] = 0
 template <int R, class V>
 __global__ void __launch_bounds__(kBlock) k_restrict(Sell<V> T, const V* __restrict__ r, V* __restrict__ bc,
-                                                     int64_t nc, int32_t maxlen) {
+                                                     V* __restrict__ xc, int64_t nc, int32_t maxlen) {
   const int64_t g = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / R;
   const bool active = g < nc;
   const V acc = row_sumR<R>(T, (int32_t)g, active, r, -1, maxlen);
-  if (active && (threadIdx.x & (R - 1)) == 0) bc[g] = acc;
+  if (active && (threadIdx.x & (R - 1)) == 0) {
+    bc[g] = acc;
+    xc[g] = V(0);
+  }
 }
 
 // x_i <- x_i + sum_t P[i, t] x_c[col_t]
@@ -283,7 +287,7 @@ template <class V>
 void restrict_to(const LevelViewT<V>& v, const LevelViewT<V>& c, hipStream_t s) {
   with_lanes(v.rt, [&](auto RC) {
     constexpr int R = decltype(RC)::value;
-    k_restrict<R, V><<<blocks_for((int64_t)c.n * R), kBlock, 0, s>>>(v.T, v.r, c.b, c.n, v.maxt);
+    k_restrict<R, V><<<blocks_for((int64_t)c.n * R), kBlock, 0, s>>>(v.T, v.r, c.b, c.x, c.n, v.maxt);
   });
 }
 
