@@ -57,6 +57,9 @@ typedef struct gmg_options {
   int32_t fallback_on_vertex;    /* 1: also use the inverse-distance fallback when the closest point of
                                     the best triangle is one of its vertices (default 0: edge and
                                     vertex projections are kept, Sec. 4.4) */
+  int32_t color_passes;          /* iterated-greedy recolouring passes after the first-fit colouring that
+                                    orders the multicolour Gauss-Seidel sweeps (3; 0 keeps the first
+                                    colouring; at most 64) */
 } gmg_options;
 
 /* Values of gmg_options.weighting. */

@@ -38,11 +38,13 @@ class Options(ctypes.Structure):
                 ("min_coarse_points", ctypes.c_int32), ("max_levels", ctypes.c_int32),
                 ("nu_pre", ctypes.c_int32), ("nu_post", ctypes.c_int32),
                 ("shift_coarse_points", ctypes.c_int32), ("sample_order", ctypes.c_int32),
-                ("seed", ctypes.c_uint64), ("weighting", ctypes.c_int32), ("fallback_on_vertex", ctypes.c_int32)]
+                ("seed", ctypes.c_uint64), ("weighting", ctypes.c_int32), ("fallback_on_vertex", ctypes.c_int32),
+                ("color_passes", ctypes.c_int32)]
 
 
 def default_options(**kw):
     o = Options(ctypes.sizeof(Options), 1.0 / 8.0, 1000, 32, 2, 2, 1, 0, 0)
+    o.color_passes = 3
     for k, v in kw.items():
         setattr(o, k, v)
     return o

@@ -54,6 +54,7 @@ struct Options {                 // field order mirrors the public options struc
   uint64_t seed;
   int32_t weighting;             // 0 barycentric (Sec. 4.4), 1 uniform, 2 inverse distance (Sec. 5.3)
   int32_t fallback_on_vertex;    // 1: a best projection onto a triangle vertex uses the fallback
+  int32_t color_passes;          // iterated-greedy passes after the first colouring (default 3)
 };
 
 enum Status { OK = 0, NOT_CONVERGED = 1, INVALID_ARGUMENT = -1, NOT_SPD = -4, DEGENERATE = -5 };
@@ -541,9 +542,26 @@ int galerkin(const Level& lv, Level& nx) {
 }
 
 // ---------------------------------------------------------------- Gauss-Seidel order
+// First-fit colour of v given the colours of the other vertices (-1: none yet).
+int32_t first_fit(const Level& lv, int32_t v, const std::vector<int32_t>& color, std::vector<char>& used) {
+  used.assign(lv.arp[v + 1] - lv.arp[v] + 1, 0);
+  for (int32_t e = lv.arp[v]; e < lv.arp[v + 1]; ++e) {
+    int32_t u = lv.acol[e];
+    if (u != v && color[u] >= 0 && color[u] < (int32_t)used.size()) used[color[u]] = 1;
+  }
+  int32_t c = 0;
+  while (used[c]) ++c;
+  return c;
+}
+
 // Multicolour ordering of A_l: first-fit greedy colouring in hashed key order
-// (equal to Jones-Plassmann colouring).  A Gauss-Seidel sweep then visits the
-// colours in ascending order.
+// (equal to Jones-Plassmann colouring), then o.color_passes passes of iterated
+// greedy colouring (Culberson): every vertex is coloured first-fit again, the
+// colour classes of the previous colouring visited from the highest colour
+// down.  The vertices of one class are not adjacent, so their order within
+// the class does not matter; a pass never needs more colours than the
+// colouring it starts from.  A Gauss-Seidel sweep then visits the colours in
+// ascending order.
 void colouring(Level& lv, int level, const Options& o) {
   int64_t n = lv.n;
   std::vector<std::pair<uint64_t, int32_t>> order(n);
@@ -555,15 +573,22 @@ void colouring(Level& lv, int level, const Options& o) {
   std::vector<char> used;
   for (auto& kv : order) {
     int32_t v = kv.second;
-    used.assign(lv.arp[v + 1] - lv.arp[v] + 1, 0);
-    for (int32_t e = lv.arp[v]; e < lv.arp[v + 1]; ++e) {
-      int32_t u = lv.acol[e];
-      if (u != v && lv.color[u] >= 0 && lv.color[u] < (int32_t)used.size()) used[lv.color[u]] = 1;
-    }
-    int32_t c = 0;
-    while (used[c]) ++c;
+    int32_t c = first_fit(lv, v, lv.color, used);
     lv.color[v] = c;
     lv.ncolors = std::max(lv.ncolors, c + 1);
+  }
+  for (int32_t p = 0; p < o.color_passes && lv.ncolors > 1; ++p) {
+    std::vector<std::vector<int32_t>> cls(lv.ncolors);
+    for (int64_t v = 0; v < n; ++v) cls[lv.color[v]].push_back((int32_t)v);
+    std::vector<int32_t> next(n, -1);
+    int32_t nc = 0;
+    for (int32_t c = lv.ncolors - 1; c >= 0; --c)
+      for (int32_t v : cls[c]) {
+        next[v] = first_fit(lv, v, next, used);
+        nc = std::max(nc, next[v] + 1);
+      }
+    lv.color.swap(next);
+    lv.ncolors = nc;
   }
   lv.color_ptr.assign(lv.ncolors + 1, 0);
   for (int64_t v = 0; v < n; ++v) lv.color_ptr[lv.color[v] + 1] += 1;
@@ -769,7 +794,8 @@ int check_options(const Options& o) {
   if (!(o.coarsening_ratio > 0.0 && o.coarsening_ratio < 1.0)) return INVALID_ARGUMENT;
   if (o.min_coarse_points < 1 || o.max_levels < 1 || o.nu_pre < 0 || o.nu_post < 0) return INVALID_ARGUMENT;
   if (o.sample_order != 0 && o.sample_order != 1) return INVALID_ARGUMENT;
-  if (o.weighting < 0 || o.weighting > 2 || (o.fallback_on_vertex != 0 && o.fallback_on_vertex != 1))
+  if (o.weighting < 0 || o.weighting > 2 || (o.fallback_on_vertex != 0 && o.fallback_on_vertex != 1) ||
+      o.color_passes < 0 || o.color_passes > 64)
     return INVALID_ARGUMENT;
   return OK;
 }

@@ -42,7 +42,8 @@ class Options(ctypes.Structure):
                 ("min_coarse_points", ctypes.c_int32), ("max_levels", ctypes.c_int32),
                 ("nu_pre", ctypes.c_int32), ("nu_post", ctypes.c_int32),
                 ("shift_coarse_points", ctypes.c_int32), ("sample_order", ctypes.c_int32),
-                ("seed", ctypes.c_uint64), ("weighting", ctypes.c_int32), ("fallback_on_vertex", ctypes.c_int32)]
+                ("seed", ctypes.c_uint64), ("weighting", ctypes.c_int32), ("fallback_on_vertex", ctypes.c_int32),
+                ("color_passes", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):

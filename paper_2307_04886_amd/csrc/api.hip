@@ -263,11 +263,11 @@ bool options_ok(const gmg_options& o) {
   return o.struct_size == (int32_t)sizeof(gmg_options) && o.coarsening_ratio > 0.0 &&
          o.coarsening_ratio < 1.0 && o.min_coarse_points >= 1 && o.max_levels >= 1 && o.nu_pre >= 0 &&
          o.nu_post >= 0 && (o.sample_order == 0 || o.sample_order == 1) && o.weighting >= 0 && o.weighting <= 2 &&
-         (o.fallback_on_vertex == 0 || o.fallback_on_vertex == 1);
+         (o.fallback_on_vertex == 0 || o.fallback_on_vertex == 1) && o.color_passes >= 0 && o.color_passes <= 64;
 }
 
-// The single-workgroup tail of a cycle: levels tail_start.. with their views,
-// iterates in LDS while they fit.
+// The single-workgroup tail of a cycle: levels tail_start.. with their views
+// and the LDS offsets of their arrays (batched layout: make_tail_batched).
 template <class V>
 void make_tail(const Handle& h, Cycle<V>& c) {
   const int nl = (int)h.L.size();
@@ -278,18 +278,26 @@ void make_tail(const Handle& h, Cycle<V>& c) {
   t.nu_post = h.opt.nu_post;
   t.descending_post = c.symmetric ? 1 : 0;
   t.cinv = h.cinv;
-  t.lds_elems = 0;
-  const int32_t cap = kTailLdsBytes / (int32_t)sizeof(V);
+  int64_t off = 0;
+  auto take = [&](int64_t bytes) {
+    const int32_t o = (int32_t)off;
+    off += (bytes + 15) & ~(int64_t)15;
+    return o;
+  };
   for (int l = h.tail_start; l < nl; ++l) {
     const LevelViewT<V>& v = c.v[l];
-    t.lv[l - h.tail_start] = v;
-    if (t.lds_elems + v.n <= cap) {
-      t.lds_off[l - h.tail_start] = t.lds_elems;
-      t.lds_elems += (int32_t)v.n;
-    } else {
-      t.lds_off[l - h.tail_start] = -1;
+    const int i = l - h.tail_start;
+    t.lv[i] = v;
+    const bool coarsest = l + 1 == nl;
+    t.o_x[i] = take(((int64_t)v.n + (coarsest ? 0 : 1)) * sizeof(V));
+    t.o_b[i] = take((int64_t)v.n * sizeof(V));
+    if (!coarsest) {
+      t.o_r[i] = take(((int64_t)v.n + 1) * sizeof(V));
+      t.o_c[i] = take((int64_t)v.ncolors * 16);
     }
   }
+  if (off > kTailLdsMax) throw Error{GMG_DEVICE_ERROR, "tail LDS layout exceeds its budget"};
+  t.lds_bytes = (int32_t)off;
 }
 
 struct PT {
@@ -425,9 +433,18 @@ void build(Handle& h, int64_t n, const double* points, int64_t m, const int32_t*
     }
   }
   // levels with few rows run their part of the V-cycle in one workgroup
+  // (the coarsest level always; above it while the levels are small and their
+  // arrays fit the LDS of one workgroup, counted in double)
   h.tail_start = nl - 1;
-  while (h.tail_start > 0 && h.L[h.tail_start - 1].n <= kTailRows && nl - (h.tail_start - 1) <= kMaxTail)
+  int64_t tail_bytes = tail_lds_bytes(h.L[nl - 1].n, 0, true, 8);
+  while (h.tail_start > 0 && h.L[h.tail_start - 1].n <= kTailRows && nl - (h.tail_start - 1) <= kMaxTail) {
+    const Level& up = h.L[h.tail_start - 1];
+    const int64_t more = tail_lds_bytes(up.n, (int64_t)up.color_ptr.size() - 1, false, 8);
+    if (tail_bytes + more > kTailLdsMax) break;
+    tail_bytes += more;
     --h.tail_start;
+  }
+  for (int l = h.tail_start; l + 1 < nl; ++l) tail_layout(h, h.L[l], h.L[l + 1]);
   h.plain.v.clear();
   for (int l = 0; l < nl; ++l) h.plain.v.push_back(h.L[l].view);
   h.plain.symmetric = false;
@@ -597,6 +614,18 @@ void kry_prepare(Handle& h, Cycle<float>& c) {
       f.T = {d.T.ptr, d.T.col, to_f32_copy(h, d.T.val, lv.t_slots, s), d.T.len};
       f.diag = to_f32_copy(h, d.diag, d.n, s);
       f.q_val = to_f32_copy(h, d.q_val, (int64_t)3 * d.n, s);
+      if (d.e_cinfo) {                       // a tail level
+        f.e_cinfo = d.e_cinfo;
+        f.e_col_gs = d.e_col_gs;
+        f.e_col = d.e_col;
+        f.e_tcol = d.e_tcol;
+        f.e_wt = d.e_wt;
+        f.e_slots = d.e_slots;
+        f.e_tslots = d.e_tslots;
+        f.e_val_gs = to_f32_copy(h, d.e_val_gs, lv.e_slots, s);
+        f.e_val = to_f32_copy(h, d.e_val, lv.e_slots, s);
+        f.e_tval = to_f32_copy(h, d.e_tval, lv.e_tslots, s);
+      }
     }
   }
   make_tail(h, c);
@@ -981,6 +1010,7 @@ int gmg_default_options(gmg_options* o) {
   o->shift_coarse_points = 1;
   o->sample_order = 0;
   o->seed = 0;
+  o->color_passes = 3;
   return GMG_OK;
 }
 
@@ -1210,6 +1240,7 @@ int gmg_update_matrix(gmg_handle hh, const double* A_val_dev, void* stream) {
     check_hip(hipMemcpyAsync(l0.aval, A_val_dev, (size_t)l0.nnzA * 8, hipMemcpyDeviceToDevice, s), "copy values");
     for (int l = 0; l + 1 < nl; ++l) galerkin_values(*h, h->L[l], h->L[l + 1]);
     for (int l = 0; l < nl; ++l) refresh_values(*h, h->L[l]);
+    for (int l = h->tail_start; l + 1 < nl; ++l) tail_values(*h, h->L[l]);
     coarse_factor(*h, h->L[nl - 1]);                 // also raises the flags of the steps above
     if (h->kry.ready[1])
       for (int l = 0; l + 1 < nl; ++l) {
@@ -1217,6 +1248,10 @@ int gmg_update_matrix(gmg_handle hh, const double* A_val_dev, void* stream) {
         LevelViewT<float>& f = h->kry.c32.v[l];
         to_f32(d.A.val, (float*)f.A.val, h->L[l].a_slots, s);
         to_f32(d.diag, (float*)f.diag, d.n, s);
+        if (d.e_cinfo) {
+          to_f32(d.e_val_gs, (float*)f.e_val_gs, h->L[l].e_slots, s);
+          to_f32(d.e_val, (float*)f.e_val, h->L[l].e_slots, s);
+        }
       }
     sync(s, "update");
   } catch (const Error& e) {

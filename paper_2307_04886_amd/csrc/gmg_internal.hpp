@@ -48,17 +48,43 @@ __device__ inline T wave_sum(T v) {
   return v;
 }
 
-// Appends v to out[] (counter *cnt) for the lanes where pred holds, with one
-// atomic per wavefront.  Every lane of the wavefront must call it.
-__device__ inline void wave_append(bool pred, int32_t v, int32_t* out, int32_t* cnt) {
+// Reduction of one value per thread over a block of kBlock threads (every
+// thread calls it); the result is valid on thread 0.  Reductions into one
+// global counter combine a block first: atomics on one address from every
+// wavefront of a large grid serialise.
+template <class T, class Op>
+__device__ inline T block_reduce(T v, Op op) {
+  __shared__ T ws[kBlock / kWave];
+  for (int o = kWave / 2; o > 0; o >>= 1) v = op(v, __shfl_xor(v, o, kWave));
+  if ((threadIdx.x & (kWave - 1)) == 0) ws[threadIdx.x / kWave] = v;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int w = 1; w < kBlock / kWave; ++w) v = op(v, ws[w]);
+  return v;
+}
+constexpr int kReduceGrid = 256;     // blocks of a grid-stride reduction into one counter
+
+// Appends v to out[] (counter *cnt) for the threads where pred holds, with
+// one atomic per block of kBlock threads.  Every thread of the block must call
+// it.
+__device__ inline void block_append(bool pred, int32_t v, int32_t* out, int32_t* cnt) {
+  __shared__ int32_t wc[kBlock / kWave + 1];     // per-wavefront offsets, then the block's base
   const unsigned long long m = __ballot(pred);
-  if (!m) return;
-  const int lane = threadIdx.x & 63;
-  const int leader = __ffsll((long long)m) - 1;
-  int32_t base = 0;
-  if (lane == leader) base = atomicAdd(cnt, (int32_t)__popcll(m));
-  base = __shfl(base, leader, 64);
-  if (pred) out[base + __popcll(m & ((1ull << lane) - 1ull))] = v;
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  if (lane == 0) wc[w] = __popcll(m);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int32_t tot = 0;
+    for (int i = 0; i < kBlock / kWave; ++i) {
+      const int32_t c = wc[i];
+      wc[i] = tot;
+      tot += c;
+    }
+    wc[kBlock / kWave] = tot ? atomicAdd(cnt, tot) : 0;
+  }
+  __syncthreads();
+  if (pred) out[wc[kBlock / kWave] + wc[w] + __popcll(m & ((1ull << lane) - 1ull))] = v;
+  __syncthreads();                               // wc is reused by the next call
 }
 
 constexpr int kRoundGrid = 1024;     // blocks of a worklist round (grid-stride)
@@ -102,6 +128,23 @@ struct LevelViewT {
   V* x = nullptr;
   V* b = nullptr;
   V* r = nullptr;
+  // Levels of the single-workgroup tail: A_l in per-colour blocked ELL
+  // (colour c: rows [lo, hi), width w a multiple of kTailGroup, element
+  // offset off; entry positions from ell_col_index / ell_val_index), once with
+  // its diagonal (residual) and once without (Gauss-Seidel: the diagonal's
+  // column is n, its value 0), and P_l^T likewise as one segment of n_c rows
+  // and width e_wt.  Padding entries have column n and value 0: the tail keeps
+  // a zero at x[n] and r[n], so that every padded term is +0 and leaves the sum
+  // unchanged.
+  const int32_t* e_cinfo = nullptr;     // [ncolors][4]: lo, hi, w, off
+  const int32_t* e_col_gs = nullptr;
+  const V* e_val_gs = nullptr;
+  const int32_t* e_col = nullptr;
+  const V* e_val = nullptr;
+  const int32_t* e_tcol = nullptr;
+  const V* e_tval = nullptr;
+  int32_t e_wt = 0;
+  int32_t e_slots = 0, e_tslots = 0;    // entries of the ELL arrays of A_l / P_l^T
 };
 using LevelView = LevelViewT<double>;
 
@@ -110,12 +153,42 @@ struct TailDescT {
   int32_t nlev = 0;                     // tail levels, the last one is the coarsest
   int32_t nu_pre = 0, nu_post = 0;
   int32_t descending_post = 0;          // 1: post-smoothing visits the colours in descending order
-  int32_t lds_elems = 0;                // LDS (elements of V) holding the tail levels' iterates
+  // single-vector tail: byte offsets in LDS of every tail level's x (n + 1),
+  // b (n), r (n + 1) and colour table (the coarsest level: x and b)
+  int32_t lds_bytes = 0;
+  int32_t o_x[kMaxTail] = {}, o_b[kMaxTail] = {}, o_r[kMaxTail] = {}, o_c[kMaxTail] = {};
+  // batched tail: LDS (elements of V) holding the tail levels' iterates
+  int32_t lds_elems = 0;
   int32_t lds_off[kMaxTail] = {};       // offset of level l's x in LDS, or -1 (global)
   const double* cinv = nullptr;
   LevelViewT<V> lv[kMaxTail];
 };
-constexpr int32_t kTailLdsBytes = 96 * 1024;
+constexpr int32_t kTailLdsBytes = 96 * 1024;      // batched tail
+constexpr int32_t kTailLdsMax = 144 * 1024;       // single-vector tail (gfx950: 160 KiB per workgroup)
+constexpr int kTailGroup = 8;                     // tail ELL widths are multiples of this
+
+// Row stride of the dense coarsest inverse: n rounded up to even, so that two
+// consecutive entries of a row are one 16-byte aligned load.
+inline __host__ __device__ int64_t inv_ld(int64_t n) { return (n + 1) & ~(int64_t)1; }
+
+// Element index of entry t of row r in a tail ELL segment (first row lo, cnt
+// rows, element offset off): columns in blocks of 4 entries per row, values in
+// blocks of 2 (one 16-byte load per block and lane).
+inline __host__ __device__ int64_t ell_col_index(int64_t off, int64_t cnt, int64_t lo, int64_t r, int64_t t) {
+  return off + (t >> 2) * (cnt * 4) + (r - lo) * 4 + (t & 3);
+}
+inline __host__ __device__ int64_t ell_val_index(int64_t off, int64_t cnt, int64_t lo, int64_t r, int64_t t) {
+  return off + (t >> 1) * (cnt * 2) + (r - lo) * 2 + (t & 1);
+}
+
+// LDS bytes of one level in the single-vector tail (value type V): x and r with
+// their zero, b, the colour table; the coarsest level keeps x and b only.
+// Arrays start on 16-byte boundaries.
+inline int64_t tail_lds_bytes(int64_t n, int64_t ncolors, bool coarsest, int64_t vbytes) {
+  auto up = [](int64_t b) { return (b + 15) & ~(int64_t)15; };
+  if (coarsest) return 2 * up(n * vbytes);
+  return 2 * up((n + 1) * vbytes) + up(n * vbytes) + up(ncolors * 16);
+}
 
 // One variant of the V-cycle: its per-level views and its tail descriptor.
 // symmetric: post-smoothing runs the colours in descending order, so that the
@@ -178,6 +251,9 @@ struct Level {
   int32_t* t_col = nullptr;
   double* t_val = nullptr;
   bool galerkin_wide = false;           // A_{l+1} has a row longer than the narrow fill kernel holds
+  // tail levels: the per-colour ELL of A_l and the ELL of P_l^T (LevelViewT)
+  std::vector<int32_t> e_cinfo_h;       // host copy of view.e_cinfo
+  int64_t e_slots = 0, e_tslots = 0;
 };
 
 // Preconditioned conjugate gradients (double) around a symmetric V-cycle in
@@ -227,7 +303,7 @@ struct Handle {
   std::vector<Level> L;
   int64_t ncoarse = 0;
   double* chol = nullptr;               // dense lower factor of the coarsest A
-  double* cinv = nullptr;               // dense inverse of the coarsest A (row-major)
+  double* cinv = nullptr;               // dense inverse of the coarsest A: inv[k inv_ld(n) + i] = (A^-1 e_k)_i
   int32_t* flags = nullptr;             // device error flags and counters
   int32_t* rounds = nullptr;            // device per-round counters of frontier loops
   double* red = nullptr;                // reduction partials
@@ -318,6 +394,8 @@ void solve_layout(Handle& h, Level& lv, const Level* nx, const int32_t* t_rp, co
                   const double* t_val);
 void coarse_factor(Handle& h, Level& lv);
 void refresh_values(Handle& h, Level& lv);                 // SELL values and diagonal from lv.aval
+void tail_layout(Handle& h, Level& lv, const Level& nx);    // tail ELL of A_l and P_l^T (view.e_*)
+void tail_values(Handle& h, Level& lv);                    // tail ELL values of A_l from its SELL
 
 // ------------------------------------------------------------------ launchers (solve.hip)
 // V-cycle phases on one level, for V = double and V = float.  gs_sweep visits

@@ -99,30 +99,24 @@ __global__ void __launch_bounds__(kBlock) k_mprolong(LevelViewT<V> L, const V* _
   mprolong_entry(L, xc, x, t);
 }
 
-// x = A_c^-1 b for the K right-hand sides, in double; one wavefront per row.
+// x = A_c^-1 b for the K right-hand sides, in double, as the single-vector
+// coarse solve: entry (i, q) is the sum over k ascending of (A_c^-1 e_k)_i b_kq.
 template <class V>
-__device__ __forceinline__ void mgemv_row(const double* M, const V* b, V* x, int64_t n, int64_t row, int lane) {
-  double s[K];
-#pragma unroll
-  for (int q = 0; q < K; ++q) s[q] = 0.0;
-  for (int64_t k = lane; k < n; k += kWave) {
-    const double m = M[row * n + k];
-#pragma unroll
-    for (int q = 0; q < K; ++q) s[q] += m * (double)b[k * K + q];
-  }
-#pragma unroll
-  for (int q = 0; q < K; ++q) {
-    const double v = wave_sum(s[q]);
-    if (lane == 0) x[row * K + q] = (V)v;
-  }
+__device__ __forceinline__ void mgemv_entry(const double* M, const V* b, V* x, int64_t n, int64_t t) {
+  const int64_t i = t / K;
+  const int q = (int)(t % K);
+  double acc = 0.0;
+  const int64_t ld = inv_ld(n);
+  for (int64_t k = 0; k < n; ++k) acc = acc + M[k * ld + i] * (double)b[k * K + q];
+  x[t] = (V)acc;
 }
 
 template <class V>
 __global__ void __launch_bounds__(kBlock) k_mgemv(const double* __restrict__ M, const V* __restrict__ b,
                                                   V* __restrict__ x, int64_t n) {
-  const int64_t row = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
-  if (row >= n) return;
-  mgemv_row(M, b, x, n, row, threadIdx.x & (kWave - 1));
+  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (t >= n * K) return;
+  mgemv_entry(M, b, x, n, t);
 }
 
 // The tail of the cycle in one workgroup (as k_tail_vcycle), one lane per
@@ -169,8 +163,7 @@ __global__ void __launch_bounds__(kTailThreads) k_mtail(TailDescT<V> d) {
   {
     const LevelViewT<V>& C = d.lv[d.nlev - 1];
     V* XC = X(d.nlev - 1);
-    for (int64_t row = tid / kWave; row < C.n; row += kTailThreads / kWave)
-      mgemv_row(d.cinv, (const V*)C.b, XC, C.n, row, tid & (kWave - 1));
+    for (int64_t t = tid; t < (int64_t)C.n * K; t += kTailThreads) mgemv_entry(d.cinv, (const V*)C.b, XC, C.n, t);
     __syncthreads();
   }
   for (int l = d.nlev - 2; l >= 0; --l) {
@@ -413,7 +406,7 @@ void mprolong(const LevelViewT<V>& v, const LevelViewT<V>& c, hipStream_t s) {
 
 template <class V>
 void mcoarse(const double* cinv, const LevelViewT<V>& c, hipStream_t s) {
-  k_mgemv<V><<<blocks_for(c.n, kBlock / kWave), kBlock, 0, s>>>(cinv, c.b, c.x, c.n);
+  k_mgemv<V><<<blocks_for(c.n * K), kBlock, 0, s>>>(cinv, c.b, c.x, c.n);
 }
 
 template <class V>

@@ -102,19 +102,15 @@ __global__ void k_edge_weights(const double* X, const int32_t* rp, const int32_t
 // (ordered like the value), combined with an unsigned 64-bit atomic max.
 __global__ void k_edge_max(const int32_t* rp, const int32_t* col, const double* w, int64_t n,
                            unsigned long long* maxbits) {
-  int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   unsigned long long m = 0;
-  if (u < n)
+  for (int64_t u = (int64_t)blockIdx.x * kBlock + threadIdx.x; u < n; u += (int64_t)gridDim.x * kBlock)
     for (int32_t e = rp[u]; e < rp[u + 1]; ++e)
       if (u < col[e]) {
         unsigned long long b = (unsigned long long)__double_as_longlong(w[e]);
         m = b > m ? b : m;
       }
-  for (int o = 32; o > 0; o >>= 1) {
-    unsigned long long t = __shfl_xor(m, o, 64);
-    m = t > m ? t : m;
-  }
-  if ((threadIdx.x & 63) == 0 && m) atomicMax(maxbits, m);
+  m = block_reduce(m, [](unsigned long long a, unsigned long long b) { return a > b ? a : b; });
+  if (threadIdx.x == 0 && m) atomicMax(maxbits, m);
 }
 
 __device__ inline int fixed_point_shift(double M, int64_t cnt) {
@@ -134,13 +130,12 @@ __global__ void k_edge_fixsum(const int32_t* rp, const int32_t* col, const doubl
   double M = __longlong_as_double((long long)*maxbits);
   if (M == 0.0) return;
   int F = fixed_point_shift(M, cnt);
-  int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   long long s = 0;
-  if (u < n)
+  for (int64_t u = (int64_t)blockIdx.x * kBlock + threadIdx.x; u < n; u += (int64_t)gridDim.x * kBlock)
     for (int32_t e = rp[u]; e < rp[u + 1]; ++e)
       if (u < col[e]) s += (long long)rint(ldexp(w[e], F));
-  s = wave_sum(s);
-  if ((threadIdx.x & 63) == 0 && s) atomicAdd(sum, (unsigned long long)s);
+  s = block_reduce(s, [](long long a, long long b) { return a + b; });
+  if (threadIdx.x == 0 && s) atomicAdd(sum, (unsigned long long)s);
 }
 
 __global__ void k_edge_mean_finish(const unsigned long long* maxbits, const unsigned long long* sum,
@@ -212,7 +207,7 @@ __global__ void __launch_bounds__(kBlock) k_lfmis_round(const int32_t* rp, const
     const bool act = i < count;
     const int32_t p = act ? (k == 0 ? (int32_t)i : wl_in[i]) : 0;
     const bool pend = act && lfmis_attempt(rp, col, w, r, key, status, p);
-    wave_append(pend, p, wl_out, &rounds[k]);
+    block_append(pend, p, wl_out, &rounds[k]);
   }
 }
 
@@ -266,8 +261,8 @@ __global__ void __launch_bounds__(kBlock) k_voronoi_round(const int32_t* rp, con
     dB[v] = bd;
     lB[v] = bl;
   }
-  unsigned long long b = __ballot(changed);
-  if ((threadIdx.x & 63) == 0 && b) atomicAdd(&rounds[k], __popcll(b));
+  const int32_t c = block_reduce((int32_t)changed, [](int32_t a, int32_t b) { return a + b; });
+  if (threadIdx.x == 0 && c) atomicAdd(&rounds[k], c);
 }
 
 // ------------------------------------------------------------------ cells, shift (Sec. 4.4)
@@ -398,8 +393,9 @@ void mean_edge(Handle& h, Level& lv, double rho) {
   hipStream_t s = h.stream;
   unsigned long long* acc = (unsigned long long*)talloc(s, 16);
   check_hip(hipMemsetAsync(acc, 0, 16, s), "memset");
-  k_edge_max<<<blocks_for(lv.n), kBlock, 0, s>>>(lv.erp, lv.ecol, lv.ew, lv.n, acc);
-  k_edge_fixsum<<<blocks_for(lv.n), kBlock, 0, s>>>(lv.erp, lv.ecol, lv.ew, lv.n, acc, acc + 1);
+  const int rg = std::min(blocks_for(lv.n), kReduceGrid);
+  k_edge_max<<<rg, kBlock, 0, s>>>(lv.erp, lv.ecol, lv.ew, lv.n, acc);
+  k_edge_fixsum<<<rg, kBlock, 0, s>>>(lv.erp, lv.ecol, lv.ew, lv.n, acc, acc + 1);
   k_edge_mean_finish<<<1, 1, 0, s>>>(acc, acc + 1, lv.erp + lv.n, rho, lv.scal);
   tfree(s, acc);
 }

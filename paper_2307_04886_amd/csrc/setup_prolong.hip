@@ -2,6 +2,8 @@
 // (Voronoi-neighbour candidate triangles, closest-point barycentric weights,
 // inverse-distance fallback), its transpose (the restriction), and the
 // Galerkin operator A_{l+1} = P_l^T A_l P_l of Alg. 1.
+#include <algorithm>
+
 #include "gmg_internal.hpp"
 
 namespace gmg {
@@ -476,14 +478,12 @@ __global__ void __launch_bounds__(kWave) k_galerkin_fill(const int32_t* trp, con
   if (lane == 0 && bal == 0) atomicOr(flags, F_NOT_SPD);
 }
 
-__global__ void k_max_i32(const int32_t* v, int64_t n, int32_t* out) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int32_t m = i < n ? v[i] : 0;
-  for (int o = 32; o > 0; o >>= 1) {
-    int32_t t = __shfl_xor(m, o, 64);
-    m = t > m ? t : m;
-  }
-  if ((threadIdx.x & 63) == 0 && m) atomicMax(out, m);
+__global__ void __launch_bounds__(kBlock) k_max_i32(const int32_t* v, int64_t n, int32_t* out) {
+  int32_t m = 0;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+    m = v[i] > m ? v[i] : m;
+  m = block_reduce(m, [](int32_t a, int32_t b) { return a > b ? a : b; });
+  if (threadIdx.x == 0 && m) atomicMax(out, m);
 }
 
 }  // namespace
@@ -532,7 +532,7 @@ void galerkin(Handle& h, Level& lv, Level& nx, const int32_t* t_rp, const int32_
   nx.arp = (int32_t*)dalloc(h, (size_t)(nc + 1) * 4);
   k_galerkin_count<1024><<<(int)nc, kWave, 0, s>>>(t_rp, t_col, t_val, lv.arp, lv.acol, lv.pcol, lv.pcnt, nc,
                                                   cnt, h.flags);
-  k_max_i32<<<blocks_for(nc), kBlock, 0, s>>>(cnt, nc, mx);
+  k_max_i32<<<std::min(blocks_for(nc), kReduceGrid), kBlock, 0, s>>>(cnt, nc, mx);
   scan_i32(cnt, nx.arp, nc, s);
   int64_t maxrow = 0, f = 0;
   ScalarRead rd[3] = {{nx.arp + nc, 4, &nx.nnzA}, {mx, 4, &maxrow}, {h.flags, 4, &f}};

@@ -69,25 +69,53 @@ __device__ inline int32_t color_attempt(const int32_t* rp, const int32_t* col, c
 // One Jones-Plassmann round; round 0 visits every row, later rounds the
 // worklist of rows still waiting after the previous round.
 __global__ void __launch_bounds__(kBlock) k_color_round(const int32_t* rp, const int32_t* col, int64_t n,
-                                                        ColorKey key, int32_t* color, int32_t* ncol,
-                                                        const int32_t* wl_in, int32_t* wl_out, int32_t* rounds,
-                                                        int k) {
+                                                        ColorKey key, int32_t* color, const int32_t* wl_in,
+                                                        int32_t* wl_out, int32_t* rounds, int k) {
   const int64_t count = k == 0 ? n : rounds[k - 1];
-  int32_t newc = 0;
   for (int64_t base = (int64_t)blockIdx.x * kBlock; base < count; base += (int64_t)gridDim.x * kBlock) {
     const int64_t i = base + threadIdx.x;
     const bool act = i < count;
     const int32_t v = act ? (k == 0 ? (int32_t)i : wl_in[i]) : 0;
     int32_t got = 0;
     if (act) got = color_attempt(rp, col, key, color, v);
-    newc = got > newc ? got : newc;
-    wave_append(act && got == 0, v, wl_out, &rounds[k]);
+    block_append(act && got == 0, v, wl_out, &rounds[k]);
   }
-  for (int o = 32; o > 0; o >>= 1) {
-    int32_t t = __shfl_xor(newc, o, 64);
-    newc = t > newc ? t : newc;
+}
+
+// One class of an iterated-greedy pass: every vertex v with old[v] == c takes
+// the smallest colour not used by a neighbour's new colour (neu[u] >= 0: the
+// classes above c, recoloured by earlier launches).  Vertices of one class are
+// not adjacent, so they are recoloured in parallel.
+__global__ void __launch_bounds__(kBlock) k_ig_class(const int32_t* rp, const int32_t* col, int64_t n,
+                                                     const int32_t* old, int32_t* neu, int32_t c) {
+  for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < n; v += (int64_t)gridDim.x * kBlock) {
+    if (old[v] != c) continue;
+    const int32_t b = rp[v], e = rp[v + 1];
+    uint64_t mask = 0;
+    bool high = false;
+    for (int32_t e0 = b; e0 < e; e0 += kColorChunk) {
+      int32_t u[kColorChunk], cu[kColorChunk];
+#pragma unroll
+      for (int k = 0; k < kColorChunk; ++k) u[k] = col[min(e0 + k, e - 1)];
+#pragma unroll
+      for (int k = 0; k < kColorChunk; ++k) cu[k] = neu[u[k]];
+#pragma unroll
+      for (int k = 0; k < kColorChunk; ++k) {
+        if (e0 + k >= e || u[k] == v || cu[k] < 0) continue;
+        if (cu[k] < 64) mask |= 1ull << cu[k];
+        else high = true;
+      }
+    }
+    int32_t k = (~mask) ? __builtin_ctzll(~mask) : 64;
+    if (k == 64 && high) {
+      for (;; ++k) {                            // rare: every colour below 64 is taken
+        bool used = false;
+        for (int32_t t = b; t < e && !used; ++t) used = col[t] != v && neu[col[t]] == k;
+        if (!used) break;
+      }
+    }
+    neu[v] = k;
   }
-  if ((threadIdx.x & 63) == 0 && newc) atomicMax(ncol, newc);
 }
 
 // ------------------------------------------------------------------ stable colour partition
@@ -166,14 +194,17 @@ __global__ void k_sell_fill(const int32_t* perm, const int32_t* cmap, const int3
   }
 }
 
-__global__ void k_max_len(const int32_t* v, int64_t n, int32_t* out) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int32_t m = i < n ? v[i] : 0;
-  for (int o = 32; o > 0; o >>= 1) {
-    int32_t t = __shfl_xor(m, o, 64);
-    m = t > m ? t : m;
-  }
-  if ((threadIdx.x & 63) == 0 && m) atomicMax(out, m);
+// *out = max(*out, max_i v[i] + add)
+__global__ void __launch_bounds__(kBlock) k_max_i32(const int32_t* v, int64_t n, int32_t add, int32_t* out) {
+  int32_t m = 0;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+    m = v[i] + add > m ? v[i] + add : m;
+  m = block_reduce(m, [](int32_t a, int32_t b) { return a > b ? a : b; });
+  if (threadIdx.x == 0 && m) atomicMax(out, m);
+}
+
+void max_i32(const int32_t* v, int64_t n, int32_t add, int32_t* out, hipStream_t s) {
+  k_max_i32<<<std::min(blocks_for(n), kReduceGrid), kBlock, 0, s>>>(v, n, add, out);
 }
 
 // nnz of colour class c = prefix[cptr[c+1]] - prefix[cptr[c]] of the row lengths
@@ -344,7 +375,63 @@ __global__ void __launch_bounds__(kWave) k_chol_inverse(const double* L, const d
     if (lane < nb) y[b0 + r] = t;
     __syncthreads();
   }
-  for (int64_t i = lane; i < n; i += kWave) inv[c * n + i] = y[i];
+  const int64_t ld = inv_ld(n);
+  for (int64_t i = lane; i < ld; i += kWave) inv[c * ld + i] = i < n ? y[i] : 0.0;
+}
+
+// Longest row of every colour, rounded up to kTailGroup: w[c].
+__global__ void k_color_width(const int32_t* len, const int32_t* cptr, int32_t* w) {
+  __shared__ int32_t ws[kBlock / kWave];
+  const int c = blockIdx.x;
+  int32_t m = 0;
+  for (int32_t r = cptr[c] + threadIdx.x; r < cptr[c + 1]; r += kBlock) m = len[r] > m ? len[r] : m;
+  for (int o = 32; o > 0; o >>= 1) {
+    const int32_t t = __shfl_xor(m, o, kWave);
+    m = t > m ? t : m;
+  }
+  if ((threadIdx.x & (kWave - 1)) == 0) ws[threadIdx.x / kWave] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < kBlock / kWave; ++i) m = ws[i] > m ? ws[i] : m;
+    w[c] = (m + kTailGroup - 1) / kTailGroup * kTailGroup;
+  }
+}
+
+// A_l (SELL) into the tail's per-colour ELL, with and without the diagonal.
+__global__ void k_tail_ell(SellView A, const int32_t* cinfo, int nc, int64_t n, int32_t* col_gs, double* val_gs,
+                           int32_t* col, double* val) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  int c = 0;
+  while (c + 1 < nc && cinfo[4 * (c + 1)] <= r) ++c;
+  const int32_t lo = cinfo[4 * c], hi = cinfo[4 * c + 1], w = cinfo[4 * c + 2], off = cinfo[4 * c + 3];
+  const int32_t len = A.len[r];
+  const int64_t base = A.ptr[r / kSlice] + (r & (kSlice - 1));
+  for (int32_t t = 0; t < w; ++t) {
+    const int64_t oc = ell_col_index(off, hi - lo, lo, r, t), ov = ell_val_index(off, hi - lo, lo, r, t);
+    int32_t j = (int32_t)n;
+    double v = 0.0;
+    if (t < len) {
+      j = A.col[base + (int64_t)t * kSlice];
+      v = A.val[base + (int64_t)t * kSlice];
+    }
+    col[oc] = j;
+    val[ov] = v;
+    col_gs[oc] = j == r ? (int32_t)n : j;
+    val_gs[ov] = j == r ? 0.0 : v;
+  }
+}
+
+// P_l^T (SELL, nc rows) into ELL of width w; padding column n (the fine level's size).
+__global__ void k_tail_ell_t(SellView T, int64_t nc, int32_t w, int64_t n, int32_t* col, double* val) {
+  const int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= nc) return;
+  const int32_t len = T.len[I];
+  const int64_t base = T.ptr[I / kSlice] + (I & (kSlice - 1));
+  for (int32_t t = 0; t < w; ++t) {
+    col[ell_col_index(0, nc, 0, I, t)] = t < len ? T.col[base + (int64_t)t * kSlice] : (int32_t)n;
+    val[ell_val_index(0, nc, 0, I, t)] = t < len ? T.val[base + (int64_t)t * kSlice] : 0.0;
+  }
 }
 
 }  // namespace
@@ -363,14 +450,42 @@ void colouring(Handle& h, Level& lv, int level) {
   int k = 0;
   for (;;) {
     for (int t = 0; t < kRoundBatch; ++t, ++k)
-      k_color_round<<<grid, kBlock, 0, s>>>(lv.arp, lv.acol, n, key, lv.color, ncol, wl + ((k + 1) % 2) * n,
+      k_color_round<<<grid, kBlock, 0, s>>>(lv.arp, lv.acol, n, key, lv.color, wl + ((k + 1) % 2) * n,
                                             wl + (k % 2) * n, h.rounds, k);
-    int64_t left = 0, nco = 0;
-    ScalarRead rd[2] = {{h.rounds + (k - 1), 4, &left}, {ncol, 4, &nco}};
-    read_scalars(h, rd, 2);
-    lv.ncolors = (int32_t)nco;
+    int64_t left = 0;
+    ScalarRead rd[1] = {{h.rounds + (k - 1), 4, &left}};
+    read_scalars(h, rd, 1);
     if (left == 0) break;
     if (k + kRoundBatch > kMaxRounds) throw Error{GMG_DEVICE_ERROR, "colouring did not terminate"};
+  }
+  {
+    max_i32(lv.color, n, 1, ncol, s);
+    int64_t nco = 0;
+    ScalarRead rd[1] = {{ncol, 4, &nco}};
+    read_scalars(h, rd, 1);
+    lv.ncolors = (int32_t)nco;
+  }
+  // iterated-greedy passes: classes of the previous colouring from the highest
+  // colour down (a pass never needs more colours, so the first count bounds
+  // the classes of every pass)
+  if (h.opt.color_passes > 0 && lv.ncolors > 1) {
+    int32_t* other = (int32_t*)talloc(s, (size_t)n * 4);
+    int32_t* cur = lv.color;
+    int32_t* nxt = other;
+    for (int p = 0; p < h.opt.color_passes; ++p) {
+      fill_i32(nxt, -1, n, s);
+      for (int32_t c = lv.ncolors - 1; c >= 0; --c)
+        k_ig_class<<<grid, kBlock, 0, s>>>(lv.arp, lv.acol, n, cur, nxt, c);
+      std::swap(cur, nxt);
+    }
+    check_hip(hipMemsetAsync(ncol, 0, 4, s), "memset");
+    max_i32(cur, n, 1, ncol, s);
+    if (cur != lv.color) check_hip(hipMemcpyAsync(lv.color, cur, (size_t)n * 4, hipMemcpyDeviceToDevice, s), "copy");
+    int64_t nco = 0;
+    ScalarRead rd[1] = {{ncol, 4, &nco}};
+    read_scalars(h, rd, 1);
+    lv.ncolors = (int32_t)nco;
+    tfree(s, other);
   }
   tfree(s, wl);
   tfree(s, ncol);
@@ -390,7 +505,7 @@ SellView make_sell(Handle& h, const int32_t* perm, const int32_t* cmap, const in
   int32_t* mx = (int32_t*)talloc(s, 4);
   check_hip(hipMemsetAsync(mx, 0, 4, s), "memset");
   k_row_len<<<blocks_for(n), kBlock, 0, s>>>(perm, rp, n, len);
-  k_max_len<<<blocks_for(n), kBlock, 0, s>>>(len, n, mx);
+  max_i32(len, n, 0, mx, s);
   k_slice_width<<<blocks_for(ns), kBlock, 0, s>>>(len, n, ns, wsz);
   scan_i32(wsz, ptr, ns, s);
   int64_t tot = 0, ml = 0;
@@ -519,7 +634,7 @@ void coarse_factor(Handle& h, Level& lv) {
     }
   }
   if (!h.chol) h.chol = (double*)dalloc(h, (size_t)n * n * 8);
-  if (!h.cinv) h.cinv = (double*)dalloc(h, (size_t)n * n * 8);
+  if (!h.cinv) h.cinv = (double*)dalloc(h, (size_t)n * inv_ld(n) * 8);
   k_split_factor<<<blocks_for(n * n), kBlock, 0, s>>>(D, n, h.chol, U);
   k_chol_inverse<<<(int)n, kWave, (size_t)n * 8, s>>>(h.chol, U, n, h.cinv);
   h.ncoarse = n;
@@ -533,6 +648,59 @@ void refresh_values(Handle& h, Level& lv) {
   const LevelView& v = lv.view;
   k_sell_fill<<<blocks_for(lv.n), kBlock, 0, h.stream>>>(lv.perm, lv.iperm, lv.arp, lv.acol, lv.aval, lv.n, v.A.ptr,
                                                          (int32_t*)v.A.col, (double*)v.A.val, lv.diag);
+}
+
+// The tail's ELL copies of A_l and P_l^T (see LevelViewT): colour widths are
+// read back once to lay the colours out.
+void tail_layout(Handle& h, Level& lv, const Level& nx) {
+  hipStream_t s = h.stream;
+  LevelView& v = lv.view;
+  const int C = v.ncolors;
+  int32_t* w = (int32_t*)talloc(s, (size_t)C * 4);
+  k_color_width<<<C, kBlock, 0, s>>>(v.A.len, v.cptr, w);
+  int32_t* stage = (int32_t*)pinned_staging((size_t)C * 4);
+  check_hip(hipMemcpyAsync(stage, w, (size_t)C * 4, hipMemcpyDeviceToHost, s), "copy");
+  sync(s, "tail layout");
+  tfree(s, w);
+  lv.e_cinfo_h.assign((size_t)4 * C, 0);
+  int64_t off = 0;
+  for (int c = 0; c < C; ++c) {
+    const int32_t lo = lv.color_ptr[c], hi = lv.color_ptr[c + 1];
+    lv.e_cinfo_h[4 * c] = lo;
+    lv.e_cinfo_h[4 * c + 1] = hi;
+    lv.e_cinfo_h[4 * c + 2] = stage[c];
+    lv.e_cinfo_h[4 * c + 3] = (int32_t)off;
+    off += (int64_t)stage[c] * (hi - lo);
+  }
+  lv.e_slots = off;
+  v.e_slots = (int32_t)off;
+  int32_t* cinfo = (int32_t*)dalloc(h, (size_t)4 * C * 4);
+  int32_t* st = (int32_t*)pinned_staging((size_t)4 * C * 4);
+  std::copy(lv.e_cinfo_h.begin(), lv.e_cinfo_h.end(), st);
+  check_hip(hipMemcpyAsync(cinfo, st, (size_t)4 * C * 4, hipMemcpyHostToDevice, s), "copy");
+  v.e_cinfo = cinfo;
+  const size_t e = (size_t)std::max<int64_t>(off, 1);
+  v.e_col_gs = (int32_t*)dalloc(h, e * 4);
+  v.e_col = (int32_t*)dalloc(h, e * 4);
+  v.e_val_gs = (double*)dalloc(h, e * 8);
+  v.e_val = (double*)dalloc(h, e * 8);
+  tail_values(h, lv);
+  v.e_wt = (v.maxt + kTailGroup - 1) / kTailGroup * kTailGroup;
+  lv.e_tslots = (int64_t)v.e_wt * nx.n;
+  v.e_tslots = (int32_t)lv.e_tslots;
+  const size_t et = (size_t)std::max<int64_t>(lv.e_tslots, 1);
+  int32_t* tcol = (int32_t*)dalloc(h, et * 4);
+  double* tval = (double*)dalloc(h, et * 8);
+  k_tail_ell_t<<<blocks_for(nx.n), kBlock, 0, s>>>(v.T, nx.n, v.e_wt, lv.n, tcol, tval);
+  v.e_tcol = tcol;
+  v.e_tval = tval;
+  sync(s, "tail layout");   // the staging buffer is reused by the next call
+}
+
+void tail_values(Handle& h, Level& lv) {
+  const LevelView& v = lv.view;
+  k_tail_ell<<<blocks_for(lv.n), kBlock, 0, h.stream>>>(v.A, v.e_cinfo, v.ncolors, lv.n, (int32_t*)v.e_col_gs,
+                                                        (double*)v.e_val_gs, (int32_t*)v.e_col, (double*)v.e_val);
 }
 
 }  // namespace gmg

@@ -131,91 +131,371 @@ __global__ void __launch_bounds__(kBlock) k_prolong_correct(LevelViewT<V> L, con
   prolong_row(L, xc, x, (int32_t)i);
 }
 
-// x = A_c^-1 b in double (b widened from V, x rounded to V), one wavefront per
-// row of the dense inverse.
+// x = A_c^-1 b in double (b widened from V, x rounded to V): row i is the sum
+// over k ascending of (A_c^-1 e_k)_i b_k, stored at inv[k ld + i]; one thread
+// per row (the loads of a wavefront are coalesced).
 template <class V>
 __global__ void __launch_bounds__(kBlock) k_dense_gemv(const double* __restrict__ M, const V* __restrict__ b,
                                                        V* __restrict__ x, int64_t n) {
-  const int64_t row = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
-  const int lane = threadIdx.x & (kWave - 1);
-  if (row >= n) return;
-  double s = 0.0;
-  for (int64_t k = lane; k < n; k += kWave) s += M[row * n + k] * (double)b[k];
-  s = wave_sum(s);
-  if (lane == 0) x[row] = (V)s;
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  double acc = 0.0;
+  const int64_t ld = inv_ld(n);
+  for (int64_t k = 0; k < n; ++k) acc = acc + M[k * ld + i] * (double)b[k];
+  x[i] = (V)acc;
 }
 
 // The V-cycle below a level with few rows, in one workgroup: every phase
 // (colour of a sweep, residual, restriction, coarsest solve, prolongation) is
-// separated by a workgroup barrier instead of a kernel boundary, and the
-// iterates x of the tail levels live in LDS when they fit.  One lane per row
-// (a single compute unit has little shuffle throughput to spare); each phase
-// performs exactly the operations of the corresponding multi-launch kernel.
-constexpr int kChunkTail = 16;
+// separated by a workgroup barrier instead of a kernel boundary, and the tail
+// levels' vectors x, b and r live in LDS.  Each phase performs exactly the
+// operations of the corresponding multi-launch kernel, in the same order.
+//
+// One lane per row, four wavefronts (one per SIMD, so that a lane can hold a
+// whole row in registers).  Rows are handled in rounds of kTailThreads1 rows;
+// the matrix entries of the next round, which do not depend on x, are loaded
+// before the current round computes, so that their latency overlaps the
+// current round and the barrier that ends a colour.  The matrices are read in
+// the per-colour ELL of the tail levels (see LevelViewT), whose padded terms
+// are exactly +0.
+constexpr int kTailThreads1 = 256;
+constexpr int kTailW = 32;                 // entries of a row held in registers; the rest load on demand
+constexpr int kTailGroups = kTailW / kTailGroup;
+constexpr int kTailProlong = 4;            // prolongation rows per thread whose loads are issued together
+constexpr int kTailGemv = 16;              // columns of the coarsest inverse per prefetched chunk
+
+struct TailSeg {
+  int32_t lo, hi, w, off;                  // rows [lo, hi), ELL width, offset of entry (0, lo)
+};
 
 template <class V>
-__device__ __forceinline__ void tail_gs(const LevelViewT<V>& L, V* X, bool descending) {
-  const int tid = threadIdx.x;
-  for (int k = 0; k < L.ncolors; ++k) {
-    const int c = descending ? L.ncolors - 1 - k : k;
-    for (int32_t r = L.cptr[c] + tid; r < L.cptr[c + 1]; r += kTailThreads) {
-      const V acc = row_sum_seq<kChunkTail>(L.A, r, X, r);
-      X[r] = (L.b[r] - acc) / L.diag[r];
+struct TailRow {
+  int32_t j[kTailW];
+  V v[kTailW];
+  V d;
+};
+
+__device__ __forceinline__ int32_t uniform(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Tail matrix loads go through buffer resources: a scalar base and bound, a
+// uniform (scalar) offset for the entry column and the lane's row offset, so
+// that no vector instruction is spent on addresses.
+using Rsrc = __amdgpu_buffer_rsrc_t;
+__device__ __forceinline__ Rsrc make_rsrc(const void* p, int64_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)(uint32_t)bytes, 0x00020000);
+}
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ u32x4 bload16(Rsrc r, uint32_t voff, uint32_t soff) {
+  return __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0);
+}
+// (the 8-byte form returns one 64-bit integer)
+__device__ __forceinline__ uint64_t bload8(Rsrc r, uint32_t voff, uint32_t soff) {
+  return (uint64_t)__builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0);
+}
+__device__ __forceinline__ double as_f64(uint32_t lo, uint32_t hi) {
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Two consecutive values of a tail ELL value array (one block) for one lane.
+template <class V>
+__device__ __forceinline__ void val_pair(Rsrc r, uint32_t voff, uint32_t soff, V& a, V& b);
+template <>
+__device__ __forceinline__ void val_pair<double>(Rsrc r, uint32_t voff, uint32_t soff, double& a, double& b) {
+  const u32x4 u = bload16(r, voff * 16u, soff * 8u);
+  a = as_f64(u.x, u.y);
+  b = as_f64(u.z, u.w);
+}
+template <>
+__device__ __forceinline__ void val_pair<float>(Rsrc r, uint32_t voff, uint32_t soff, float& a, float& b) {
+  const uint64_t u = bload8(r, voff * 8u, soff * 4u);
+  a = __builtin_bit_cast(float, (uint32_t)u);
+  b = __builtin_bit_cast(float, (uint32_t)(u >> 32));
+}
+
+// An ELL matrix of the tail: column and value arrays.
+template <class V>
+struct TailMat {
+  Rsrc col, val;
+};
+template <class V>
+__device__ __forceinline__ TailMat<V> tail_mat(const int32_t* col, const V* val, int64_t slots) {
+  return TailMat<V>{make_rsrc(col, slots * 4), make_rsrc(val, slots * (int64_t)sizeof(V))};
+}
+
+// Entries t0..t0+7 of the lane's row (row offset lo in a segment of cnt rows
+// at element offset off): two 4-entry column blocks, four 2-entry value blocks.
+template <class V>
+__device__ __forceinline__ void tail_group(const TailMat<V>& M, uint32_t off, uint32_t cnt, uint32_t lo,
+                                           uint32_t t0, int32_t* j, V* v) {
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    const u32x4 c = bload16(M.col, lo * 16u, (off + ((t0 >> 2) + b) * cnt * 4u) * 4u);
+    j[4 * b] = (int32_t)c.x;
+    j[4 * b + 1] = (int32_t)c.y;
+    j[4 * b + 2] = (int32_t)c.z;
+    j[4 * b + 3] = (int32_t)c.w;
+  }
+#pragma unroll
+  for (int b = 0; b < 4; ++b) val_pair<V>(M.val, lo, off + ((t0 >> 1) + b) * cnt * 2u, v[2 * b], v[2 * b + 1]);
+}
+
+// Entries 0..kTailW-1 (up to the segment's width) of row r (clamped into the
+// segment by the caller), and its diagonal when D.
+template <bool D, class V>
+__device__ __forceinline__ void tail_fetch(const TailMat<V>& M, const V* diag, const TailSeg& sg, int32_t r,
+                                           TailRow<V>& q) {
+  const uint32_t cnt = (uint32_t)(sg.hi - sg.lo);
+  const uint32_t lo = (uint32_t)(r - sg.lo);
+#pragma unroll
+  for (int g = 0; g < kTailGroups; ++g)
+    if (g * kTailGroup < sg.w)
+      tail_group(M, (uint32_t)sg.off, cnt, lo, (uint32_t)(g * kTailGroup), q.j + g * kTailGroup,
+                 q.v + g * kTailGroup);
+  if (D) q.d = diag[r];
+}
+
+// sum over the row's entries in entry order of val * X[col] (padding adds +0)
+template <class V>
+__device__ __forceinline__ V tail_sum(const TailMat<V>& M, const TailSeg& sg, int32_t r, const TailRow<V>& q,
+                                      const V* X) {
+  V p[kTailW];
+#pragma unroll
+  for (int g = 0; g < kTailGroups; ++g)
+    if (g * kTailGroup < sg.w) {
+#pragma unroll
+      for (int u = 0; u < kTailGroup; ++u) p[g * kTailGroup + u] = q.v[g * kTailGroup + u] * X[q.j[g * kTailGroup + u]];
     }
-    __syncthreads();
+  V acc = V(0);
+#pragma unroll
+  for (int g = 0; g < kTailGroups; ++g)
+    if (g * kTailGroup < sg.w) {
+#pragma unroll
+      for (int u = 0; u < kTailGroup; ++u) acc = acc + p[g * kTailGroup + u];
+    }
+  const uint32_t cnt = (uint32_t)(sg.hi - sg.lo);
+  const uint32_t lo = (uint32_t)(r - sg.lo);
+  for (int32_t t0 = kTailW; t0 < sg.w; t0 += kTailGroup) {
+    int32_t j[kTailGroup];
+    V v[kTailGroup];
+    tail_group(M, (uint32_t)sg.off, cnt, lo, (uint32_t)t0, j, v);
+#pragma unroll
+    for (int u = 0; u < kTailGroup; ++u) acc = acc + v[u] * X[j[u]];
+  }
+  return acc;
+}
+
+// Runs the rows of segments 0..nseg-1 (seg(s) -> TailSeg) through the
+// pipeline; out(r, acc, diag) consumes each row's sum.  A workgroup barrier
+// follows every segment when `barrier_each` (colours of a sweep), else only
+// the last.  Two row buffers alternate (no copies between rounds).
+template <bool D, class V, class Seg, class Out>
+__device__ __forceinline__ void tail_rows(const TailMat<V>& M, const V* diag, int nseg, Seg seg, const V* X,
+                                          bool barrier_each, Out out) {
+  const int32_t tid = threadIdx.x;
+  TailSeg sg = seg(0);
+  int s = 0;
+  int32_t r0 = sg.lo;
+  TailRow<V> ra, rb;
+  tail_fetch<D>(M, diag, sg, max(min(r0 + tid, sg.hi - 1), 0), ra);
+  // one round: loads the next round into nxt, then computes cur; false after the last
+  auto round = [&](TailRow<V>& cur, TailRow<V>& nxt) {
+    TailSeg sg2 = sg;
+    int s2 = s;
+    int32_t r2 = r0 + kTailThreads1;
+    const bool last_round = r2 >= sg.hi;
+    if (last_round) {
+      s2 = s + 1;
+      if (s2 < nseg) {
+        sg2 = seg(s2);
+        r2 = sg2.lo;
+      }
+    }
+    const bool more = s2 < nseg;
+    if (!more) {                // the loads stay unconditional (same count in flight on every path)
+      sg2 = sg;
+      r2 = r0;
+    }
+    tail_fetch<D>(M, diag, sg2, max(min(r2 + tid, sg2.hi - 1), 0), nxt);
+    const int32_t r = r0 + tid;
+    const V acc = tail_sum(M, sg, max(min(r, sg.hi - 1), 0), cur, X);
+    if (r < sg.hi) out(r, acc, cur.d);
+    if (last_round && (barrier_each || !more)) __syncthreads();
+    sg = sg2;
+    s = s2;
+    r0 = r2;
+    return more;
+  };
+  while (round(ra, rb) && round(rb, ra)) {
   }
 }
 
 template <class V>
-__global__ void __launch_bounds__(kTailThreads) k_tail_vcycle(TailDescT<V> d) {
+struct TailLds {
+  V *x, *b, *r;
+  const int4* c;                           // colour table (lo, hi, w, off)
+};
+
+template <class V>
+__device__ __forceinline__ TailLds<V> tail_lds(const TailDescT<V>& d, char* lds, int l) {
+  TailLds<V> t;
+  t.x = reinterpret_cast<V*>(lds + d.o_x[l]);
+  t.b = reinterpret_cast<V*>(lds + d.o_b[l]);
+  t.r = reinterpret_cast<V*>(lds + d.o_r[l]);
+  t.c = reinterpret_cast<const int4*>(lds + d.o_c[l]);
+  return t;
+}
+
+__device__ __forceinline__ TailSeg colour_seg(const int4* ct, int c) {
+  const int4 e = ct[c];
+  return TailSeg{uniform(e.x), uniform(e.y), uniform(e.z), uniform(e.w)};
+}
+
+// nsweeps Gauss-Seidel sweeps over the colours of one tail level.
+template <class V>
+__device__ __forceinline__ void tail_gs(const LevelViewT<V>& L, const TailLds<V>& t, int nsweeps, bool descending) {
+  const int nc = L.ncolors;
+  if (nsweeps <= 0) return;
+  tail_rows<true>(
+      tail_mat(L.e_col_gs, L.e_val_gs, L.e_slots), L.diag, nsweeps * nc,
+      [&](int s) {
+        const int i = s % nc;
+        return colour_seg(t.c, descending ? nc - 1 - i : i);
+      },
+      t.x, true, [&](int32_t r, V acc, V dr) { t.x[r] = (t.b[r] - acc) / dr; });
+}
+
+template <class V>
+__global__ void __launch_bounds__(kTailThreads1) k_tail_vcycle(TailDescT<V> d) {
   extern __shared__ double lds_raw[];
-  V* lds = reinterpret_cast<V*>(lds_raw);
+  char* lds = reinterpret_cast<char*>(lds_raw);
   const int tid = threadIdx.x;
-  V* X0 = d.lds_off[0] >= 0 ? lds + d.lds_off[0] : d.lv[0].x;
-  if (d.lds_off[0] >= 0)
-    for (int32_t i = tid; i < d.lv[0].n; i += kTailThreads) X0[i] = d.lv[0].x[i];
-  __syncthreads();
-  for (int l = 0; l + 1 < d.nlev; ++l) {
+  const int lc = d.nlev - 1;   // the coarsest level
+  // colour tables and the zeros behind x and r; the first tail level's x and b
+  for (int l = 0; l < lc; ++l) {
     const LevelViewT<V>& L = d.lv[l];
-    V* XL = d.lds_off[l] >= 0 ? lds + d.lds_off[l] : L.x;
-    for (int s = 0; s < d.nu_pre; ++s) tail_gs(L, XL, false);
-    for (int32_t r = tid; r < L.n; r += kTailThreads) L.r[r] = L.b[r] - row_sum_seq<kChunkTail>(L.A, r, XL, -1);
-    __syncthreads();
-    const LevelViewT<V>& C = d.lv[l + 1];
-    V* XC = d.lds_off[l + 1] >= 0 ? lds + d.lds_off[l + 1] : C.x;
-    for (int32_t I = tid; I < C.n; I += kTailThreads) {
-      C.b[I] = row_sum_seq<kChunkTail>(L.T, I, (const V*)L.r, -1);
-      XC[I] = V(0);
+    const TailLds<V> t = tail_lds(d, lds, l);
+    int32_t* ct = reinterpret_cast<int32_t*>(lds + d.o_c[l]);
+    for (int i = tid; i < 4 * L.ncolors; i += kTailThreads1) ct[i] = L.e_cinfo[i];
+    if (tid == 0) {
+      t.x[L.n] = V(0);
+      t.r[L.n] = V(0);
     }
-    __syncthreads();
   }
   {
-    const LevelViewT<V>& C = d.lv[d.nlev - 1];
-    V* XC = d.lds_off[d.nlev - 1] >= 0 ? lds + d.lds_off[d.nlev - 1] : C.x;
-    const int lane = tid & (kWave - 1), w = tid / kWave;
-    for (int64_t row = w; row < C.n; row += kTailThreads / kWave) {
-      double s = 0.0;
-      for (int64_t k = lane; k < C.n; k += kWave) s += d.cinv[row * C.n + k] * (double)C.b[k];
-      s = wave_sum(s);
-      if (lane == 0) XC[row] = (V)s;
+    const TailLds<V> t = tail_lds(d, lds, 0);
+    const int32_t n = d.lv[0].n;
+    for (int32_t i0 = 0; i0 < n; i0 += 8 * kTailThreads1) {
+      V xv[8], bv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int32_t i = min(i0 + u * kTailThreads1 + tid, n - 1);
+        xv[u] = d.lv[0].x[i];
+        bv[u] = d.lv[0].b[i];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int32_t i = i0 + u * kTailThreads1 + tid;
+        if (i < n) {
+          t.x[i] = xv[u];
+          t.b[i] = bv[u];
+        }
+      }
     }
-    __syncthreads();
   }
-  for (int l = d.nlev - 2; l >= 0; --l) {
+  __syncthreads();
+  for (int l = 0; l < lc; ++l) {
     const LevelViewT<V>& L = d.lv[l];
-    V* XL = d.lds_off[l] >= 0 ? lds + d.lds_off[l] : L.x;
-    const V* XC = d.lds_off[l + 1] >= 0 ? lds + d.lds_off[l + 1] : d.lv[l + 1].x;
-    for (int32_t i = tid; i < L.n; i += kTailThreads) {
-      const int32_t c = L.q_cnt[i];
-      V acc = V(0);
-      for (int t = 0; t < c; ++t) acc = acc + L.q_val[(int64_t)t * L.n + i] * XC[L.q_col[(int64_t)t * L.n + i]];
-      XL[i] = XL[i] + acc;
+    const TailLds<V> t = tail_lds(d, lds, l);
+    tail_gs(L, t, d.nu_pre, false);
+    // r = b - A x, colour by colour
+    tail_rows<false>(
+        tail_mat(L.e_col, L.e_val, L.e_slots), L.diag, L.ncolors, [&](int s) { return colour_seg(t.c, s); }, t.x,
+        false,
+        [&](int32_t r, V acc, V) { t.r[r] = t.b[r] - acc; });
+    // b_c = P^T r, x_c = 0
+    const TailLds<V> tc = tail_lds(d, lds, l + 1);
+    const int32_t nc = d.lv[l + 1].n;
+    tail_rows<false>(
+        tail_mat(L.e_tcol, L.e_tval, L.e_tslots), L.diag, 1, [&](int) { return TailSeg{0, nc, uniform(L.e_wt), 0}; },
+        t.r, false,
+        [&](int32_t r, V acc, V) {
+          tc.b[r] = acc;
+          tc.x[r] = V(0);
+        });
+  }
+  {
+    // x_c = A_c^-1 b_c in double: row i is the sum over k ascending of
+    // (A_c^-1 e_k)_i b_k, stored at inv[k ld + i].  Each lane sums two rows
+    // (2l, 2l + 1: one 16-byte load per column); the next chunk of columns is
+    // loaded while one is summed.
+    const TailLds<V> t = tail_lds(d, lds, lc);
+    const int32_t n = d.lv[lc].n;
+    const int32_t ld = (int32_t)inv_ld(n);
+    const Rsrc inv = make_rsrc(d.cinv, (int64_t)n * ld * 8);
+    for (int32_t i0 = 0; i0 < n; i0 += 2 * kTailThreads1) {
+      const int32_t i = min(i0 + 2 * tid, ld - 2);       // even: rows i, i + 1 (i + 1 = ld - 1 may be padding)
+      u32x4 m[kTailGemv], mn[kTailGemv];
+#pragma unroll
+      for (int u = 0; u < kTailGemv; ++u) m[u] = bload16(inv, (uint32_t)i * 8u, (uint32_t)(min(u, n - 1) * ld) * 8u);
+      double acc0 = 0.0, acc1 = 0.0;
+      for (int32_t k0 = 0; k0 < n; k0 += kTailGemv) {
+#pragma unroll
+        for (int u = 0; u < kTailGemv; ++u)
+          mn[u] = bload16(inv, (uint32_t)i * 8u, (uint32_t)(min(k0 + kTailGemv + u, n - 1) * ld) * 8u);
+#pragma unroll
+        for (int u = 0; u < kTailGemv; ++u)
+          if (k0 + u < n) {
+            const double bk = (double)t.b[min(k0 + u, n - 1)];
+            acc0 = acc0 + as_f64(m[u].x, m[u].y) * bk;
+            acc1 = acc1 + as_f64(m[u].z, m[u].w) * bk;
+          }
+#pragma unroll
+        for (int u = 0; u < kTailGemv; ++u) m[u] = mn[u];
+      }
+      const int32_t r = i0 + 2 * tid;
+      if (r < n) t.x[r] = (V)acc0;
+      if (r + 1 < n) t.x[r + 1] = (V)acc1;
     }
     __syncthreads();
-    for (int s = 0; s < d.nu_post; ++s) tail_gs(L, XL, d.descending_post != 0);
   }
-  if (d.lds_off[0] >= 0)
-    for (int32_t i = tid; i < d.lv[0].n; i += kTailThreads) d.lv[0].x[i] = X0[i];
+  for (int l = lc - 1; l >= 0; --l) {
+    const LevelViewT<V>& L = d.lv[l];
+    const TailLds<V> t = tail_lds(d, lds, l);
+    const V* XC = tail_lds(d, lds, l + 1).x;
+    // x_i += sum_t P[i, t] x_c[col_t]; the loads of kTailProlong rows per thread are issued together
+    for (int32_t i0 = 0; i0 < L.n; i0 += kTailProlong * kTailThreads1) {
+      int32_t c[kTailProlong];
+      int32_t j[kTailProlong][3];
+      V v[kTailProlong][3];
+#pragma unroll
+      for (int u = 0; u < kTailProlong; ++u) {
+        const int32_t i = min(i0 + u * kTailThreads1 + tid, L.n - 1);
+        c[u] = L.q_cnt[i];
+#pragma unroll
+        for (int e = 0; e < 3; ++e) {
+          j[u][e] = L.q_col[(int64_t)e * L.n + i];
+          v[u][e] = L.q_val[(int64_t)e * L.n + i];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kTailProlong; ++u) {
+        const int32_t i = i0 + u * kTailThreads1 + tid;
+        if (i < L.n) {
+          V acc = V(0);
+#pragma unroll
+          for (int e = 0; e < 3; ++e)
+            if (e < c[u]) acc = acc + v[u][e] * XC[j[u][e]];
+          t.x[i] = t.x[i] + acc;
+        }
+      }
+    }
+    __syncthreads();
+    tail_gs(L, t, d.nu_post, d.descending_post != 0);
+  }
+  {
+    const TailLds<V> t = tail_lds(d, lds, 0);
+    for (int32_t i = tid; i < d.lv[0].n; i += kTailThreads1) d.lv[0].x[i] = t.x[i];
+  }
 }
 
 __global__ void k_gather(const int32_t* perm, const double* src, double* dst, int64_t n) {
@@ -298,12 +578,12 @@ void prolong_correct(const LevelViewT<V>& v, const LevelViewT<V>& c, hipStream_t
 
 template <class V>
 void coarse_solve(const double* cinv, const LevelViewT<V>& c, hipStream_t s) {
-  k_dense_gemv<V><<<blocks_for(c.n, kBlock / kWave), kBlock, 0, s>>>(cinv, c.b, c.x, c.n);
+  k_dense_gemv<V><<<blocks_for(c.n), kBlock, 0, s>>>(cinv, c.b, c.x, c.n);
 }
 
 template <class V>
 void tail_vcycle(const TailDescT<V>& d, hipStream_t s) {
-  k_tail_vcycle<V><<<1, kTailThreads, (size_t)d.lds_elems * sizeof(V), s>>>(d);
+  k_tail_vcycle<V><<<1, kTailThreads1, (size_t)d.lds_bytes, s>>>(d);
 }
 
 template <class V>

@@ -422,7 +422,8 @@ def test_galerkin_keeps_constants_in_the_null_space():
 
 @pytest.mark.parametrize("name", SMALL)
 def test_colouring_first_fit(name):
-    p, h = hier(name)
+    """Without recolouring passes: first-fit in hashed key order (Jones-Plassmann)."""
+    p, h = hier(name, color_passes=0)
     for l in range(h.num_levels - 1):
         lv = h.level(l)
         col = lv["colors"]
@@ -435,6 +436,63 @@ def test_colouring_first_fit(name):
             while mex in lower:
                 mex += 1
             assert col[v] == mex
+
+
+def _iterated_greedy(arp, acol, col, passes):
+    """Culberson's iterated greedy colouring, written out: each pass colours the
+    vertices first-fit, the classes of the previous colouring visited from the
+    highest colour down and by index within a class."""
+    n = len(col)
+    nb = [[u for u in acol[arp[v]:arp[v + 1]] if u != v] for v in range(n)]
+    for _ in range(passes):
+        order = sorted(range(n), key=lambda v: (-col[v], v))
+        new = [-1] * n
+        for v in order:
+            used = {new[u] for u in nb[v] if new[u] >= 0}
+            c = 0
+            while c in used:
+                c += 1
+            new[v] = c
+        col = new
+    return col
+
+
+@pytest.mark.parametrize("name", SMALL)
+def test_colouring_iterated_greedy(name):
+    """The default colouring (3 recolouring passes): valid; first-fit (every vertex of
+    colour c has neighbours of all colours below c); never more colours than the
+    first colouring nor than the previous pass; equal to the passes written out from
+    the pinned first colouring."""
+    p, h0 = hier(name, color_passes=0)
+    counts = [h0.sizes(l)["colors"] for l in range(h0.num_levels - 1)]
+    for passes in (1, 2, 3):
+        _, h = hier(name, color_passes=passes)
+        assert h.num_levels == h0.num_levels
+        for l in range(h.num_levels - 1):
+            lv, l0 = h.level(l), h0.level(l)
+            col = lv["colors"]
+            nc = int(col.max()) + 1
+            assert h.sizes(l)["colors"] == nc <= counts[l]
+            counts[l] = nc
+            for v in range(lv["n"]):
+                nb = [u for u in lv["acol"][lv["arp"][v]:lv["arp"][v + 1]] if u != v]
+                seen = {int(col[u]) for u in nb}
+                assert col[v] not in seen
+                assert all(c in seen for c in range(col[v]))
+            if passes == 3:
+                ref = _iterated_greedy(l0["arp"], l0["acol"], list(l0["colors"]), 3)
+                assert list(col) == ref
+    # the default options are these three passes
+    _, hd = hier(name)
+    for l in range(hd.num_levels - 1):
+        assert np.array_equal(hd.level(l)["colors"], h.level(l)["colors"])
+
+
+def test_colour_passes_out_of_range():
+    p = problem("ico3")
+    for k in (-1, 65):
+        with pytest.raises(oracle.OracleError):
+            oracle.Hierarchy.from_problem(p, oracle.default_options(color_passes=k))
 
 
 @pytest.mark.parametrize("name", SMALL)
