@@ -444,7 +444,7 @@ void build(Handle& h, int64_t n, const double* points, int64_t m, const int32_t*
     tail_bytes += more;
     --h.tail_start;
   }
-  for (int l = h.tail_start; l + 1 < nl; ++l) tail_layout(h, h.L[l], h.L[l + 1]);
+  for (int l = ell_first_level(h); l + 1 < nl; ++l) ell_layout(h, h.L[l], h.L[l + 1]);
   h.plain.v.clear();
   for (int l = 0; l < nl; ++l) h.plain.v.push_back(h.L[l].view);
   h.plain.symmetric = false;
@@ -1240,7 +1240,7 @@ int gmg_update_matrix(gmg_handle hh, const double* A_val_dev, void* stream) {
     check_hip(hipMemcpyAsync(l0.aval, A_val_dev, (size_t)l0.nnzA * 8, hipMemcpyDeviceToDevice, s), "copy values");
     for (int l = 0; l + 1 < nl; ++l) galerkin_values(*h, h->L[l], h->L[l + 1]);
     for (int l = 0; l < nl; ++l) refresh_values(*h, h->L[l]);
-    for (int l = h->tail_start; l + 1 < nl; ++l) tail_values(*h, h->L[l]);
+    for (int l = ell_first_level(*h); l + 1 < nl; ++l) ell_values(*h, h->L[l]);
     coarse_factor(*h, h->L[nl - 1]);                 // also raises the flags of the steps above
     if (h->kry.ready[1])
       for (int l = 0; l + 1 < nl; ++l) {

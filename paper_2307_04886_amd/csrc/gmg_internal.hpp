@@ -128,7 +128,8 @@ struct LevelViewT {
   V* x = nullptr;
   V* b = nullptr;
   V* r = nullptr;
-  // Levels of the single-workgroup tail: A_l in per-colour blocked ELL
+  // Levels of the single-workgroup tail (not the coarsest): A_l in per-colour
+  // blocked ELL
   // (colour c: rows [lo, hi), width w a multiple of kTailGroup, element
   // offset off; entry positions from ell_col_index / ell_val_index), once with
   // its diagonal (residual) and once without (Gauss-Seidel: the diagonal's
@@ -394,8 +395,9 @@ void solve_layout(Handle& h, Level& lv, const Level* nx, const int32_t* t_rp, co
                   const double* t_val);
 void coarse_factor(Handle& h, Level& lv);
 void refresh_values(Handle& h, Level& lv);                 // SELL values and diagonal from lv.aval
-void tail_layout(Handle& h, Level& lv, const Level& nx);    // tail ELL of A_l and P_l^T (view.e_*)
-void tail_values(Handle& h, Level& lv);                    // tail ELL values of A_l from its SELL
+void ell_layout(Handle& h, Level& lv, const Level& nx);    // blocked ELL of A_l and P_l^T (view.e_*)
+void ell_values(Handle& h, Level& lv);                     // blocked ELL values of A_l from its SELL
+int ell_first_level(const Handle& h);                      // levels ell_first_level.. (not the coarsest) have it
 
 // ------------------------------------------------------------------ launchers (solve.hip)
 // V-cycle phases on one level, for V = double and V = float.  gs_sweep visits

@@ -41,6 +41,7 @@ __global__ void __launch_bounds__(kBlock) k_tile_sums(const int32_t* in, int64_t
   if (threadIdx.x == 0) sums[blockIdx.x] = tot;
 }
 
+// The last block also writes out[n] = the total.
 __global__ void __launch_bounds__(kBlock) k_tile_scan(const int32_t* in, int64_t n,
                                                       const int32_t* offs, int32_t* out) {
   __shared__ int32_t tile[kScanTile];
@@ -57,18 +58,15 @@ __global__ void __launch_bounds__(kBlock) k_tile_scan(const int32_t* in, int64_t
     s += tile[threadIdx.x * kScanItems + k];
   }
   int32_t tot;
-  int32_t ex = block_exclusive_scan(s, &tot) + (offs ? offs[blockIdx.x] : 0);
+  const int32_t off = offs ? offs[blockIdx.x] : 0;
+  int32_t ex = block_exclusive_scan(s, &tot) + off;
   for (int k = 0; k < kScanItems; ++k) tile[threadIdx.x * kScanItems + k] = ex + loc[k];
   __syncthreads();
   for (int k = 0; k < kScanItems; ++k) {
     int64_t i = base + (int64_t)k * kBlock + threadIdx.x;
     if (i < n) out[i] = tile[k * kBlock + threadIdx.x];
   }
-}
-
-// out[n] = total, from the last scanned element.
-__global__ void k_scan_total(const int32_t* in, int64_t n, int32_t* out) {
-  out[n] = n > 0 ? out[n - 1] + in[n - 1] : 0;
+  if (threadIdx.x == 0 && blockIdx.x == gridDim.x - 1) out[n] = off + tot;
 }
 
 template <typename T>
@@ -129,7 +127,6 @@ void scan_i32(const int32_t* in, int32_t* out, int64_t n, hipStream_t s) {
     tfree(s, sums);
     tfree(s, offs);
   }
-  k_scan_total<<<1, 1, 0, s>>>(in, n, out);
 }
 
 void fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s) {

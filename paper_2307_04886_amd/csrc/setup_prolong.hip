@@ -276,10 +276,10 @@ __global__ void __launch_bounds__(kBlock) k_sort_pairs(const int32_t* ptr, int32
 // The (i, j) pairs of a row are enumerated 64 at a time (one per lane, after
 // a wavefront prefix sum over the row lengths), so a row's dependent loads
 // are issued for 64 pairs at once.
-// Symbolic pass: the distinct J go into an LDS hash set.  Numeric pass: the
-// terms are staged in LDS in definition order, and the lane that owns output
-// column J adds the staged terms of J in that order, so each entry is summed
-// exactly like the definition's row accumulation.
+// Symbolic pass: the distinct J go into an LDS hash set.  Numeric pass: for
+// every 64 pairs the lane that owns output column J adds the terms of J of
+// those pairs in pair order, so each entry is summed exactly like the
+// definition's row accumulation.
 
 // Inclusive scan of one int per lane over a wavefront.
 __device__ inline int wave_incl_scan(int v) {
@@ -382,12 +382,14 @@ __global__ void __launch_bounds__(kWave) k_galerkin_fill(const int32_t* trp, con
                                                          const int32_t* pcol, const double* pval,
                                                          const int32_t* pcnt, int64_t nc, const int32_t* crp,
                                                          int32_t* ccol, double* cval, int32_t* flags) {
-  constexpr int kT = HS;               // terms staged at a time
+  constexpr int kOut = HS * 3 / 4;     // distinct columns of a row (the symbolic pass checked the bound)
   __shared__ int32_t keys[HS];
-  __shared__ int32_t sorted[HS * 3 / 4];
-  __shared__ double accum[HS * 3 / 4];
-  __shared__ int32_t termJ[kT];
-  __shared__ double termV[kT];
+  __shared__ int32_t rank_of[HS];      // hash slot -> position of its column in the sorted row
+  __shared__ int32_t sorted[kOut];
+  __shared__ double accum[kOut];
+  __shared__ unsigned long long hits[kOut];   // per output column: the pairs of the chunk that add to it
+  __shared__ int32_t tR[3 * kWave];    // per pair of the chunk: output position of each term (-1: none)
+  __shared__ double tV[3 * kWave];     // and its value
   __shared__ PairChunk pc;
   __shared__ int32_t nlist;
   const int32_t I = blockIdx.x;
@@ -412,60 +414,87 @@ __global__ void __launch_bounds__(kWave) k_galerkin_fill(const int32_t* trp, con
     __syncthreads();
   }
   for (int s = lane; s < HS; s += kWave)
-    if (keys[s] >= 0) termJ[atomicAdd(&nlist, 1)] = keys[s];      // termJ used as scratch here
+    if (keys[s] >= 0) sorted[atomicAdd(&nlist, 1)] = s;            // slots, in any order
   __syncthreads();
   const int k = nlist;
-  for (int a = lane; a < k; a += kWave) {
-    int32_t key = termJ[a];
-    int rank = 0;
-    for (int b = 0; b < k; ++b) rank += termJ[b] < key;
-    sorted[rank] = key;
-    accum[rank] = 0.0;
+  int32_t myslot[kOut / kWave], mykey[kOut / kWave];
+#pragma unroll
+  for (int g = 0; g < kOut / kWave; ++g) {
+    const int a = lane + g * kWave;
+    myslot[g] = a < k ? sorted[a] : -1;
+    mykey[g] = a < k ? keys[myslot[g]] : 0;
   }
   __syncthreads();
-  int base = 0;
-  auto flush = [&]() {
-    __syncthreads();
-    for (int o = lane; o < k; o += kWave) {
-      const int32_t J = sorted[o];
-      double acc = accum[o];
-      for (int t = 0; t < base; ++t)
-        if (termJ[t] == J) acc = acc + termV[t];
-      accum[o] = acc;
+#pragma unroll
+  for (int g = 0; g < kOut / kWave; ++g)
+    if (lane + g * kWave < k) {
+      int rank = 0;
+      for (int b = 0; b < k; ++b) rank += keys[sorted[b]] < mykey[g];
+      rank_of[myslot[g]] = rank;
     }
-    __syncthreads();
-    base = 0;
-  };
+  __syncthreads();
+#pragma unroll
+  for (int g = 0; g < kOut / kWave; ++g)
+    if (lane + g * kWave < k) {
+      sorted[rank_of[myslot[g]]] = mykey[g];
+      accum[rank_of[myslot[g]]] = 0.0;
+    }
+  __syncthreads();
+  // Numeric pass, 64 (i, j) pairs at a time in definition order.  Each pair
+  // adds at most one term to an output column (the columns of a row of P are
+  // distinct), so the owner of column o adds the terms of the pairs flagged in
+  // hits[o] in ascending pair order: every entry is summed in the order of the
+  // definition.
   for (int32_t q0 = trp[I]; q0 < trp[I + 1]; q0 += kWave) {
     const int tot = load_pairs(q0, trp[I + 1], tcol, tval, arp, pc);
     for (int p0 = 0; p0 < tot; p0 += kWave) {
       const int p = p0 + lane;
       const bool on = p < tot;
-      int src = 0;
-      int32_t e = 0, j = 0;
+      int32_t j = 0;
       int c = 0;
       double t1 = 0.0;
       if (on) {
+        int src;
+        int32_t e;
         locate_pair(pc, p, src, e);
         j = acol[e];
         c = pcnt[j];
         t1 = pc.piI[src] * aval[e];
       }
-      const int incl = wave_incl_scan(c);
-      const int total = __shfl(incl, kWave - 1, kWave);
-      if (base + total > kT) flush();
-      if (on) {
-        const int pos = base + incl - c;
-        for (int t = 0; t < c; ++t) {
-          termJ[pos + t] = pcol[3 * j + t];
-          termV[pos + t] = t1 * pval[3 * j + t];
+      for (int o = lane; o < k; o += kWave) hits[o] = 0ull;
+#pragma unroll
+      for (int t = 0; t < 3; ++t) {
+        int32_t r = -1;
+        double v = 0.0;
+        if (t < c) {
+          const int32_t J = pcol[3 * j + t];
+          uint32_t h = ((uint32_t)J * 2654435761u) & (HS - 1);
+          while (keys[h] != J) h = (h + 1) & (HS - 1);
+          r = rank_of[h];
+          v = t1 * pval[3 * j + t];
         }
+        tR[3 * lane + t] = r;
+        tV[3 * lane + t] = v;
       }
-      base += total;
+      __syncthreads();
+#pragma unroll
+      for (int t = 0; t < 3; ++t)
+        if (t < c) atomicOr(&hits[tR[3 * lane + t]], 1ull << lane);
+      __syncthreads();
+      for (int o = lane; o < k; o += kWave) {
+        unsigned long long m = hits[o];
+        double acc = accum[o];
+        while (m) {
+          const int q = __builtin_ctzll(m);
+          m &= m - 1;
+          const int t = tR[3 * q] == o ? 0 : (tR[3 * q + 1] == o ? 1 : 2);
+          acc = acc + tV[3 * q + t];
+        }
+        accum[o] = acc;
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
-  flush();
   const int32_t out = crp[I];
   bool diag_ok = false;
   for (int o = lane; o < k; o += kWave) {

@@ -650,9 +650,15 @@ void refresh_values(Handle& h, Level& lv) {
                                                          (int32_t*)v.A.col, (double*)v.A.val, lv.diag);
 }
 
-// The tail's ELL copies of A_l and P_l^T (see LevelViewT): colour widths are
-// read back once to lay the colours out.
-void tail_layout(Handle& h, Level& lv, const Level& nx) {
+// The levels of the single-workgroup tail keep blocked ELL copies of A_l and
+// P_l^T.  (The same layout for the multi-launch Gauss-Seidel kernels of the
+// Galerkin levels measured no faster than SELL: their launches are bound by
+// the per-launch cost.)
+int ell_first_level(const Handle& h) { return h.tail_start; }
+
+// Blocked ELL copies of A_l and P_l^T (see LevelViewT): colour widths are read
+// back once to lay the colours out.
+void ell_layout(Handle& h, Level& lv, const Level& nx) {
   hipStream_t s = h.stream;
   LevelView& v = lv.view;
   const int C = v.ncolors;
@@ -684,7 +690,7 @@ void tail_layout(Handle& h, Level& lv, const Level& nx) {
   v.e_col = (int32_t*)dalloc(h, e * 4);
   v.e_val_gs = (double*)dalloc(h, e * 8);
   v.e_val = (double*)dalloc(h, e * 8);
-  tail_values(h, lv);
+  ell_values(h, lv);
   v.e_wt = (v.maxt + kTailGroup - 1) / kTailGroup * kTailGroup;
   lv.e_tslots = (int64_t)v.e_wt * nx.n;
   v.e_tslots = (int32_t)lv.e_tslots;
@@ -697,7 +703,7 @@ void tail_layout(Handle& h, Level& lv, const Level& nx) {
   sync(s, "tail layout");   // the staging buffer is reused by the next call
 }
 
-void tail_values(Handle& h, Level& lv) {
+void ell_values(Handle& h, Level& lv) {
   const LevelView& v = lv.view;
   k_tail_ell<<<blocks_for(lv.n), kBlock, 0, h.stream>>>(v.A, v.e_cinfo, v.ncolors, lv.n, (int32_t*)v.e_col_gs,
                                                         (double*)v.e_val_gs, (int32_t*)v.e_col, (double*)v.e_val);
