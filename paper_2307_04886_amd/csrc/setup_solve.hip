@@ -244,34 +244,60 @@ __global__ void k_dense_scatter(const int32_t* rp, const int32_t* col, const dou
 // same order as the column-by-column definition, whatever the blocking.
 constexpr int kPanel = 32;
 
+// Lane l's value of v, for a lane index known at compile time.
+__device__ __forceinline__ double read_lane(double v, int l) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), l);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
 // Factor the diagonal block of panel k0 and solve the panel rows below it.
-__global__ void __launch_bounds__(1024) k_chol_panel(double* D, int64_t n, int64_t k0, int32_t* flags) {
+// The diagonal block is factored by the first wavefront, lane i holding row i
+// in registers: column c of the block is l_ic = (a_ic - sum_{m<c} l_im l_cm)
+// / l_cc (ascending m), l_cc = sqrt(a_cc - sum_{m<c} l_cm^2).
+__global__ void __launch_bounds__(256) k_chol_panel(double* D, int64_t n, int64_t k0, int32_t* flags) {
   __shared__ double T[kPanel][kPanel + 1];
   __shared__ int bad;
   const int tid = threadIdx.x;
   const int kb = (int)(n - k0 < kPanel ? n - k0 : kPanel);
-  const int ti = tid / kPanel, tc = tid % kPanel;
-  if (tid == 0) bad = 0;
-  if (ti < kb && tc <= ti) T[ti][tc] = D[(k0 + ti) * n + k0 + tc];
-  __syncthreads();
-  for (int j = 0; j < kb; ++j) {
-    if (tid == 0) {
-      const double sv = T[j][j];
-      if (!(sv > 0.0)) {
-        bad = 1;
-        atomicOr(flags, F_NOT_SPD);
-      } else {
-        T[j][j] = sqrt(sv);
+  if (tid < kWave) {
+    const int i = tid;
+    double r[kPanel];
+#pragma unroll
+    for (int c = 0; c < kPanel; ++c) r[c] = (i < kb && c <= i) ? D[(k0 + i) * n + k0 + c] : 0.0;
+    bool ok = true;
+#pragma unroll
+    for (int c = 0; c < kPanel; ++c) {
+      if (c < kb) {
+        double t = r[c];
+#pragma unroll
+        for (int m = 0; m < c; ++m) t = t - r[m] * read_lane(r[m], c);
+        const double dc = read_lane(t, c);
+        ok = ok && dc > 0.0;
+        const double d = ok ? sqrt(dc) : 1.0;
+        if (i == c) r[c] = d;
+        else if (i > c) r[c] = t / d;
       }
+      __builtin_amdgcn_sched_barrier(0);   // one column at a time: bounds the live registers
     }
-    __syncthreads();
-    if (bad) return;
-    if (tid > j && tid < kb) T[tid][j] = T[tid][j] / T[j][j];
-    __syncthreads();
-    if (ti > j && ti < kb && tc > j && tc <= ti) T[ti][tc] = T[ti][tc] - T[ti][j] * T[tc][j];
-    __syncthreads();
+    if (i < kb) {
+#pragma unroll
+      for (int c = 0; c < kPanel; ++c)
+        if (c <= i) T[i][c] = r[c];
+    }
+    if (ok && i < kb) {
+#pragma unroll
+      for (int c = 0; c < kPanel; ++c)
+        if (c <= i) D[(k0 + i) * n + k0 + c] = r[c];
+    }
+    if (tid == 0) {
+      bad = ok ? 0 : 1;
+      if (!ok) atomicOr(flags, F_NOT_SPD);
+    }
   }
-  if (ti < kb && tc <= ti) D[(k0 + ti) * n + k0 + tc] = T[ti][tc];
+  __syncthreads();
+  if (bad) return;
   // panel rows: l_ij = (a_ij - sum_{k0 <= m < j} l_im l_jm) / l_jj, ascending j
   for (int64_t i = k0 + kb + tid; i < n; i += blockDim.x) {
     double a[kPanel];
@@ -279,10 +305,13 @@ __global__ void __launch_bounds__(1024) k_chol_panel(double* D, int64_t n, int64
     for (int j = 0; j < kPanel; ++j) a[j] = j < kb ? D[i * n + k0 + j] : 0.0;
 #pragma unroll
     for (int j = 0; j < kPanel; ++j) {
-      if (j >= kb) break;
-      double t = a[j];
-      for (int m = 0; m < j; ++m) t = t - a[m] * T[j][m];
-      a[j] = t / T[j][j];
+      if (j < kb) {
+        double t = a[j];
+#pragma unroll
+        for (int m = 0; m < j; ++m) t = t - a[m] * T[j][m];
+        a[j] = t / T[j][j];
+      }
+      __builtin_amdgcn_sched_barrier(0);
     }
 #pragma unroll
     for (int j = 0; j < kPanel; ++j)
@@ -321,16 +350,44 @@ __global__ void k_split_factor(const double* D, int64_t n, double* L, double* U)
   U[k * n + i] = v;
 }
 
-// Column c of A^-1 = L^-T L^-1 e_c by blocked forward then backward
-// substitution, one wavefront per column: for each block of 32 rows the
-// wavefront forms the products with the already-solved part in parallel,
-// then solves the block's triangle column by column (lane k owns row k of
-// the block; the 32x32 diagonal block is staged in LDS).  Written as row c
-// (A^-1 is symmetric).
-__global__ void __launch_bounds__(kWave) k_chol_inverse(const double* L, const double* U, int64_t n,
-                                                        double* inv) {
+// Inverses of the diagonal blocks of L (kPanel x kPanel, lower triangular,
+// row-major, identity outside a short last block): one wavefront per block,
+// lane j solving L_bb x = e_j by forward substitution.
+__global__ void __launch_bounds__(kWave) k_chol_block_inv(const double* L, int64_t n, double* Dinv) {
+  __shared__ double T[kPanel][kPanel + 1];
+  const int64_t b0 = (int64_t)blockIdx.x * kPanel;
+  const int nb = (int)(n - b0 < kPanel ? n - b0 : kPanel);
+  const int lane = threadIdx.x;
+  for (int e = lane; e < kPanel * kPanel; e += kWave) {
+    const int i = e / kPanel, k = e % kPanel;
+    T[i][k] = (i < nb && k < nb) ? L[(b0 + i) * n + b0 + k] : (i == k ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  if (lane >= kPanel) return;
+  double x[kPanel];
+#pragma unroll
+  for (int i = 0; i < kPanel; ++i) {
+    double s = i == lane ? 1.0 : 0.0;
+#pragma unroll
+    for (int m = 0; m < i; ++m) s = s - T[i][m] * x[m];
+    x[i] = s / T[i][i];
+    __builtin_amdgcn_sched_barrier(0);
+  }
+#pragma unroll
+  for (int i = 0; i < kPanel; ++i) Dinv[((int64_t)blockIdx.x * kPanel + i) * kPanel + lane] = x[i];
+}
+
+constexpr int kInvChunk = 8;
+
+// Column c of A^-1 = L^-T L^-1 e_c, one wavefront per column, by blocks of
+// kPanel rows: forward y_b = Dinv_b (e_b - sum_{k<b} L_bk y_k), then backward
+// x_b = Dinv_b^T (y_b - sum_{k>b} L_kb^T x_k).  The two halves of the
+// wavefront sum alternate terms of the off-diagonal products.
+__global__ void __launch_bounds__(kWave) k_chol_inverse(const double* L, const double* U, const double* Dinv,
+                                                        int64_t n, double* inv) {
   extern __shared__ double y[];
-  __shared__ double tile[kPanel][kPanel + 1];
+  __shared__ double Di[kPanel][kPanel + 1];
+  __shared__ double sv[kPanel];
   const int64_t c = blockIdx.x;
   const int lane = threadIdx.x;
   const int r = lane & (kPanel - 1), half = lane / kPanel;
@@ -338,41 +395,55 @@ __global__ void __launch_bounds__(kWave) k_chol_inverse(const double* L, const d
   __syncthreads();
   for (int64_t b0 = (c / kPanel) * kPanel; b0 < n; b0 += kPanel) {
     const int nb = (int)(n - b0 < kPanel ? n - b0 : kPanel);
+    const double* D = Dinv + (b0 / kPanel) * kPanel * kPanel;
     double sacc = 0.0;
     if (r < nb)
-      for (int64_t m = c + half; m < b0; m += 2) sacc += L[(b0 + r) * n + m] * y[m];
+      for (int64_t m0 = c + half; m0 < b0; m0 += 2 * kInvChunk) {   // loads of a chunk in flight together
+        double lv[kInvChunk], yv[kInvChunk];
+#pragma unroll
+        for (int u = 0; u < kInvChunk; ++u) {
+          const int64_t m = m0 + 2 * u;
+          lv[u] = m < b0 ? L[(b0 + r) * n + m] : 0.0;
+          yv[u] = m < b0 ? y[m] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kInvChunk; ++u) sacc += lv[u] * yv[u];
+      }
     sacc += __shfl_xor(sacc, kPanel, kWave);
-    for (int k = half; k < kPanel; k += 2)
-      tile[r][k] = (r < nb && k < nb) ? L[(b0 + r) * n + b0 + k] : 0.0;
+    for (int k = half; k < kPanel; k += 2) Di[r][k] = D[r * kPanel + k];
+    if (half == 0) sv[r] = (b0 + r == c ? 1.0 : 0.0) - sacc;
     __syncthreads();
-    const int64_t row = b0 + r;
-    double t = (row == c ? 1.0 : 0.0) - sacc;
-    for (int k = 0; k < nb; ++k) {
-      if (lane == k) t = (b0 + k < c) ? 0.0 : t / tile[k][k];
-      const double yk = __shfl(t, k, kWave);
-      if (r > k) t = t - tile[r][k] * yk;
-    }
-    if (lane < nb) y[row] = (row < c) ? 0.0 : t;
+    double t = 0.0;
+    for (int k = 0; k <= r; ++k) t += Di[r][k] * sv[k];
+    __syncthreads();
+    if (half == 0 && r < nb) y[b0 + r] = t;
     __syncthreads();
   }
-  for (int64_t b1 = n; b1 > 0; b1 -= kPanel) {
-    const int64_t b0 = b1 - kPanel > 0 ? b1 - kPanel : 0;
-    const int nb = (int)(b1 - b0);
+  for (int64_t b0 = (n - 1) / kPanel * kPanel; b0 >= 0; b0 -= kPanel) {
+    const int nb = (int)(n - b0 < kPanel ? n - b0 : kPanel);
+    const int64_t b1 = b0 + nb;
+    const double* D = Dinv + (b0 / kPanel) * kPanel * kPanel;
     double sacc = 0.0;
     if (r < nb)
-      for (int64_t m = b1 + half; m < n; m += 2) sacc += U[(b0 + r) * n + m] * y[m];
+      for (int64_t m0 = b1 + half; m0 < n; m0 += 2 * kInvChunk) {
+        double uv[kInvChunk], yv[kInvChunk];
+#pragma unroll
+        for (int u = 0; u < kInvChunk; ++u) {
+          const int64_t m = m0 + 2 * u;
+          uv[u] = m < n ? U[(b0 + r) * n + m] : 0.0;
+          yv[u] = m < n ? y[m] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kInvChunk; ++u) sacc += uv[u] * yv[u];
+      }
     sacc += __shfl_xor(sacc, kPanel, kWave);
-    for (int k = half; k < kPanel; k += 2)
-      tile[r][k] = (r < nb && k < nb) ? U[(b0 + r) * n + b0 + k] : 0.0;
+    for (int k = half; k < kPanel; k += 2) Di[r][k] = D[r * kPanel + k];
+    if (half == 0) sv[r] = (r < nb ? y[b0 + r] : 0.0) - sacc;
     __syncthreads();
-    double t = (r < nb ? y[b0 + r] : 0.0) - sacc;
-    for (int k = nb - 1; k >= 0; --k) {
-      if (lane == k) t = t / tile[k][k];
-      const double xk = __shfl(t, k, kWave);
-      if (r < k) t = t - tile[r][k] * xk;
-    }
+    double t = 0.0;
+    for (int k = r; k < kPanel; ++k) t += Di[k][r] * sv[k];
     __syncthreads();
-    if (lane < nb) y[b0 + r] = t;
+    if (half == 0 && r < nb) y[b0 + r] = t;
     __syncthreads();
   }
   const int64_t ld = inv_ld(n);
@@ -626,7 +697,7 @@ void coarse_factor(Handle& h, Level& lv) {
   k_dense_scatter<<<blocks_for(n), kBlock, 0, s>>>(lv.arp, lv.acol, lv.aval, n, D);
   for (int64_t k0 = 0; k0 < n; k0 += kPanel) {
     const int kb = (int)std::min<int64_t>(kPanel, n - k0);
-    k_chol_panel<<<1, 1024, 0, s>>>(D, n, k0, h.flags);
+    k_chol_panel<<<1, 256, 0, s>>>(D, n, k0, h.flags);
     const int64_t m = n - k0 - kb;
     if (m > 0) {
       const int t = (int)((m + kPanel - 1) / kPanel);
@@ -636,11 +707,15 @@ void coarse_factor(Handle& h, Level& lv) {
   if (!h.chol) h.chol = (double*)dalloc(h, (size_t)n * n * 8);
   if (!h.cinv) h.cinv = (double*)dalloc(h, (size_t)n * inv_ld(n) * 8);
   k_split_factor<<<blocks_for(n * n), kBlock, 0, s>>>(D, n, h.chol, U);
-  k_chol_inverse<<<(int)n, kWave, (size_t)n * 8, s>>>(h.chol, U, n, h.cinv);
+  const int64_t nbk = (n + kPanel - 1) / kPanel;
+  double* Dinv = (double*)talloc(s, (size_t)nbk * kPanel * kPanel * 8);
+  k_chol_block_inv<<<(int)nbk, kWave, 0, s>>>(h.chol, n, Dinv);
+  k_chol_inverse<<<(int)n, kWave, (size_t)n * 8, s>>>(h.chol, U, Dinv, n, h.cinv);
   h.ncoarse = n;
   check_flags(h, "coarsest factorisation");
   tfree(s, D);
   tfree(s, U);
+  tfree(s, Dinv);
 }
 
 // New values of A_l (same pattern) into its SELL layout and diagonal.
