@@ -196,17 +196,76 @@ __device__ inline bool lfmis_attempt(const int32_t* rp, const int32_t* col, cons
   return !out && blocked;
 }
 
+// On levels of up to kListLevel points the first visit of p also records the
+// points in conflict with it that come earlier in the sweep (its whole 2-ring
+// search, in search order, repeats included) in list[p * kConflicts ..], with
+// their number in cnt[p] (kConflicts + 1: too many, later visits search
+// again); later visits then only read those points' statuses.  (On larger
+// levels the first round streams the graph at full bandwidth, and writing the
+// lists cost more than the later rounds saved.)
+constexpr int kConflicts = 32;
+constexpr int64_t kListLevel = 262144;
+
+__device__ inline bool lfmis_first(const int32_t* rp, const int32_t* col, const double* w, double r,
+                                   const SweepKey& key, uint8_t* status, int32_t p, int32_t* list, uint8_t* cnt) {
+  const uint64_t kp = key(p);
+  bool blocked = false, out = false;
+  int32_t k = 0;
+  int32_t* lp = list + (int64_t)p * kConflicts;
+  auto note = [&](int32_t q) {
+    const uint8_t s = __atomic_load_n(&status[q], __ATOMIC_RELAXED);
+    if (s == 1) out = true; else if (s == 0) blocked = true;
+    if (k < kConflicts) lp[k] = q;
+    ++k;
+  };
+  for (int32_t e = rp[p]; e < rp[p + 1]; ++e) {
+    const int32_t m = col[e];
+    const double wpm = w[e];
+    if (wpm <= r && key_less(key(m), m, kp, p)) note(m);
+    for (int32_t f = rp[m]; f < rp[m + 1]; ++f) {
+      const int32_t q = col[f];
+      if (q != p && wpm + w[f] <= r && key_less(key(q), q, kp, p)) note(q);
+    }
+  }
+  cnt[p] = (uint8_t)(k <= kConflicts ? k : kConflicts + 1);
+  if (out) status[p] = 2;
+  else if (!blocked) status[p] = 1;
+  return !out && blocked;
+}
+
+__device__ inline bool lfmis_again(const int32_t* rp, const int32_t* col, const double* w, double r,
+                                   const SweepKey& key, uint8_t* status, int32_t p, const int32_t* list,
+                                   const uint8_t* cnt) {
+  const int32_t k = cnt[p];
+  if (k > kConflicts) return lfmis_attempt(rp, col, w, r, key, status, p);
+  const int32_t* lp = list + (int64_t)p * kConflicts;
+  bool blocked = false, out = false;
+  for (int32_t i = 0; i < k; ++i) {
+    const uint8_t s = __atomic_load_n(&status[lp[i]], __ATOMIC_RELAXED);
+    if (s == 1) out = true; else if (s == 0) blocked = true;
+  }
+  if (out) status[p] = 2;
+  else if (!blocked) status[p] = 1;
+  return !out && blocked;
+}
+
 __global__ void __launch_bounds__(kBlock) k_lfmis_round(const int32_t* rp, const int32_t* col,
                                                         const double* w, int64_t n, const double* scal,
                                                         SweepKey key, uint8_t* status, const int32_t* wl_in,
-                                                        int32_t* wl_out, int32_t* rounds, int k) {
+                                                        int32_t* wl_out, int32_t* rounds, int k, int32_t* list,
+                                                        uint8_t* cnt) {
   const int64_t count = k == 0 ? n : rounds[k - 1];
   const double r = scal[1];
   for (int64_t base = (int64_t)blockIdx.x * kBlock; base < count; base += (int64_t)gridDim.x * kBlock) {
     const int64_t i = base + threadIdx.x;
     const bool act = i < count;
     const int32_t p = act ? (k == 0 ? (int32_t)i : wl_in[i]) : 0;
-    const bool pend = act && lfmis_attempt(rp, col, w, r, key, status, p);
+    bool pend = false;
+    if (act) {
+      if (!list) pend = lfmis_attempt(rp, col, w, r, key, status, p);
+      else if (k == 0) pend = lfmis_first(rp, col, w, r, key, status, p, list, cnt);
+      else pend = lfmis_again(rp, col, w, r, key, status, p, list, cnt);
+    }
     block_append(pend, p, wl_out, &rounds[k]);
   }
 }
@@ -413,12 +472,15 @@ int64_t sample_lfmis(Handle& h, Level& lv, int level) {
   const int grid = std::min(blocks_for(n), kRoundGrid);
   int32_t* f = (int32_t*)talloc(s, (size_t)(n + 1) * 4);
   int32_t* ids = (int32_t*)talloc(s, (size_t)(n + 1) * 4);
+  const bool lists = n <= kListLevel;
+  int32_t* list = lists ? (int32_t*)talloc(s, (size_t)n * kConflicts * 4) : nullptr;
+  uint8_t* cnt = lists ? (uint8_t*)talloc(s, (size_t)n) : nullptr;
   int k = 0;
   int64_t nc = 0;
   for (;;) {
     for (int t = 0; t < kRoundBatch; ++t, ++k)
       k_lfmis_round<<<grid, kBlock, 0, s>>>(lv.erp, lv.ecol, lv.ew, n, lv.scal, key, status,
-                                            wl + ((k + 1) % 2) * n, wl + (k % 2) * n, h.rounds, k);
+                                            wl + ((k + 1) % 2) * n, wl + (k % 2) * n, h.rounds, k, list, cnt);
     // coarse ids, valid if this batch finished the sweep (read together with the round count)
     k_seed_flags<<<blocks_for(n), kBlock, 0, s>>>(status, n, f);
     scan_i32(f, ids, n, s);
@@ -429,6 +491,10 @@ int64_t sample_lfmis(Handle& h, Level& lv, int level) {
     if (k + kRoundBatch > kMaxRounds) throw Error{GMG_DEVICE_ERROR, "sampling did not terminate"};
   }
   tfree(s, wl);
+  if (lists) {
+    tfree(s, list);
+    tfree(s, cnt);
+  }
   lv.nc = nc;
   lv.samples = (int32_t*)dalloc(h, (size_t)(nc + 1) * 4);
   k_collect_samples<<<blocks_for(n), kBlock, 0, s>>>(status, ids, n, lv.samples);
