@@ -152,6 +152,7 @@ void throw_flags(int32_t f, const char* phase) {
   if (f & F_INVALID) throw Error{GMG_INVALID_ARGUMENT, std::string(phase) + ": invalid input"};
   if (f & F_NOT_SPD) throw Error{GMG_NOT_SPD, std::string(phase) + ": non-positive diagonal or pivot"};
   if (f & F_OVERFLOW) throw Error{GMG_DEVICE_ERROR, std::string(phase) + ": a coarse row is too dense"};
+  if (f & F_TIMEOUT) throw Error{GMG_DEVICE_ERROR, std::string(phase) + ": rounds did not terminate"};
 }
 
 void set_error(const std::string& m) { g_last_error = m; }

@@ -20,10 +20,14 @@ constexpr double kDegenerateTau = 1e-12;
 constexpr int64_t kMaxDenseCoarse = 4096;
 constexpr uint64_t kColorSalt = 0xC2B2AE3D27D4EB4FULL;
 constexpr int kRoundBatch = 8;       // rounds launched between host checks of a frontier loop
+// A frontier loop whose worklist has shrunk to kDrainItems finishes in one
+// workgroup of that many threads (one item per thread and round, rounds
+// separated by barriers, worklists in LDS).
+constexpr int kDrainItems = 1024;
 constexpr int kMaxRounds = 4096;
 
 // Device error flags (bit set in Handle::flags[0]).
-enum : int { F_INVALID = 1, F_NOT_SPD = 2, F_OVERFLOW = 4 };
+enum : int { F_INVALID = 1, F_NOT_SPD = 2, F_OVERFLOW = 4, F_TIMEOUT = 8 };
 
 // ------------------------------------------------------------------ device helpers
 // SplitMix64 finaliser (Steele, Lea & Flood 2014), the hashed sweep/colour order key.

@@ -270,6 +270,39 @@ __global__ void __launch_bounds__(kBlock) k_lfmis_round(const int32_t* rp, const
   }
 }
 
+// The remaining rounds of the sweep in one workgroup, once at most
+// kDrainItems points are undecided: count_in points in wl_in (or, if wl_in is
+// null, all points 0 .. count_in - 1).
+__global__ void __launch_bounds__(kDrainItems) k_lfmis_drain(const int32_t* rp, const int32_t* col, const double* w,
+                                                             const double* scal, SweepKey key, uint8_t* status,
+                                                             const int32_t* wl_in, const int32_t* count_in,
+                                                             int64_t n, const int32_t* list, const uint8_t* cnt,
+                                                             int32_t* flags) {
+  __shared__ int32_t buf[2][kDrainItems];
+  __shared__ int32_t c;
+  const double r = scal[1];
+  int32_t count = wl_in ? *count_in : (int32_t)n;
+  int cur = 0;
+  for (int round = 0; round < kMaxRounds; ++round) {
+    if (threadIdx.x == 0) c = 0;
+    __syncthreads();
+    if ((int32_t)threadIdx.x < count) {
+      const int32_t p = round == 0 ? (wl_in ? wl_in[threadIdx.x] : (int32_t)threadIdx.x) : buf[cur][threadIdx.x];
+      bool pend;
+      if (!list) pend = lfmis_attempt(rp, col, w, r, key, status, p);
+      else if (round == 0 && !wl_in) pend = lfmis_first(rp, col, w, r, key, status, p, (int32_t*)list, (uint8_t*)cnt);
+      else pend = lfmis_again(rp, col, w, r, key, status, p, list, cnt);
+      if (pend) buf[cur ^ 1][atomicAdd(&c, 1)] = p;
+    }
+    __syncthreads();
+    count = c;
+    cur ^= 1;
+    __syncthreads();
+    if (count == 0) return;
+  }
+  if (threadIdx.x == 0) atomicOr(flags, F_TIMEOUT);
+}
+
 __global__ void k_seed_flags(const uint8_t* status, int64_t n, int32_t* f) {
   int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v < n) f[v] = status[v] == 1 ? 1 : 0;
@@ -477,17 +510,31 @@ int64_t sample_lfmis(Handle& h, Level& lv, int level) {
   uint8_t* cnt = lists ? (uint8_t*)talloc(s, (size_t)n) : nullptr;
   int k = 0;
   int64_t nc = 0;
+  bool drained = false;
+  if (n <= kDrainItems) {
+    k_lfmis_drain<<<1, kDrainItems, 0, s>>>(lv.erp, lv.ecol, lv.ew, lv.scal, key, status, nullptr, nullptr, n, list,
+                                           cnt, h.flags);
+    drained = true;
+  }
   for (;;) {
-    for (int t = 0; t < kRoundBatch; ++t, ++k)
-      k_lfmis_round<<<grid, kBlock, 0, s>>>(lv.erp, lv.ecol, lv.ew, n, lv.scal, key, status,
-                                            wl + ((k + 1) % 2) * n, wl + (k % 2) * n, h.rounds, k, list, cnt);
-    // coarse ids, valid if this batch finished the sweep (read together with the round count)
+    if (!drained)
+      for (int t = 0; t < kRoundBatch; ++t, ++k)
+        k_lfmis_round<<<grid, kBlock, 0, s>>>(lv.erp, lv.ecol, lv.ew, n, lv.scal, key, status,
+                                              wl + ((k + 1) % 2) * n, wl + (k % 2) * n, h.rounds, k, list, cnt);
+    // coarse ids, valid if the sweep has finished (read together with the round count)
     k_seed_flags<<<blocks_for(n), kBlock, 0, s>>>(status, n, f);
     scan_i32(f, ids, n, s);
-    int64_t left = 0;
-    ScalarRead rd[2] = {{h.rounds + (k - 1), 4, &left}, {ids + n, 4, &nc}};
-    read_scalars(h, rd, 2);
-    if (left == 0) break;
+    int64_t left = 0, fl = 0;
+    ScalarRead rd[3] = {{h.rounds + (drained ? 0 : k - 1), 4, &left}, {ids + n, 4, &nc}, {h.flags, 4, &fl}};
+    read_scalars(h, rd, 3);
+    if (fl & F_TIMEOUT) throw Error{GMG_DEVICE_ERROR, "sampling did not terminate"};
+    if (drained || left == 0) break;
+    if (left <= kDrainItems) {
+      k_lfmis_drain<<<1, kDrainItems, 0, s>>>(lv.erp, lv.ecol, lv.ew, lv.scal, key, status, wl + ((k - 1) % 2) * n,
+                                             h.rounds + (k - 1), n, list, cnt, h.flags);
+      drained = true;
+      continue;
+    }
     if (k + kRoundBatch > kMaxRounds) throw Error{GMG_DEVICE_ERROR, "sampling did not terminate"};
   }
   tfree(s, wl);

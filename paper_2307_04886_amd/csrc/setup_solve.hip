@@ -118,6 +118,32 @@ __global__ void __launch_bounds__(kBlock) k_ig_class(const int32_t* rp, const in
   }
 }
 
+// The remaining Jones-Plassmann rounds in one workgroup, once at most
+// kDrainItems rows wait: count_in rows in wl_in (or, if wl_in is null, all
+// rows 0 .. n - 1).
+__global__ void __launch_bounds__(kDrainItems) k_color_drain(const int32_t* rp, const int32_t* col, int64_t n,
+                                                             ColorKey key, int32_t* color, const int32_t* wl_in,
+                                                             const int32_t* count_in, int32_t* flags) {
+  __shared__ int32_t buf[2][kDrainItems];
+  __shared__ int32_t c;
+  int32_t count = wl_in ? *count_in : (int32_t)n;
+  int cur = 0;
+  for (int round = 0; round < kMaxRounds; ++round) {
+    if (threadIdx.x == 0) c = 0;
+    __syncthreads();
+    if ((int32_t)threadIdx.x < count) {
+      const int32_t v = round == 0 ? (wl_in ? wl_in[threadIdx.x] : (int32_t)threadIdx.x) : buf[cur][threadIdx.x];
+      if (!color_attempt(rp, col, key, color, v)) buf[cur ^ 1][atomicAdd(&c, 1)] = v;
+    }
+    __syncthreads();
+    count = c;
+    cur ^= 1;
+    __syncthreads();
+    if (count == 0) return;
+  }
+  if (threadIdx.x == 0) atomicOr(flags, F_TIMEOUT);
+}
+
 // ------------------------------------------------------------------ stable colour partition
 // hist[c * nb + b] = rows of colour c in block b; its exclusive scan gives,
 // for every (colour, block), the first new index, so new indices are sorted
@@ -519,21 +545,31 @@ void colouring(Handle& h, Level& lv, int level) {
   int32_t* wl = (int32_t*)talloc(s, (size_t)2 * n * 4);
   const int grid = std::min(blocks_for(n), 4 * kRoundGrid);
   int k = 0;
-  for (;;) {
-    for (int t = 0; t < kRoundBatch; ++t, ++k)
-      k_color_round<<<grid, kBlock, 0, s>>>(lv.arp, lv.acol, n, key, lv.color, wl + ((k + 1) % 2) * n,
-                                            wl + (k % 2) * n, h.rounds, k);
-    int64_t left = 0;
-    ScalarRead rd[1] = {{h.rounds + (k - 1), 4, &left}};
-    read_scalars(h, rd, 1);
-    if (left == 0) break;
-    if (k + kRoundBatch > kMaxRounds) throw Error{GMG_DEVICE_ERROR, "colouring did not terminate"};
+  if (n <= kDrainItems) {
+    k_color_drain<<<1, kDrainItems, 0, s>>>(lv.arp, lv.acol, n, key, lv.color, nullptr, nullptr, h.flags);
+  } else {
+    for (;;) {
+      for (int t = 0; t < kRoundBatch; ++t, ++k)
+        k_color_round<<<grid, kBlock, 0, s>>>(lv.arp, lv.acol, n, key, lv.color, wl + ((k + 1) % 2) * n,
+                                              wl + (k % 2) * n, h.rounds, k);
+      int64_t left = 0;
+      ScalarRead rd[1] = {{h.rounds + (k - 1), 4, &left}};
+      read_scalars(h, rd, 1);
+      if (left == 0) break;
+      if (left <= kDrainItems) {
+        k_color_drain<<<1, kDrainItems, 0, s>>>(lv.arp, lv.acol, n, key, lv.color, wl + ((k - 1) % 2) * n,
+                                               h.rounds + (k - 1), h.flags);
+        break;
+      }
+      if (k + kRoundBatch > kMaxRounds) throw Error{GMG_DEVICE_ERROR, "colouring did not terminate"};
+    }
   }
   {
     max_i32(lv.color, n, 1, ncol, s);
-    int64_t nco = 0;
-    ScalarRead rd[1] = {{ncol, 4, &nco}};
-    read_scalars(h, rd, 1);
+    int64_t nco = 0, fl = 0;
+    ScalarRead rd[2] = {{ncol, 4, &nco}, {h.flags, 4, &fl}};
+    read_scalars(h, rd, 2);
+    if (fl & F_TIMEOUT) throw Error{GMG_DEVICE_ERROR, "colouring did not terminate"};
     lv.ncolors = (int32_t)nco;
   }
   // iterated-greedy passes: classes of the previous colouring from the highest
