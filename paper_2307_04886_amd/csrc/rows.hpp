@@ -9,8 +9,11 @@
 //    the 64 consecutive rows of a slice), loads issued CH at a time;
 //  - R lanes per row (Galerkin levels: 15-40 entries, latency-bound): the R
 //    lanes load and multiply the row's entries in parallel and the first lane
-//    of the group adds the products in entry order (wavefront shuffles).
+//    of the group adds the products in entry order (DPP quad broadcasts for
+//    R = 4, wavefront shuffles for wider groups, where DPP measured slower).
 #pragma once
+
+#include <type_traits>
 
 #include "gmg_internal.hpp"
 
@@ -47,6 +50,34 @@ __device__ __forceinline__ V row_sum_seq(const Sell<V>& A, int32_t r, const V* x
     t0 += CH;
   } while (t0 < len);
   return acc;
+}
+
+// Value of lane S of each group of 4 consecutive lanes, as seen by every lane
+// of the group: a DPP quad permutation, with no LDS round trip.
+template <int S>
+__device__ __forceinline__ uint32_t quad_bcast(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, S * 0x55, 0xF, 0xF, false);
+}
+
+template <int S, class V>
+__device__ __forceinline__ V quad_lane(V v) {
+  if constexpr (sizeof(V) == 4) {
+    return __builtin_bit_cast(V, quad_bcast<S>(__builtin_bit_cast(uint32_t, v)));
+  } else {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = quad_bcast<S>((uint32_t)u);
+    const uint32_t hi = quad_bcast<S>((uint32_t)(u >> 32));
+    return __builtin_bit_cast(V, ((uint64_t)hi << 32) | lo);
+  }
+}
+
+// Calls f(std::integral_constant<int, S>) for S = 0 .. N-1 in order.
+template <int N, class F, int S = 0>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (S < N) {
+    f(std::integral_constant<int, S>{});
+    static_for<N, F, S + 1>(static_cast<F&&>(f));
+  }
 }
 
 // R lanes per row (R divides 64; the lanes of a group are consecutive).  All
@@ -88,15 +119,29 @@ __device__ __forceinline__ V row_sumR(const Sell<V>& A, int32_t r, bool active, 
       mask |= ok ? (1u << k) : 0u;
     }
     uint32_t m[R];
+    if constexpr (R == 4) {
+      V q[kLaneEntries][R];
+      static_for<R>([&](auto S) {
+        m[S] = quad_bcast<S>(mask);
 #pragma unroll
-    for (int s = 0; s < R; ++s) m[s] = __shfl(mask, lane0 + s, kWave);
+        for (int k = 0; k < kLaneEntries; ++k) q[k][S] = quad_lane<S>(p[k]);
+      });
 #pragma unroll
-    for (int k = 0; k < kLaneEntries; ++k)
+      for (int k = 0; k < kLaneEntries; ++k)
 #pragma unroll
-      for (int s = 0; s < R; ++s) {
-        const V q = __shfl(p[k], lane0 + s, kWave);
-        if ((m[s] >> k) & 1u) acc = acc + q;
-      }
+        for (int s = 0; s < R; ++s)
+          if ((m[s] >> k) & 1u) acc = acc + q[k][s];
+    } else {
+#pragma unroll
+      for (int s = 0; s < R; ++s) m[s] = __shfl(mask, lane0 + s, kWave);
+#pragma unroll
+      for (int k = 0; k < kLaneEntries; ++k)
+#pragma unroll
+        for (int s = 0; s < R; ++s) {
+          const V q = __shfl(p[k], lane0 + s, kWave);
+          if ((m[s] >> k) & 1u) acc = acc + q;
+        }
+    }
   }
   return acc;
 }
