@@ -37,6 +37,17 @@ __host__ __device__ inline uint64_t mix64(uint64_t z) {
   return z ^ (z >> 31);
 }
 
+// Workgroups are dealt to the 8 XCDs round-robin, and each XCD has its own L2.
+// The logical block index below gives every XCD one contiguous range of
+// logical blocks (a bijection on [0, gridDim.x)), so blocks of neighbouring
+// rows, which gather the same cache lines, share an L2.
+constexpr uint32_t kXcds = 8;
+__device__ __forceinline__ uint32_t xcd_block() {
+  const uint32_t b = blockIdx.x, nb = gridDim.x;
+  const uint32_t q = nb / kXcds, r = nb % kXcds, x = b % kXcds, i = b / kXcds;
+  return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + i;
+}
+
 struct V3 { double x, y, z; };
 __device__ inline V3 ld3(const double* X, int64_t i) { return {X[3 * i], X[3 * i + 1], X[3 * i + 2]}; }
 __device__ inline V3 sub3(V3 a, V3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }

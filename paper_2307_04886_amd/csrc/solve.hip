@@ -36,7 +36,7 @@ __device__ __forceinline__ void prolong_row(const LevelViewT<V>& L, const V* __r
 template <class V>
 __global__ void __launch_bounds__(kBlock) k_gs_color_fine(Sell<V> A, const V* __restrict__ diag,
                                                           const V* __restrict__ b, V* x, int32_t r0, int32_t r1) {
-  const int32_t r = (r0 & ~(kSlice - 1)) + (int32_t)(blockIdx.x * kBlock + threadIdx.x);
+  const int32_t r = (r0 & ~(kSlice - 1)) + (int32_t)(xcd_block() * kBlock + threadIdx.x);
   if (r < r0 || r >= r1) return;
   const V br = b[r], dr = diag[r];        // issued with the row's loads
   const V acc = row_sum_seq<kChunkFine>(A, r, x, r);
@@ -48,7 +48,7 @@ template <int R, class V>
 __global__ void __launch_bounds__(kBlock) k_gs_color(Sell<V> A, const V* __restrict__ diag,
                                                      const V* __restrict__ b, V* x, int32_t r0, int32_t r1,
                                                      int32_t maxlen) {
-  const int64_t g = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / R;
+  const int64_t g = ((int64_t)xcd_block() * kBlock + threadIdx.x) / R;
   const int32_t r = r0 + (int32_t)g;
   const bool active = r < r1;
   const int32_t rc = active ? r : r0;     // in range for every lane: the loads need no branch
@@ -62,7 +62,7 @@ template <class V>
 __global__ void __launch_bounds__(kBlock) k_residual_fine(Sell<V> A, const V* __restrict__ b,
                                                           const V* __restrict__ x, V* __restrict__ res,
                                                           int64_t n) {
-  const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t r = (int64_t)xcd_block() * kBlock + threadIdx.x;
   if (r >= n) return;
   res[r] = b[r] - row_sum_seq<kChunkFine>(A, (int32_t)r, x, -1);
 }
@@ -71,7 +71,7 @@ __global__ void __launch_bounds__(kBlock) k_residual_fine(Sell<V> A, const V* __
 template <int R, class V>
 __global__ void __launch_bounds__(kBlock) k_residual(Sell<V> A, const V* __restrict__ b, const V* __restrict__ x,
                                                      V* __restrict__ res, int64_t n, int32_t maxlen) {
-  const int64_t g = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / R;
+  const int64_t g = ((int64_t)xcd_block() * kBlock + threadIdx.x) / R;
   const bool active = g < n;
   const V acc = row_sumR<R>(A, (int32_t)g, active, x, -1, maxlen);
   if (active && (threadIdx.x & (R - 1)) == 0) res[g] = b[g] - acc;
@@ -83,14 +83,17 @@ __global__ void __launch_bounds__(kBlock) k_residual_norm(SellView A, const doub
                                                           const double* __restrict__ x,
                                                           double* __restrict__ res, int64_t n,
                                                           double* partials) {
+  // logical block lb covers rows lb * kBlock + k * gridDim.x * kBlock and
+  // writes partials[lb], whichever XCD runs it
+  const uint32_t lb = xcd_block();
   double sq = 0.0;
-  for (int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x; r < n; r += (int64_t)gridDim.x * kBlock) {
+  for (int64_t r = (int64_t)lb * kBlock + threadIdx.x; r < n; r += (int64_t)gridDim.x * kBlock) {
     const double v = b[r] - row_sum_seq<kChunkFine>(A, (int32_t)r, x, -1);
     res[r] = v;
     sq += v * v;
   }
   double t = block_sum(sq);
-  if (threadIdx.x == 0) partials[blockIdx.x] = t;
+  if (threadIdx.x == 0) partials[lb] = t;
 }
 
 __global__ void __launch_bounds__(kBlock) k_norm_partials(const double* v, int64_t n, double* partials) {
@@ -113,7 +116,7 @@ __global__ void __launch_bounds__(kBlock) k_finish_norm(const double* partials, 
 template <int R, class V>
 __global__ void __launch_bounds__(kBlock) k_restrict(Sell<V> T, const V* __restrict__ r, V* __restrict__ bc,
                                                      V* __restrict__ xc, int64_t nc, int32_t maxlen) {
-  const int64_t g = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / R;
+  const int64_t g = ((int64_t)xcd_block() * kBlock + threadIdx.x) / R;
   const bool active = g < nc;
   const V acc = row_sumR<R>(T, (int32_t)g, active, r, -1, maxlen);
   if (active && (threadIdx.x & (R - 1)) == 0) {
@@ -126,7 +129,7 @@ __global__ void __launch_bounds__(kBlock) k_restrict(Sell<V> T, const V* __restr
 template <class V>
 __global__ void __launch_bounds__(kBlock) k_prolong_correct(LevelViewT<V> L, const V* __restrict__ xc,
                                                             V* __restrict__ x) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t i = (int64_t)xcd_block() * kBlock + threadIdx.x;
   if (i >= L.n) return;
   prolong_row(L, xc, x, (int32_t)i);
 }
