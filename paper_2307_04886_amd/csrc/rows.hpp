@@ -8,9 +8,9 @@
 //  - one lane per row (level 0: about 7 entries, streaming, coalesced across
 //    the 64 consecutive rows of a slice), loads issued CH at a time;
 //  - R lanes per row (Galerkin levels: 15-40 entries, latency-bound): the R
-//    lanes load and multiply the row's entries in parallel and the first lane
-//    of the group adds the products in entry order (DPP quad broadcasts for
-//    R = 4, wavefront shuffles for wider groups, where DPP measured slower).
+//    lanes load and multiply consecutive runs of the row's entries in
+//    parallel and the running sum passes from lane to lane (DPP row shifts),
+//    so the terms are added in entry order.
 #pragma once
 
 #include <type_traits>
@@ -52,25 +52,6 @@ __device__ __forceinline__ V row_sum_seq(const Sell<V>& A, int32_t r, const V* x
   return acc;
 }
 
-// Value of lane S of each group of 4 consecutive lanes, as seen by every lane
-// of the group: a DPP quad permutation, with no LDS round trip.
-template <int S>
-__device__ __forceinline__ uint32_t quad_bcast(uint32_t v) {
-  return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, S * 0x55, 0xF, 0xF, false);
-}
-
-template <int S, class V>
-__device__ __forceinline__ V quad_lane(V v) {
-  if constexpr (sizeof(V) == 4) {
-    return __builtin_bit_cast(V, quad_bcast<S>(__builtin_bit_cast(uint32_t, v)));
-  } else {
-    const uint64_t u = __builtin_bit_cast(uint64_t, v);
-    const uint32_t lo = quad_bcast<S>((uint32_t)u);
-    const uint32_t hi = quad_bcast<S>((uint32_t)(u >> 32));
-    return __builtin_bit_cast(V, ((uint64_t)hi << 32) | lo);
-  }
-}
-
 // Calls f(std::integral_constant<int, S>) for S = 0 .. N-1 in order.
 template <int N, class F, int S = 0>
 __device__ __forceinline__ void static_for(F&& f) {
@@ -80,70 +61,96 @@ __device__ __forceinline__ void static_for(F&& f) {
   }
 }
 
+// DPP move of a 32-bit value (CTRL: a row shift or quad permutation; all
+// lanes of the wavefront active).
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, false);
+}
+
+template <int CTRL, class V>
+__device__ __forceinline__ V dpp(V v) {
+  if constexpr (sizeof(V) == 4) {
+    return __builtin_bit_cast(V, dpp_u32<CTRL>(__builtin_bit_cast(uint32_t, v)));
+  } else {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = dpp_u32<CTRL>((uint32_t)u);
+    const uint32_t hi = dpp_u32<CTRL>((uint32_t)(u >> 32));
+    return __builtin_bit_cast(V, ((uint64_t)hi << 32) | lo);
+  }
+}
+
+// Within groups of R consecutive lanes: lane i receives lane i - 1's value
+// (meaningful for every lane but the group's first).  Groups of up to 16
+// lanes lie in one DPP row: a row shift by one.
+template <int R, class V>
+__device__ __forceinline__ V lane_up(V v) {
+  if constexpr (R <= 16) return dpp<0x111>(v);
+  else return __shfl_up(v, 1, kWave);
+}
+
+// The value of the group's last lane, as seen by its first lane: a quad
+// permutation for R = 4, a row shift by R - 1 lanes for R = 8 and 16.
+template <int R, class V>
+__device__ __forceinline__ V last_to_first(V v) {
+  if constexpr (R == 4) return dpp<0xFF>(v);
+  else if constexpr (R <= 16) return dpp<0x100 + R - 1>(v);
+  else return __shfl(v, (int)(threadIdx.x & (kWave - 1)) - (int)(threadIdx.x & (R - 1)) + R - 1, kWave);
+}
+
 // R lanes per row (R divides 64; the lanes of a group are consecutive).  All
-// lanes of the wavefront must call this (shuffles); `active` marks lanes whose
-// group has a row.  maxlen bounds every row length (uniform).  The result is
+// lanes of the wavefront must call this (cross-lane moves); `active` marks
+// lanes whose group has a row.  maxlen bounds every row length.  The result is
 // valid on the group's first lane.
+//
+// A pass covers R * kLaneEntries entries of every row: lane s of a group holds
+// entries [s K, s K + K) of the pass (K = kLaneEntries).  The running sum
+// starts on lane 0, which adds its products in entry order; it then moves one
+// lane up (a DPP row shift) and the next lane continues, so the row is summed
+// in entry order with R - 1 cross-lane moves per pass.  A wavefront stops
+// after the pass that covers its longest row.
 template <int R, class V>
 __device__ __forceinline__ V row_sumR(const Sell<V>& A, int32_t r, bool active, const V* x, int32_t skip,
                                       int32_t maxlen) {
-  const int lane = threadIdx.x & (kWave - 1);
-  const int sub = lane & (R - 1);
-  const int lane0 = lane - sub;
+  constexpr int K = kLaneEntries;
+  const int sub = threadIdx.x & (R - 1);
   int32_t base = 0, len = 0;
   if (active) {
     base = A.ptr[r / kSlice] + (r & (kSlice - 1));
     len = A.len[r];
   }
-  V acc = V(0);
-  for (int32_t t0 = 0; t0 < maxlen; t0 += R * kLaneEntries) {
-    int32_t j[kLaneEntries];
-    V v[kLaneEntries], p[kLaneEntries];
-    uint32_t mask = 0;
+  V carry = V(0);
+  for (int32_t t0 = 0; t0 < maxlen && __ballot(t0 < len) != 0; t0 += R * K) {
+    int32_t j[K];
+    V v[K], xv[K], p[K];
+    bool ok[K];
     // Branch-free loads, as in row_sum_seq: positions past the row's end (or
     // of an inactive group: row 0's first entry) re-read a valid entry.
 #pragma unroll
-    for (int k = 0; k < kLaneEntries; ++k) {
-      const int32_t t = t0 + sub + R * k;
+    for (int k = 0; k < K; ++k) {
+      const int32_t t = t0 + sub * K + k;
       const int32_t o = base + max(min(t, len - 1), 0) * kSlice;
       j[k] = A.col[o];
       v[k] = A.val[o];
     }
-    V xv[kLaneEntries];
 #pragma unroll
-    for (int k = 0; k < kLaneEntries; ++k) xv[k] = x[j[k]];
+    for (int k = 0; k < K; ++k) xv[k] = x[j[k]];
 #pragma unroll
-    for (int k = 0; k < kLaneEntries; ++k) {
-      const bool ok = (t0 + sub + R * k < len) && j[k] != skip;
-      p[k] = ok ? v[k] * xv[k] : V(0);
-      mask |= ok ? (1u << k) : 0u;
+    for (int k = 0; k < K; ++k) {
+      ok[k] = (t0 + sub * K + k < len) && j[k] != skip;
+      p[k] = v[k] * xv[k];
     }
-    uint32_t m[R];
-    if constexpr (R == 4) {
-      V q[kLaneEntries][R];
-      static_for<R>([&](auto S) {
-        m[S] = quad_bcast<S>(mask);
+    V in = carry, a = carry;
+    static_for<R>([&](auto S) {
+      a = in;
 #pragma unroll
-        for (int k = 0; k < kLaneEntries; ++k) q[k][S] = quad_lane<S>(p[k]);
-      });
-#pragma unroll
-      for (int k = 0; k < kLaneEntries; ++k)
-#pragma unroll
-        for (int s = 0; s < R; ++s)
-          if ((m[s] >> k) & 1u) acc = acc + q[k][s];
-    } else {
-#pragma unroll
-      for (int s = 0; s < R; ++s) m[s] = __shfl(mask, lane0 + s, kWave);
-#pragma unroll
-      for (int k = 0; k < kLaneEntries; ++k)
-#pragma unroll
-        for (int s = 0; s < R; ++s) {
-          const V q = __shfl(p[k], lane0 + s, kWave);
-          if ((m[s] >> k) & 1u) acc = acc + q;
-        }
-    }
+      for (int k = 0; k < K; ++k)
+        if (ok[k]) a = a + p[k];
+      if constexpr (S + 1 < R) in = lane_up<R>(a);
+    });
+    carry = last_to_first<R>(a);
   }
-  return acc;
+  return carry;
 }
 
 // Block-level sum in a fixed tree order (every thread of the block calls it).
