@@ -266,7 +266,7 @@ struct Level {
   int32_t* t_rp = nullptr;
   int32_t* t_col = nullptr;
   double* t_val = nullptr;
-  bool galerkin_wide = false;           // A_{l+1} has a row longer than the narrow fill kernel holds
+  int32_t galerkin_hs = 1024;           // hash slots of the numeric Galerkin pass (3/4 hold the longest row)
   // tail levels: the per-colour ELL of A_l and the ELL of P_l^T (LevelViewT)
   std::vector<int32_t> e_cinfo_h;       // host copy of view.e_cinfo
   int64_t e_slots = 0, e_tslots = 0;

@@ -383,6 +383,7 @@ __global__ void __launch_bounds__(kWave) k_galerkin_fill(const int32_t* trp, con
                                                          const int32_t* pcnt, int64_t nc, const int32_t* crp,
                                                          int32_t* ccol, double* cval, int32_t* flags) {
   constexpr int kOut = HS * 3 / 4;     // distinct columns of a row (the symbolic pass checked the bound)
+  constexpr int kPer = (kOut + kWave - 1) / kWave;   // output columns per lane
   __shared__ int32_t keys[HS];
   __shared__ int32_t rank_of[HS];      // hash slot -> position of its column in the sorted row
   __shared__ int32_t sorted[kOut];
@@ -417,16 +418,16 @@ __global__ void __launch_bounds__(kWave) k_galerkin_fill(const int32_t* trp, con
     if (keys[s] >= 0) sorted[atomicAdd(&nlist, 1)] = s;            // slots, in any order
   __syncthreads();
   const int k = nlist;
-  int32_t myslot[kOut / kWave], mykey[kOut / kWave];
+  int32_t myslot[kPer], mykey[kPer];
 #pragma unroll
-  for (int g = 0; g < kOut / kWave; ++g) {
+  for (int g = 0; g < kPer; ++g) {
     const int a = lane + g * kWave;
     myslot[g] = a < k ? sorted[a] : -1;
     mykey[g] = a < k ? keys[myslot[g]] : 0;
   }
   __syncthreads();
 #pragma unroll
-  for (int g = 0; g < kOut / kWave; ++g)
+  for (int g = 0; g < kPer; ++g)
     if (lane + g * kWave < k) {
       int rank = 0;
       for (int b = 0; b < k; ++b) rank += keys[sorted[b]] < mykey[g];
@@ -434,7 +435,7 @@ __global__ void __launch_bounds__(kWave) k_galerkin_fill(const int32_t* trp, con
     }
   __syncthreads();
 #pragma unroll
-  for (int g = 0; g < kOut / kWave; ++g)
+  for (int g = 0; g < kPer; ++g)
     if (lane + g * kWave < k) {
       sorted[rank_of[myslot[g]]] = mykey[g];
       accum[rank_of[myslot[g]]] = 0.0;
@@ -569,8 +570,9 @@ void galerkin(Handle& h, Level& lv, Level& nx, const int32_t* t_rp, const int32_
   throw_flags((int32_t)f, "Galerkin operator");
   nx.acol = (int32_t*)dalloc(h, (size_t)(nx.nnzA + 1) * 4);
   nx.aval = (double*)dalloc(h, (size_t)(nx.nnzA + 1) * 8);
-  // a smaller LDS footprint (more resident wavefronts) when every row fits
-  lv.galerkin_wide = maxrow > 256 * 3 / 4;
+  // the smallest hash table that holds every row (3/4 full at most): a
+  // smaller LDS footprint keeps more rows in flight per CU
+  lv.galerkin_hs = maxrow <= 64 * 3 / 4 ? 64 : (maxrow <= 256 * 3 / 4 ? 256 : 1024);
   lv.t_rp = (int32_t*)t_rp;
   lv.t_col = (int32_t*)t_col;
   lv.t_val = (double*)t_val;
@@ -583,13 +585,13 @@ void galerkin(Handle& h, Level& lv, Level& nx, const int32_t* t_rp, const int32_
 void galerkin_values(Handle& h, Level& lv, Level& nx) {
   hipStream_t s = h.stream;
   const int64_t nc = nx.n;
-  if (!lv.galerkin_wide)
-    k_galerkin_fill<256><<<(int)nc, kWave, 0, s>>>(lv.t_rp, lv.t_col, lv.t_val, lv.arp, lv.acol, lv.aval, lv.pcol,
-                                                   lv.pval, lv.pcnt, nc, nx.arp, nx.acol, nx.aval, h.flags);
-  else
-    k_galerkin_fill<1024><<<(int)nc, kWave, 0, s>>>(lv.t_rp, lv.t_col, lv.t_val, lv.arp, lv.acol, lv.aval,
-                                                    lv.pcol, lv.pval, lv.pcnt, nc, nx.arp, nx.acol, nx.aval,
-                                                    h.flags);
+  auto fill = [&](auto kern) {
+    kern<<<(int)nc, kWave, 0, s>>>(lv.t_rp, lv.t_col, lv.t_val, lv.arp, lv.acol, lv.aval, lv.pcol, lv.pval, lv.pcnt,
+                                   nc, nx.arp, nx.acol, nx.aval, h.flags);
+  };
+  if (lv.galerkin_hs == 64) fill(k_galerkin_fill<64>);
+  else if (lv.galerkin_hs == 256) fill(k_galerkin_fill<256>);
+  else fill(k_galerkin_fill<1024>);
 }
 
 }  // namespace gmg

@@ -22,15 +22,48 @@ struct ColorKey {
 
 constexpr int kColorChunk = 16;
 
+// On levels of up to kColorListLevel rows the first visit of v also records
+// the lower-key neighbours not yet coloured, in list[v * kColorList ..] with
+// their number in cnt[v], and the colours of those already coloured as a bit
+// mask (cnt[v] = kColorList + 1: too many neighbours to list, or a colour of
+// 64 or more; later visits read the row again).  Colours are final once
+// written, so a later visit reads only the listed neighbours' colours and
+// takes the same decision as a visit that reads the whole row.
+constexpr int kColorList = 32;
+constexpr int64_t kColorListLevel = 262144;
+
+struct ColorLists {
+  int32_t* list = nullptr;   // null: no lists, every visit reads the row
+  uint64_t* mask = nullptr;
+  uint8_t* cnt = nullptr;
+};
+
+__device__ inline int32_t first_fit_above(const int32_t* rp, const int32_t* col, const ColorKey& key,
+                                          const int32_t* color, int32_t v, uint64_t kv) {
+  for (int32_t c = 64;; ++c) {                  // rare: every colour below 64 is taken
+    bool used = false;
+    for (int32_t e = rp[v]; e < rp[v + 1] && !used; ++e) {
+      int32_t u = col[e];
+      if (u == v) continue;
+      uint64_t ku = key(u);
+      if ((ku < kv || (ku == kv && u < v)) && color[u] == c) used = true;
+    }
+    if (!used) return c;
+  }
+}
+
 // Returns 0 if v must wait for a lower-key neighbour, else colours v and
 // returns its colour + 1.  The row is read kColorChunk entries at a time with
 // every column and neighbour-colour load in flight together (positions past
-// the row's end re-read its last entry; every row holds its diagonal).
+// the row's end re-read its last entry; every row holds its diagonal).  With
+// Record, a waiting row also writes its lists.
+template <bool Record>
 __device__ inline int32_t color_attempt(const int32_t* rp, const int32_t* col, const ColorKey& key,
-                                        int32_t* color, int32_t v) {
+                                        int32_t* color, int32_t v, const ColorLists& L) {
   const uint64_t kv = key(v);
   uint64_t mask = 0;
   bool high = false, wait = false;
+  int32_t nrec = 0;
   const int32_t b = rp[v], e = rp[v + 1];
   for (int32_t e0 = b; e0 < e; e0 += kColorChunk) {
     int32_t u[kColorChunk], cu[kColorChunk];
@@ -43,6 +76,49 @@ __device__ inline int32_t color_attempt(const int32_t* rp, const int32_t* col, c
       if (e0 + k >= e || u[k] == v) continue;
       const uint64_t ku = key(u[k]);
       if (!(ku < kv || (ku == kv && u[k] < v))) continue;
+      if (cu[k] < 0) {
+        wait = true;
+        if constexpr (Record) {
+          if (nrec < kColorList) L.list[(int64_t)v * kColorList + nrec] = u[k];
+          ++nrec;
+        }
+      } else if (cu[k] < 64) {
+        mask |= 1ull << cu[k];
+      } else {
+        high = true;
+      }
+    }
+  }
+  if (wait) {
+    if constexpr (Record) {
+      L.mask[v] = mask;
+      L.cnt[v] = (uint8_t)(nrec <= kColorList && !high ? nrec : kColorList + 1);
+    }
+    return 0;
+  }
+  int32_t c = (~mask) ? __builtin_ctzll(~mask) : 64;
+  if (c == 64 && high) c = first_fit_above(rp, col, key, color, v, kv);
+  color[v] = c;
+  return c + 1;
+}
+
+// A later visit of a row with lists: the colours of the listed neighbours.
+__device__ inline int32_t color_again(const int32_t* rp, const int32_t* col, const ColorKey& key,
+                                      int32_t* color, int32_t v, const ColorLists& L) {
+  const int32_t n = L.cnt[v];
+  if (n > kColorList) return color_attempt<false>(rp, col, key, color, v, L);
+  uint64_t mask = L.mask[v];
+  bool high = false, wait = false;
+  const int32_t* lp = L.list + (int64_t)v * kColorList;
+  for (int32_t e0 = 0; e0 < n; e0 += kColorChunk) {
+    int32_t u[kColorChunk], cu[kColorChunk];
+#pragma unroll
+    for (int k = 0; k < kColorChunk; ++k) u[k] = lp[min(e0 + k, n - 1)];
+#pragma unroll
+    for (int k = 0; k < kColorChunk; ++k) cu[k] = __atomic_load_n(&color[u[k]], __ATOMIC_RELAXED);
+#pragma unroll
+    for (int k = 0; k < kColorChunk; ++k) {
+      if (e0 + k >= n) continue;
       if (cu[k] < 0) wait = true;
       else if (cu[k] < 64) mask |= 1ull << cu[k];
       else high = true;
@@ -50,34 +126,31 @@ __device__ inline int32_t color_attempt(const int32_t* rp, const int32_t* col, c
   }
   if (wait) return 0;
   int32_t c = (~mask) ? __builtin_ctzll(~mask) : 64;
-  if (c == 64 && high) {
-    for (;; ++c) {                              // rare: every colour below 64 is taken
-      bool used = false;
-      for (int32_t e = rp[v]; e < rp[v + 1] && !used; ++e) {
-        int32_t u = col[e];
-        if (u == v) continue;
-        uint64_t ku = key(u);
-        if ((ku < kv || (ku == kv && u < v)) && color[u] == c) used = true;
-      }
-      if (!used) break;
-    }
-  }
+  if (c == 64 && high) c = first_fit_above(rp, col, key, color, v, key(v));
   color[v] = c;
   return c + 1;
+}
+
+// Any visit: the first (round 0 over every row) records the lists.
+__device__ inline int32_t color_visit(const int32_t* rp, const int32_t* col, const ColorKey& key, int32_t* color,
+                                      int32_t v, const ColorLists& L, bool first) {
+  if (!L.list) return color_attempt<false>(rp, col, key, color, v, L);
+  if (first) return color_attempt<true>(rp, col, key, color, v, L);
+  return color_again(rp, col, key, color, v, L);
 }
 
 // One Jones-Plassmann round; round 0 visits every row, later rounds the
 // worklist of rows still waiting after the previous round.
 __global__ void __launch_bounds__(kBlock) k_color_round(const int32_t* rp, const int32_t* col, int64_t n,
                                                         ColorKey key, int32_t* color, const int32_t* wl_in,
-                                                        int32_t* wl_out, int32_t* rounds, int k) {
+                                                        int32_t* wl_out, int32_t* rounds, int k, ColorLists L) {
   const int64_t count = k == 0 ? n : rounds[k - 1];
   for (int64_t base = (int64_t)blockIdx.x * kBlock; base < count; base += (int64_t)gridDim.x * kBlock) {
     const int64_t i = base + threadIdx.x;
     const bool act = i < count;
     const int32_t v = act ? (k == 0 ? (int32_t)i : wl_in[i]) : 0;
     int32_t got = 0;
-    if (act) got = color_attempt(rp, col, key, color, v);
+    if (act) got = color_visit(rp, col, key, color, v, L, k == 0);
     block_append(act && got == 0, v, wl_out, &rounds[k]);
   }
 }
@@ -123,7 +196,7 @@ __global__ void __launch_bounds__(kBlock) k_ig_class(const int32_t* rp, const in
 // rows 0 .. n - 1).
 __global__ void __launch_bounds__(kDrainItems) k_color_drain(const int32_t* rp, const int32_t* col, int64_t n,
                                                              ColorKey key, int32_t* color, const int32_t* wl_in,
-                                                             const int32_t* count_in, int32_t* flags) {
+                                                             const int32_t* count_in, ColorLists L, int32_t* flags) {
   __shared__ int32_t buf[2][kDrainItems];
   __shared__ int32_t c;
   int32_t count = wl_in ? *count_in : (int32_t)n;
@@ -133,7 +206,7 @@ __global__ void __launch_bounds__(kDrainItems) k_color_drain(const int32_t* rp, 
     __syncthreads();
     if ((int32_t)threadIdx.x < count) {
       const int32_t v = round == 0 ? (wl_in ? wl_in[threadIdx.x] : (int32_t)threadIdx.x) : buf[cur][threadIdx.x];
-      if (!color_attempt(rp, col, key, color, v)) buf[cur ^ 1][atomicAdd(&c, 1)] = v;
+      if (!color_visit(rp, col, key, color, v, L, round == 0 && !wl_in)) buf[cur ^ 1][atomicAdd(&c, 1)] = v;
     }
     __syncthreads();
     count = c;
@@ -543,22 +616,28 @@ void colouring(Handle& h, Level& lv, int level) {
   check_hip(hipMemsetAsync(h.rounds, 0, kMaxRounds * 4, s), "memset");
   ColorKey key{(h.opt.seed ^ kColorSalt) ^ ((uint64_t)level << 32)};
   int32_t* wl = (int32_t*)talloc(s, (size_t)2 * n * 4);
+  ColorLists L;
+  if (n <= kColorListLevel) {
+    L.list = (int32_t*)talloc(s, (size_t)n * kColorList * 4);
+    L.mask = (uint64_t*)talloc(s, (size_t)n * 8);
+    L.cnt = (uint8_t*)talloc(s, (size_t)n);
+  }
   const int grid = std::min(blocks_for(n), 4 * kRoundGrid);
   int k = 0;
   if (n <= kDrainItems) {
-    k_color_drain<<<1, kDrainItems, 0, s>>>(lv.arp, lv.acol, n, key, lv.color, nullptr, nullptr, h.flags);
+    k_color_drain<<<1, kDrainItems, 0, s>>>(lv.arp, lv.acol, n, key, lv.color, nullptr, nullptr, L, h.flags);
   } else {
     for (;;) {
       for (int t = 0; t < kRoundBatch; ++t, ++k)
         k_color_round<<<grid, kBlock, 0, s>>>(lv.arp, lv.acol, n, key, lv.color, wl + ((k + 1) % 2) * n,
-                                              wl + (k % 2) * n, h.rounds, k);
+                                              wl + (k % 2) * n, h.rounds, k, L);
       int64_t left = 0;
       ScalarRead rd[1] = {{h.rounds + (k - 1), 4, &left}};
       read_scalars(h, rd, 1);
       if (left == 0) break;
       if (left <= kDrainItems) {
         k_color_drain<<<1, kDrainItems, 0, s>>>(lv.arp, lv.acol, n, key, lv.color, wl + ((k - 1) % 2) * n,
-                                               h.rounds + (k - 1), h.flags);
+                                               h.rounds + (k - 1), L, h.flags);
         break;
       }
       if (k + kRoundBatch > kMaxRounds) throw Error{GMG_DEVICE_ERROR, "colouring did not terminate"};
@@ -595,6 +674,11 @@ void colouring(Handle& h, Level& lv, int level) {
     tfree(s, other);
   }
   tfree(s, wl);
+  if (L.list) {
+    tfree(s, L.list);
+    tfree(s, L.mask);
+    tfree(s, L.cnt);
+  }
   tfree(s, ncol);
 }
 
