@@ -408,20 +408,21 @@ __global__ void k_cell_degree(const int32_t* ptr, const int32_t* mem, const int3
   cdeg[I] = s;
 }
 
-// The distinct cells J != I reached by an edge from cell I, kept sorted in
-// this cell's slot range of `tmp` by insertion.
-__global__ void k_cell_neighbours(const int32_t* ptr, const int32_t* mem, const int32_t* rp,
-                                  const int32_t* col, const int32_t* lab, const int32_t* cptr,
-                                  int64_t nc, int32_t* tmp, int32_t* ucnt) {
-  int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (I >= nc) return;
-  int32_t* out = tmp + cptr[I];
+// The distinct cells J != I reached by an edge from cell I, written sorted to
+// this cell's slot range of `tmp` (cptr[I] .. : one slot per edge of its
+// members), their number to ucnt[I].
+//
+// Cells with more than kCellCand edges: one lane, insertion into the sorted
+// range.
+__device__ inline void cell_neighbours_serial(const int32_t* ptr, const int32_t* mem, const int32_t* rp,
+                                              const int32_t* col, const int32_t* lab, int32_t I, int32_t* out,
+                                              int32_t* ucnt) {
   int32_t u = 0;
   for (int32_t k = ptr[I]; k < ptr[I + 1]; ++k) {
     int32_t a = mem[k];
     for (int32_t e = rp[a]; e < rp[a + 1]; ++e) {
       int32_t J = lab[col[e]];
-      if (J == (int32_t)I) continue;
+      if (J == I) continue;
       int32_t lo = 0, hi = u;
       while (lo < hi) {
         int32_t mid = (lo + hi) >> 1;
@@ -434,6 +435,83 @@ __global__ void k_cell_neighbours(const int32_t* ptr, const int32_t* mem, const 
     }
   }
   ucnt[I] = u;
+}
+
+// Other cells: kCellLanes lanes per cell.  The lanes take the members in turn,
+// write the cell label of each member edge's end to LDS (the members' edges
+// placed one after another by a scan of their degrees), then every distinct
+// label J != I finds its rank among the distinct labels and is written there.
+constexpr int kCellLanes = 16;
+constexpr int kCellCand = 128;
+constexpr int kCellChunk = 8;
+constexpr int kCellsPerBlock = kBlock / kCellLanes;
+
+__global__ void __launch_bounds__(kBlock) k_cell_neighbours(const int32_t* ptr, const int32_t* mem,
+                                                            const int32_t* rp, const int32_t* col,
+                                                            const int32_t* lab, const int32_t* cptr, int64_t nc,
+                                                            int32_t* tmp, int32_t* ucnt) {
+  __shared__ int32_t cand[kCellsPerBlock][kCellCand];
+  __shared__ uint8_t first[kCellsPerBlock][kCellCand];
+  const int g = threadIdx.x / kCellLanes, sub = threadIdx.x & (kCellLanes - 1);
+  const int64_t I = (int64_t)blockIdx.x * kCellsPerBlock + g;
+  const bool act = I < nc;
+  const int32_t slots = act ? cptr[I + 1] - cptr[I] : 0;   // the members' degree sum
+  const bool group = act && slots <= kCellCand;
+  int32_t* out = act ? tmp + cptr[I] : tmp;
+  int32_t total = 0;
+  if (act && !group) {
+    if (sub == 0) cell_neighbours_serial(ptr, mem, rp, col, lab, (int32_t)I, out, ucnt);
+  } else if (group) {
+    const int32_t m0 = ptr[I], m1 = ptr[I + 1];
+    for (int32_t k0 = m0; k0 < m1; k0 += kCellLanes) {     // uniform within the group
+      const int32_t k = k0 + sub;
+      int32_t rb = 0, deg = 0;
+      if (k < m1) {
+        const int32_t a = mem[k];
+        rb = rp[a];
+        deg = rp[a + 1] - rb;
+      }
+      int32_t incl = deg;
+      for (int o = 1; o < kCellLanes; o <<= 1) {
+        const int32_t t = __shfl_up(incl, o, kCellLanes);
+        if (sub >= o) incl += t;
+      }
+      const int32_t pos = total + incl - deg;
+      for (int32_t e0 = 0; e0 < deg; e0 += kCellChunk) {
+        int32_t c[kCellChunk], J[kCellChunk];
+#pragma unroll
+        for (int q = 0; q < kCellChunk; ++q) c[q] = col[rb + min(e0 + q, deg - 1)];
+#pragma unroll
+        for (int q = 0; q < kCellChunk; ++q) J[q] = lab[c[q]];
+#pragma unroll
+        for (int q = 0; q < kCellChunk; ++q)
+          if (e0 + q < deg) cand[g][pos + e0 + q] = J[q] == (int32_t)I ? INT32_MIN : J[q];
+      }
+      total += __shfl(incl, kCellLanes - 1, kCellLanes);
+    }
+  }
+  __syncthreads();
+  if (group)
+    for (int32_t q = sub; q < total; q += kCellLanes) {
+      const int32_t key = cand[g][q];
+      bool f = key != INT32_MIN;
+      for (int32_t q2 = 0; q2 < q && f; ++q2) f = cand[g][q2] != key;
+      first[g][q] = f;
+    }
+  __syncthreads();
+  if (group) {
+    int32_t u = 0;
+    for (int32_t q = sub; q < total; q += kCellLanes) {
+      if (!first[g][q]) continue;
+      const int32_t key = cand[g][q];
+      int32_t rank = 0;
+      for (int32_t q2 = 0; q2 < total; ++q2) rank += first[g][q2] && cand[g][q2] < key;
+      out[rank] = key;
+      ++u;
+    }
+    for (int o = kCellLanes / 2; o > 0; o >>= 1) u += __shfl_xor(u, o, kCellLanes);
+    if (sub == 0) ucnt[I] = u;
+  }
 }
 
 }  // namespace
@@ -612,8 +690,8 @@ void coarse_edges(Handle& h, Level& lv, Level& nx, const int32_t* cell_ptr, cons
   int32_t* tmp = (int32_t*)talloc(s, (size_t)(lv.nnzE_cap + 1) * 4);
   k_cell_degree<<<blocks_for(nc), kBlock, 0, s>>>(cell_ptr, cell_mem, lv.erp, nc, cdeg);
   scan_i32(cdeg, cptr, nc, s);
-  k_cell_neighbours<<<blocks_for(nc), kBlock, 0, s>>>(cell_ptr, cell_mem, lv.erp, lv.ecol, lv.label, cptr,
-                                                      nc, tmp, cdeg);
+  k_cell_neighbours<<<blocks_for(nc, kCellsPerBlock), kBlock, 0, s>>>(cell_ptr, cell_mem, lv.erp, lv.ecol,
+                                                                      lv.label, cptr, nc, tmp, cdeg);
   nx.erp = (int32_t*)dalloc(h, (size_t)(nc + 1) * 4);
   scan_i32(cdeg, nx.erp, nc, s);
   // every coarse edge entry comes from a distinct fine edge entry: nnz(E_{l+1}) <= nnz(E_l)

@@ -270,25 +270,47 @@ __global__ void k_slice_width(const int32_t* len, int64_t n, int64_t ns, int32_t
   wsz[s] = w * kSlice;
 }
 
-__global__ void k_sell_fill(const int32_t* perm, const int32_t* cmap, const int32_t* rp, const int32_t* col,
-                            const double* val, int64_t n, const int32_t* sptr, int32_t* scol, double* sval,
-                            double* diag) {
+constexpr int kFillChunk = 8;
+
+// The loads of kFillChunk entries of the source row are issued together
+// (positions past the row's end re-read its last entry and store padding).
+__global__ void k_sell_fill(const int32_t* __restrict__ perm, const int32_t* __restrict__ cmap,
+                            const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                            const double* __restrict__ val, int64_t n, const int32_t* __restrict__ sptr,
+                            int32_t* __restrict__ scol, double* __restrict__ sval, double* __restrict__ diag) {
   int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n) return;
   int64_t s = r / kSlice, ln = r % kSlice;
   int32_t src = perm ? perm[r] : (int32_t)r;
-  int32_t b = rp[src], e = rp[src + 1];
-  int32_t w = (sptr[s + 1] - sptr[s]) / kSlice;
-  for (int32_t t = 0; t < w; ++t) {
-    int64_t o = sptr[s] + (int64_t)t * kSlice + ln;
-    if (b + t < e) {
-      int32_t j = col[b + t];
-      scol[o] = cmap ? cmap[j] : j;
-      sval[o] = val[b + t];
-      if (diag && j == src) diag[r] = val[b + t];
-    } else {
-      scol[o] = 0;
-      sval[o] = 0.0;
+  const int32_t b = rp[src], len = rp[src + 1] - b;
+  const int32_t base = sptr[s];
+  const int32_t w = (sptr[s + 1] - base) / kSlice;
+  for (int32_t t0 = 0; t0 < w; t0 += kFillChunk) {
+    int32_t j[kFillChunk], m[kFillChunk];
+    double v[kFillChunk];
+    if (len > 0) {
+#pragma unroll
+      for (int k = 0; k < kFillChunk; ++k) {
+        const int32_t q = b + min(t0 + k, len - 1);
+        j[k] = col[q];
+        v[k] = val[q];
+      }
+#pragma unroll
+      for (int k = 0; k < kFillChunk; ++k) m[k] = cmap ? cmap[j[k]] : j[k];
+    }
+#pragma unroll
+    for (int k = 0; k < kFillChunk; ++k) {
+      const int32_t t = t0 + k;
+      if (t >= w) break;
+      const int64_t o = base + (int64_t)t * kSlice + ln;
+      if (t < len) {
+        scol[o] = m[k];
+        sval[o] = v[k];
+        if (diag && j[k] == src) diag[r] = v[k];
+      } else {
+        scol[o] = 0;
+        sval[o] = 0.0;
+      }
     }
   }
 }
