@@ -457,6 +457,15 @@ void build(Handle& h, int64_t n, const double* points, int64_t m, const int32_t*
 // MGI(x, b, l) of Alg. 2: pre-relax, restrict the residual, recurse from a
 // zero guess, prolong and correct the pre-relaxed iterate, post-relax.  In a
 // symmetric cycle the post-relaxation visits the colours in descending order.
+// Rows of level l whose first pre-smoothing update the restriction into l
+// performs (its first colour; 0 when level l is solved by the tail kernel or
+// has no pre-smoothing).
+int32_t folded_rows(const Handle& h, size_t l) {
+  const Level& lv = h.L[l];
+  if ((int)l >= h.tail_start || h.opt.nu_pre < 1 || lv.color_ptr.size() < 2) return 0;
+  return lv.color_ptr[1];
+}
+
 template <class V>
 void vcycle(Handle& h, const Cycle<V>& c, size_t l, hipStream_t s) {
   const LevelViewT<V>& v = c.v[l];
@@ -467,9 +476,11 @@ void vcycle(Handle& h, const Cycle<V>& c, size_t l, hipStream_t s) {
   const LevelViewT<V>& cv = c.v[l + 1];
   const Level& lv = h.L[l];
   const bool timed = !c.symmetric;            // the solve's cycle is the measured one
-  for (int k = 0; k < h.opt.nu_pre; ++k) gs_sweep(v, lv, s, l == 0, false, timed);
+  // on a coarse level the restriction into it already did the first colour
+  const int skip = l > 0 && folded_rows(h, l) > 0 ? 1 : 0;
+  for (int k = 0; k < h.opt.nu_pre; ++k) gs_sweep(v, lv, s, l == 0, false, timed, k == 0 ? skip : 0);
   residual(v, s, l == 0);
-  restrict_to(v, cv, s);
+  restrict_to(v, cv, s, folded_rows(h, l + 1));
   vcycle(h, c, l + 1, s);
   prolong_correct(v, cv, s);
   for (int k = 0; k < h.opt.nu_post; ++k) gs_sweep(v, lv, s, l == 0, c.symmetric, timed);
@@ -479,7 +490,7 @@ void vcycle(Handle& h, const Cycle<V>& c, size_t l, hipStream_t s) {
 void cycle_inner(Handle& h, hipStream_t s) {
   const Cycle<double>& c = h.plain;
   residual(c.v[0], s, true);
-  restrict_to(c.v[0], c.v[1], s);
+  restrict_to(c.v[0], c.v[1], s, folded_rows(h, 1));
   vcycle(h, c, 1, s);
   prolong_correct(c.v[0], c.v[1], s);
 }

@@ -419,11 +419,16 @@ int ell_first_level(const Handle& h);                      // levels ell_first_l
 // the colours of lv (host ranges) in ascending or descending order; `timed`
 // lets the level-0 measurement timer see the launches.
 template <class V>
-void gs_sweep(const LevelViewT<V>& v, const Level& lv, hipStream_t s, bool finest, bool descending, bool timed);
+// skip: colours at the start of the sweep already done (the first pre-sweep
+// colour of a coarse level, folded into the restriction)
+void gs_sweep(const LevelViewT<V>& v, const Level& lv, hipStream_t s, bool finest, bool descending, bool timed,
+              int skip = 0);
 template <class V>
 void residual(const LevelViewT<V>& v, hipStream_t s, bool finest);
 template <class V>
-void restrict_to(const LevelViewT<V>& v, const LevelViewT<V>& c, hipStream_t s);
+// first > 0: rows [0, first) of the coarse level also take their first
+// pre-smoothing Gauss-Seidel update from the zero iterate
+void restrict_to(const LevelViewT<V>& v, const LevelViewT<V>& c, hipStream_t s, int32_t first = 0);
 template <class V>
 void prolong_correct(const LevelViewT<V>& v, const LevelViewT<V>& c, hipStream_t s);
 template <class V>

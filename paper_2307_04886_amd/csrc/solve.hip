@@ -112,16 +112,21 @@ __global__ void __launch_bounds__(kBlock) k_finish_norm(const double* partials, 
 }
 
 // b_c[I] = sum over row I of P^T (ascending original fine index) of P[i,I] r_i,
-// and the coarse iterate starts from zero: x_c[I] = 0
+// and the coarse iterate starts from zero: x_c[I] = 0.  Rows I < first (the
+// first colour of the coarse level, when its first pre-smoothing colour is
+// folded in here) take that colour's Gauss-Seidel update from the zero
+// iterate instead: every neighbour term is a product with +0, the sum is +0,
+// and x_c[I] = (b_c[I] - 0) / A_c[I,I], the value the sweep would write.
 template <int R, class V>
 __global__ void __launch_bounds__(kBlock) k_restrict(Sell<V> T, const V* __restrict__ r, V* __restrict__ bc,
-                                                     V* __restrict__ xc, int64_t nc, int32_t maxlen) {
+                                                     V* __restrict__ xc, int64_t nc, int32_t maxlen,
+                                                     const V* __restrict__ diag_c, int32_t first) {
   const int64_t g = ((int64_t)xcd_block() * kBlock + threadIdx.x) / R;
   const bool active = g < nc;
   const V acc = row_sumR<R>(T, (int32_t)g, active, r, -1, maxlen);
   if (active && (threadIdx.x & (R - 1)) == 0) {
     bc[g] = acc;
-    xc[g] = V(0);
+    xc[g] = g < first ? (acc - V(0)) / diag_c[g] : V(0);
   }
 }
 
@@ -531,9 +536,10 @@ __global__ void k_check_finite(const double* v, int64_t n, int32_t* flag) {
 }  // namespace
 
 template <class V>
-void gs_sweep(const LevelViewT<V>& v, const Level& lv, hipStream_t s, bool finest, bool descending, bool timed) {
+void gs_sweep(const LevelViewT<V>& v, const Level& lv, hipStream_t s, bool finest, bool descending, bool timed,
+              int skip) {
   const int C = (int)lv.color_ptr.size() - 1;
-  for (int k = 0; k < C; ++k) {
+  for (int k = skip; k < C; ++k) {
     const int c = descending ? C - 1 - k : k;
     const int32_t r0 = lv.color_ptr[c], r1 = lv.color_ptr[c + 1];
     if (r1 <= r0) continue;
@@ -567,10 +573,11 @@ void residual(const LevelViewT<V>& v, hipStream_t s, bool finest) {
 }
 
 template <class V>
-void restrict_to(const LevelViewT<V>& v, const LevelViewT<V>& c, hipStream_t s) {
+void restrict_to(const LevelViewT<V>& v, const LevelViewT<V>& c, hipStream_t s, int32_t first) {
   with_lanes(v.rt, [&](auto RC) {
     constexpr int R = decltype(RC)::value;
-    k_restrict<R, V><<<blocks_for((int64_t)c.n * R), kBlock, 0, s>>>(v.T, v.r, c.b, c.x, c.n, v.maxt);
+    k_restrict<R, V><<<blocks_for((int64_t)c.n * R), kBlock, 0, s>>>(v.T, v.r, c.b, c.x, c.n, v.maxt,
+                                                                      (const V*)c.diag, first);
   });
 }
 
@@ -627,9 +634,9 @@ void check_finite(const double* v, int64_t n, int32_t* flag, hipStream_t s) {
 }
 
 #define GMG_INSTANTIATE(V)                                                                              \
-  template void gs_sweep<V>(const LevelViewT<V>&, const Level&, hipStream_t, bool, bool, bool);       \
+  template void gs_sweep<V>(const LevelViewT<V>&, const Level&, hipStream_t, bool, bool, bool, int);  \
   template void residual<V>(const LevelViewT<V>&, hipStream_t, bool);                                  \
-  template void restrict_to<V>(const LevelViewT<V>&, const LevelViewT<V>&, hipStream_t);               \
+  template void restrict_to<V>(const LevelViewT<V>&, const LevelViewT<V>&, hipStream_t, int32_t);      \
   template void prolong_correct<V>(const LevelViewT<V>&, const LevelViewT<V>&, hipStream_t);           \
   template void coarse_solve<V>(const double*, const LevelViewT<V>&, hipStream_t);                     \
   template void tail_vcycle<V>(const TailDescT<V>&, hipStream_t);                                      \
