@@ -172,22 +172,55 @@ __device__ inline bool key_less(uint64_t ka, int32_t a, uint64_t kb, int32_t b) 
 // final, so statuses are updated in place; the result equals the sequential
 // sweep's for any interleaving.  Round 0 visits every point; later rounds
 // visit the worklist of points still undecided after the previous round.
+// The loads are issued a chunk at a time: kSweepChunk neighbours m of p with
+// their row bounds and statuses, then each m's row kSweepChunk entries at a
+// time with the statuses of their ends (positions past a row's end re-read
+// its last entry and are not counted).
+constexpr int kSweepChunk = 8;
+
 __device__ inline bool lfmis_attempt(const int32_t* rp, const int32_t* col, const double* w, double r,
                                      const SweepKey& key, uint8_t* status, int32_t p) {
   const uint64_t kp = key(p);
   bool blocked = false, out = false;
-  for (int32_t e = rp[p]; e < rp[p + 1] && !out; ++e) {
-    int32_t m = col[e];
-    double wpm = w[e];
-    if (wpm <= r && key_less(key(m), m, kp, p)) {
-      uint8_t s = __atomic_load_n(&status[m], __ATOMIC_RELAXED);
-      if (s == 1) out = true; else if (s == 0) blocked = true;
+  auto note = [&](uint8_t s) {
+    if (s == 1) out = true; else if (s == 0) blocked = true;
+  };
+  const int32_t b = rp[p], e = rp[p + 1];
+  for (int32_t e0 = b; e0 < e && !out; e0 += kSweepChunk) {
+    int32_t m[kSweepChunk], mb[kSweepChunk], me[kSweepChunk];
+    double wm[kSweepChunk];
+    uint8_t sm[kSweepChunk];
+#pragma unroll
+    for (int k = 0; k < kSweepChunk; ++k) {
+      const int32_t i = min(e0 + k, e - 1);
+      m[k] = col[i];
+      wm[k] = w[i];
     }
-    for (int32_t f = rp[m]; f < rp[m + 1] && !out; ++f) {
-      int32_t q = col[f];
-      if (q != p && wpm + w[f] <= r && key_less(key(q), q, kp, p)) {
-        uint8_t s = __atomic_load_n(&status[q], __ATOMIC_RELAXED);
-        if (s == 1) out = true; else if (s == 0) blocked = true;
+#pragma unroll
+    for (int k = 0; k < kSweepChunk; ++k) {
+      mb[k] = rp[m[k]];
+      me[k] = rp[m[k] + 1];
+      sm[k] = __atomic_load_n(&status[m[k]], __ATOMIC_RELAXED);
+    }
+#pragma unroll
+    for (int k = 0; k < kSweepChunk; ++k)
+      if (e0 + k < e && wm[k] <= r && key_less(key(m[k]), m[k], kp, p)) note(sm[k]);
+    for (int k = 0; k < kSweepChunk && e0 + k < e && !out; ++k) {
+      for (int32_t f0 = mb[k]; f0 < me[k] && !out; f0 += kSweepChunk) {
+        int32_t q[kSweepChunk];
+        double wq[kSweepChunk];
+        uint8_t sq[kSweepChunk];
+#pragma unroll
+        for (int t = 0; t < kSweepChunk; ++t) {
+          const int32_t i = min(f0 + t, me[k] - 1);
+          q[t] = col[i];
+          wq[t] = w[i];
+        }
+#pragma unroll
+        for (int t = 0; t < kSweepChunk; ++t) sq[t] = __atomic_load_n(&status[q[t]], __ATOMIC_RELAXED);
+#pragma unroll
+        for (int t = 0; t < kSweepChunk; ++t)
+          if (f0 + t < me[k] && q[t] != p && wm[k] + wq[t] <= r && key_less(key(q[t]), q[t], kp, p)) note(sq[t]);
       }
     }
   }
@@ -338,14 +371,32 @@ __global__ void __launch_bounds__(kBlock) k_voronoi_round(const int32_t* rp, con
     double bd = dA[v];
     int32_t bl = lA[v];
     if (status[v] != 1) {
-      for (int32_t e = rp[v]; e < rp[v + 1]; ++e) {
-        int32_t u = col[e];
-        int32_t lu = lA[u];
-        if (lu < 0) continue;
-        double c = dA[u] + w[e];
-        if (c < bd || (c == bd && lu < bl)) {
-          bd = c;
-          bl = lu;
+      // the lexicographic minimum of (distance, label): the neighbours' loads
+      // are issued kSweepChunk at a time (positions past the row's end
+      // re-read its last entry and are not counted)
+      const int32_t b = rp[v], e = rp[v + 1];
+      for (int32_t e0 = b; e0 < e; e0 += kSweepChunk) {
+        int32_t u[kSweepChunk], lu[kSweepChunk];
+        double wu[kSweepChunk], du[kSweepChunk];
+#pragma unroll
+        for (int k = 0; k < kSweepChunk; ++k) {
+          const int32_t i = min(e0 + k, e - 1);
+          u[k] = col[i];
+          wu[k] = w[i];
+        }
+#pragma unroll
+        for (int k = 0; k < kSweepChunk; ++k) {
+          lu[k] = lA[u[k]];
+          du[k] = dA[u[k]];
+        }
+#pragma unroll
+        for (int k = 0; k < kSweepChunk; ++k) {
+          if (e0 + k >= e || lu[k] < 0) continue;
+          const double c = du[k] + wu[k];
+          if (c < bd || (c == bd && lu[k] < bl)) {
+            bd = c;
+            bl = lu[k];
+          }
         }
       }
       changed = (bd != dA[v]) || (bl != lA[v]);
