@@ -231,7 +231,7 @@ __device__ inline bool lfmis_attempt(const int32_t* rp, const int32_t* col, cons
 
 // On levels of up to kListLevel points the first visit of p also records the
 // points in conflict with it that come earlier in the sweep (its whole 2-ring
-// search, in search order, repeats included) in list[p * kConflicts ..], with
+// search, repeats included) in list[p * kConflicts ..], with
 // their number in cnt[p] (kConflicts + 1: too many, later visits search
 // again); later visits then only read those points' statuses.  (On larger
 // levels the first round streams the graph at full bandwidth, and writing the
@@ -245,19 +245,50 @@ __device__ inline bool lfmis_first(const int32_t* rp, const int32_t* col, const 
   bool blocked = false, out = false;
   int32_t k = 0;
   int32_t* lp = list + (int64_t)p * kConflicts;
-  auto note = [&](int32_t q) {
-    const uint8_t s = __atomic_load_n(&status[q], __ATOMIC_RELAXED);
+  auto note = [&](int32_t q, uint8_t s) {
     if (s == 1) out = true; else if (s == 0) blocked = true;
     if (k < kConflicts) lp[k] = q;
     ++k;
   };
-  for (int32_t e = rp[p]; e < rp[p + 1]; ++e) {
-    const int32_t m = col[e];
-    const double wpm = w[e];
-    if (wpm <= r && key_less(key(m), m, kp, p)) note(m);
-    for (int32_t f = rp[m]; f < rp[m + 1]; ++f) {
-      const int32_t q = col[f];
-      if (q != p && wpm + w[f] <= r && key_less(key(q), q, kp, p)) note(q);
+  // the same chunked search as lfmis_attempt, recording every conflict
+  const int32_t b = rp[p], e = rp[p + 1];
+  for (int32_t e0 = b; e0 < e; e0 += kSweepChunk) {
+    int32_t m[kSweepChunk], mb[kSweepChunk], me[kSweepChunk];
+    double wm[kSweepChunk];
+    uint8_t sm[kSweepChunk];
+#pragma unroll
+    for (int j = 0; j < kSweepChunk; ++j) {
+      const int32_t i = min(e0 + j, e - 1);
+      m[j] = col[i];
+      wm[j] = w[i];
+    }
+#pragma unroll
+    for (int j = 0; j < kSweepChunk; ++j) {
+      mb[j] = rp[m[j]];
+      me[j] = rp[m[j] + 1];
+      sm[j] = __atomic_load_n(&status[m[j]], __ATOMIC_RELAXED);
+    }
+#pragma unroll
+    for (int j = 0; j < kSweepChunk; ++j)
+      if (e0 + j < e && wm[j] <= r && key_less(key(m[j]), m[j], kp, p)) note(m[j], sm[j]);
+    for (int j = 0; j < kSweepChunk && e0 + j < e; ++j) {
+      for (int32_t f0 = mb[j]; f0 < me[j]; f0 += kSweepChunk) {
+        int32_t q[kSweepChunk];
+        double wq[kSweepChunk];
+        uint8_t sq[kSweepChunk];
+#pragma unroll
+        for (int t = 0; t < kSweepChunk; ++t) {
+          const int32_t i = min(f0 + t, me[j] - 1);
+          q[t] = col[i];
+          wq[t] = w[i];
+        }
+#pragma unroll
+        for (int t = 0; t < kSweepChunk; ++t) sq[t] = __atomic_load_n(&status[q[t]], __ATOMIC_RELAXED);
+#pragma unroll
+        for (int t = 0; t < kSweepChunk; ++t)
+          if (f0 + t < me[j] && q[t] != p && wm[j] + wq[t] <= r && key_less(key(q[t]), q[t], kp, p))
+            note(q[t], sq[t]);
+      }
     }
   }
   cnt[p] = (uint8_t)(k <= kConflicts ? k : kConflicts + 1);
@@ -273,9 +304,19 @@ __device__ inline bool lfmis_again(const int32_t* rp, const int32_t* col, const 
   if (k > kConflicts) return lfmis_attempt(rp, col, w, r, key, status, p);
   const int32_t* lp = list + (int64_t)p * kConflicts;
   bool blocked = false, out = false;
-  for (int32_t i = 0; i < k; ++i) {
-    const uint8_t s = __atomic_load_n(&status[lp[i]], __ATOMIC_RELAXED);
-    if (s == 1) out = true; else if (s == 0) blocked = true;
+  constexpr int kListChunk = 16;
+  for (int32_t i0 = 0; i0 < k && !out; i0 += kListChunk) {
+    int32_t q[kListChunk];
+    uint8_t sq[kListChunk];
+#pragma unroll
+    for (int t = 0; t < kListChunk; ++t) q[t] = lp[min(i0 + t, k - 1)];
+#pragma unroll
+    for (int t = 0; t < kListChunk; ++t) sq[t] = __atomic_load_n(&status[q[t]], __ATOMIC_RELAXED);
+#pragma unroll
+    for (int t = 0; t < kListChunk; ++t) {
+      if (i0 + t >= k) continue;
+      if (sq[t] == 1) out = true; else if (sq[t] == 0) blocked = true;
+    }
   }
   if (out) status[p] = 2;
   else if (!blocked) status[p] = 1;
