@@ -47,8 +47,15 @@ __global__ void k_edge_scatter(const int32_t* edges, int64_t m, int64_t n, const
 
 // Row i of the system matrix: valid offsets, strictly ascending in-range
 // columns, finite values, diagonal present and positive, symmetric pattern.
-__global__ void k_validate_matrix(const int32_t* rp, const int32_t* col, const double* val, int64_t n,
-                                  int64_t nnz, int32_t* flags) {
+// Per row: offsets in range, columns in range and strictly ascending, values
+// finite, a positive diagonal, and every entry (i, j) matched by (j, i) (a
+// binary search in row j).  The row's entries are checked kValidChunk at a
+// time with their loads and search steps in flight together; the flags do not
+// depend on the order of the checks.
+constexpr int kValidChunk = 8;
+
+__global__ void k_validate_matrix(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                  const double* __restrict__ val, int64_t n, int64_t nnz, int32_t* flags) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i == 0 && (rp[0] != 0 || rp[n] != nnz)) atomicOr(flags, F_INVALID);
   if (i >= n) return;
@@ -57,44 +64,86 @@ __global__ void k_validate_matrix(const int32_t* rp, const int32_t* col, const d
     atomicOr(flags, F_INVALID);
     return;
   }
-  bool diag = false;
-  for (int32_t k = b; k < e; ++k) {
-    int32_t j = col[k];
-    if (j < 0 || j >= n || (k > b && j <= col[k - 1]) || !isfinite(val[k])) {
-      atomicOr(flags, F_INVALID);
-      return;
+  bool diag = false, bad = false, notspd = false;
+  for (int32_t k0 = b; k0 < e; k0 += kValidChunk) {
+    int32_t j[kValidChunk], jprev[kValidChunk], lo[kValidChunk], hi[kValidChunk];
+    double v[kValidChunk];
+    bool on[kValidChunk];
+#pragma unroll
+    for (int q = 0; q < kValidChunk; ++q) {
+      const int32_t k = min(k0 + q, e - 1);
+      on[q] = k0 + q < e;
+      j[q] = col[k];
+      jprev[q] = k > b ? col[k - 1] : -1;
+      v[q] = val[k];
     }
-    if (j == i) {
-      diag = true;
-      if (!(val[k] > 0.0)) atomicOr(flags, F_NOT_SPD);
+#pragma unroll
+    for (int q = 0; q < kValidChunk; ++q) {
+      const bool jok = j[q] >= 0 && j[q] < n;
+      if (on[q] && (!jok || (k0 + q > b && j[q] <= jprev[q]) || !isfinite(v[q]))) bad = true;
+      if (on[q] && j[q] == i) {
+        diag = true;
+        if (!(v[q] > 0.0)) notspd = true;
+      }
+      lo[q] = 0;
+      hi[q] = 0;
+      if (on[q] && jok) {
+        lo[q] = rp[j[q]];
+        hi[q] = rp[j[q] + 1];
+      }
     }
-    int32_t jb = rp[j], je = rp[j + 1];
-    if (jb < 0 || je < jb || je > nnz) {
-      atomicOr(flags, F_INVALID);
-      return;
+    int32_t je[kValidChunk];
+#pragma unroll
+    for (int q = 0; q < kValidChunk; ++q) {
+      je[q] = hi[q];
+      if (lo[q] < 0 || hi[q] < lo[q] || hi[q] > nnz) {
+        bad = true;
+        lo[q] = hi[q] = je[q] = 0;
+      }
     }
-    int32_t lo = jb, hi = je;                     // binary search for i in row j
-    while (lo < hi) {
-      int32_t mid = (lo + hi) >> 1;
-      if (col[mid] < i) lo = mid + 1; else hi = mid;
+    // binary searches for i in rows j, one step of each per pass
+    for (;;) {
+      bool more = false;
+#pragma unroll
+      for (int q = 0; q < kValidChunk; ++q)
+        if (lo[q] < hi[q]) {
+          const int32_t mid = (lo[q] + hi[q]) >> 1;
+          if (col[mid] < i) lo[q] = mid + 1; else hi[q] = mid;
+          more = true;
+        }
+      if (!more) break;
     }
-    if (lo >= je || col[lo] != i) {
-      atomicOr(flags, F_INVALID);
-      return;
-    }
+#pragma unroll
+    for (int q = 0; q < kValidChunk; ++q)
+      if (on[q] && j[q] >= 0 && j[q] < n && (lo[q] >= je[q] || col[lo[q]] != i)) bad = true;
   }
-  if (!diag) atomicOr(flags, F_INVALID);
+  if (notspd) atomicOr(flags, F_NOT_SPD);
+  if (bad || !diag) atomicOr(flags, F_INVALID);
 }
 
 // ------------------------------------------------------------------ edge lengths, Eq. (1)
-__global__ void k_edge_weights(const double* X, const int32_t* rp, const int32_t* col, int64_t n,
-                               double* w) {
+// The row's end points are loaded kEdgeChunk at a time.
+constexpr int kEdgeChunk = 8;
+
+__global__ void k_edge_weights(const double* __restrict__ X, const int32_t* __restrict__ rp,
+                               const int32_t* __restrict__ col, int64_t n, double* __restrict__ w) {
   int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (u >= n) return;
   V3 pu = ld3(X, u);
-  for (int32_t e = rp[u]; e < rp[u + 1]; ++e) {
-    V3 d = sub3(pu, ld3(X, col[e]));
-    w[e] = sqrt(dot3(d, d));
+  const int32_t b = rp[u], e = rp[u + 1];
+  for (int32_t e0 = b; e0 < e; e0 += kEdgeChunk) {
+    int32_t c[kEdgeChunk];
+    V3 pv[kEdgeChunk];
+#pragma unroll
+    for (int q = 0; q < kEdgeChunk; ++q) c[q] = col[min(e0 + q, e - 1)];
+#pragma unroll
+    for (int q = 0; q < kEdgeChunk; ++q) pv[q] = ld3(X, c[q]);
+#pragma unroll
+    for (int q = 0; q < kEdgeChunk; ++q) {
+      if (e0 + q >= e) break;
+      V3 d = sub3(pu, pv[q]);
+      w[e0 + q] = sqrt(dot3(d, d));
+    }
   }
 }
 

@@ -336,18 +336,29 @@ __global__ void k_color_nnz(const int32_t* prefix, const int32_t* cptr, int nc, 
 
 // P in the new numbering, SoA ELL-3 ([3][n]); padding repeats the first
 // column with weight 0.
-__global__ void k_p_layout(const int32_t* perm, const int32_t* ciperm, const int32_t* pcol,
-                           const double* pval, const int32_t* pcnt, int64_t n, int32_t* qcol, double* qval,
-                           int32_t* qcnt) {
+__global__ void k_p_layout(const int32_t* __restrict__ perm, const int32_t* __restrict__ ciperm,
+                           const int32_t* __restrict__ pcol, const double* __restrict__ pval,
+                           const int32_t* __restrict__ pcnt, int64_t n, int32_t* __restrict__ qcol,
+                           double* __restrict__ qval, int32_t* __restrict__ qcnt) {
   int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n) return;
-  int32_t old = perm[r];
-  int32_t c = pcnt[old];
-  qcnt[r] = c;
-  int32_t first = c > 0 ? ciperm[pcol[3 * old]] : 0;
+  const int32_t old = perm[r];
+  const int32_t c = pcnt[old];
+  int32_t pc[3], cc[3];
+  double pv[3];
+#pragma unroll
   for (int t = 0; t < 3; ++t) {
-    qcol[t * n + r] = t < c ? ciperm[pcol[3 * old + t]] : first;
-    qval[t * n + r] = t < c ? pval[3 * old + t] : 0.0;
+    pc[t] = pcol[3 * old + t];
+    pv[t] = pval[3 * old + t];
+  }
+#pragma unroll
+  for (int t = 0; t < 3; ++t) cc[t] = t < c ? ciperm[pc[t]] : 0;
+  qcnt[r] = c;
+  const int32_t first = c > 0 ? cc[0] : 0;
+#pragma unroll
+  for (int t = 0; t < 3; ++t) {
+    qcol[t * n + r] = t < c ? cc[t] : first;
+    qval[t * n + r] = t < c ? pv[t] : 0.0;
   }
 }
 
