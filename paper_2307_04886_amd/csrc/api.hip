@@ -131,11 +131,42 @@ void* pinned_staging(size_t bytes) {
   return (char*)pinned_scratch() + kStaging / 2;      // second half: bulk staging
 }
 
+// Up to kScalarGather device scalars copied by one launch into 8-byte slots
+// of the pinned buffer (lane k takes item k; a 4-byte item fills the low half).
+constexpr int kScalarGather = 8;
+struct ScalarGather {
+  const void* src[kScalarGather];
+  int32_t bytes[kScalarGather];
+};
+
+__global__ void k_read_scalars(ScalarGather g, int count, uint64_t* out) {
+  const int k = (int)threadIdx.x;
+  if (k >= count) return;
+  const void* src = g.src[0];
+  int32_t bytes = g.bytes[0];
+#pragma unroll
+  for (int j = 1; j < kScalarGather; ++j)
+    if (j == k) {
+      src = g.src[j];
+      bytes = g.bytes[j];
+    }
+  out[k] = bytes == 4 ? (uint64_t)*(const uint32_t*)src : *(const uint64_t*)src;
+}
+
 void read_scalars(Handle& h, const ScalarRead* items, int count) {
   char* buf = (char*)pinned_scratch();
-  for (int k = 0; k < count; ++k)
-    check_hip(hipMemcpyAsync(buf + 8 * k, items[k].src, items[k].bytes, hipMemcpyDeviceToHost, h.stream),
-              "device-to-host copy");
+  static thread_local uint64_t* dbuf = nullptr;      // the buffer's device address
+  if (!dbuf) check_hip(hipHostGetDevicePointer((void**)&dbuf, buf, 0), "pinned host buffer");
+  for (int k0 = 0; k0 < count; k0 += kScalarGather) {
+    ScalarGather g{};
+    const int c = std::min(count - k0, kScalarGather);
+    for (int k = 0; k < c; ++k) {
+      g.src[k] = items[k0 + k].src;
+      g.bytes[k] = items[k0 + k].bytes;
+    }
+    k_read_scalars<<<1, kWave, 0, h.stream>>>(g, c, dbuf + k0);
+  }
+  check_hip(hipGetLastError(), "scalar read");
   sync(h.stream, "device-to-host copy");
   for (int k = 0; k < count; ++k) {
     if (items[k].bytes == 4) {
