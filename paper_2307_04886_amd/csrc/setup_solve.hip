@@ -315,6 +315,64 @@ __global__ void k_sell_fill(const int32_t* __restrict__ perm, const int32_t* __r
   }
 }
 
+// The same fill, one workgroup per slice of 64 rows, transposed through LDS:
+// every source row is read contiguously (its entries across lanes), the slice
+// is written column by column (entry t of the 64 rows contiguous).  pitch is
+// at least the longest row of the matrix.
+constexpr int kSliceFillMax = 64;
+
+__global__ void __launch_bounds__(kBlock) k_sell_fill_slice(const int32_t* __restrict__ perm,
+                                                            const int32_t* __restrict__ cmap,
+                                                            const int32_t* __restrict__ rp,
+                                                            const int32_t* __restrict__ col,
+                                                            const double* __restrict__ val, int64_t n,
+                                                            const int32_t* __restrict__ sptr,
+                                                            int32_t* __restrict__ scol, double* __restrict__ sval,
+                                                            double* __restrict__ diag, int pitch) {
+  extern __shared__ double fill_lds[];
+  double* lv = fill_lds;                                   // [kSlice][pitch]
+  int32_t* lc = (int32_t*)(fill_lds + kSlice * pitch);     // [kSlice][pitch]
+  __shared__ int32_t rb[kSlice], rl[kSlice], rs[kSlice];
+  const int64_t s = blockIdx.x;
+  const int64_t r0 = s * kSlice;
+  const int tid = threadIdx.x;
+  if (tid < kSlice) {
+    const int64_t r = r0 + tid;
+    int32_t src = -1, b = 0, len = 0;
+    if (r < n) {
+      src = perm ? perm[r] : (int32_t)r;
+      b = rp[src];
+      len = rp[src + 1] - b;
+    }
+    rb[tid] = b;
+    rl[tid] = len;
+    rs[tid] = src;
+  }
+  __syncthreads();
+  const int32_t base = sptr[s];
+  const int w = (sptr[s + 1] - base) / kSlice;
+  for (int idx = tid; idx < kSlice * w; idx += kBlock) {
+    const int row = idx / w, t = idx - row * w;
+    int32_t c = 0;
+    double v = 0.0;
+    if (t < rl[row]) {
+      const int32_t j = col[rb[row] + t];
+      v = val[rb[row] + t];
+      c = cmap ? cmap[j] : j;
+      if (diag && j == rs[row]) diag[r0 + row] = v;
+    }
+    lc[row * pitch + t] = c;
+    lv[row * pitch + t] = v;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < kSlice * w; idx += kBlock) {
+    const int t = idx / kSlice, ln = idx - t * kSlice;
+    const int64_t o = base + (int64_t)t * kSlice + ln;
+    scol[o] = lc[ln * pitch + t];
+    sval[o] = lv[ln * pitch + t];
+  }
+}
+
 // *out = max(*out, max_i v[i] + add)
 __global__ void __launch_bounds__(kBlock) k_max_i32(const int32_t* v, int64_t n, int32_t add, int32_t* out) {
   int32_t m = 0;
@@ -739,7 +797,13 @@ SellView make_sell(Handle& h, const int32_t* perm, const int32_t* cmap, const in
   *slots = tot + 1;
   int32_t* scol = (int32_t*)dalloc(h, (size_t)(tot + 1) * 4);
   double* sval = (double*)dalloc(h, (size_t)(tot + 1) * 8);
-  k_sell_fill<<<blocks_for(n), kBlock, 0, s>>>(perm, cmap, rp, col, val, n, ptr, scol, sval, diag);
+  if (ml <= kSliceFillMax) {
+    const int pitch = (int)ml | 1;                 // odd: rows of the tile fall in different banks
+    k_sell_fill_slice<<<(int)ns, kBlock, (size_t)kSlice * pitch * 12, s>>>(perm, cmap, rp, col, val, n, ptr, scol,
+                                                                          sval, diag, pitch);
+  } else {
+    k_sell_fill<<<blocks_for(n), kBlock, 0, s>>>(perm, cmap, rp, col, val, n, ptr, scol, sval, diag);
+  }
   tfree(s, wsz);
   tfree(s, mx);
   SellView v;
