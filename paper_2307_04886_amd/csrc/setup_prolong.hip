@@ -65,6 +65,52 @@ __device__ inline int closest_point(V3 P, V3 A, V3 B, V3 C, double& wa, double& 
   return 6;
 }
 
+// Candidate triangles of each coarse point c: the pairs (j, k) of its sorted
+// neighbour list, positions e1 < e2, with {j, k} a coarse edge and (c, j, k)
+// not degenerate, in ascending (e1, e2) -- the candidates, in order, that the
+// projection of every fine point of c's cell visits.  One wavefront per coarse
+// point, a pair per lane; tcnt[c] = -1 when there are more than kTriMax.
+constexpr int kTriMax = 32;
+
+__global__ void __launch_bounds__(kBlock) k_tri_candidates(const double* __restrict__ Xc,
+                                                           const int32_t* __restrict__ crp,
+                                                           const int32_t* __restrict__ ccol, int64_t nc,
+                                                           int32_t* __restrict__ tlist, int32_t* __restrict__ tcnt) {
+  const int64_t c = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+  const int lane = threadIdx.x & (kWave - 1);
+  if (c >= nc) return;                                   // uniform over the wavefront
+  const int32_t rb = crp[c], d = crp[c + 1] - rb;
+  const int32_t np = d * (d - 1) / 2;
+  const V3 A = ld3(Xc, c);
+  int32_t cnt = 0;
+  for (int32_t p0 = 0; p0 < np; p0 += kWave) {
+    const int32_t p = p0 + lane;
+    bool ok = false;
+    int32_t j = 0, k = 0;
+    if (p < np) {
+      int32_t e1 = 0, off = 0;                           // pair p -> (e1, e2) in lexicographic order
+      while (off + (d - 1 - e1) <= p) {
+        off += d - 1 - e1;
+        ++e1;
+      }
+      const int32_t e2 = e1 + 1 + (p - off);
+      j = ccol[rb + e1];
+      k = ccol[rb + e2];
+      if (has_edge(crp, ccol, j, k)) ok = !degenerate(A, ld3(Xc, j), ld3(Xc, k));
+    }
+    const unsigned long long m = __ballot(ok);
+    if (ok) {
+      const int32_t pos = cnt + __popcll(m & ((1ull << lane) - 1ull));
+      if (pos < kTriMax) {
+        tlist[(c * kTriMax + pos) * 2] = j;
+        tlist[(c * kTriMax + pos) * 2 + 1] = k;
+      }
+    }
+    cnt += __popcll(m);
+  }
+  if (lane == 0) tcnt[c] = cnt <= kTriMax ? cnt : -1;
+}
+
 // One thread per fine point p; c = label(p) is the coarse point closest to p.
 // Candidates are the triangles (c, j, k), j < k neighbours of c with {j, k} a
 // coarse edge, visited in ascending (j, k); the first candidate at the
@@ -80,7 +126,8 @@ __global__ void __launch_bounds__(kBlock) k_project(const double* X, const int32
                                                     const double* Xc, const int32_t* crp, const int32_t* ccol,
                                                     int32_t weighting, int32_t fallback_on_vertex,
                                                     int32_t* pcol, double* pval, int32_t* pcnt, int32_t* tri,
-                                                    unsigned long long* fallback) {
+                                                    unsigned long long* fallback, const int32_t* tlist,
+                                                    const int32_t* tcnt) {
   int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   bool fb = false;
   if (p < n) {
@@ -92,29 +139,57 @@ __global__ void __launch_bounds__(kBlock) k_project(const double* X, const int32
     double best = 0.0, bw0 = 0.0, bw1 = 0.0, bw2 = 0.0;
     int32_t bj = -1, bk = -1;
     int breg = -1;
-    for (int32_t e1 = rb; e1 < re; ++e1) {
-      int32_t j = ccol[e1];
-      V3 B = ld3(Xc, j);
-      for (int32_t e2 = e1 + 1; e2 < re; ++e2) {
-        int32_t k = ccol[e2];
-        if (!has_edge(crp, ccol, j, k)) continue;
-        V3 C = ld3(Xc, k);
-        if (degenerate(A, B, C)) continue;
-        double w0, w1, w2;
-        const int reg = closest_point(P, A, B, C, w0, w1, w2);
-        V3 q = {(w0 * A.x + w1 * B.x) + w2 * C.x, (w0 * A.y + w1 * B.y) + w2 * C.y,
-                (w0 * A.z + w1 * B.z) + w2 * C.z};
-        V3 d = sub3(P, q);
-        double d2 = dot3(d, d);
-        if (!found || d2 < best) {
-          found = true;
-          best = d2;
-          bj = j;
-          bk = k;
-          bw0 = w0;
-          bw1 = w1;
-          bw2 = w2;
-          breg = reg;
+    // a candidate (c, j, k); the first at the smallest distance is kept
+    auto consider = [&](int32_t j, int32_t k, V3 B, V3 C) {
+      double w0, w1, w2;
+      const int reg = closest_point(P, A, B, C, w0, w1, w2);
+      V3 q = {(w0 * A.x + w1 * B.x) + w2 * C.x, (w0 * A.y + w1 * B.y) + w2 * C.y,
+              (w0 * A.z + w1 * B.z) + w2 * C.z};
+      V3 d = sub3(P, q);
+      double d2 = dot3(d, d);
+      if (!found || d2 < best) {
+        found = true;
+        best = d2;
+        bj = j;
+        bk = k;
+        bw0 = w0;
+        bw1 = w1;
+        bw2 = w2;
+        breg = reg;
+      }
+    };
+    const int32_t nt = tcnt[c];
+    if (nt >= 0) {
+      // the cell's listed candidates, kTriChunk at a time with their loads together
+      constexpr int kTriChunk = 4;
+      for (int32_t t0 = 0; t0 < nt; t0 += kTriChunk) {
+        int32_t jj[kTriChunk], kk[kTriChunk];
+        V3 B[kTriChunk], C[kTriChunk];
+#pragma unroll
+        for (int u = 0; u < kTriChunk; ++u) {
+          const int64_t o = ((int64_t)c * kTriMax + min(t0 + u, nt - 1)) * 2;
+          jj[u] = tlist[o];
+          kk[u] = tlist[o + 1];
+        }
+#pragma unroll
+        for (int u = 0; u < kTriChunk; ++u) {
+          B[u] = ld3(Xc, jj[u]);
+          C[u] = ld3(Xc, kk[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < kTriChunk; ++u)
+          if (t0 + u < nt) consider(jj[u], kk[u], B[u], C[u]);
+      }
+    } else {
+      for (int32_t e1 = rb; e1 < re; ++e1) {
+        int32_t j = ccol[e1];
+        V3 B = ld3(Xc, j);
+        for (int32_t e2 = e1 + 1; e2 < re; ++e2) {
+          int32_t k = ccol[e2];
+          if (!has_edge(crp, ccol, j, k)) continue;
+          V3 C = ld3(Xc, k);
+          if (degenerate(A, B, C)) continue;
+          consider(j, k, B, C);
         }
       }
     }
@@ -525,9 +600,15 @@ void prolongation(Handle& h, Level& lv, Level& nx) {
   lv.pval = (double*)dalloc(h, (size_t)3 * n * 8);
   lv.pcnt = (int32_t*)dalloc(h, (size_t)n * 4);
   lv.tri = (int32_t*)dalloc(h, (size_t)2 * n * 4);
+  const int64_t nc = nx.n;
+  int32_t* tlist = (int32_t*)talloc(s, (size_t)nc * kTriMax * 2 * 4);
+  int32_t* tcnt = (int32_t*)talloc(s, (size_t)nc * 4);
+  k_tri_candidates<<<blocks_for(nc, kBlock / kWave), kBlock, 0, s>>>(nx.X, nx.erp, nx.ecol, nc, tlist, tcnt);
   k_project<<<blocks_for(n), kBlock, 0, s>>>(lv.X, lv.label, n, nx.X, nx.erp, nx.ecol, h.opt.weighting,
                                              h.opt.fallback_on_vertex, lv.pcol, lv.pval, lv.pcnt, lv.tri,
-                                             lv.stats);
+                                             lv.stats, tlist, tcnt);
+  tfree(s, tlist);
+  tfree(s, tcnt);
 }
 
 void transpose_p(Handle& h, Level& lv, int64_t nc, int32_t** t_rp, int32_t** t_col, double** t_val) {
