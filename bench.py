@@ -25,8 +25,8 @@ sys.path.insert(0, ROOT)
 # HBM bytes per launch from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE, scaled by what the counters read
 # for a plain device copy (profiles/k_gs_color_*_torus1024.md); valid only for the kernel sources
 # they were taken on (sha256 prefix of solve.hip + rows.hpp).
-TRAFFIC = {"gs_finest": {"bytes_per_launch": 26815935, "src_sha256_16": "47049dbed20cd951"},
-           "gs_galerkin": {"bytes_per_launch": 2573342, "src_sha256_16": "47049dbed20cd951"}}
+TRAFFIC = {"gs_finest": {"bytes_per_launch": 26822506, "src_sha256_16": "c193cd04f86734a6"},
+           "gs_galerkin": {"bytes_per_launch": 2557707, "src_sha256_16": "c193cd04f86734a6"}}
 
 KERNEL_NAMES = {"gs_finest": "k_gs_color_fine (one colour of a Gauss-Seidel sweep, level 0)",
                 "residual_finest": "k_residual_norm (residual + norm partials, level 0)",
