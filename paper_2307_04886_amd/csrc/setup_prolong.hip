@@ -68,23 +68,28 @@ __device__ inline int closest_point(V3 P, V3 A, V3 B, V3 C, double& wa, double& 
 // Candidate triangles of each coarse point c: the pairs (j, k) of its sorted
 // neighbour list, positions e1 < e2, with {j, k} a coarse edge and (c, j, k)
 // not degenerate, in ascending (e1, e2) -- the candidates, in order, that the
-// projection of every fine point of c's cell visits.  One wavefront per coarse
-// point, a pair per lane; tcnt[c] = -1 when there are more than kTriMax.
+// projection of every fine point of c's cell visits.  kTriLanes lanes per
+// coarse point, a pair per lane; tcnt[c] = -1 when there are more than kTriMax.
 constexpr int kTriMax = 32;
+constexpr int kTriLanes = 16;
 
 __global__ void __launch_bounds__(kBlock) k_tri_candidates(const double* __restrict__ Xc,
                                                            const int32_t* __restrict__ crp,
                                                            const int32_t* __restrict__ ccol, int64_t nc,
                                                            int32_t* __restrict__ tlist, int32_t* __restrict__ tcnt) {
-  const int64_t c = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
-  const int lane = threadIdx.x & (kWave - 1);
-  if (c >= nc) return;                                   // uniform over the wavefront
-  const int32_t rb = crp[c], d = crp[c + 1] - rb;
+  const int64_t c = (int64_t)blockIdx.x * (kBlock / kTriLanes) + threadIdx.x / kTriLanes;
+  const int sub = threadIdx.x & (kTriLanes - 1);
+  const int gbase = (threadIdx.x & (kWave - 1)) & ~(kTriLanes - 1);   // the group's first lane in the wavefront
+  const bool act = c < nc;
+  const int32_t rb = act ? crp[c] : 0, d = act ? crp[c + 1] - rb : 0;
   const int32_t np = d * (d - 1) / 2;
-  const V3 A = ld3(Xc, c);
+  // trip count uniform over the wavefront: the largest pair count of its groups
+  int32_t npw = np;
+  for (int o = kTriLanes; o < kWave; o <<= 1) npw = max(npw, __shfl_xor(npw, o, kWave));
+  const V3 A = act ? ld3(Xc, c) : V3{0.0, 0.0, 0.0};
   int32_t cnt = 0;
-  for (int32_t p0 = 0; p0 < np; p0 += kWave) {
-    const int32_t p = p0 + lane;
+  for (int32_t p0 = 0; p0 < npw; p0 += kTriLanes) {
+    const int32_t p = p0 + sub;
     bool ok = false;
     int32_t j = 0, k = 0;
     if (p < np) {
@@ -98,9 +103,9 @@ __global__ void __launch_bounds__(kBlock) k_tri_candidates(const double* __restr
       k = ccol[rb + e2];
       if (has_edge(crp, ccol, j, k)) ok = !degenerate(A, ld3(Xc, j), ld3(Xc, k));
     }
-    const unsigned long long m = __ballot(ok);
+    const unsigned long long m = (__ballot(ok) >> gbase) & ((1ull << kTriLanes) - 1ull);
     if (ok) {
-      const int32_t pos = cnt + __popcll(m & ((1ull << lane) - 1ull));
+      const int32_t pos = cnt + __popcll(m & ((1ull << sub) - 1ull));
       if (pos < kTriMax) {
         tlist[(c * kTriMax + pos) * 2] = j;
         tlist[(c * kTriMax + pos) * 2 + 1] = k;
@@ -108,7 +113,7 @@ __global__ void __launch_bounds__(kBlock) k_tri_candidates(const double* __restr
     }
     cnt += __popcll(m);
   }
-  if (lane == 0) tcnt[c] = cnt <= kTriMax ? cnt : -1;
+  if (act && sub == 0) tcnt[c] = cnt <= kTriMax ? cnt : -1;
 }
 
 // One thread per fine point p; c = label(p) is the coarse point closest to p.
@@ -603,7 +608,7 @@ void prolongation(Handle& h, Level& lv, Level& nx) {
   const int64_t nc = nx.n;
   int32_t* tlist = (int32_t*)talloc(s, (size_t)nc * kTriMax * 2 * 4);
   int32_t* tcnt = (int32_t*)talloc(s, (size_t)nc * 4);
-  k_tri_candidates<<<blocks_for(nc, kBlock / kWave), kBlock, 0, s>>>(nx.X, nx.erp, nx.ecol, nc, tlist, tcnt);
+  k_tri_candidates<<<blocks_for(nc, kBlock / kTriLanes), kBlock, 0, s>>>(nx.X, nx.erp, nx.ecol, nc, tlist, tcnt);
   k_project<<<blocks_for(n), kBlock, 0, s>>>(lv.X, lv.label, n, nx.X, nx.erp, nx.ecol, h.opt.weighting,
                                              h.opt.fallback_on_vertex, lv.pcol, lv.pval, lv.pcnt, lv.tri,
                                              lv.stats, tlist, tcnt);

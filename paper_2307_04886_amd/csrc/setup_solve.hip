@@ -697,6 +697,10 @@ __global__ void k_tail_ell_t(SellView T, int64_t nc, int32_t w, int64_t n, int32
 
 }  // namespace
 
+// Jones-Plassmann colouring takes tens of rounds on the Galerkin levels (about
+// the degree): the host checks the worklist every kColorBatch rounds.
+constexpr int kColorBatch = 16;
+
 void colouring(Handle& h, Level& lv, int level) {
   hipStream_t s = h.stream;
   int64_t n = lv.n;
@@ -719,7 +723,7 @@ void colouring(Handle& h, Level& lv, int level) {
     k_color_drain<<<1, kDrainItems, 0, s>>>(lv.arp, lv.acol, n, key, lv.color, nullptr, nullptr, L, h.flags);
   } else {
     for (;;) {
-      for (int t = 0; t < kRoundBatch; ++t, ++k)
+      for (int t = 0; t < kColorBatch; ++t, ++k)
         k_color_round<<<grid, kBlock, 0, s>>>(lv.arp, lv.acol, n, key, lv.color, wl + ((k + 1) % 2) * n,
                                               wl + (k % 2) * n, h.rounds, k, L);
       int64_t left = 0;
@@ -731,7 +735,7 @@ void colouring(Handle& h, Level& lv, int level) {
                                                h.rounds + (k - 1), L, h.flags);
         break;
       }
-      if (k + kRoundBatch > kMaxRounds) throw Error{GMG_DEVICE_ERROR, "colouring did not terminate"};
+      if (k + kColorBatch > kMaxRounds) throw Error{GMG_DEVICE_ERROR, "colouring did not terminate"};
     }
   }
   {
