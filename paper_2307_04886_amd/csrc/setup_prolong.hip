@@ -463,6 +463,7 @@ __global__ void __launch_bounds__(kWave) k_galerkin_fill(const int32_t* trp, con
                                                          const int32_t* pcnt, int64_t nc, const int32_t* crp,
                                                          int32_t* ccol, double* cval, int32_t* flags) {
   constexpr int kOut = HS * 3 / 4;     // distinct columns of a row (the symbolic pass checked the bound)
+  constexpr int kFastSub = 4;          // pairs per lane of the one-chunk form
   constexpr int kPer = (kOut + kWave - 1) / kWave;   // output columns per lane
   __shared__ int32_t keys[HS];
   __shared__ int32_t rank_of[HS];      // hash slot -> position of its column in the sorted row
@@ -480,19 +481,51 @@ __global__ void __launch_bounds__(kWave) k_galerkin_fill(const int32_t* trp, con
   for (int s = lane; s < HS; s += kWave) keys[s] = -1;
   if (lane == 0) nlist = 0;
   __syncthreads();
-  for (int32_t q0 = trp[I]; q0 < trp[I + 1]; q0 += kWave) {
-    const int tot = load_pairs(q0, trp[I + 1], tcol, tval, arp, pc);
-    for (int p0 = 0; p0 < tot; p0 += kWave) {
-      const int p = p0 + lane;
-      if (p < tot) {
-        int src;
-        int32_t e;
-        locate_pair(pc, p, src, e);
-        const int32_t j = acol[e];
-        for (int t = 0; t < pcnt[j]; ++t) hash_insert<HS>(keys, pcol[3 * j + t]);
-      }
+  // Rows with one chunk of P^T entries and at most kFastSub * 64 pairs keep
+  // the chunk and each lane's pairs (pair lane + 64 s) in registers for both
+  // passes, with every gather of a pass issued together; other rows reload
+  // them chunk by chunk.
+  const int32_t qb = trp[I], qe = trp[I + 1];
+  int tot = qe - qb <= kWave ? load_pairs(qb, qe, tcol, tval, arp, pc) : kFastSub * kWave + 1;
+  const bool fast = tot <= kFastSub * kWave;                        // uniform over the wavefront
+  int fsrc[kFastSub], fc[kFastSub];
+  int32_t fe[kFastSub], fj[kFastSub], fJ[kFastSub][3];
+  if (fast) {
+#pragma unroll
+    for (int u = 0; u < kFastSub; ++u) {
+      fsrc[u] = 0;
+      fe[u] = 0;
+      if (lane + u * kWave < tot) locate_pair(pc, lane + u * kWave, fsrc[u], fe[u]);
     }
+#pragma unroll
+    for (int u = 0; u < kFastSub; ++u) fj[u] = lane + u * kWave < tot ? acol[fe[u]] : 0;
+#pragma unroll
+    for (int u = 0; u < kFastSub; ++u) {
+      fc[u] = lane + u * kWave < tot ? pcnt[fj[u]] : 0;
+#pragma unroll
+      for (int t = 0; t < 3; ++t) fJ[u][t] = pcol[3 * fj[u] + t];
+    }
+#pragma unroll
+    for (int u = 0; u < kFastSub; ++u)
+#pragma unroll
+      for (int t = 0; t < 3; ++t)
+        if (t < fc[u]) hash_insert<HS>(keys, fJ[u][t]);
     __syncthreads();
+  } else {
+    for (int32_t q0 = qb; q0 < qe; q0 += kWave) {
+      const int tc = load_pairs(q0, qe, tcol, tval, arp, pc);
+      for (int p0 = 0; p0 < tc; p0 += kWave) {
+        const int p = p0 + lane;
+        if (p < tc) {
+          int src;
+          int32_t e;
+          locate_pair(pc, p, src, e);
+          const int32_t j = acol[e];
+          for (int t = 0; t < pcnt[j]; ++t) hash_insert<HS>(keys, pcol[3 * j + t]);
+        }
+      }
+      __syncthreads();
+    }
   }
   for (int s = lane; s < HS; s += kWave)
     if (keys[s] >= 0) sorted[atomicAdd(&nlist, 1)] = s;            // slots, in any order
@@ -526,54 +559,108 @@ __global__ void __launch_bounds__(kWave) k_galerkin_fill(const int32_t* trp, con
   // distinct), so the owner of column o adds the terms of the pairs flagged in
   // hits[o] in ascending pair order: every entry is summed in the order of the
   // definition.
-  for (int32_t q0 = trp[I]; q0 < trp[I + 1]; q0 += kWave) {
-    const int tot = load_pairs(q0, trp[I + 1], tcol, tval, arp, pc);
-    for (int p0 = 0; p0 < tot; p0 += kWave) {
-      const int p = p0 + lane;
-      const bool on = p < tot;
-      int32_t j = 0;
-      int c = 0;
-      double t1 = 0.0;
-      if (on) {
-        int src;
-        int32_t e;
-        locate_pair(pc, p, src, e);
-        j = acol[e];
-        c = pcnt[j];
-        t1 = pc.piI[src] * aval[e];
-      }
-      for (int o = lane; o < k; o += kWave) hits[o] = 0ull;
+  // The terms of one 64-pair chunk of the one-chunk form: pair lane has c
+  // terms (P row of j, t1 = P[i,I] A[i,j] times P[j,J_t]); the owner of each
+  // output column adds them in pair order.  (The general form below does the
+  // same with its loads inline.)
+  auto add_chunk = [&](int c, const int32_t* J, const double* v) {
+    for (int o = lane; o < k; o += kWave) hits[o] = 0ull;
 #pragma unroll
-      for (int t = 0; t < 3; ++t) {
-        int32_t r = -1;
-        double v = 0.0;
-        if (t < c) {
-          const int32_t J = pcol[3 * j + t];
-          uint32_t h = ((uint32_t)J * 2654435761u) & (HS - 1);
-          while (keys[h] != J) h = (h + 1) & (HS - 1);
-          r = rank_of[h];
-          v = t1 * pval[3 * j + t];
-        }
-        tR[3 * lane + t] = r;
-        tV[3 * lane + t] = v;
+    for (int t = 0; t < 3; ++t) {
+      int32_t r = -1;
+      if (t < c) {
+        uint32_t h = ((uint32_t)J[t] * 2654435761u) & (HS - 1);
+        while (keys[h] != J[t]) h = (h + 1) & (HS - 1);
+        r = rank_of[h];
       }
-      __syncthreads();
+      tR[3 * lane + t] = r;
+      tV[3 * lane + t] = t < c ? v[t] : 0.0;
+    }
+    __syncthreads();
 #pragma unroll
-      for (int t = 0; t < 3; ++t)
-        if (t < c) atomicOr(&hits[tR[3 * lane + t]], 1ull << lane);
-      __syncthreads();
-      for (int o = lane; o < k; o += kWave) {
-        unsigned long long m = hits[o];
-        double acc = accum[o];
-        while (m) {
-          const int q = __builtin_ctzll(m);
-          m &= m - 1;
-          const int t = tR[3 * q] == o ? 0 : (tR[3 * q + 1] == o ? 1 : 2);
-          acc = acc + tV[3 * q + t];
-        }
-        accum[o] = acc;
+    for (int t = 0; t < 3; ++t)
+      if (t < c) atomicOr(&hits[tR[3 * lane + t]], 1ull << lane);
+    __syncthreads();
+    for (int o = lane; o < k; o += kWave) {
+      unsigned long long m = hits[o];
+      double acc = accum[o];
+      while (m) {
+        const int q = __builtin_ctzll(m);
+        m &= m - 1;
+        const int t = tR[3 * q] == o ? 0 : (tR[3 * q + 1] == o ? 1 : 2);
+        acc = acc + tV[3 * q + t];
       }
-      __syncthreads();
+      accum[o] = acc;
+    }
+    __syncthreads();
+  };
+  if (fast) {
+    double fa[kFastSub], fp[kFastSub][3];
+#pragma unroll
+    for (int u = 0; u < kFastSub; ++u) {
+      fa[u] = aval[fe[u]];
+#pragma unroll
+      for (int t = 0; t < 3; ++t) fp[u][t] = pval[3 * fj[u] + t];
+    }
+#pragma unroll
+    for (int u = 0; u < kFastSub; ++u) {
+      if (u * kWave >= tot) break;                                   // uniform
+      const double t1 = pc.piI[fsrc[u]] * fa[u];
+      double v[3];
+#pragma unroll
+      for (int t = 0; t < 3; ++t) v[t] = t1 * fp[u][t];
+      add_chunk(fc[u], fJ[u], v);
+    }
+  } else {
+    for (int32_t q0 = qb; q0 < qe; q0 += kWave) {
+      const int tc = load_pairs(q0, qe, tcol, tval, arp, pc);
+      for (int p0 = 0; p0 < tc; p0 += kWave) {
+        const int p = p0 + lane;
+        const bool on = p < tc;
+        int32_t j = 0;
+        int c = 0;
+        double t1 = 0.0;
+        if (on) {
+          int src;
+          int32_t e;
+          locate_pair(pc, p, src, e);
+          j = acol[e];
+          c = pcnt[j];
+          t1 = pc.piI[src] * aval[e];
+        }
+        for (int o = lane; o < k; o += kWave) hits[o] = 0ull;
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+          int32_t r = -1;
+          double v = 0.0;
+          if (t < c) {
+            const int32_t J = pcol[3 * j + t];
+            uint32_t h = ((uint32_t)J * 2654435761u) & (HS - 1);
+            while (keys[h] != J) h = (h + 1) & (HS - 1);
+            r = rank_of[h];
+            v = t1 * pval[3 * j + t];
+          }
+          tR[3 * lane + t] = r;
+          tV[3 * lane + t] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < 3; ++t)
+          if (t < c) atomicOr(&hits[tR[3 * lane + t]], 1ull << lane);
+        __syncthreads();
+        for (int o = lane; o < k; o += kWave) {
+          unsigned long long m = hits[o];
+          double acc = accum[o];
+          while (m) {
+            const int q = __builtin_ctzll(m);
+            m &= m - 1;
+            const int t = tR[3 * q] == o ? 0 : (tR[3 * q + 1] == o ? 1 : 2);
+            acc = acc + tV[3 * q + t];
+          }
+          accum[o] = acc;
+        }
+        __syncthreads();
+      }
     }
   }
   const int32_t out = crp[I];
