@@ -22,7 +22,10 @@ __global__ void k_validate_points(const double* X, int64_t n3, int32_t* flags) {
   if (i < n3 && !isfinite(X[i])) atomicOr(flags, F_INVALID);
 }
 
-__global__ void k_edge_degree(const int32_t* edges, int64_t m, int64_t n, int32_t* deg, int32_t* flags) {
+// Degrees of the edge list's end points; the count each end point had before
+// this edge is the edge's slot in that end point's row (slot[2e], slot[2e+1]).
+__global__ void k_edge_degree(const int32_t* edges, int64_t m, int64_t n, int32_t* deg, int32_t* slot,
+                              int32_t* flags) {
   int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= m) return;
   int32_t u = edges[2 * e], v = edges[2 * e + 1];
@@ -31,18 +34,21 @@ __global__ void k_edge_degree(const int32_t* edges, int64_t m, int64_t n, int32_
     return;
   }
   if (u == v) return;
-  atomicAdd(&deg[u], 1);
-  atomicAdd(&deg[v], 1);
+  slot[2 * e] = atomicAdd(&deg[u], 1);
+  slot[2 * e + 1] = atomicAdd(&deg[v], 1);
 }
 
-__global__ void k_edge_scatter(const int32_t* edges, int64_t m, int64_t n, const int32_t* ptr,
-                               int32_t* cur, int32_t* out) {
+// Row entries at the slots the degree count handed out (rows are sorted
+// afterwards, so the order of the slots does not matter).
+__global__ void k_edge_scatter(const int32_t* __restrict__ edges, int64_t m, int64_t n,
+                               const int32_t* __restrict__ ptr, const int32_t* __restrict__ slot,
+                               int32_t* __restrict__ out) {
   int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= m) return;
   int32_t u = edges[2 * e], v = edges[2 * e + 1];
   if (u < 0 || v < 0 || u >= n || v >= n || u == v) return;
-  out[ptr[u] + atomicAdd(&cur[u], 1)] = v;
-  out[ptr[v] + atomicAdd(&cur[v], 1)] = u;
+  out[ptr[u] + slot[2 * e]] = v;
+  out[ptr[v] + slot[2 * e + 1]] = u;
 }
 
 // Row i of the system matrix: valid offsets, strictly ascending in-range
@@ -666,13 +672,12 @@ void edges_to_csr(Handle& h, Level& lv, const int32_t* edges, int64_t m) {
   int64_t n = lv.n;
   int32_t* deg = (int32_t*)talloc(s, (size_t)(n + 1) * 4);
   int32_t* tptr = (int32_t*)talloc(s, (size_t)(n + 1) * 4);
-  int32_t* cur = (int32_t*)talloc(s, (size_t)(n + 1) * 4);
+  int32_t* slot = (int32_t*)talloc(s, (size_t)(2 * m + 1) * 4);
   int32_t* tmp = (int32_t*)talloc(s, (size_t)(2 * m + 1) * 4);
   check_hip(hipMemsetAsync(deg, 0, (size_t)(n + 1) * 4, s), "memset");
-  check_hip(hipMemsetAsync(cur, 0, (size_t)(n + 1) * 4, s), "memset");
-  if (m > 0) k_edge_degree<<<blocks_for(m), kBlock, 0, s>>>(edges, m, n, deg, h.flags);
+  if (m > 0) k_edge_degree<<<blocks_for(m), kBlock, 0, s>>>(edges, m, n, deg, slot, h.flags);
   scan_i32(deg, tptr, n, s);
-  if (m > 0) k_edge_scatter<<<blocks_for(m), kBlock, 0, s>>>(edges, m, n, tptr, cur, tmp);
+  if (m > 0) k_edge_scatter<<<blocks_for(m), kBlock, 0, s>>>(edges, m, n, tptr, slot, tmp);
   segment_sort_unique(tmp, tptr, deg, n, s);
   lv.erp = (int32_t*)dalloc(h, (size_t)(n + 1) * 4);
   scan_i32(deg, lv.erp, n, s);
@@ -687,7 +692,7 @@ void edges_to_csr(Handle& h, Level& lv, const int32_t* edges, int64_t m) {
   compact_segments(tmp, tptr, lv.erp, lv.ecol, n, s);
   tfree(s, deg);
   tfree(s, tptr);
-  tfree(s, cur);
+  tfree(s, slot);
   tfree(s, tmp);
 }
 

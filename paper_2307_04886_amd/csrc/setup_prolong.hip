@@ -288,19 +288,27 @@ __global__ void __launch_bounds__(kBlock) k_project(const double* X, const int32
 // ------------------------------------------------------------------ P^T
 __global__ void k_store_total(const int32_t* total, unsigned long long* out) { *out = (unsigned long long)*total; }
 
-__global__ void k_count_cols(const int32_t* pcol, const int32_t* pcnt, int64_t n, int32_t* cnt) {
+// Entries per column of P; the count a column had before entry (i, t) is that
+// entry's slot in row I of P^T (slot[3 i + t]).
+__global__ void k_count_cols(const int32_t* pcol, const int32_t* pcnt, int64_t n, int32_t* cnt, int32_t* slot) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  for (int t = 0; t < pcnt[i]; ++t) atomicAdd(&cnt[pcol[3 * i + t]], 1);
+  for (int t = 0; t < pcnt[i]; ++t) slot[3 * i + t] = atomicAdd(&cnt[pcol[3 * i + t]], 1);
 }
 
-__global__ void k_scatter_cols(const int32_t* pcol, const double* pval, const int32_t* pcnt, int64_t n,
-                               const int32_t* ptr, int32_t* cur, int32_t* tcol, double* tval) {
+// P^T entries at the slots the count handed out (each row is sorted by fine
+// index afterwards).
+__global__ void k_scatter_cols(const int32_t* __restrict__ pcol, const double* __restrict__ pval,
+                               const int32_t* __restrict__ pcnt, int64_t n, const int32_t* __restrict__ ptr,
+                               const int32_t* __restrict__ slot, int32_t* __restrict__ tcol,
+                               double* __restrict__ tval) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  for (int t = 0; t < pcnt[i]; ++t) {
-    int32_t I = pcol[3 * i + t];
-    int32_t pos = ptr[I] + atomicAdd(&cur[I], 1);
+  const int c = pcnt[i];
+#pragma unroll
+  for (int t = 0; t < 3; ++t) {
+    if (t >= c) break;
+    const int32_t pos = ptr[pcol[3 * i + t]] + slot[3 * i + t];
     tcol[pos] = (int32_t)i;
     tval[pos] = pval[3 * i + t];
   }
@@ -707,19 +715,18 @@ void transpose_p(Handle& h, Level& lv, int64_t nc, int32_t** t_rp, int32_t** t_c
   hipStream_t s = h.stream;
   int64_t n = lv.n;
   int32_t* cnt = (int32_t*)talloc(s, (size_t)(nc + 1) * 4);
-  int32_t* cur = (int32_t*)talloc(s, (size_t)(nc + 1) * 4);
+  int32_t* slot = (int32_t*)talloc(s, (size_t)3 * n * 4);
   int32_t* rp = (int32_t*)dalloc(h, (size_t)(nc + 1) * 4);   // kept by the handle
   check_hip(hipMemsetAsync(cnt, 0, (size_t)(nc + 1) * 4, s), "memset");
-  check_hip(hipMemsetAsync(cur, 0, (size_t)(nc + 1) * 4, s), "memset");
-  k_count_cols<<<blocks_for(n), kBlock, 0, s>>>(lv.pcol, lv.pcnt, n, cnt);
+  k_count_cols<<<blocks_for(n), kBlock, 0, s>>>(lv.pcol, lv.pcnt, n, cnt, slot);
   scan_i32(cnt, rp, nc, s);
   k_store_total<<<1, 1, 0, s>>>(rp + nc, lv.stats + 1);      // nnz(P), read at the end of the build
   int32_t* col = (int32_t*)dalloc(h, (size_t)(3 * n + 1) * 4);   // nnz(P) <= 3n
   double* val = (double*)dalloc(h, (size_t)(3 * n + 1) * 8);
-  k_scatter_cols<<<blocks_for(n), kBlock, 0, s>>>(lv.pcol, lv.pval, lv.pcnt, n, rp, cur, col, val);
+  k_scatter_cols<<<blocks_for(n), kBlock, 0, s>>>(lv.pcol, lv.pval, lv.pcnt, n, rp, slot, col, val);
   k_sort_pairs<<<blocks_for(nc, kBlock / kWave), kBlock, 0, s>>>(rp, col, val, nc);
   tfree(s, cnt);
-  tfree(s, cur);
+  tfree(s, slot);
   *t_rp = rp;
   *t_col = col;
   *t_val = val;
