@@ -505,17 +505,17 @@ __global__ void __launch_bounds__(kBlock) k_voronoi_round(const int32_t* rp, con
 }
 
 // ------------------------------------------------------------------ cells, shift (Sec. 4.4)
-__global__ void k_count_labels(const int32_t* lab, int64_t n, int32_t* cnt) {
+// Cell sizes; the count a cell had before point v is v's slot in the cell.
+__global__ void k_count_labels(const int32_t* lab, int64_t n, int32_t* cnt, int32_t* slot) {
   int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v < n) atomicAdd(&cnt[lab[v]], 1);
+  if (v < n) slot[v] = atomicAdd(&cnt[lab[v]], 1);
 }
 
-__global__ void k_scatter_labels(const int32_t* lab, int64_t n, const int32_t* ptr, int32_t* cur, int32_t* mem) {
+// Cell members at their slots (sorted afterwards).
+__global__ void k_scatter_labels(const int32_t* __restrict__ lab, int64_t n, const int32_t* __restrict__ ptr,
+                                 const int32_t* __restrict__ slot, int32_t* __restrict__ mem) {
   int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v < n) {
-    int32_t I = lab[v];
-    mem[ptr[I] + atomicAdd(&cur[I], 1)] = (int32_t)v;
-  }
+  if (v < n) mem[ptr[lab[v]] + slot[v]] = (int32_t)v;
 }
 
 // Coarse point I = mean of its cell's points, summed in ascending fine index
@@ -810,20 +810,19 @@ void cells_and_shift(Handle& h, Level& lv, Level& nx, bool shift, int32_t** cell
   hipStream_t s = h.stream;
   int64_t n = lv.n, nc = lv.nc;
   int32_t* cnt = (int32_t*)talloc(s, (size_t)(nc + 1) * 4);
-  int32_t* cur = (int32_t*)talloc(s, (size_t)(nc + 1) * 4);
+  int32_t* slot = (int32_t*)talloc(s, (size_t)n * 4);
   int32_t* ptr = (int32_t*)talloc(s, (size_t)(nc + 1) * 4);
   int32_t* mem = (int32_t*)talloc(s, (size_t)n * 4);
   check_hip(hipMemsetAsync(cnt, 0, (size_t)(nc + 1) * 4, s), "memset");
-  check_hip(hipMemsetAsync(cur, 0, (size_t)(nc + 1) * 4, s), "memset");
-  k_count_labels<<<blocks_for(n), kBlock, 0, s>>>(lv.label, n, cnt);
+  k_count_labels<<<blocks_for(n), kBlock, 0, s>>>(lv.label, n, cnt, slot);
   scan_i32(cnt, ptr, nc, s);
-  k_scatter_labels<<<blocks_for(n), kBlock, 0, s>>>(lv.label, n, ptr, cur, mem);
+  k_scatter_labels<<<blocks_for(n), kBlock, 0, s>>>(lv.label, n, ptr, slot, mem);
   segment_sort_unique(mem, ptr, cnt, nc, s);     // members ascending (they are distinct)
   nx.n = nc;
   nx.X = (double*)dalloc(h, (size_t)nc * 3 * 8);
   k_cell_mean<<<blocks_for(nc), kBlock, 0, s>>>(lv.X, ptr, mem, lv.samples, nc, shift ? 1 : 0, nx.X);
   tfree(s, cnt);
-  tfree(s, cur);
+  tfree(s, slot);
   *cell_ptr = ptr;
   *cell_mem = mem;
 }

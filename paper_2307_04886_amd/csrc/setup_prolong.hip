@@ -438,20 +438,50 @@ __global__ void __launch_bounds__(kWave) k_galerkin_count(const int32_t* trp, co
   for (int s = lane; s < HS; s += kWave) keys[s] = -1;
   __syncthreads();
   bool ok = true;
-  for (int32_t q0 = trp[I]; q0 < trp[I + 1]; q0 += kWave) {
-    const int tot = load_pairs(q0, trp[I + 1], tcol, tval, arp, pc);
-    for (int p0 = 0; p0 < tot; p0 += kWave) {
-      const int p = p0 + lane;
-      if (p < tot) {
-        int src;
-        int32_t e;
-        locate_pair(pc, p, src, e);
-        const int32_t j = acol[e];
-        const int c = pcnt[j];
-        for (int t = 0; t < c; ++t) ok &= hash_insert<HS>(keys, pcol[3 * j + t]);
-      }
+  // one chunk of P^T entries and at most kFastSub * 64 pairs: every lane's
+  // pairs gathered together (as in the numeric pass); otherwise chunk by chunk
+  constexpr int kFastSub = 4;
+  const int32_t qb = trp[I], qe = trp[I + 1];
+  const int tot1 = qe - qb <= kWave ? load_pairs(qb, qe, tcol, tval, arp, pc) : kFastSub * kWave + 1;
+  if (tot1 <= kFastSub * kWave) {                                    // uniform over the wavefront
+    int32_t fe[kFastSub], fj[kFastSub], fJ[kFastSub][3];
+    int fc[kFastSub];
+#pragma unroll
+    for (int u = 0; u < kFastSub; ++u) {
+      int src = 0;
+      fe[u] = 0;
+      if (lane + u * kWave < tot1) locate_pair(pc, lane + u * kWave, src, fe[u]);
     }
+#pragma unroll
+    for (int u = 0; u < kFastSub; ++u) fj[u] = lane + u * kWave < tot1 ? acol[fe[u]] : 0;
+#pragma unroll
+    for (int u = 0; u < kFastSub; ++u) {
+      fc[u] = lane + u * kWave < tot1 ? pcnt[fj[u]] : 0;
+#pragma unroll
+      for (int t = 0; t < 3; ++t) fJ[u][t] = pcol[3 * fj[u] + t];
+    }
+#pragma unroll
+    for (int u = 0; u < kFastSub; ++u)
+#pragma unroll
+      for (int t = 0; t < 3; ++t)
+        if (t < fc[u]) ok &= hash_insert<HS>(keys, fJ[u][t]);
     __syncthreads();
+  } else {
+    for (int32_t q0 = qb; q0 < qe; q0 += kWave) {
+      const int tot = load_pairs(q0, qe, tcol, tval, arp, pc);
+      for (int p0 = 0; p0 < tot; p0 += kWave) {
+        const int p = p0 + lane;
+        if (p < tot) {
+          int src;
+          int32_t e;
+          locate_pair(pc, p, src, e);
+          const int32_t j = acol[e];
+          const int c = pcnt[j];
+          for (int t = 0; t < c; ++t) ok &= hash_insert<HS>(keys, pcol[3 * j + t]);
+        }
+      }
+      __syncthreads();
+    }
   }
   int c = 0;
   for (int s = lane; s < HS; s += kWave) c += keys[s] >= 0;
