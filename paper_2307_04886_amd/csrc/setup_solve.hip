@@ -255,19 +255,26 @@ __global__ void k_color_ptr(const int32_t* off, int nb, int nc, int32_t* cptr) {
 // Row r of the result is source row perm[r] (or r) of a CSR matrix; columns
 // are renumbered through cmap (or kept); entries keep their CSR order, so
 // every row sum adds its terms in the same order as the source row.
-__global__ void k_row_len(const int32_t* perm, const int32_t* rp, int64_t n, int32_t* len) {
-  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= n) return;
-  int32_t src = perm ? perm[r] : (int32_t)r;
-  len[r] = rp[src + 1] - rp[src];
-}
-
-__global__ void k_slice_width(const int32_t* len, int64_t n, int64_t ns, int32_t* wsz) {
-  int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= ns) return;
-  int32_t w = 0;
-  for (int64_t r = s * kSlice; r < (s + 1) * kSlice && r < n; ++r) w = len[r] > w ? len[r] : w;
-  wsz[s] = w * kSlice;
+// Row lengths, slice sizes and the longest row in one pass: one thread per
+// row over whole slices (a wavefront's 64 rows are one slice, so the slice
+// width is a wavefront maximum); *mx = max(*mx, longest row).
+__global__ void __launch_bounds__(kBlock) k_row_len_width(const int32_t* __restrict__ perm,
+                                                          const int32_t* __restrict__ rp, int64_t n, int64_t ns,
+                                                          int32_t* __restrict__ len, int32_t* __restrict__ wsz,
+                                                          int32_t* mx) {
+  const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  int32_t l = 0;
+  if (r < n) {
+    const int32_t src = perm ? perm[r] : (int32_t)r;
+    l = rp[src + 1] - rp[src];
+    len[r] = l;
+  }
+  int32_t w = l;
+  for (int o = kWave / 2; o > 0; o >>= 1) w = max(w, __shfl_xor(w, o, kWave));
+  const int64_t sl = r / kSlice;
+  if ((threadIdx.x & (kWave - 1)) == 0 && sl < ns) wsz[sl] = w * kSlice;
+  const int32_t b = block_reduce(l, [](int32_t a, int32_t c) { return a > c ? a : c; });
+  if (threadIdx.x == 0 && b) atomicMax(mx, b);
 }
 
 constexpr int kFillChunk = 8;
@@ -790,9 +797,7 @@ SellView make_sell(Handle& h, const int32_t* perm, const int32_t* cmap, const in
   int32_t* wsz = (int32_t*)talloc(s, (size_t)(ns + 1) * 4);
   int32_t* mx = (int32_t*)talloc(s, 4);
   check_hip(hipMemsetAsync(mx, 0, 4, s), "memset");
-  k_row_len<<<blocks_for(n), kBlock, 0, s>>>(perm, rp, n, len);
-  max_i32(len, n, 0, mx, s);
-  k_slice_width<<<blocks_for(ns), kBlock, 0, s>>>(len, n, ns, wsz);
+  k_row_len_width<<<blocks_for(ns * kSlice), kBlock, 0, s>>>(perm, rp, n, ns, len, wsz, mx);
   scan_i32(wsz, ptr, ns, s);
   int64_t tot = 0, ml = 0;
   ScalarRead rd[2] = {{ptr + ns, 4, &tot}, {mx, 4, &ml}};
