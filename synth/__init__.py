@@ -11,12 +11,12 @@ from .meshes import icosphere, torus_grid, flat_grid, bumpy_sphere_points, edges
 from .operators import cotan_laplacian, lumped_mass, gaussian_knn_laplacian, Problem
 from .configs import (config_icosphere, config_torus, config_bumpy_sphere, config_adjoint, config_poisson, config_batched,
                       small_icosphere,
-                      small_torus, small_flat_grid, small_pointcloud, CONFIGS)
+                      small_torus, small_flat_grid, small_pointcloud, small_hubs, CONFIGS)
 
 __all__ = [
     "mix64", "uniform", "normal", "icosphere", "torus_grid", "flat_grid", "bumpy_sphere_points",
     "edges_from_faces", "knn_edges", "cotan_laplacian", "lumped_mass", "gaussian_knn_laplacian",
     "Problem", "config_icosphere", "config_torus", "config_bumpy_sphere", "config_adjoint", "config_poisson", "config_batched",
     "small_icosphere",
-    "small_torus", "small_flat_grid", "small_pointcloud", "CONFIGS",
+    "small_torus", "small_flat_grid", "small_pointcloud", "small_hubs", "CONFIGS",
 ]

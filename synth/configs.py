@@ -10,7 +10,7 @@ import numpy as np
 from .meshes import (icosphere, torus_grid, flat_grid, bumpy_sphere_points, edges_from_faces,
                      knn_edges, mean_edge_length, radial_noise, gaussian_jitter)
 from .operators import cotan_laplacian, lumped_mass, gaussian_knn_laplacian, assemble, Problem
-from .rng import uniform
+from .rng import uniform, normal
 
 
 def _mesh_problem(name, pts, faces, alpha, seed, eta=None):
@@ -114,6 +114,29 @@ def small_flat_grid(nx=24, ny=20, seed=0, jitter=0.2, alpha=1e-3):
 
 def small_pointcloud(n=4000, k=8, seed=0):
     return config_bumpy_sphere(n, k, seed)
+
+
+def small_hubs(nu=96, nv=80, hubs=3, spokes=150, seed=0):
+    """The small torus with a few hub points, each joined to `spokes` points drawn
+    at random: long rows in every operator of the hierarchy.  A = L + I with L
+    the unit-weight Laplacian of the edge graph (symmetric, diagonally
+    dominant); rhs standard normal."""
+    import scipy.sparse as sp
+    base = config_torus(nu, nv, seed)
+    n = base.n
+    draws = uniform(seed, "hubs", hubs * (spokes + 1))
+    idx = np.minimum((draws * n).astype(np.int64), n - 1).reshape(hubs, spokes + 1)
+    extra = [(min(r[0], o), max(r[0], o)) for r in idx for o in r[1:] if o != r[0]]
+    e = np.sort(base.edges.astype(np.int64), axis=1)
+    e = np.unique(np.concatenate([e, np.array(extra, dtype=np.int64)]), axis=0)
+    w = sp.coo_matrix((np.ones(len(e)), (e[:, 0], e[:, 1])), shape=(n, n)).tocsr()
+    w = (w + w.T).tocsr()
+    w.data[:] = 1.0
+    deg = np.asarray(w.sum(axis=1)).ravel()
+    a = (sp.diags(deg + 1.0) - w).tocsr()
+    a.sort_indices()
+    return Problem(f"hubs{nu}x{nv}", base.points, e.astype(np.int32), a.indptr.astype(np.int32),
+                   a.indices.astype(np.int32), a.data.astype(np.float64), normal(seed, "rhs", n))
 
 
 CONFIGS = {

@@ -13,7 +13,7 @@ _M2 = np.uint64(0x94D049BB133111EB)
 
 # Named streams, so that geometry, noise and right-hand sides never share draws.
 STREAMS = {"geom": 1, "jitter": 2, "rhs": 3, "dirs": 4, "noise": 5, "target": 6, "sizes": 7,
-           "entries": 8}
+           "entries": 8, "hubs": 9}
 
 
 def mix64(z):

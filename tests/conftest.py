@@ -29,6 +29,7 @@ def problem(name):
             "flat": lambda: synth.small_flat_grid(40, 36),
             "pc4k": lambda: synth.small_pointcloud(4000),
             "pc20k": lambda: synth.small_pointcloud(20000),
+            "hubs": lambda: synth.small_hubs(),
             "torus1024": lambda: synth.config_torus(),
             "bumpy2m": lambda: synth.config_bumpy_sphere(),
         }

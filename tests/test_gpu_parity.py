@@ -246,6 +246,18 @@ def test_determinism():
     assert np.array_equal(x1, x2)
 
 
+def test_hub_vertices():
+    """Hub points joined to 150 others each: rows longer than every fast path
+    holds (SELL fill by slice, conflict and colouring lists, cell neighbours by
+    lanes, candidate-triangle lists, the 64-slot Galerkin table, the tail's
+    32-entry rounds), so the general forms run and must agree with the oracle."""
+    _say("[gpu] hub vertices")
+    prob = problem("hubs")
+    orc, gpu = both(prob, min_coarse_points=100)
+    compare_hierarchies(orc, gpu, "hubs")
+    compare_solves(orc, gpu, prob)
+
+
 def test_edge_cases():
     _say("[gpu] edge cases")
     g = gmg()
