@@ -30,6 +30,7 @@ def problem(name):
             "pc4k": lambda: synth.small_pointcloud(4000),
             "pc20k": lambda: synth.small_pointcloud(20000),
             "hubs": lambda: synth.small_hubs(),
+            "hubs_big": lambda: synth.small_hubs(256, 200),
             "torus1024": lambda: synth.config_torus(),
             "bumpy2m": lambda: synth.config_bumpy_sphere(),
         }

@@ -31,7 +31,7 @@ def rhs_block(prob, nrhs, seed=3):
 
 @pytest.mark.parametrize("precision", ["f64", "f32"])
 @pytest.mark.parametrize("name,minc,nrhs", [("ico4", 100, 8), ("torus96", 200, 3), ("pc20k", 500, 11),
-                                            ("ico3", 100, 1)])
+                                            ("ico3", 100, 1), ("hubs_big", 1000, 8)])
 def test_batched_preconditioner_parity(name, minc, nrhs, precision):
     _say(f"[gpu] batched preconditioner {precision} {name} nrhs={nrhs}")
     prob = problem(name)
@@ -49,7 +49,8 @@ def test_batched_preconditioner_parity(name, minc, nrhs, precision):
 
 
 @pytest.mark.parametrize("precision", ["f64", "f32"])
-@pytest.mark.parametrize("name,minc,nrhs", [("ico4", 100, 8), ("torus96", 200, 5), ("pc20k", 500, 10)])
+@pytest.mark.parametrize("name,minc,nrhs", [("ico4", 100, 8), ("torus96", 200, 5), ("pc20k", 500, 10),
+                                            ("hubs_big", 1000, 8)])
 def test_batched_pcg_parity(name, minc, nrhs, precision):
     _say(f"[gpu] batched CG {precision} {name} nrhs={nrhs}")
     prob = problem(name)

@@ -246,15 +246,18 @@ def test_determinism():
     assert np.array_equal(x1, x2)
 
 
-def test_hub_vertices():
+@pytest.mark.parametrize("name,minc", [("hubs", 100), ("hubs_big", 1000)])
+def test_hub_vertices(name, minc):
     """Hub points joined to 150 others each: rows longer than every fast path
     holds (SELL fill by slice, conflict and colouring lists, cell neighbours by
     lanes, candidate-triangle lists, the 64-slot Galerkin table, the tail's
-    32-entry rounds), so the general forms run and must agree with the oracle."""
-    _say("[gpu] hub vertices")
-    prob = problem("hubs")
-    orc, gpu = both(prob, min_coarse_points=100)
-    compare_hierarchies(orc, gpu, "hubs")
+    32-entry rounds), so the general forms run and must agree with the oracle.
+    On the larger mesh the 5,920-row level with rows of up to 472 entries is
+    swept by separate launches with 64 lanes per row."""
+    _say(f"[gpu] hub vertices {name}")
+    prob = problem(name)
+    orc, gpu = both(prob, min_coarse_points=minc)
+    compare_hierarchies(orc, gpu, name)
     compare_solves(orc, gpu, prob)
 
 
