@@ -266,7 +266,10 @@ enum gmg_export_what {
   GMG_EXPORT_A_COL = 13,       /* int32[nnz] */
   GMG_EXPORT_A_VAL = 14,       /* double[nnz] */
   GMG_EXPORT_COLORS = 15,      /* int32[n] Gauss-Seidel colour of each row */
-  GMG_EXPORT_CHOL = 16         /* double[n*n] row-major lower Cholesky factor (coarsest level only) */
+  GMG_EXPORT_CHOL = 16,        /* double[n*n] row-major lower Cholesky factor (coarsest level only) */
+  GMG_EXPORT_COARSE_INVERSE = 17 /* double[n*n] inverse of the coarsest A by columns: element k*n + i is
+                                    (A^-1 e_k)_i (coarsest level only; the direct solve of Alg. 2 is the
+                                    product with it, summed over k ascending) */
 };
 
 /*

@@ -17,7 +17,7 @@ _SRC = os.path.join(_HERE, "oracle.cpp")
 
 # export codes (mirrors the enumeration in oracle.cpp)
 POSITIONS, EDGE_ROWPTR, EDGE_COL, EDGE_W, SCALARS, SAMPLES, LABELS, DIST = range(8)
-P_COL, P_VAL, P_CNT, TRI, A_ROWPTR, A_COL, A_VAL, COLORS, CHOL = range(8, 17)
+P_COL, P_VAL, P_CNT, TRI, A_ROWPTR, A_COL, A_VAL, COLORS, CHOL, CINV = range(8, 18)
 
 STATUS = {0: "OK", 1: "NOT_CONVERGED", -1: "INVALID_ARGUMENT", -4: "NOT_SPD", -5: "DEGENERATE"}
 
@@ -148,6 +148,7 @@ class Hierarchy:
             A_ROWPTR: ((n + 1,), np.int32), A_COL: ((s["nnzA"],), np.int32),
             A_VAL: ((s["nnzA"],), np.float64),
             COLORS: ((n if s["colors"] else 0,), np.int32), CHOL: ((n, n), np.float64),
+            CINV: ((n, n), np.float64),
         }[what]
         out = np.zeros(shape, dtype=dt)
         st = lib().orc_export(self._h, l, what, _ptr(out), out.nbytes)
@@ -168,6 +169,10 @@ class Hierarchy:
 
     def chol(self):
         return self.export(self.num_levels - 1, CHOL)
+
+    def coarse_inverse(self):
+        """A_coarsest^-1 stored by columns: row k of the result is A^-1 e_k."""
+        return self.export(self.num_levels - 1, CINV)
 
     def solve(self, b, x0=None, tol=1e-8, max_iters=100, gs_mode=0):
         """Returns (x, iterations, relative-residual history, status)."""

@@ -78,6 +78,7 @@ enum What {
   W_A_VAL = 14,      // double[nnz]
   W_COLORS = 15,     // int32[n]
   W_CHOL = 16,       // double[n*n] row-major lower Cholesky factor (coarsest level only)
+  W_CINV = 17,       // double[n*n] coarsest inverse by columns: [k*n + i] = (A^-1 e_k)_i
 };
 
 constexpr double kDegenerateTau = 1e-12;   // sin^2 of the smallest accepted triangle angle
@@ -122,6 +123,7 @@ struct Hier {
   Options opt;
   std::vector<Level> L;                         // L[0] finest ... L.back() coarsest
   std::vector<double> chol;                     // dense lower Cholesky factor of the coarsest A
+  std::vector<double> cinv;                     // its inverse by columns: cinv[k n + i] = (A^-1 e_k)_i
 };
 
 V3 pos(const Level& lv, int64_t i) { return {lv.X[3 * i], lv.X[3 * i + 1], lv.X[3 * i + 2]}; }
@@ -622,6 +624,9 @@ int cholesky(const Level& lv, std::vector<double>& Lf) {
   return OK;
 }
 
+// A x = b by forward (L y = b) and back (L^T x = y) substitution.  Forward,
+// row i subtracts L_ik y_k for k ascending; back, row i subtracts L_ki x_k for
+// k descending from n-1 (the order in which the x_k become known).
 void cholesky_solve(const std::vector<double>& Lf, int64_t n, const double* b, double* x) {
   std::vector<double> y(n);
   for (int64_t i = 0; i < n; ++i) {
@@ -631,8 +636,29 @@ void cholesky_solve(const std::vector<double>& Lf, int64_t n, const double* b, d
   }
   for (int64_t i = n - 1; i >= 0; --i) {
     double s = y[i];
-    for (int64_t k = i + 1; k < n; ++k) s = s - Lf[k * n + i] * x[k];
+    for (int64_t k = n - 1; k > i; --k) s = s - Lf[k * n + i] * x[k];
     x[i] = s / Lf[i * n + i];
+  }
+}
+
+// The direct solve of the coarsest level (Alg. 2) as a product with A^-1:
+// column k of A^-1 is A^-1 e_k, by the substitutions above (inv[k n + i]).
+void coarse_inverse(const std::vector<double>& Lf, int64_t n, std::vector<double>& inv) {
+  inv.assign(n * n, 0.0);
+  std::vector<double> e(n, 0.0);
+  for (int64_t k = 0; k < n; ++k) {
+    e[k] = 1.0;
+    cholesky_solve(Lf, n, e.data(), &inv[k * n]);
+    e[k] = 0.0;
+  }
+}
+
+// x = A^-1 b: x_i = sum over k ascending of (A^-1 e_k)_i b_k.
+void coarse_solve(const std::vector<double>& inv, int64_t n, const double* b, double* x) {
+  for (int64_t i = 0; i < n; ++i) {
+    double s = 0.0;
+    for (int64_t k = 0; k < n; ++k) s = s + inv[k * n + i] * b[k];
+    x[i] = s;
   }
 }
 
@@ -676,7 +702,7 @@ double norm2(const double* v, int64_t n) {
 void vcycle(const Hier& h, size_t l, const double* b, double* x, int mode) {
   const Level& lv = h.L[l];
   if (l + 1 == h.L.size()) {
-    cholesky_solve(h.chol, lv.n, b, x);
+    coarse_solve(h.cinv, lv.n, b, x);
     return;
   }
   for (int s = 0; s < h.opt.nu_pre; ++s) gs_sweep(lv, b, x, mode);
@@ -734,7 +760,7 @@ void vcycle_sym(const Hier& h, size_t l, const T* b, T* x) {
   if (l + 1 == h.L.size()) {
     std::vector<double> bd(lv.n), xd(lv.n);
     for (int64_t i = 0; i < lv.n; ++i) bd[i] = (double)b[i];
-    cholesky_solve(h.chol, lv.n, bd.data(), xd.data());
+    coarse_solve(h.cinv, lv.n, bd.data(), xd.data());
     for (int64_t i = 0; i < lv.n; ++i) x[i] = (T)xd[i];
     return;
   }
@@ -848,6 +874,7 @@ int orc_build(int64_t n, const double* pts, int64_t m, const int32_t* edges, con
   for (size_t l = 0; l + 1 < h->L.size(); ++l) colouring(h->L[l], (int)l, o);
   st = cholesky(last, h->chol);
   if (st != OK) { delete h; return st; }
+  coarse_inverse(h->chol, last.n, h->cinv);
   *out = h;
   return OK;
 }
@@ -901,6 +928,9 @@ int orc_export(void* hp, int32_t l, int32_t what, void* dst, int64_t bytes) {
     case W_CHOL:
       if (l + 1 != (int32_t)h->L.size()) return INVALID_ARGUMENT;
       src = h->chol.data(); nb = 8 * (int64_t)h->chol.size(); break;
+    case W_CINV:
+      if (l + 1 != (int32_t)h->L.size()) return INVALID_ARGUMENT;
+      src = h->cinv.data(); nb = 8 * (int64_t)h->cinv.size(); break;
     default: return INVALID_ARGUMENT;
   }
   if (bytes != nb) return INVALID_ARGUMENT;

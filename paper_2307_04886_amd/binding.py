@@ -23,6 +23,7 @@ EXPORTS = {
     "labels": (6, np.int32), "dist": (7, np.float64), "p_col": (8, np.int32), "p_val": (9, np.float64),
     "p_cnt": (10, np.int32), "tri": (11, np.int32), "a_rowptr": (12, np.int32), "a_col": (13, np.int32),
     "a_val": (14, np.float64), "colors": (15, np.int32), "chol": (16, np.float64),
+    "coarse_inverse": (17, np.float64),
 }
 
 # Symbols the library exports (checked on load).
@@ -187,6 +188,7 @@ class Hierarchy:
             "edge_w": s["nnzE"], "scalars": 2, "samples": s["samples"], "labels": has, "dist": has,
             "p_col": 3 * has, "p_val": 3 * has, "p_cnt": has, "tri": 2 * has, "a_rowptr": n + 1,
             "a_col": s["nnzA"], "a_val": s["nnzA"], "colors": n if s["colors"] else 0, "chol": n * n,
+            "coarse_inverse": n * n,
         }[what]
         out = np.zeros(count, dtype=dt)
         st = library().gmg_export_level(self._h, level, code, out.ctypes.data_as(ctypes.c_void_p),
@@ -194,7 +196,7 @@ class Hierarchy:
         if st:
             raise _err(st)
         shapes = {"positions": (n, 3), "p_col": (has, 3), "p_val": (has, 3), "tri": (has, 2),
-                  "chol": (n, n)}
+                  "chol": (n, n), "coarse_inverse": (n, n)}
         return out.reshape(shapes[what]) if what in shapes else out
 
     def solve(self, b, x=None, tol=1e-8, max_iters=100, stream=None, history=False):

@@ -29,10 +29,19 @@ thread_local std::string g_last_error;
 // whole cache when an allocation fails.
 constexpr size_t kCacheIdleMax = size_t(16) << 30;
 
+// A free block: reusable on any stream once `settled` (every use of it on
+// the device has finished), before that only on `stream`, the stream that
+// freed it (which may be the null stream).
+struct FreeBlock {
+  void* p;
+  hipStream_t stream;
+  bool settled;
+};
+
 struct Cache {
   std::mutex m;
-  std::multimap<size_t, std::pair<void*, hipStream_t>> idle;  // size class -> (block, stream tag)
-  std::unordered_map<void*, size_t> live;                     // block -> size class
+  std::multimap<size_t, FreeBlock> idle;       // size class -> free block
+  std::unordered_map<void*, size_t> live;      // block -> size class
   size_t idle_bytes = 0;
 };
 Cache g_cache[64];
@@ -59,11 +68,11 @@ void trim_locked(Cache& c, size_t keep) {
   bool synced = false;
   for (auto it = c.idle.end(); it != c.idle.begin() && c.idle_bytes > keep;) {
     --it;
-    if (it->second.second && !synced) {
+    if (!it->second.settled && !synced) {
       (void)hipDeviceSynchronize();
       synced = true;
     }
-    (void)hipFree(it->second.first);
+    (void)hipFree(it->second.p);
     c.idle_bytes -= it->first;
     it = c.idle.erase(it);
   }
@@ -75,8 +84,8 @@ void* cache_get(size_t bytes, hipStream_t s) {
   std::lock_guard<std::mutex> lock(c.m);
   auto range = c.idle.equal_range(cls);
   for (auto it = range.first; it != range.second; ++it) {
-    if (it->second.second == nullptr || it->second.second == s) {
-      void* p = it->second.first;
+    if (it->second.settled || it->second.stream == s) {
+      void* p = it->second.p;
       c.idle.erase(it);
       c.idle_bytes -= cls;
       c.live[p] = cls;
@@ -104,7 +113,7 @@ void cache_put(void* p, hipStream_t s, bool idle) {
   if (it == c.live.end()) return;
   const size_t cls = it->second;
   c.live.erase(it);
-  c.idle.emplace(cls, std::make_pair(p, idle ? hipStream_t(nullptr) : s));
+  c.idle.emplace(cls, FreeBlock{p, s, idle});
   c.idle_bytes += cls;
   if (idle) trim_locked(c, kCacheIdleMax);
 }
@@ -114,7 +123,7 @@ void cache_settle(hipStream_t s) {
   Cache& c = cache_for_current();
   std::lock_guard<std::mutex> lock(c.m);
   for (auto& kv : c.idle)
-    if (kv.second.second == s) kv.second.second = nullptr;
+    if (kv.second.stream == s) kv.second.settled = true;
 }
 
 constexpr size_t kStaging = 1 << 16;
@@ -1486,6 +1495,22 @@ int gmg_export_level(gmg_handle h, int32_t l, int32_t what, void* dst, int64_t b
     case GMG_EXPORT_CHOL:
       if (!coarse) return GMG_INVALID_ARGUMENT;
       src = h->chol; nb = 8 * n * n; break;
+    case GMG_EXPORT_COARSE_INVERSE: {
+      // stored with the padded column stride inv_ld(n): copied column by column
+      if (!coarse) return GMG_INVALID_ARGUMENT;
+      if (bytes != 8 * n * n) {
+        set_error("export size mismatch");
+        return GMG_INVALID_ARGUMENT;
+      }
+      if (n == 0) return GMG_OK;
+      hipError_t e = hipMemcpy2D(dst, (size_t)n * 8, h->cinv, (size_t)inv_ld(n) * 8, (size_t)n * 8, (size_t)n,
+                                 hipMemcpyDeviceToHost);
+      if (e != hipSuccess) {
+        set_error(hipGetErrorString(e));
+        return GMG_DEVICE_ERROR;
+      }
+      return GMG_OK;
+    }
     default: return GMG_INVALID_ARGUMENT;
   }
   if (bytes != nb) {

@@ -547,104 +547,124 @@ __global__ void k_split_factor(const double* D, int64_t n, double* L, double* U)
   U[k * n + i] = v;
 }
 
-// Inverses of the diagonal blocks of L (kPanel x kPanel, lower triangular,
-// row-major, identity outside a short last block): one wavefront per block,
-// lane j solving L_bb x = e_j by forward substitution.
-__global__ void __launch_bounds__(kWave) k_chol_block_inv(const double* L, int64_t n, double* Dinv) {
-  __shared__ double T[kPanel][kPanel + 1];
-  const int64_t b0 = (int64_t)blockIdx.x * kPanel;
-  const int nb = (int)(n - b0 < kPanel ? n - b0 : kPanel);
+// Column c of the coarsest inverse, A^-1 e_c, by substitution with the
+// factor: forward L y = e_c, row i subtracting L_ik y_k for k ascending, then
+// back L^T x = y, row i subtracting L_ki x_k for k descending from n - 1; each
+// row is then divided by its pivot.  Both run column-oriented: once y_k (x_k)
+// is known, every row that needs it subtracts its term, so each row performs
+// its subtractions in the order of the row-by-row definition, bit for bit.
+// Rows above c start at +0 and stay +0 (every term they would subtract is a
+// product with y_k = +0), so the forward pass starts at row c.
+//
+// One wavefront per column: lane l holds rows l, l + 64, ... (S slots) in
+// registers and the pivot row's value is read across lanes; the factor
+// entries of the next D steps are loaded ahead (phase k mod D of a ring).
+template <int S, int D>
+__global__ void __launch_bounds__(kWave) k_coarse_inverse(const double* __restrict__ L,
+                                                         const double* __restrict__ U, int32_t n,
+                                                         double* __restrict__ inv) {
+  const int32_t c = blockIdx.x;
   const int lane = threadIdx.x;
-  for (int e = lane; e < kPanel * kPanel; e += kWave) {
-    const int i = e / kPanel, k = e % kPanel;
-    T[i][k] = (i < nb && k < nb) ? L[(b0 + i) * n + b0 + k] : (i == k ? 1.0 : 0.0);
+  double s[S];
+#pragma unroll
+  for (int q = 0; q < S; ++q) s[q] = q * kWave + lane == c ? 1.0 : 0.0;
+  double f[D][S], d[D];                       // ring: factor entries and pivot of step k at phase k mod D
+  // forward: step k uses column k of L (row k of U) for rows i > k
+  auto load_fwd = [&](int j, int32_t k) {
+    if (k >= n) return;
+    d[j] = L[(int64_t)k * n + k];
+#pragma unroll
+    for (int q = 0; q < S; ++q)
+      if (q * kWave + kWave - 1 > k) f[j][q] = U[(int64_t)k * n + min(q * kWave + lane, n - 1)];
+  };
+#pragma unroll
+  for (int j = 0; j < D; ++j) load_fwd(j, c + ((j - c) % D + D) % D);
+#pragma unroll
+  for (int q = 0; q < S; ++q) {
+    const int32_t k_lo = max(c, q * kWave), k_hi = min(n, (q + 1) * kWave);
+    for (int32_t k0 = k_lo - k_lo % D; k0 < k_hi; k0 += D) {
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        const int32_t k = k0 + j;
+        if (k >= k_lo && k < k_hi) {
+          const double y = read_lane(s[q], k & (kWave - 1)) / d[j];
+          if (lane == (k & (kWave - 1))) s[q] = y;
+#pragma unroll
+          for (int q2 = q; q2 < S; ++q2) {
+            const int32_t i = q2 * kWave + lane;
+            if (i > k && i < n) s[q2] = s[q2] - f[j][q2] * y;
+          }
+          load_fwd(j, k + D);
+        }
+      }
+    }
   }
-  __syncthreads();
-  if (lane >= kPanel) return;
-  double x[kPanel];
+  // back: step i uses row i of L for rows r < i
+  auto load_bwd = [&](int j, int32_t i) {
+    if (i < 0) return;
+    d[j] = L[(int64_t)i * n + i];
 #pragma unroll
-  for (int i = 0; i < kPanel; ++i) {
-    double s = i == lane ? 1.0 : 0.0;
+    for (int q = 0; q < S; ++q)
+      if (q * kWave < i) f[j][q] = L[(int64_t)i * n + min(q * kWave + lane, n - 1)];
+  };
 #pragma unroll
-    for (int m = 0; m < i; ++m) s = s - T[i][m] * x[m];
-    x[i] = s / T[i][i];
-    __builtin_amdgcn_sched_barrier(0);
+  for (int j = 0; j < D; ++j) load_bwd(j, (n - 1) - (((n - 1 - j) % D) + D) % D);
+#pragma unroll
+  for (int q = S - 1; q >= 0; --q) {
+    const int32_t i_hi = min(n, (q + 1) * kWave) - 1, i_lo = q * kWave;
+    if (i_hi < i_lo) continue;
+    // groups of D steps aligned to multiples of D, top step i0 first
+    for (int32_t i0 = i_hi + (D - 1 - i_hi % D); i0 >= i_lo; i0 -= D) {
+#pragma unroll
+      for (int jj = D - 1; jj >= 0; --jj) {
+        const int32_t i = i0 - (D - 1) + jj;        // descending within the group
+        const int j = jj;
+        if (i >= i_lo && i <= i_hi) {
+          const double x = read_lane(s[q], i & (kWave - 1)) / d[j];
+          if (lane == (i & (kWave - 1))) s[q] = x;
+#pragma unroll
+          for (int q2 = 0; q2 <= q; ++q2) {
+            const int32_t r = q2 * kWave + lane;
+            if (r < i) s[q2] = s[q2] - f[j][q2] * x;
+          }
+          load_bwd(j, i - D);
+        }
+      }
+    }
   }
+  const int32_t ld = (int32_t)inv_ld(n);
 #pragma unroll
-  for (int i = 0; i < kPanel; ++i) Dinv[((int64_t)blockIdx.x * kPanel + i) * kPanel + lane] = x[i];
+  for (int q = 0; q < S; ++q) {
+    const int32_t i = q * kWave + lane;
+    if (i < ld) inv[(int64_t)c * ld + i] = i < n ? s[q] : 0.0;
+  }
 }
 
-constexpr int kInvChunk = 8;
-
-// Column c of A^-1 = L^-T L^-1 e_c, one wavefront per column, by blocks of
-// kPanel rows: forward y_b = Dinv_b (e_b - sum_{k<b} L_bk y_k), then backward
-// x_b = Dinv_b^T (y_b - sum_{k>b} L_kb^T x_k).  The two halves of the
-// wavefront sum alternate terms of the off-diagonal products.
-__global__ void __launch_bounds__(kWave) k_chol_inverse(const double* L, const double* U, const double* Dinv,
-                                                        int64_t n, double* inv) {
-  extern __shared__ double y[];
-  __shared__ double Di[kPanel][kPanel + 1];
-  __shared__ double sv[kPanel];
-  const int64_t c = blockIdx.x;
-  const int lane = threadIdx.x;
-  const int r = lane & (kPanel - 1), half = lane / kPanel;
-  for (int64_t i = lane; i < n; i += kWave) y[i] = 0.0;
+// The same operations for coarsest levels beyond the register form: the
+// column lives in LDS, one workgroup per column, a barrier per step.
+__global__ void __launch_bounds__(kBlock) k_coarse_inverse_lds(const double* __restrict__ L,
+                                                               const double* __restrict__ U, int32_t n,
+                                                               double* __restrict__ inv) {
+  extern __shared__ double col[];
+  const int32_t c = blockIdx.x;
+  for (int32_t i = threadIdx.x; i < n; i += kBlock) col[i] = i == c ? 1.0 : 0.0;
   __syncthreads();
-  for (int64_t b0 = (c / kPanel) * kPanel; b0 < n; b0 += kPanel) {
-    const int nb = (int)(n - b0 < kPanel ? n - b0 : kPanel);
-    const double* D = Dinv + (b0 / kPanel) * kPanel * kPanel;
-    double sacc = 0.0;
-    if (r < nb)
-      for (int64_t m0 = c + half; m0 < b0; m0 += 2 * kInvChunk) {   // loads of a chunk in flight together
-        double lv[kInvChunk], yv[kInvChunk];
-#pragma unroll
-        for (int u = 0; u < kInvChunk; ++u) {
-          const int64_t m = m0 + 2 * u;
-          lv[u] = m < b0 ? L[(b0 + r) * n + m] : 0.0;
-          yv[u] = m < b0 ? y[m] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < kInvChunk; ++u) sacc += lv[u] * yv[u];
-      }
-    sacc += __shfl_xor(sacc, kPanel, kWave);
-    for (int k = half; k < kPanel; k += 2) Di[r][k] = D[r * kPanel + k];
-    if (half == 0) sv[r] = (b0 + r == c ? 1.0 : 0.0) - sacc;
-    __syncthreads();
-    double t = 0.0;
-    for (int k = 0; k <= r; ++k) t += Di[r][k] * sv[k];
-    __syncthreads();
-    if (half == 0 && r < nb) y[b0 + r] = t;
+  for (int32_t k = c; k < n; ++k) {
+    const double y = col[k] / L[(int64_t)k * n + k];
+    for (int32_t i = k + 1 + threadIdx.x; i < n; i += kBlock) col[i] = col[i] - U[(int64_t)k * n + i] * y;
+    __syncthreads();                          // every thread has read col[k]
+    if (threadIdx.x == 0) col[k] = y;
     __syncthreads();
   }
-  for (int64_t b0 = (n - 1) / kPanel * kPanel; b0 >= 0; b0 -= kPanel) {
-    const int nb = (int)(n - b0 < kPanel ? n - b0 : kPanel);
-    const int64_t b1 = b0 + nb;
-    const double* D = Dinv + (b0 / kPanel) * kPanel * kPanel;
-    double sacc = 0.0;
-    if (r < nb)
-      for (int64_t m0 = b1 + half; m0 < n; m0 += 2 * kInvChunk) {
-        double uv[kInvChunk], yv[kInvChunk];
-#pragma unroll
-        for (int u = 0; u < kInvChunk; ++u) {
-          const int64_t m = m0 + 2 * u;
-          uv[u] = m < n ? U[(b0 + r) * n + m] : 0.0;
-          yv[u] = m < n ? y[m] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < kInvChunk; ++u) sacc += uv[u] * yv[u];
-      }
-    sacc += __shfl_xor(sacc, kPanel, kWave);
-    for (int k = half; k < kPanel; k += 2) Di[r][k] = D[r * kPanel + k];
-    if (half == 0) sv[r] = (r < nb ? y[b0 + r] : 0.0) - sacc;
+  for (int32_t i = n - 1; i >= 0; --i) {
+    const double x = col[i] / L[(int64_t)i * n + i];
+    for (int32_t r = threadIdx.x; r < i; r += kBlock) col[r] = col[r] - L[(int64_t)i * n + r] * x;
     __syncthreads();
-    double t = 0.0;
-    for (int k = r; k < kPanel; ++k) t += Di[k][r] * sv[k];
-    __syncthreads();
-    if (half == 0 && r < nb) y[b0 + r] = t;
+    if (threadIdx.x == 0) col[i] = x;
     __syncthreads();
   }
-  const int64_t ld = inv_ld(n);
-  for (int64_t i = lane; i < ld; i += kWave) inv[c * ld + i] = i < n ? y[i] : 0.0;
+  const int32_t ld = (int32_t)inv_ld(n);
+  for (int32_t i = threadIdx.x; i < ld; i += kBlock) inv[(int64_t)c * ld + i] = i < n ? col[i] : 0.0;
 }
 
 // Longest row of every colour, rounded up to kTailGroup: w[c].
@@ -914,6 +934,31 @@ void solve_layout(Handle& h, Level& lv, const Level* nx, const int32_t* t_rp, co
   tfree(s, off);
 }
 
+// Slots per lane of the register form, with the depth of its load ring.
+template <int S>
+void launch_inverse(const double* L, const double* U, int32_t n, double* inv, hipStream_t s) {
+  constexpr int D = S <= 4 ? 8 : (S <= 8 ? 4 : 2);
+  k_coarse_inverse<S, D><<<n, kWave, 0, s>>>(L, U, n, inv);
+}
+
+void coarse_inverse(const double* L, const double* U, int64_t n64, double* inv, hipStream_t s) {
+  const int32_t n = (int32_t)n64;
+  switch ((n + kWave - 1) / kWave) {
+    case 1: launch_inverse<1>(L, U, n, inv, s); break;
+    case 2: launch_inverse<2>(L, U, n, inv, s); break;
+    case 3: launch_inverse<3>(L, U, n, inv, s); break;
+    case 4: launch_inverse<4>(L, U, n, inv, s); break;
+    case 5: launch_inverse<5>(L, U, n, inv, s); break;
+    case 6: launch_inverse<6>(L, U, n, inv, s); break;
+    case 7: launch_inverse<7>(L, U, n, inv, s); break;
+    case 8: launch_inverse<8>(L, U, n, inv, s); break;
+    case 9: case 10: case 11: case 12: launch_inverse<12>(L, U, n, inv, s); break;
+    case 13: case 14: case 15: case 16: launch_inverse<16>(L, U, n, inv, s); break;
+    default:
+      k_coarse_inverse_lds<<<n, kBlock, (size_t)n * 8, s>>>(L, U, n, inv);
+  }
+}
+
 void coarse_factor(Handle& h, Level& lv) {
   hipStream_t s = h.stream;
   const int64_t n = lv.n;
@@ -933,15 +978,11 @@ void coarse_factor(Handle& h, Level& lv) {
   if (!h.chol) h.chol = (double*)dalloc(h, (size_t)n * n * 8);
   if (!h.cinv) h.cinv = (double*)dalloc(h, (size_t)n * inv_ld(n) * 8);
   k_split_factor<<<blocks_for(n * n), kBlock, 0, s>>>(D, n, h.chol, U);
-  const int64_t nbk = (n + kPanel - 1) / kPanel;
-  double* Dinv = (double*)talloc(s, (size_t)nbk * kPanel * kPanel * 8);
-  k_chol_block_inv<<<(int)nbk, kWave, 0, s>>>(h.chol, n, Dinv);
-  k_chol_inverse<<<(int)n, kWave, (size_t)n * 8, s>>>(h.chol, U, Dinv, n, h.cinv);
+  coarse_inverse(h.chol, U, n, h.cinv, s);
   h.ncoarse = n;
   check_flags(h, "coarsest factorisation");
   tfree(s, D);
   tfree(s, U);
-  tfree(s, Dinv);
 }
 
 // New values of A_l (same pattern) into its SELL layout and diagonal.

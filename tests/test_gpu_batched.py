@@ -13,6 +13,7 @@ import oracle
 import synth
 from tests.conftest import problem
 from tests.test_gpu_pcg import PREC, both
+from tests.test_gpu_parity import assert_same_bits
 
 pytestmark = pytest.mark.gpu
 
@@ -42,8 +43,7 @@ def test_batched_preconditioner_parity(name, minc, nrhs, precision):
               for q in range(nrhs)]
     for q in range(nrhs):
         zo = orc.precondition(R[q], PREC[precision])
-        rel = np.linalg.norm(Z[q] - zo) / np.linalg.norm(zo)
-        assert rel <= (1e-11 if precision == "f64" else 1e-6), (q, rel)
+        assert_same_bits(zo, Z[q], f"{name} {precision} right-hand side {q}")
         # each right-hand side gets the single-vector arithmetic
         assert np.array_equal(Z[q], single[q]), q
 

@@ -2,12 +2,10 @@
 and of preconditioned CG against the CPU oracle, through the C ABI.
 
 Tolerances:
-- double cycle: the GPU and the oracle perform the same operations except the
-  coarsest solve (explicit inverse vs. triangular substitution, 1e-15
-  relative), so one cycle agrees to 1e-11 relative;
-- float cycle: the same, but a coarse value that lands near a float rounding
-  boundary may round the other way (one float ulp, 6e-8 relative), which the
-  cycle carries to the fine level: 1e-6 relative;
+- the cycle (double and float): the GPU performs the oracle's operations in
+  its order on every level, the coarsest solve included (the product with the
+  inverse whose columns are the oracle's substitutions), so z = B r is
+  compared bit for bit, entry by entry;
 - CG: the dot products are summed in a different order (tree vs. sequential),
   which perturbs the iterates at the rounding level of the previous residual:
   each iteration adds a difference of about u |r_{k-1}| (u the unit roundoff
@@ -28,6 +26,7 @@ import pytest
 
 import oracle
 from tests.conftest import problem
+from tests.test_gpu_parity import assert_same_bits
 
 pytestmark = pytest.mark.gpu
 
@@ -63,12 +62,9 @@ def test_preconditioner_parity(name, minc, precision):
     r = np.random.default_rng(11).uniform(-1, 1, prob.n)
     zo = orc.precondition(r, PREC[precision])
     zg = gpu.precondition(torch.from_numpy(r).cuda(), precision=precision).cpu().numpy()
-    rel = np.linalg.norm(zg - zo) / np.linalg.norm(zo)
-    tol = 1e-11 if precision == "f64" else 1e-6
-    assert rel <= tol, rel
+    assert_same_bits(zo, zg, f"{name} {precision} preconditioner")
     if precision == "f32":
         assert np.array_equal(zg, zg.astype(np.float32).astype(np.float64))
-        _say(f"[gpu]   float cycle: {np.mean(zg == zo):.4f} of the entries bit-equal, rel. diff {rel:.2e}")
 
 
 def test_preconditioner_single_level():
@@ -80,7 +76,7 @@ def test_preconditioner_single_level():
     for precision in ("f64", "f32"):
         zo = orc.precondition(r, PREC[precision])
         zg = gpu.precondition(torch.from_numpy(r).cuda(), precision=precision).cpu().numpy()
-        assert np.linalg.norm(zg - zo) <= (1e-13 if precision == "f64" else 1e-7) * np.linalg.norm(zo)
+        assert_same_bits(zo, zg, f"single level {precision}")
 
 
 def compare_pcg(orc, gpu, prob, precision, tol=1e-8, max_iters=100, check_x=True):

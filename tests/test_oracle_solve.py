@@ -160,3 +160,45 @@ def test_indefinite_matrix_is_reported():
         oracle.Hierarchy(p.points, p.edges, A.indptr, A.indices, A.data,
                          oracle.default_options(min_coarse_points=2000))
     assert e.value.status == -4
+
+
+@pytest.mark.parametrize("name,minc", [("torus48", 300), ("ico4", 100), ("pc4k", 200)])
+def test_coarse_inverse_is_the_inverse(name, minc):
+    """The coarsest direct solve (Alg. 2) is a product with A^-1, whose columns
+    come from substitutions with the Cholesky factor.  Checked against LAPACK's
+    inverse and triangular solves (other operation orders), A A^-1 = I, and
+    symmetry, each within the rounding bound of a backward-stable solve."""
+    import scipy.linalg as sla
+    p = problem(name)
+    h = oracle.Hierarchy.from_problem(p, oracle.default_options(min_coarse_points=minc))
+    L = h.num_levels - 1
+    lv = h.level(L)
+    n = lv["n"]
+    A = brute.dense(lv["arp"], lv["acol"], lv["aval"], (n, n))
+    inv = h.coarse_inverse().T                # column k = A^-1 e_k
+    u = 2.0 ** -53
+    kappa = np.linalg.cond(A)
+    bound = 8 * n * kappa * u
+    ref = np.linalg.inv(A)
+    assert np.linalg.norm(inv - ref) <= bound * np.linalg.norm(ref)
+    assert np.linalg.norm(A @ inv - np.eye(n)) <= 8 * n * kappa * u * np.sqrt(n)
+    assert np.linalg.norm(inv - inv.T) <= bound * np.linalg.norm(ref)
+    # every column is the substitution solve with the exported factor
+    Lf = h.chol()
+    y = sla.solve_triangular(Lf, np.eye(n), lower=True)
+    x = sla.solve_triangular(Lf.T, y, lower=False)
+    assert np.linalg.norm(inv - x) <= bound * np.linalg.norm(x)
+
+
+def test_one_level_solve_is_the_inverse_product():
+    """On one level the V-cycle is the coarsest solve: x_i = sum_k (A^-1 e_k)_i b_k.
+    Compared with the product formed by NumPy in another summation order (within
+    n u |A^-1||b|), and with the exact solution of the rounded inverse."""
+    p = problem("ico3")
+    h = oracle.Hierarchy.from_problem(p, oracle.default_options(min_coarse_points=p.n))
+    assert h.num_levels == 1
+    inv = h.coarse_inverse().T
+    x, it, hist, st = h.solve(p.rhs, max_iters=1, tol=0.0)
+    ref = inv @ p.rhs
+    scale = np.abs(inv) @ np.abs(p.rhs)
+    assert np.all(np.abs(x - ref) <= p.n * 2.0 ** -53 * scale)
