@@ -227,6 +227,30 @@ int gmg_solve_pcg(gmg_handle h, const double* b_dev, double* x_dev, double tol, 
  */
 int gmg_precondition(gmg_handle h, const double* r_dev, double* z_dev, int32_t precision, void* stream);
 
+/*
+ * gmg_precondition without allocation, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  Same z = B r, same kernels and the same bits as
+ * gmg_precondition; the residual in the solve numbering and the cycle's
+ * level-0 output live in a fixed device array of the library (32 MiB per
+ * device, held until the process ends), so the call allocates nothing, does
+ * not synchronise and does not check r for non-finite values (a non-finite r
+ * gives a non-finite z).
+ *
+ *  h                  a handle of the current device with at most 2,097,152 points
+ *  r_dev, z_dev       float64 device vectors of length n (may not alias)
+ *  precision          GMG_PRECISION_F64, or GMG_PRECISION_F32 once the handle holds its float
+ *                     level data (made by its first F32 call of gmg_precondition or gmg_solve_pcg)
+ *  stream             the work is enqueued on it; z is ready when the stream reaches that point
+ *
+ * Every call on a device shares that device's array, which keeps the last
+ * call's contents: calls that overlap on one device race, and so do
+ * overlapping calls on one handle.
+ * Returns GMG_OK, GMG_INVALID_ARGUMENT (bad arguments, too many points, float data not made yet,
+ * another device current) or GMG_DEVICE_ERROR (a launch failed).
+ */
+int gmg_precondition_noalloc(gmg_handle h, const double* r_dev, double* z_dev, int32_t precision, void* stream);
+
 /* Releases the handle and its device memory.  NULL is ignored. */
 void gmg_free(gmg_handle h);
 

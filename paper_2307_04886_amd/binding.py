@@ -28,7 +28,7 @@ EXPORTS = {
 
 # Symbols the library exports (checked on load).
 SYMBOLS = ["gmg_default_options", "gmg_build_hierarchy", "gmg_solve", "gmg_solve_pcg", "gmg_precondition",
-           "gmg_update_matrix", "gmg_pattern_outer", "gmg_solve_pcg_batched", "gmg_precondition_batched", "gmg_free", "gmg_status_string", "gmg_last_error",
+           "gmg_update_matrix", "gmg_pattern_outer", "gmg_solve_pcg_batched", "gmg_precondition_batched", "gmg_precondition_noalloc", "gmg_free", "gmg_status_string", "gmg_last_error",
            "gmg_num_levels", "gmg_level_sizes", "gmg_export_level", "gmg_timer_start", "gmg_timer_stop"]
 
 # gmg_precision
@@ -79,6 +79,7 @@ def library():
     L.gmg_update_matrix.argtypes = [P, P, P]
     L.gmg_solve_pcg_batched.argtypes = [P, I32, P, P, ctypes.c_double, I32, I32, P, ctypes.POINTER(SolveInfo)]
     L.gmg_precondition_batched.argtypes = [P, I32, P, P, I32, P]
+    L.gmg_precondition_noalloc.argtypes = [P, P, P, I32, P]
     L.gmg_pattern_outer.argtypes = [I64, P, P, P, P, ctypes.c_double, P, P]
     L.gmg_free.argtypes = [P]
     L.gmg_free.restype = None
@@ -247,6 +248,16 @@ class Hierarchy:
             raise _err(st)
         return z
 
+
+    def precondition_noalloc(self, r, z, precision="f64", stream=None):
+        """gmg_precondition_noalloc: z = B r into the caller's z, no allocation, no synchronisation."""
+        import torch
+        pr = _dev(r, torch.float64, (self.n,), "r")
+        pz = _dev(z, torch.float64, (self.n,), "z")
+        st = library().gmg_precondition_noalloc(self._h, pr, pz, PRECISION[precision], _stream_ptr(stream))
+        if st:
+            raise _err(st)
+        return z
 
     def solve_pcg_batched(self, B, X=None, tol=1e-8, max_iters=100, precision="f32", stream=None):
         """gmg_solve_pcg_batched: B, X of shape (nrhs, n).  Returns (X, [SolveInfo], status)."""

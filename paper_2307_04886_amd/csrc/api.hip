@@ -1027,6 +1027,61 @@ int pcg_batched(Handle& h, int nq, double tol, int32_t max_iters, hipStream_t s,
   return status;
 }
 
+// ------------------------------------------------------------------ preconditioner without allocation
+// Scratch of gmg_precondition_noalloc: the residual in the solve numbering
+// (first half) and the cycle's level-0 output (second half).  Each device
+// holds its own copy of the array; host code uses only the address returned
+// by hipGetSymbolAddress for the current device, never the array's name.
+constexpr int64_t kNoAllocMaxPoints = int64_t(1) << 21;
+static __device__ __align__(256) double scratch[2 * kNoAllocMaxPoints];
+
+std::mutex g_scratch_mutex;
+double* g_scratch_dev[64] = {};
+
+// The scratch address on the current device, looked up on the first call
+// there (with that device current).
+double* scratch_on_current_device() {
+  int dev = 0;
+  check_hip(hipGetDevice(&dev), "hipGetDevice");
+  if (dev < 0 || dev >= 64) throw Error{GMG_DEVICE_ERROR, "device index out of range"};
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    check_hip(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "scratch address");
+    g_scratch_dev[dev] = static_cast<double*>(p);
+  }
+  return g_scratch_dev[dev];
+}
+
+// z = B r with the scratch above; nothing is allocated and nothing waits.
+void precondition_noalloc(Handle& h, const double* r, double* z, int32_t precision, hipStream_t s) {
+  const Level& l0 = h.L[0];
+  const int64_t n = l0.n;
+  double* sr = scratch_on_current_device();
+  permute_in(l0.perm, r, sr, n, s);
+  if (precision == GMG_PRECISION_F32) {
+    const Cycle<float>& c = h.kry.c32;
+    to_f32(sr, (float*)c.v[0].b, n, s);
+    fill_zero(c.v[0].x, n, s);
+    vcycle(h, c, 0, s);
+    permute_out(l0.perm, (const float*)c.v[0].x, z, n, s);
+  } else {
+    if (h.noalloc_base != sr) {             // host-side views of the cycle, made once per handle
+      h.noalloc64.v = h.plain.v;
+      h.noalloc64.symmetric = true;
+      h.noalloc64.v[0].b = sr;
+      h.noalloc64.v[0].x = sr + kNoAllocMaxPoints;
+      make_tail(h, h.noalloc64);
+      h.noalloc_base = sr;
+    }
+    const Cycle<double>& c = h.noalloc64;
+    fill_zero(c.v[0].x, n, s);
+    vcycle(h, c, 0, s);
+    permute_out(l0.perm, (const double*)c.v[0].x, z, n, s);
+  }
+  check_hip(hipGetLastError(), "preconditioner launch");
+}
+
 const char* status_text(int st) {
   switch (st) {
     case GMG_OK: return "ok";
@@ -1410,6 +1465,34 @@ int gmg_precondition_batched(gmg_handle hh, int32_t nrhs, const double* R_dev, d
   }
   h->stream = saved;
   return status;
+}
+
+int gmg_precondition_noalloc(gmg_handle hh, const double* r_dev, double* z_dev, int32_t precision, void* stream) {
+  set_error("");
+  Handle* h = hh;
+  if (!h || !r_dev || !z_dev || (precision != GMG_PRECISION_F64 && precision != GMG_PRECISION_F32)) {
+    set_error("invalid preconditioner arguments");
+    return GMG_INVALID_ARGUMENT;
+  }
+  if (h->L[0].n > kNoAllocMaxPoints) {
+    set_error("gmg_precondition_noalloc: more points than its scratch holds (2,097,152)");
+    return GMG_INVALID_ARGUMENT;
+  }
+  if (precision == GMG_PRECISION_F32 && !h->kry.ready[1]) {
+    set_error("gmg_precondition_noalloc: the float level data is made by a first GMG_PRECISION_F32 call of "
+              "gmg_precondition or gmg_solve_pcg");
+    return GMG_INVALID_ARGUMENT;
+  }
+  try {
+    int dev = 0;
+    check_hip(hipGetDevice(&dev), "hipGetDevice");
+    if (dev != h->device) throw Error{GMG_INVALID_ARGUMENT, "the handle's device is not the current device"};
+    precondition_noalloc(*h, r_dev, z_dev, precision, (hipStream_t)stream);
+  } catch (const Error& e) {
+    set_error(e.msg);
+    return e.status;
+  }
+  return GMG_OK;
 }
 
 void gmg_free(gmg_handle h) { release(h); }

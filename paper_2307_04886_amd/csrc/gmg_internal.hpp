@@ -325,6 +325,8 @@ struct Handle {
   double* red = nullptr;                // reduction partials
   int tail_start = -1;                  // first level solved by the single-workgroup tail kernel
   Cycle<double> plain;                  // the V-cycle of the solve (Alg. 2)
+  Cycle<double> noalloc64;              // the symmetric double cycle on the no-allocation scratch
+  const double* noalloc_base = nullptr; // scratch address noalloc64 was made for
   Krylov kry;
   Batch bat;
   // one V-cycle plus the convergence residual, captured once and replayed
