@@ -10,6 +10,15 @@ The workload is the 1024 x 1024 jittered torus (1,048,576 points) with the
 cotan smoothing system (M + 1e-3 L) x = M b.  Inputs are resident in HBM
 before the timed region starts.
 
+Besides the headline the line carries: the whole step against the HBM
+roofline (the algorithmic byte model below on the step's own level sizes),
+the method's per-level statistics (coarsening ratio, fallback and
+single-entry prolongation rows), the 2,000,000-point bumpy-sphere point
+cloud (kNN graph) in the plain FP64 form and in the mixed form (float
+V-cycles preconditioning double CG to 1e-10), the many-mesh batched form
+against the plain double path on the same number of streams, and the CPU
+oracle on one pinned host core.
+
 Prints one JSON line (see the keys below).
 """
 import argparse
@@ -48,6 +57,92 @@ def traffic_for(kind):
     return rec["bytes_per_launch"] if kernel_src_sha() == rec["src_sha256_16"] else None
 
 
+# Algorithmic bytes of the method's data movement (each array read or written once per logical
+# pass; 8 B per value, 4 B per index), on the actual level sizes.  n, z = nnz(A_l), p = nnz(P_l),
+# m = undirected edges, nc = n_{l+1}.
+def vcycle_bytes(lv, nu):
+    """One V-cycle: nu sweeps, residual, restriction, prolongation + correction per level, the
+    coarsest product with the dense inverse, and the level-0 residual of the convergence test."""
+    tot = 0.0
+    for l in range(len(lv) - 1):
+        n, z, p, nc = lv[l]["n"], lv[l]["nnzA"], lv[l]["nnzP"], lv[l + 1]["n"]
+        sweep = 12 * z + 28 * n
+        tot += nu * sweep + sweep + (12 * p + 8 * n + 12 * nc) + (12 * p + 8 * nc + 16 * n)
+    tot += 8 * lv[-1]["n"] ** 2
+    return tot + 12 * lv[0]["nnzA"] + 28 * lv[0]["n"]
+
+
+def setup_bytes(lv):
+    """The build: inputs copied; per level the edge CSR, edge lengths and mean, the conflict test
+    and sampling rounds (conflict entries counted as the edge CSR's 2m, a lower bound), one
+    Voronoi relaxation pass, cells and shift, coarse edges, projection, P^T, the Galerkin
+    product, colouring and the solve layouts; the coarsest factor and inverse."""
+    tot = 0.0
+    L = len(lv)
+    for l, s in enumerate(lv):
+        n, m, z = s["n"], s["m"], s["nnzA"]
+        C = 2 * m
+        if l == 0:
+            tot += 24 * n + 8 * m + 12 * z
+        tot += 16 * m + 4 * n + 28 * n + 24 * m
+        if l + 1 < L:
+            p, zc = s["nnzP"], lv[l + 1]["nnzA"]
+            tot += 16 * m + (24 * m + 8 * n + 4 * C) + 2 * (4 * C + n) + (24 * m + 28 * n) + 36 * n
+            tot += (8 * m + 8 * n) + 64 * n + 72 * n + (12 * z + 72 * n + 12 * zc) + 2 * (4 * z + 12 * n)
+            tot += 24 * z + 24 * p
+        else:
+            tot += 24 * n * n
+    return tot
+
+
+def level_stats(h):
+    """Per level: sizes, colours, coarsening ratio and the prolongation's fallback and
+    single-entry rows (Sec. 4.4 reports a fallback rate of about 0.25%)."""
+    import numpy as np
+    out = []
+    L = h.num_levels
+    for l in range(L):
+        s = h.sizes(l)
+        row = {"n": s["n"], "edges": s["m"], "nnz_A": s["nnzA"], "colours": s["colors"]}
+        if l + 1 < L:
+            cnt = h.export(l, "p_cnt")
+            row.update({"nnz_P": s["nnzP"], "coarse_points": s["samples"],
+                        "coarsening_ratio": s["samples"] / s["n"],
+                        "fallback_rows": s["fallback"], "fallback_pct": 100.0 * s["fallback"] / s["n"],
+                        "single_entry_rows": int((cnt == 1).sum()),
+                        "single_entry_pct": 100.0 * float((cnt == 1).mean())})
+        out.append(row)
+    return out
+
+
+def host_cpu():
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "allowed_cores": len(os.sched_getaffinity(0)), "model": model}
+
+
+def pinned(fn):
+    """Runs fn() with the calling thread pinned to one allowed core (the equivalent of
+    taskset -c <core>); returns (result, core)."""
+    saved = os.sched_getaffinity(0)
+    core = min(saved)
+    os.sched_setaffinity(0, {core})
+    try:
+        return fn(), core
+    finally:
+        os.sched_setaffinity(0, saved)
+
+
+def progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -56,6 +151,7 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the many-mesh batched measurement")
+    ap.add_argument("--no-pointcloud", action="store_true", help="skip the 2M-point point-cloud measurement")
     ap.add_argument("--headline-only", action="store_true",
                     help="only the plain steps (and roofline passes): for profiler runs")
     ap.add_argument("--size", type=int, default=1024, help="torus grid size (default 1024)")
@@ -94,6 +190,8 @@ def main():
     opt = default_options()
     stream = torch.cuda.current_stream()
 
+    stats = {}
+
     def step(form="plain"):
         h = build_hierarchy(pts, edges, rp, ci, va, opt, stream)
         x.zero_()
@@ -104,6 +202,9 @@ def main():
         if st != 0:
             raise RuntimeError(f"{form} solve did not converge (status {st})")
         levels = h.num_levels
+        if "levels" not in stats:
+            stats["levels"] = level_stats(h)
+            stats["sizes"] = [h.sizes(l) for l in range(levels)]
         h.free()
         return info, levels
 
@@ -116,7 +217,15 @@ def main():
     dt = time.perf_counter() - t0
     info, levels = infos[-1]
     ms = 1e3 * dt / args.steps
+    progress(f"headline: {args.steps} steps, {ms:.2f} ms per step")
     x_plain = x.cpu().numpy()
+    nu = opt.nu_pre + opt.nu_post
+    sb, cb = setup_bytes(stats["sizes"]), vcycle_bytes(stats["sizes"], nu)
+    step_b = sb + info.iterations * cb
+    step_roofline = {"bound": "hbm", "what": "whole setup + solve step, algorithmic bytes",
+                     "bytes": step_b, "setup_bytes": sb, "vcycle_bytes": cb, "v_cycles": info.iterations,
+                     "achieved": step_b / (ms * 1e-3) / 1e9, "peak": 8000.0, "unit": "GB/s",
+                     "frac": step_b / (ms * 1e-3) / 8e12}
 
     # Roofline: the same K steps again, every launch of one kernel class timed with a pair of
     # HIP events recorded by the dispatch itself on the launch stream (instrumented launches are
@@ -138,6 +247,7 @@ def main():
 
     kinds = {"auto": ["gs_galerkin", "gs_finest"], "none": []}.get(args.timer, [args.timer])
     lines = sorted([roofline_pass(k) for k in kinds], key=lambda r: -r["kernel_ms_per_step"])
+    progress("roofline passes done")
 
     # the same workload solved by CG preconditioned with the symmetric V-cycle, in double and in
     # float (mixed precision): whole setup + solve per step, same tolerance
@@ -178,6 +288,79 @@ def main():
             so.append(tc - tb)
         return {"setup_ms": 1e3 * float(np.median(su)), "solve_ms": 1e3 * float(np.median(so))}
 
+    # the 2,000,000-point bumpy sphere (kNN k = 8, Gaussian graph Laplacian): plain FP64 to
+    # 1e-8 and the mixed form (float V-cycles preconditioning double CG) to 1e-10, each a whole
+    # setup + solve per step; errors against a plain FP64 solve to 1e-12 (the plain path's
+    # iterates are bit-identical to the oracle's FP64 iterates)
+    pointcloud = None
+    if not args.no_pointcloud and not args.headline_only:
+        t0 = time.time()
+        pc = synth.config_bumpy_sphere()
+        pc_gen = time.time() - t0
+        progress(f"point cloud generated in {pc_gen:.1f} s")
+        pct = [torch.from_numpy(a).to(dev) for a in (pc.points, pc.edges, pc.indptr, pc.indices, pc.data, pc.rhs)]
+        pcx = torch.zeros_like(pct[5])
+        pstats = {}
+
+        def pc_step(form, tol, timed=None):
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            h = build_hierarchy(*pct[:5], opt, stream)
+            if timed is not None:
+                torch.cuda.synchronize()
+            tb = time.perf_counter()
+            pcx.zero_()
+            if form == "plain":
+                _, inf, st = h.solve(pct[5], pcx, tol=tol, max_iters=400, stream=stream)
+            else:
+                _, inf, st = h.solve_pcg(pct[5], pcx, tol=tol, max_iters=200, precision="f32", stream=stream)
+            if st != 0:
+                raise RuntimeError(f"point cloud {form} solve did not converge (status {st})")
+            if "sizes" not in pstats:
+                pstats["sizes"] = [h.sizes(l) for l in range(h.num_levels)]
+                pstats["levels"] = level_stats(h)
+            h.free()
+            torch.cuda.synchronize()
+            tc = time.perf_counter()
+            if timed is not None:
+                timed.append((tb - ta, tc - tb))
+            return inf
+        ref_info = pc_step("plain", 1e-12)
+        x_ref = pcx.cpu().numpy()
+        pc_steps = max(2, min(args.steps, 5))
+        legs = {}
+        for form, tol in (("plain", args.tol), ("pcg_f32", 1e-10)):
+            pc_step(form, tol)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(pc_steps):
+                inf = pc_step(form, tol)
+            torch.cuda.synchronize()
+            fdt = (time.perf_counter() - t1) / pc_steps
+            xs = pcx.cpu().numpy()
+            parts = []
+            for _ in range(2):
+                pc_step(form, tol, parts)
+            leg = {"value": 1.0 / fdt, "unit": "solves/s", "ms_per_step": 1e3 * fdt,
+                   "setup_ms": 1e3 * min(p[0] for p in parts), "solve_ms": 1e3 * min(p[1] for p in parts),
+                   "iterations": inf.iterations, "rel_residual": inf.rel_residual, "tol": tol,
+                   "rel_error_vs_fp64_reference": float(np.linalg.norm(xs - x_ref) / np.linalg.norm(x_ref))}
+            if form == "plain":
+                psb = setup_bytes(pstats["sizes"])
+                pcb = vcycle_bytes(pstats["sizes"], nu)
+                pb_ = psb + inf.iterations * pcb
+                leg["step_roofline"] = {"bytes": pb_, "achieved": pb_ / fdt / 1e9, "peak": 8000.0, "unit": "GB/s",
+                                        "frac": pb_ / fdt / 8e12}
+            legs[form] = leg
+            progress(f"point cloud {form}: {leg['ms_per_step']:.1f} ms per step")
+        pointcloud = {"workload": f"bumpy sphere point cloud, {pc.n} points, symmetrised kNN (k = 8) graph "
+                                  f"({pc.m} edges), Gaussian graph Laplacian, (M + 1e-2 L) x = M b",
+                      "generation_s": pc_gen, "plain_fp64": legs["plain"], "mixed_f32_cycle_fp64_cg": legs["pcg_f32"],
+                      "fp64_reference": f"plain FP64 V-cycles to 1e-12 ({ref_info.iterations} cycles); the plain "
+                                        "path's iterates are bit-identical to the CPU oracle's FP64 iterates",
+                      "levels": pstats["levels"]}
+        del pct, pcx
+
     out = {
         "metric": "setup+solve solves/s to 1e-8 rel. residual",
         "value": args.steps / dt,
@@ -196,11 +379,15 @@ def main():
                    "v_cycles": info.iterations, "rel_residual": info.rel_residual, "tol": args.tol},
         "roofline": lines[0] if lines else None,
         "roofline_other": lines[1:],
+        "step_roofline": step_roofline,
+        "levels": stats["levels"],
+        "paper_fallback_pct": 0.25,
         "cpu_baseline": None,
         "mixed_vs_fp64": dict(forms, note="double CG preconditioned by one symmetric V-cycle per iteration "
                                           "(f64: cycle in double, f32: cycle in float); whole setup + solve "
                                           "per step, same workload and tolerance"),
         "split_ms": None if args.headline_only else {"plain": split("plain"), "pcg_f32": split("pcg_f32")},
+        "pointcloud": pointcloud,
     }
 
     # many meshes of uneven size with 8 right-hand sides each: every hierarchy built and every
@@ -214,6 +401,7 @@ def main():
             t = [torch.from_numpy(a).to(dev) for a in (bp.points, bp.edges, bp.indptr, bp.indices, bp.data)]
             systems.append(tuple(t) + (torch.from_numpy(B).to(dev),))
         nsolves = sum(B.shape[0] for _, B in batch)
+        progress("many-mesh workload generated")
         solve_many(systems, streams=4, tol=args.tol, precision="f32")
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -223,26 +411,23 @@ def main():
         if any(st != 0 for _, _, st in res):
             raise RuntimeError("batched solve did not converge")
 
-        def plain_all():
-            for (pts_, e_, rp_, ci_, va_, B) in systems:
-                hh = build_hierarchy(pts_, e_, rp_, ci_, va_, opt, stream)
-                for q in range(B.shape[0]):
-                    xq = torch.zeros_like(B[q])
-                    _, inf, st = hh.solve(B[q].contiguous(), xq, tol=args.tol, max_iters=200, stream=stream)
-                    if st != 0:
-                        raise RuntimeError("plain solve did not converge")
-                hh.free()
+        # the plain double V-cycle solve of each right-hand side, on the same 4-stream pool
+        solve_many(systems, streams=4, tol=args.tol, max_iters=200, form="plain")
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        plain_all()
+        pres = solve_many(systems, streams=4, tol=args.tol, max_iters=200, form="plain")
         torch.cuda.synchronize()
         pdt = time.perf_counter() - t1
+        if any(st != 0 for _, _, st in pres):
+            raise RuntimeError("plain solve did not converge")
         out["batched"] = {"workload": f"{len(batch)} jittered tori and icospheres, {min(b.n for b, _ in batch)}"
                                       f"-{max(b.n for b, _ in batch)} vertices ({sum(b.n for b, _ in batch)} in total),"
                                       f" 8 right-hand sides each, (M + 1e-3 L), tol {args.tol}",
                           "value": nsolves / bdt, "unit": "solves/s", "ms": 1e3 * bdt, "solves": nsolves,
                           "form": "setup + float-preconditioned double CG, 8 right-hand sides per launch, "
                                   "4 streams",
+                          "plain_fp64_form": "setup + plain double V-cycle solve of each right-hand side in turn, "
+                                             "the same 4 streams",
                           "plain_fp64_value": nsolves / pdt, "plain_fp64_ms": 1e3 * pdt,
                           "vs_plain_fp64": pdt / bdt}
 
@@ -256,17 +441,27 @@ def main():
 
     if not args.no_cpu_baseline:
         import oracle
-        t0 = time.perf_counter()
-        orc = oracle.Hierarchy.from_problem(prob)
-        xo, it, hist, st = orc.solve(prob.rhs, tol=args.tol)
-        cdt = time.perf_counter() - t0
+        progress("CPU oracle on one pinned core")
+
+        def run_oracle():
+            t0 = time.perf_counter()
+            orc = oracle.Hierarchy.from_problem(prob)
+            res = orc.solve(prob.rhs, tol=args.tol)
+            return res, time.perf_counter() - t0
+        ((xo, it, hist, st), cdt), core = pinned(run_oracle)
         err = float(np.linalg.norm(x_plain - xo) / np.linalg.norm(xo))
         for form, xf in x_forms.items():
             forms[form]["rel_error_vs_oracle_fp64"] = float(np.linalg.norm(xf - xo) / np.linalg.norm(xo))
+        hc = host_cpu()
         out["cpu_baseline"] = {"value": 1.0 / cdt, "unit": "solves/s", "cores": 1, "kind": "oracle",
                                "sample": f"one full setup+solve of the same torus workload "
                                          f"({it} V-cycles, {cdt:.1f} s, single-threaded C++)",
-                               "gpu_vs_oracle_rel_error": err}
+                               "host": f"1 core of {hc['nproc']} ({hc['allowed_cores']} allowed to this "
+                                       f"process), {hc['model']}",
+                               "pinned_core": core, "nproc": hc["nproc"], "cpu_model": hc["model"],
+                               "gpu_vs_oracle_rel_error": err,
+                               "gpu_vs_oracle_bitwise": bool(np.array_equal(x_plain.view(np.int64),
+                                                                            xo.view(np.int64)))}
     print(json.dumps(out), flush=True)
 
 
