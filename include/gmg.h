@@ -60,6 +60,13 @@ typedef struct gmg_options {
   int32_t color_passes;          /* iterated-greedy recolouring passes after the first-fit colouring that
                                     orders the multicolour Gauss-Seidel sweeps (3; 0 keeps the first
                                     colouring; at most 64) */
+  int32_t block_min_rows;        /* levels 1.. (not the coarsest) with more points than this sweep in block
+                                    order (4096): the points, projected onto the two coordinate axes of
+                                    largest extent, are binned into square cells slightly wider than the
+                                    longest coupling of A_l along those axes; the four parity classes of
+                                    the cells are swept one after the other, and within a cell the
+                                    colours in order.  A valid Gauss-Seidel order (the paper leaves the
+                                    order open, Sec. 3) that needs four launches per sweep. */
 } gmg_options;
 
 /* Values of gmg_options.weighting. */
@@ -264,11 +271,12 @@ const char* gmg_last_error(void);
 int gmg_num_levels(gmg_handle h, int32_t* levels);
 
 /*
- * Sizes of level l, written to sizes_host[0..7]:
+ * Sizes of level l, written to sizes_host[0..8]:
  *  0 points n_l, 1 undirected edges of E_l, 2 nnz(A_l), 3 nnz(P_l) (0 on the
  *  coarsest level), 4 colours, 5 rows of P_l that used the inverse-distance
  *  fallback, 6 coarse points sampled from this level (0 on the coarsest),
- *  7 entries of the symmetric edge CSR (2 x edges).
+ *  7 entries of the symmetric edge CSR (2 x edges), 8 one if the level's
+ *  Gauss-Seidel sweeps run in block order (see gmg_options.block_min_rows).
  */
 int gmg_level_sizes(gmg_handle h, int32_t level, int64_t* sizes_host);
 
@@ -291,9 +299,11 @@ enum gmg_export_what {
   GMG_EXPORT_A_VAL = 14,       /* double[nnz] */
   GMG_EXPORT_COLORS = 15,      /* int32[n] Gauss-Seidel colour of each row */
   GMG_EXPORT_CHOL = 16,        /* double[n*n] row-major lower Cholesky factor (coarsest level only) */
-  GMG_EXPORT_COARSE_INVERSE = 17 /* double[n*n] inverse of the coarsest A by columns: element k*n + i is
+  GMG_EXPORT_COARSE_INVERSE = 17, /* double[n*n] inverse of the coarsest A by columns: element k*n + i is
                                     (A^-1 e_k)_i (coarsest level only; the direct solve of Alg. 2 is the
                                     product with it, summed over k ascending) */
+  GMG_EXPORT_BLOCK_COLORS = 18 /* int32[n] block colour 0..3 (parity class of the grid cell) of each point,
+                                  on levels swept in block order; size 0 elsewhere */
 };
 
 /*

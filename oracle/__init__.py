@@ -17,7 +17,7 @@ _SRC = os.path.join(_HERE, "oracle.cpp")
 
 # export codes (mirrors the enumeration in oracle.cpp)
 POSITIONS, EDGE_ROWPTR, EDGE_COL, EDGE_W, SCALARS, SAMPLES, LABELS, DIST = range(8)
-P_COL, P_VAL, P_CNT, TRI, A_ROWPTR, A_COL, A_VAL, COLORS, CHOL, CINV = range(8, 18)
+P_COL, P_VAL, P_CNT, TRI, A_ROWPTR, A_COL, A_VAL, COLORS, CHOL, CINV, BLOCK_COLORS = range(8, 19)
 
 STATUS = {0: "OK", 1: "NOT_CONVERGED", -1: "INVALID_ARGUMENT", -4: "NOT_SPD", -5: "DEGENERATE"}
 
@@ -39,12 +39,13 @@ class Options(ctypes.Structure):
                 ("nu_pre", ctypes.c_int32), ("nu_post", ctypes.c_int32),
                 ("shift_coarse_points", ctypes.c_int32), ("sample_order", ctypes.c_int32),
                 ("seed", ctypes.c_uint64), ("weighting", ctypes.c_int32), ("fallback_on_vertex", ctypes.c_int32),
-                ("color_passes", ctypes.c_int32)]
+                ("color_passes", ctypes.c_int32), ("block_min_rows", ctypes.c_int32)]
 
 
 def default_options(**kw):
     o = Options(ctypes.sizeof(Options), 1.0 / 8.0, 1000, 32, 2, 2, 1, 0, 0)
     o.color_passes = 3
+    o.block_min_rows = 4096
     for k, v in kw.items():
         setattr(o, k, v)
     return o
@@ -125,12 +126,12 @@ class Hierarchy:
         return lib().orc_num_levels(self._h)
 
     def sizes(self, l):
-        s = np.zeros(8, dtype=np.int64)
+        s = np.zeros(9, dtype=np.int64)
         st = lib().orc_level_sizes(self._h, l, _ptr(s))
         if st != 0:
             raise OracleError(st)
         return dict(n=int(s[0]), m=int(s[1]), nnzA=int(s[2]), nnzP=int(s[3]), colors=int(s[4]),
-                    fallback=int(s[5]), samples=int(s[6]), nnzE=int(s[7]))
+                    fallback=int(s[5]), samples=int(s[6]), nnzE=int(s[7]), blocks=int(s[8]))
 
     def export(self, l, what):
         s = self.sizes(l)
@@ -148,7 +149,7 @@ class Hierarchy:
             A_ROWPTR: ((n + 1,), np.int32), A_COL: ((s["nnzA"],), np.int32),
             A_VAL: ((s["nnzA"],), np.float64),
             COLORS: ((n if s["colors"] else 0,), np.int32), CHOL: ((n, n), np.float64),
-            CINV: ((n, n), np.float64),
+            CINV: ((n, n), np.float64), BLOCK_COLORS: ((n if s["blocks"] else 0,), np.int32),
         }[what]
         out = np.zeros(shape, dtype=dt)
         st = lib().orc_export(self._h, l, what, _ptr(out), out.nbytes)
@@ -163,7 +164,7 @@ class Hierarchy:
                            ("scalars", SCALARS), ("samples", SAMPLES), ("labels", LABELS),
                            ("dist", DIST), ("pcol", P_COL), ("pval", P_VAL), ("pcnt", P_CNT),
                            ("tri", TRI), ("arp", A_ROWPTR), ("acol", A_COL), ("aval", A_VAL),
-                           ("colors", COLORS)]:
+                           ("colors", COLORS), ("block_colors", BLOCK_COLORS)]:
             d[name] = self.export(l, code)
         return d
 

@@ -55,6 +55,7 @@ struct Options {                 // field order mirrors the public options struc
   int32_t weighting;             // 0 barycentric (Sec. 4.4), 1 uniform, 2 inverse distance (Sec. 5.3)
   int32_t fallback_on_vertex;    // 1: a best projection onto a triangle vertex uses the fallback
   int32_t color_passes;          // iterated-greedy passes after the first colouring (default 3)
+  int32_t block_min_rows;        // levels 1.. above this many points sweep in block order (4096)
 };
 
 enum Status { OK = 0, NOT_CONVERGED = 1, INVALID_ARGUMENT = -1, NOT_SPD = -4, DEGENERATE = -5 };
@@ -79,11 +80,14 @@ enum What {
   W_COLORS = 15,     // int32[n]
   W_CHOL = 16,       // double[n*n] row-major lower Cholesky factor (coarsest level only)
   W_CINV = 17,       // double[n*n] coarsest inverse by columns: [k*n + i] = (A^-1 e_k)_i
+  W_BLOCK_COLORS = 18, // int32[n] block colour 0..3 of each row (levels swept in block order; else empty)
 };
 
 constexpr double kDegenerateTau = 1e-12;   // sin^2 of the smallest accepted triangle angle
 constexpr int64_t kMaxDenseCoarse = 4096;  // largest coarsest level factored densely
 constexpr uint64_t kColorSalt = 0xC2B2AE3D27D4EB4FULL;
+constexpr double kBlockMargin = 1.0 + 1.0 / (1 << 20);   // cell side over the largest coupling distance
+constexpr int64_t kMaxGridCells = int64_t(1) << 22;       // grids with more cells keep the colour order
 
 // SplitMix64 finaliser (Steele, Lea & Flood 2014): a bijective 64-bit mixer.
 uint64_t mix64(uint64_t z) {
@@ -115,7 +119,8 @@ struct Level {
   std::vector<double> aval, adiag;
   std::vector<int32_t> color;
   int32_t ncolors = 0;
-  std::vector<int32_t> color_rows;              // rows sorted by (colour, index)
+  std::vector<int32_t> block_color;             // grid-cell parity class 0..3 per row (block order), or empty
+  std::vector<int32_t> color_rows;              // rows in sweep order: (block colour, colour, index)
   std::vector<int32_t> color_ptr;               // colour c rows: color_rows[color_ptr[c] .. color_ptr[c+1])
 };
 
@@ -592,12 +597,69 @@ void colouring(Level& lv, int level, const Options& o) {
     lv.color.swap(next);
     lv.ncolors = nc;
   }
-  lv.color_ptr.assign(lv.ncolors + 1, 0);
-  for (int64_t v = 0; v < n; ++v) lv.color_ptr[lv.color[v] + 1] += 1;
-  for (int32_t c = 0; c < lv.ncolors; ++c) lv.color_ptr[c + 1] += lv.color_ptr[c];
+}
+
+// Block order of the sweeps on a level (a reading: the paper leaves the
+// Gauss-Seidel order open).  The level's points are projected onto the two
+// coordinate axes of largest extent (the axis of smallest extent is dropped,
+// the first on ties) and binned into square cells whose side is slightly more
+// than w, the largest distance along either kept axis between two points
+// coupled by A_l.  Two coupled points then lie in the same cell or in
+// neighbouring ones (sharing a side or a corner), so cells of equal parity
+// (cx mod 2, cy mod 2) are never coupled: the four parity classes, the block
+// colours, are swept one after the other, all cells of a class at once and
+// within a cell the colours in ascending order.  Without couplings (w = 0),
+// or with more than kMaxGridCells cells, the level keeps the colour order.
+void block_order(Level& lv) {
+  const int64_t n = lv.n;
+  lv.block_color.clear();
+  double lo[3], hi[3], ext[3];
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = lv.X[a];
+    hi[a] = lv.X[a];
+    for (int64_t i = 1; i < n; ++i) {
+      lo[a] = std::min(lo[a], lv.X[3 * i + a]);
+      hi[a] = std::max(hi[a], lv.X[3 * i + a]);
+    }
+    ext[a] = hi[a] - lo[a];
+  }
+  int drop = 0;
+  for (int a = 1; a < 3; ++a)
+    if (ext[a] < ext[drop]) drop = a;
+  const int a0 = drop == 0 ? 1 : 0, a1 = drop == 2 ? 1 : 2;
+  double w = 0.0;
+  for (int64_t i = 0; i < n; ++i)
+    for (int32_t e = lv.arp[i]; e < lv.arp[i + 1]; ++e) {
+      const int64_t j = lv.acol[e];
+      if (j == i) continue;
+      w = std::max(w, std::fabs(lv.X[3 * j + a0] - lv.X[3 * i + a0]));
+      w = std::max(w, std::fabs(lv.X[3 * j + a1] - lv.X[3 * i + a1]));
+    }
+  if (!(w > 0.0)) return;
+  const double side = w * kBlockMargin;
+  const int64_t ncx = (int64_t)std::floor(ext[a0] / side) + 1, ncy = (int64_t)std::floor(ext[a1] / side) + 1;
+  if (ncx * ncy > kMaxGridCells) return;
+  lv.block_color.assign(n, 0);
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t cx = (int64_t)std::floor((lv.X[3 * i + a0] - lo[a0]) / side);
+    const int64_t cy = (int64_t)std::floor((lv.X[3 * i + a1] - lo[a1]) / side);
+    lv.block_color[i] = (int32_t)((cx & 1) + 2 * (cy & 1));
+  }
+}
+
+// The rows in sweep order, sorted by (block colour, colour, index); rows of
+// one (block colour, colour) class are never coupled.
+void sweep_order(Level& lv) {
+  const int64_t n = lv.n;
+  const int32_t C = lv.ncolors;
+  const int32_t K = lv.block_color.empty() ? C : 4 * C;
+  auto key = [&](int64_t v) { return (lv.block_color.empty() ? 0 : lv.block_color[v] * C) + lv.color[v]; };
+  lv.color_ptr.assign(K + 1, 0);
+  for (int64_t v = 0; v < n; ++v) lv.color_ptr[key(v) + 1] += 1;
+  for (int32_t c = 0; c < K; ++c) lv.color_ptr[c + 1] += lv.color_ptr[c];
   lv.color_rows.assign(n, 0);
   std::vector<int32_t> fill(lv.color_ptr.begin(), lv.color_ptr.end() - 1);
-  for (int64_t v = 0; v < n; ++v) lv.color_rows[fill[lv.color[v]]++] = (int32_t)v;
+  for (int64_t v = 0; v < n; ++v) lv.color_rows[fill[key(v)]++] = (int32_t)v;
 }
 
 // ---------------------------------------------------------------- coarsest level (Alg. 2)
@@ -821,7 +883,7 @@ int check_options(const Options& o) {
   if (o.min_coarse_points < 1 || o.max_levels < 1 || o.nu_pre < 0 || o.nu_post < 0) return INVALID_ARGUMENT;
   if (o.sample_order != 0 && o.sample_order != 1) return INVALID_ARGUMENT;
   if (o.weighting < 0 || o.weighting > 2 || (o.fallback_on_vertex != 0 && o.fallback_on_vertex != 1) ||
-      o.color_passes < 0 || o.color_passes > 64)
+      o.color_passes < 0 || o.color_passes > 64 || o.block_min_rows < 0)
     return INVALID_ARGUMENT;
   return OK;
 }
@@ -871,7 +933,11 @@ int orc_build(int64_t n, const double* pts, int64_t m, const int32_t* edges, con
   last.label.clear();
   last.dist.clear();
   if (last.n > kMaxDenseCoarse) { delete h; return DEGENERATE; }
-  for (size_t l = 0; l + 1 < h->L.size(); ++l) colouring(h->L[l], (int)l, o);
+  for (size_t l = 0; l + 1 < h->L.size(); ++l) {
+    colouring(h->L[l], (int)l, o);
+    if (l >= 1 && h->L[l].n > o.block_min_rows) block_order(h->L[l]);
+    sweep_order(h->L[l]);
+  }
   st = cholesky(last, h->chol);
   if (st != OK) { delete h; return st; }
   coarse_inverse(h->chol, last.n, h->cinv);
@@ -883,7 +949,8 @@ void orc_free(void* hp) { delete static_cast<Hier*>(hp); }
 
 int orc_num_levels(void* hp) { return hp ? (int)static_cast<Hier*>(hp)->L.size() : 0; }
 
-// sizes[0..7]: n, undirected edges, nnz(A), nnz(P), colours, fallback rows, samples, nnz(E CSR)
+// sizes[0..8]: n, undirected edges, nnz(A), nnz(P), colours, fallback rows, samples, nnz(E CSR),
+// 1 if the level sweeps in block order
 int orc_level_sizes(void* hp, int32_t l, int64_t* sizes) {
   Hier* h = static_cast<Hier*>(hp);
   if (!h || l < 0 || l >= (int32_t)h->L.size()) return INVALID_ARGUMENT;
@@ -898,6 +965,7 @@ int orc_level_sizes(void* hp, int32_t l, int64_t* sizes) {
   sizes[5] = lv.fallback;
   sizes[6] = (int64_t)lv.samples.size();
   sizes[7] = (int64_t)lv.ecol.size();
+  sizes[8] = lv.block_color.empty() ? 0 : 1;
   return OK;
 }
 
@@ -928,6 +996,7 @@ int orc_export(void* hp, int32_t l, int32_t what, void* dst, int64_t bytes) {
     case W_CHOL:
       if (l + 1 != (int32_t)h->L.size()) return INVALID_ARGUMENT;
       src = h->chol.data(); nb = 8 * (int64_t)h->chol.size(); break;
+    case W_BLOCK_COLORS: src = lv.block_color.data(); nb = 4 * (int64_t)lv.block_color.size(); break;
     case W_CINV:
       if (l + 1 != (int32_t)h->L.size()) return INVALID_ARGUMENT;
       src = h->cinv.data(); nb = 8 * (int64_t)h->cinv.size(); break;

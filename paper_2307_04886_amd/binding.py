@@ -23,7 +23,7 @@ EXPORTS = {
     "labels": (6, np.int32), "dist": (7, np.float64), "p_col": (8, np.int32), "p_val": (9, np.float64),
     "p_cnt": (10, np.int32), "tri": (11, np.int32), "a_rowptr": (12, np.int32), "a_col": (13, np.int32),
     "a_val": (14, np.float64), "colors": (15, np.int32), "chol": (16, np.float64),
-    "coarse_inverse": (17, np.float64),
+    "coarse_inverse": (17, np.float64), "block_colors": (18, np.int32),
 }
 
 # Symbols the library exports (checked on load).
@@ -44,7 +44,7 @@ class Options(ctypes.Structure):
                 ("nu_pre", ctypes.c_int32), ("nu_post", ctypes.c_int32),
                 ("shift_coarse_points", ctypes.c_int32), ("sample_order", ctypes.c_int32),
                 ("seed", ctypes.c_uint64), ("weighting", ctypes.c_int32), ("fallback_on_vertex", ctypes.c_int32),
-                ("color_passes", ctypes.c_int32)]
+                ("color_passes", ctypes.c_int32), ("block_min_rows", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -173,12 +173,12 @@ class Hierarchy:
         return v.value
 
     def sizes(self, level):
-        s = np.zeros(8, dtype=np.int64)
+        s = np.zeros(9, dtype=np.int64)
         st = library().gmg_level_sizes(self._h, level, s.ctypes.data_as(ctypes.c_void_p))
         if st:
             raise _err(st)
         return dict(n=int(s[0]), m=int(s[1]), nnzA=int(s[2]), nnzP=int(s[3]), colors=int(s[4]),
-                    fallback=int(s[5]), samples=int(s[6]), nnzE=int(s[7]))
+                    fallback=int(s[5]), samples=int(s[6]), nnzE=int(s[7]), blocks=int(s[8]))
 
     def export(self, level, what):
         code, dt = EXPORTS[what]
@@ -189,7 +189,7 @@ class Hierarchy:
             "edge_w": s["nnzE"], "scalars": 2, "samples": s["samples"], "labels": has, "dist": has,
             "p_col": 3 * has, "p_val": 3 * has, "p_cnt": has, "tri": 2 * has, "a_rowptr": n + 1,
             "a_col": s["nnzA"], "a_val": s["nnzA"], "colors": n if s["colors"] else 0, "chol": n * n,
-            "coarse_inverse": n * n,
+            "coarse_inverse": n * n, "block_colors": n if s["blocks"] else 0,
         }[what]
         out = np.zeros(count, dtype=dt)
         st = library().gmg_export_level(self._h, level, code, out.ctypes.data_as(ctypes.c_void_p),

@@ -304,7 +304,8 @@ bool options_ok(const gmg_options& o) {
   return o.struct_size == (int32_t)sizeof(gmg_options) && o.coarsening_ratio > 0.0 &&
          o.coarsening_ratio < 1.0 && o.min_coarse_points >= 1 && o.max_levels >= 1 && o.nu_pre >= 0 &&
          o.nu_post >= 0 && (o.sample_order == 0 || o.sample_order == 1) && o.weighting >= 0 && o.weighting <= 2 &&
-         (o.fallback_on_vertex == 0 || o.fallback_on_vertex == 1) && o.color_passes >= 0 && o.color_passes <= 64;
+         (o.fallback_on_vertex == 0 || o.fallback_on_vertex == 1) && o.color_passes >= 0 && o.color_passes <= 64 &&
+         o.block_min_rows >= 0;
 }
 
 // The single-workgroup tail of a cycle: levels tail_start.. with their views
@@ -446,6 +447,7 @@ void build(Handle& h, int64_t n, const double* points, int64_t m, const int32_t*
   const int nl = (int)h.L.size();
   for (int l = 0; l + 1 < nl; ++l) {
     colouring(h, h.L[l], l);
+    if (l >= 1 && h.L[l].n > o.block_min_rows) block_order(h, h.L[l]);
     mark("colouring", l);
   }
   solve_layout(h, h.L[nl - 1], nullptr, nullptr, nullptr, nullptr);
@@ -666,6 +668,8 @@ void kry_prepare(Handle& h, Cycle<float>& c) {
       f.T = {d.T.ptr, d.T.col, to_f32_copy(h, d.T.val, lv.t_slots, s), d.T.len};
       f.diag = to_f32_copy(h, d.diag, d.n, s);
       f.q_val = to_f32_copy(h, d.q_val, (int64_t)3 * d.n, s);
+      if (d.B.nblk > 0)                      // block sweep: same layout, float values
+        f.B = d.B.with_values(to_f32_copy(h, d.B.elv, lv.blk_entries, s));
       if (d.e_cinfo) {                       // a tail level
         f.e_cinfo = d.e_cinfo;
         f.e_col_gs = d.e_col_gs;
@@ -1118,6 +1122,7 @@ int gmg_default_options(gmg_options* o) {
   o->sample_order = 0;
   o->seed = 0;
   o->color_passes = 3;
+  o->block_min_rows = 4096;
   return GMG_OK;
 }
 
@@ -1346,7 +1351,10 @@ int gmg_update_matrix(gmg_handle hh, const double* A_val_dev, void* stream) {
     validate_matrix(l0.arp, l0.acol, A_val_dev, l0.n, l0.nnzA, h->flags, s);
     check_hip(hipMemcpyAsync(l0.aval, A_val_dev, (size_t)l0.nnzA * 8, hipMemcpyDeviceToDevice, s), "copy values");
     for (int l = 0; l + 1 < nl; ++l) galerkin_values(*h, h->L[l], h->L[l + 1]);
-    for (int l = 0; l < nl; ++l) refresh_values(*h, h->L[l]);
+    for (int l = 0; l < nl; ++l) {
+      refresh_values(*h, h->L[l]);
+      block_values(*h, h->L[l]);
+    }
     for (int l = ell_first_level(*h); l + 1 < nl; ++l) ell_values(*h, h->L[l]);
     coarse_factor(*h, h->L[nl - 1]);                 // also raises the flags of the steps above
     if (h->kry.ready[1])
@@ -1355,6 +1363,7 @@ int gmg_update_matrix(gmg_handle hh, const double* A_val_dev, void* stream) {
         LevelViewT<float>& f = h->kry.c32.v[l];
         to_f32(d.A.val, (float*)f.A.val, h->L[l].a_slots, s);
         to_f32(d.diag, (float*)f.diag, d.n, s);
+        if (d.B.nblk > 0) to_f32(d.B.elv, (float*)f.B.elv, h->L[l].blk_entries, s);
         if (d.e_cinfo) {
           to_f32(d.e_val_gs, (float*)f.e_val_gs, h->L[l].e_slots, s);
           to_f32(d.e_val, (float*)f.e_val, h->L[l].e_slots, s);
@@ -1547,6 +1556,7 @@ int gmg_level_sizes(gmg_handle h, int32_t l, int64_t* sz) {
   sz[5] = lv.nc ? lv.fallback : 0;
   sz[6] = lv.nc;
   sz[7] = lv.nnzE;
+  sz[8] = lv.bcolor ? 1 : 0;
   return GMG_OK;
 }
 
@@ -1575,6 +1585,7 @@ int gmg_export_level(gmg_handle h, int32_t l, int32_t what, void* dst, int64_t b
     case GMG_EXPORT_A_COL: src = lv.acol; nb = 4 * lv.nnzA; break;
     case GMG_EXPORT_A_VAL: src = lv.aval; nb = 8 * lv.nnzA; break;
     case GMG_EXPORT_COLORS: src = lv.color; nb = lv.color ? 4 * n : 0; break;
+    case GMG_EXPORT_BLOCK_COLORS: src = lv.bcolor; nb = lv.bcolor ? 4 * n : 0; break;
     case GMG_EXPORT_CHOL:
       if (!coarse) return GMG_INVALID_ARGUMENT;
       src = h->chol; nb = 8 * n * n; break;

@@ -125,6 +125,63 @@ struct Sell {
 };
 using SellView = Sell<double>;
 
+// Block layout of a level swept in block order (gmg_options.block_min_rows):
+// blocks are the occupied grid cells, numbered block colour by block colour.
+// Block b has rows brows[boff[b] .. boff[b+1]) (solve numbering, ascending,
+// so grouped by colour), its local rows of colour c start at
+// bcls[b (C + 1) + c], its halo (rows of other blocks that its rows read) is
+// hlist[hoff[b] .. hoff[b+1]), and entry t of its local row p, in the row's
+// entry order, is at beoff[b] + t rows_b + p: elx the LDS slot of the column
+// (local row, rows_b + halo position, or the zero slot rows_b + halo_b for
+// the diagonal and padding up to the block's width bw[b]) and elv its value
+// (0 for the diagonal and padding).  rinfo packs each local row's length and
+// colour, bmask the colours present in each block.
+constexpr int kBlkThreads = 256;     // threads of a block-sweep workgroup
+constexpr int kBlkMaxColors = 64;    // colours a block sweep handles
+template <class V>
+struct BlockView {
+  int32_t nblk = 0;                     // 0: no block sweep (the colour classes are launched one by one)
+  int32_t bstart[5] = {};               // blocks of block colour k: [bstart[k], bstart[k + 1])
+  int32_t ncls = 0;                     // colours C of the level
+  int32_t rows_per_thread = 1, width = 32;   // kernel shape: local rows per thread, register entries per row
+  int32_t lds_bytes = 0;                // (largest block + largest halo + 1) values
+  const int32_t* boff = nullptr;
+  const int32_t* brows = nullptr;
+  const int32_t* bcls = nullptr;
+  const int32_t* hoff = nullptr;
+  const int32_t* hlist = nullptr;
+  const int32_t* bw = nullptr;
+  const int32_t* beoff = nullptr;
+  const int32_t* elx = nullptr;
+  const V* elv = nullptr;
+  const int32_t* rinfo = nullptr;       // per local row (boff order): row length << 8 | colour
+  const uint64_t* bmask = nullptr;      // [nblk] colours with rows in the block
+
+  // The same layout with values of another type (the float cycle's copy).
+  template <class W>
+  BlockView<W> with_values(const W* values) const {
+    BlockView<W> o;
+    o.nblk = nblk;
+    for (int k = 0; k < 5; ++k) o.bstart[k] = bstart[k];
+    o.ncls = ncls;
+    o.rows_per_thread = rows_per_thread;
+    o.width = width;
+    o.lds_bytes = lds_bytes;
+    o.boff = boff;
+    o.brows = brows;
+    o.bcls = bcls;
+    o.hoff = hoff;
+    o.hlist = hlist;
+    o.bw = bw;
+    o.beoff = beoff;
+    o.elx = elx;
+    o.elv = values;
+    o.rinfo = rinfo;
+    o.bmask = bmask;
+    return o;
+  }
+};
+
 // What the V-cycle kernels need of one level (device pointers, new numbering),
 // with values and vectors in V (double; float for the mixed-precision cycle).
 template <class V>
@@ -161,6 +218,7 @@ struct LevelViewT {
   const V* e_tval = nullptr;
   int32_t e_wt = 0;
   int32_t e_slots = 0, e_tslots = 0;    // entries of the ELL arrays of A_l / P_l^T
+  BlockView<V> B;                       // block sweep of a level swept in block order
 };
 using LevelView = LevelViewT<double>;
 
@@ -249,6 +307,11 @@ struct Level {
   // Gauss-Seidel colouring
   int32_t* color = nullptr;
   int32_t ncolors = 0;
+  // block order (levels swept in block order): grid cell and its parity class per row
+  int32_t* bcolor = nullptr;            // [n] block colour 0..3, original numbering
+  int32_t* bcell = nullptr;             // [n] cell cy * gx + cx (until the solve layout is built)
+  int32_t gx = 0, gy = 0;               // grid cells along the two kept axes
+  int64_t blk_entries = 0;              // elements of the block ELL
   std::vector<int32_t> color_ptr;       // host: rows [color_ptr[c], color_ptr[c+1]) in new numbering
   std::vector<double> color_bytes;      // algorithmic bytes of one colour's sweep
   double residual_bytes = 0;            // algorithmic bytes of one residual
@@ -408,6 +471,8 @@ void galerkin_values(Handle& h, Level& lv, Level& nx);     // same pattern, valu
 
 // ------------------------------------------------------------------ launchers (setup_solve.hip)
 void colouring(Handle& h, Level& lv, int level);
+void block_order(Handle& h, Level& lv);                     // grid cells and block colours of a level
+void block_values(Handle& h, Level& lv);                    // block ELL values from the current A_l
 void solve_layout(Handle& h, Level& lv, const Level* nx, const int32_t* t_rp, const int32_t* t_col,
                   const double* t_val);
 void coarse_factor(Handle& h, Level& lv);

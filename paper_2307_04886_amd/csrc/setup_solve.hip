@@ -3,6 +3,7 @@
 // rows), and the dense factorisation of the coarsest operator (Alg. 2 solves
 // the coarsest level directly).
 #include <algorithm>
+#include <cstring>
 
 #include "gmg_internal.hpp"
 
@@ -722,6 +723,359 @@ __global__ void k_tail_ell_t(SellView T, int64_t nc, int32_t w, int64_t n, int32
   }
 }
 
+
+// ------------------------------------------------------------------ block order
+// Order-preserving 64-bit key of a double (a larger double gets a larger
+// key), so that minima and maxima are exact integer atomics.
+__device__ __forceinline__ unsigned long long ordered_key(double v) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  return (u >> 63) ? ~u : (u | (1ull << 63));
+}
+
+__global__ void k_grid_keys_init(unsigned long long* keys) {
+  const int i = threadIdx.x;
+  if (i < 9) keys[i] = i < 3 ? ~0ull : 0ull;
+}
+
+// keys[0..2]: minima and keys[3..5]: maxima of the three coordinates (ordered
+// keys); keys[6..8]: largest |X_j,a - X_i,a| over the stored off-diagonal
+// entries (i, j) of A_l, per axis a (non-negative doubles, whose bit patterns
+// order as integers).
+__global__ void __launch_bounds__(kBlock) k_grid_extents(const double* __restrict__ X, const int32_t* __restrict__ rp,
+                                                         const int32_t* __restrict__ col, int64_t n,
+                                                         unsigned long long* keys) {
+  unsigned long long mn[3] = {~0ull, ~0ull, ~0ull}, mx[3] = {0, 0, 0}, dm[3] = {0, 0, 0};
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+    const double xi[3] = {X[3 * i], X[3 * i + 1], X[3 * i + 2]};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const unsigned long long k = ordered_key(xi[a]);
+      mn[a] = k < mn[a] ? k : mn[a];
+      mx[a] = k > mx[a] ? k : mx[a];
+    }
+    for (int32_t e = rp[i]; e < rp[i + 1]; ++e) {
+      const int64_t j = col[e];
+      if (j == i) continue;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const unsigned long long d = __builtin_bit_cast(unsigned long long, fabs(X[3 * j + a] - xi[a]));
+        dm[a] = d > dm[a] ? d : dm[a];
+      }
+    }
+  }
+  auto lo = [](unsigned long long u, unsigned long long v) { return u < v ? u : v; };
+  auto hi = [](unsigned long long u, unsigned long long v) { return u > v ? u : v; };
+  unsigned long long r[9];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    r[a] = block_reduce(mn[a], lo);
+    __syncthreads();
+    r[3 + a] = block_reduce(mx[a], hi);
+    __syncthreads();
+    r[6 + a] = block_reduce(dm[a], hi);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      atomicMin(&keys[a], r[a]);
+      atomicMax(&keys[3 + a], r[3 + a]);
+      atomicMax(&keys[6 + a], r[6 + a]);
+    }
+  }
+}
+
+// Grid cell (cy gx + cx) and block colour (cx mod 2) + 2 (cy mod 2) of every point.
+__global__ void k_grid_cells(const double* __restrict__ X, int64_t n, int a0, int a1, double lo0, double lo1,
+                             double side, int32_t gx, int32_t* bcolor, int32_t* bcell) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t cx = (int64_t)floor((X[3 * i + a0] - lo0) / side);
+  const int64_t cy = (int64_t)floor((X[3 * i + a1] - lo1) / side);
+  bcolor[i] = (int32_t)((cx & 1) + 2 * (cy & 1));
+  bcell[i] = (int32_t)(cy * gx + cx);
+}
+
+// Sweep class of a row: block colour, then colour.
+__global__ void k_sweep_class(const int32_t* bcolor, const int32_t* color, int64_t n, int32_t C, int32_t* cls) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) cls[i] = bcolor[i] * C + color[i];
+}
+
+__global__ void k_count_cells(const int32_t* bcell, int64_t n, int32_t* cnt) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) atomicAdd(&cnt[bcell[i]], 1);
+}
+
+// Occupied cells enumerated block colour by block colour: slot v of
+// [0, 4 H), H = hx hy, is cell (2 (v mod H mod hx) + (k & 1), 2 (v mod H div hx) + (k >> 1))
+// of block colour k = v div H.
+__device__ __forceinline__ int32_t grid_cell_of(int64_t v, int64_t H, int32_t hx, int32_t gx, int32_t gy) {
+  const int32_t k = (int32_t)(v / H);
+  const int64_t u = v % H;
+  const int32_t cx = 2 * (int32_t)(u % hx) + (k & 1), cy = 2 * (int32_t)(u / hx) + (k >> 1);
+  return cx < gx && cy < gy ? cy * gx + cx : -1;
+}
+
+__global__ void k_cell_flags(const int32_t* cnt, int64_t H, int32_t hx, int32_t gx, int32_t gy, int32_t* flag) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= 4 * H) return;
+  const int32_t c = grid_cell_of(v, H, hx, gx, gy);
+  flag[v] = c >= 0 && cnt[c] > 0 ? 1 : 0;
+}
+
+// Block (compact id) of every solve row.
+__global__ void k_row_block(const int32_t* perm, const int32_t* bcell, int64_t n, const int32_t* vid, int64_t H,
+                            int32_t hx, int32_t gx, int32_t* blk) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  const int32_t c = bcell[perm[g]];
+  const int32_t cx = c % gx, cy = c / gx;
+  const int32_t k = (cx & 1) + 2 * (cy & 1);
+  blk[g] = vid[(int64_t)k * H + (int64_t)(cy >> 1) * hx + (cx >> 1)];
+}
+
+// First local row of every colour c = 0..C in every block (rows of a block are
+// ascending solve rows, so ascending colours).
+__global__ void k_block_cls(const int32_t* boff, const int32_t* brows, const int32_t* perm, const int32_t* color,
+                            int32_t nblk, int32_t C, int32_t* bcls) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)nblk * (C + 1)) return;
+  const int32_t b = (int32_t)(t / (C + 1)), c = (int32_t)(t % (C + 1));
+  int32_t lo = boff[b], hi = boff[b + 1];
+  const int32_t base = lo;
+  while (lo < hi) {
+    const int32_t mid = (lo + hi) >> 1;
+    if (color[perm[brows[mid]]] < c) lo = mid + 1; else hi = mid;
+  }
+  bcls[t] = lo - base;
+}
+
+// Per local row: its length (entries of A_l, diagonal included) and colour,
+// packed as len << 8 | colour; per block: the mask of its colours.
+__global__ void k_block_rowinfo(const int32_t* rp, const int32_t* perm, const int32_t* color, const int32_t* brows,
+                                int64_t n, int32_t* rinfo) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int32_t o = perm[brows[k]];
+  rinfo[k] = ((rp[o + 1] - rp[o]) << 8) | color[o];
+}
+
+__global__ void k_block_mask(const int32_t* bcls, int32_t nblk, int32_t C, uint64_t* bmask) {
+  const int32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nblk) return;
+  uint64_t m = 0;
+  for (int32_t c = 0; c < C; ++c)
+    if (bcls[(int64_t)b * (C + 1) + c] < bcls[(int64_t)b * (C + 1) + c + 1]) m |= uint64_t(1) << c;
+  bmask[b] = m;
+}
+
+// Largest row (entries of A_l, diagonal included) of every block.
+__global__ void k_block_width(const int32_t* rp, const int32_t* perm, const int32_t* blk, int64_t n, int32_t* bw) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  const int32_t o = perm[g];
+  atomicMax(&bw[blk[g]], rp[o + 1] - rp[o]);
+}
+
+__global__ void k_block_cells(const int32_t* boff, const int32_t* bw, int32_t nblk, int32_t* sz) {
+  const int32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < nblk) sz[b] = bw[b] * (boff[b + 1] - boff[b]);
+}
+
+// The halo of every block, one workgroup per block: the rows of other blocks
+// that its rows read, collected in LDS, sorted (bitonic) and kept once each,
+// written at the block's slot base tmp + tcap[b] (capacity: its entries);
+// hcnt[b] receives their number.  A coupling to another block of the same
+// block colour (which the grid excludes), or more than kHaloSort collected
+// entries, raises *bad.
+constexpr int kHaloSort = 4096;
+__global__ void __launch_bounds__(kBlock) k_block_halo(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                                       const int32_t* __restrict__ perm,
+                                                       const int32_t* __restrict__ iperm,
+                                                       const int32_t* __restrict__ blk,
+                                                       const int32_t* __restrict__ bcolor,
+                                                       const int32_t* __restrict__ boff,
+                                                       const int32_t* __restrict__ brows, int32_t* tmp,
+                                                       const int32_t* __restrict__ tcap, int32_t* hcnt, int32_t* bad) {
+  __shared__ int32_t a[kHaloSort];
+  __shared__ int32_t part[kBlock + 1];
+  __shared__ int32_t na;
+  const int32_t b = blockIdx.x;
+  const int32_t r0 = boff[b], rows = boff[b + 1] - r0;
+  if (threadIdx.x == 0) na = 0;
+  __syncthreads();
+  for (int32_t p = threadIdx.x; p < rows; p += kBlock) {
+    const int32_t g = brows[r0 + p], o = perm[g];
+    for (int32_t e = rp[o]; e < rp[o + 1]; ++e) {
+      const int32_t oc = col[e];
+      if (oc == o) continue;
+      const int32_t j = iperm[oc];
+      if (blk[j] == b) continue;
+      if (bcolor[oc] == bcolor[o]) atomicOr(bad, 1);
+      const int32_t k = atomicAdd(&na, 1);
+      if (k < kHaloSort) a[k] = j;
+    }
+  }
+  __syncthreads();
+  const int32_t len = na;
+  if (len > kHaloSort) {
+    if (threadIdx.x == 0) {
+      atomicOr(bad, 2);
+      hcnt[b] = 0;
+    }
+    return;
+  }
+  int32_t P = 1;
+  while (P < len) P <<= 1;
+  for (int32_t i = len + threadIdx.x; i < P; i += kBlock) a[i] = INT32_MAX;
+  __syncthreads();
+  for (int32_t k = 2; k <= P; k <<= 1)
+    for (int32_t j = k >> 1; j > 0; j >>= 1) {
+      for (int32_t i = threadIdx.x; i < P; i += kBlock) {
+        const int32_t l = i ^ j;
+        if (l > i) {
+          const bool up = (i & k) == 0;
+          const int32_t x = a[i], y = a[l];
+          if ((x > y) == up) {
+            a[i] = y;
+            a[l] = x;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  // distinct values: each thread counts the first occurrences in its chunk
+  const int32_t chunk = (len + kBlock - 1) / kBlock;
+  const int32_t c0 = threadIdx.x * chunk, c1 = min(len, c0 + chunk);
+  int32_t cnt = 0;
+  for (int32_t i = c0; i < c1; ++i) cnt += (i == 0 || a[i] != a[i - 1]) ? 1 : 0;
+  part[threadIdx.x + 1] = cnt;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    part[0] = 0;
+    for (int t = 1; t <= kBlock; ++t) part[t] += part[t - 1];
+    hcnt[b] = part[kBlock];
+  }
+  __syncthreads();
+  int32_t w = tcap[b] + part[threadIdx.x];
+  for (int32_t i = c0; i < c1; ++i)
+    if (i == 0 || a[i] != a[i - 1]) tmp[w++] = a[i];
+}
+
+// Entries of A_l (diagonal included) in the rows of every block: the halo's capacity.
+__global__ void k_block_entries(const int32_t* rp, const int32_t* perm, const int32_t* brows, const int32_t* boff,
+                                int32_t nblk, int32_t* cap) {
+  const int32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nblk) return;
+  int32_t s = 0;
+  for (int32_t k = boff[b]; k < boff[b + 1]; ++k) {
+    const int32_t o = perm[brows[k]];
+    s += rp[o + 1] - rp[o];
+  }
+  cap[b] = s;
+}
+
+// The block ELL, one workgroup per block (its halo in LDS): entry t of local
+// row p of block b at beoff[b] + t rows_b + p; the LDS slot of its column
+// (own row: its local row; another block's row: rows_b + its position in the
+// block's halo) and its value; the diagonal and the padding up to the block's
+// width point at the zero slot rows_b + halo_b with value 0.
+__global__ void __launch_bounds__(kBlock) k_block_ell(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                                      const double* __restrict__ val, const int32_t* __restrict__ perm,
+                                                      const int32_t* __restrict__ iperm,
+                                                      const int32_t* __restrict__ blk,
+                                                      const int32_t* __restrict__ lpos,
+                                                      const int32_t* __restrict__ boff,
+                                                      const int32_t* __restrict__ brows,
+                                                      const int32_t* __restrict__ hoff,
+                                                      const int32_t* __restrict__ hlist,
+                                                      const int32_t* __restrict__ bw,
+                                                      const int32_t* __restrict__ beoff, int32_t* elx, double* elv) {
+  __shared__ int32_t hl[kHaloSort];
+  const int32_t b = blockIdx.x;
+  const int32_t r0 = boff[b], rows = boff[b + 1] - r0;
+  const int32_t h0 = hoff[b], nh = hoff[b + 1] - h0;
+  for (int32_t k = threadIdx.x; k < nh; k += kBlock) hl[k] = hlist[h0 + k];
+  __syncthreads();
+  const int32_t pad = rows + nh, w = bw[b], e0 = beoff[b];
+  for (int32_t p = threadIdx.x; p < rows; p += kBlock) {
+    const int32_t o = perm[brows[r0 + p]];
+    const int32_t len = rp[o + 1] - rp[o];
+    for (int32_t t = 0; t < w; ++t) {
+      int32_t slot = pad;
+      double v = 0.0;
+      if (t < len) {
+        const int32_t e = rp[o] + t, oc = col[e];
+        if (oc != o) {
+          const int32_t j = iperm[oc];
+          if (blk[j] == b) {
+            slot = lpos[j];
+          } else {
+            int32_t lo = 0, hi = nh;
+            while (lo < hi) {
+              const int32_t mid = (lo + hi) >> 1;
+              if (hl[mid] < j) lo = mid + 1; else hi = mid;
+            }
+            slot = rows + lo;
+          }
+          v = val[e];
+        }
+      }
+      elx[e0 + t * rows + p] = slot;
+      elv[e0 + t * rows + p] = v;
+    }
+  }
+}
+
+// Local row of every solve row: its position in the block's row list.
+__global__ void k_local_rows(const int32_t* bpos, const int32_t* blk, const int32_t* boff, int64_t n, int32_t* lpos) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g < n) lpos[g] = bpos[g] - boff[blk[g]];
+}
+
+// mx[0] = most rows, mx[1] = longest halo, mx[2] = widest ELL of any block.
+__global__ void __launch_bounds__(kBlock) k_block_maxima(const int32_t* boff, const int32_t* hoff, const int32_t* bw,
+                                                         int32_t nblk, int32_t* mx) {
+  int32_t r = 0, hl = 0, w = 0;
+  for (int32_t b = blockIdx.x * kBlock + threadIdx.x; b < nblk; b += gridDim.x * kBlock) {
+    r = max(r, boff[b + 1] - boff[b]);
+    hl = max(hl, hoff[b + 1] - hoff[b]);
+    w = max(w, bw[b]);
+  }
+  auto mxop = [](int32_t a, int32_t b) { return a > b ? a : b; };
+  r = block_reduce(r, mxop);
+  __syncthreads();
+  hl = block_reduce(hl, mxop);
+  __syncthreads();
+  w = block_reduce(w, mxop);
+  if (threadIdx.x == 0) {
+    atomicMax(&mx[0], r);
+    atomicMax(&mx[1], hl);
+    atomicMax(&mx[2], w);
+  }
+}
+
+constexpr int32_t kMaxBlocks = 8192;         // blocks of a level (the partition's LDS histogram)
+constexpr int64_t kBlkLdsMax = 64 * 1024;    // LDS of a block sweep (its rows, halo and zero slot)
+
+// New values of A_l into the block ELL (same slots).
+__global__ void k_block_values(const int32_t* rp, const int32_t* col, const double* val, const int32_t* perm,
+                               const int32_t* boff, const int32_t* brows, const int32_t* bw, const int32_t* beoff,
+                               int32_t nblk, double* elv) {
+  const int32_t b = blockIdx.x;
+  if (b >= nblk) return;
+  const int32_t r0 = boff[b], rows = boff[b + 1] - r0, w = bw[b], e0 = beoff[b];
+  for (int32_t p = threadIdx.x; p < rows; p += blockDim.x) {
+    const int32_t o = perm[brows[r0 + p]];
+    const int32_t len = rp[o + 1] - rp[o];
+    for (int32_t t = 0; t < w; ++t) {
+      double v = 0.0;
+      if (t < len && col[rp[o] + t] != o) v = val[rp[o] + t];
+      elv[e0 + t * rows + p] = v;
+    }
+  }
+}
 }  // namespace
 
 // Jones-Plassmann colouring takes tens of rounds on the Galerkin levels (about
@@ -804,6 +1158,193 @@ void colouring(Handle& h, Level& lv, int level) {
   tfree(s, ncol);
 }
 
+// ------------------------------------------------------------------ block order
+// The grid of a level swept in block order (gmg_options.block_min_rows): the
+// two coordinate axes of largest extent (the first smallest one dropped),
+// cells of side w (1 + 2^-20), w the longest coupling of A_l along those axes.
+// The host reads the extents and w, decides the grid, and the device assigns
+// every point its cell and block colour.  The level keeps the colour order
+// when it has no couplings or more than kMaxGridCells cells.
+constexpr double kBlockMargin = 1.0 + 1.0 / (1 << 20);
+constexpr int64_t kMaxGridCells = int64_t(1) << 22;
+
+void block_order(Handle& h, Level& lv) {
+  hipStream_t s = h.stream;
+  const int64_t n = lv.n;
+  unsigned long long* keys = (unsigned long long*)talloc(s, 9 * 8);
+  k_grid_keys_init<<<1, kWave, 0, s>>>(keys);
+  k_grid_extents<<<std::min(blocks_for(n), kReduceGrid), kBlock, 0, s>>>(lv.X, lv.arp, lv.acol, n, keys);
+  int64_t kv[9];
+  ScalarRead rd[9];
+  for (int i = 0; i < 9; ++i) rd[i] = {keys + i, 8, &kv[i]};
+  read_scalars(h, rd, 9);
+  tfree(s, keys);
+  auto from_key = [](int64_t k) {
+    const uint64_t u = (uint64_t)k;
+    const uint64_t b = (u >> 63) ? (u & ~(uint64_t(1) << 63)) : ~u;
+    double d;
+    std::memcpy(&d, &b, 8);
+    return d;
+  };
+  double lo[3], ext[3], d[3];
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = from_key(kv[a]);
+    ext[a] = from_key(kv[3 + a]) - lo[a];
+    std::memcpy(&d[a], &kv[6 + a], 8);
+  }
+  int drop = 0;
+  for (int a = 1; a < 3; ++a)
+    if (ext[a] < ext[drop]) drop = a;
+  const int a0 = drop == 0 ? 1 : 0, a1 = drop == 2 ? 1 : 2;
+  const double w = std::max(d[a0], d[a1]);
+  if (!(w > 0.0)) return;
+  const double side = w * kBlockMargin;
+  const int64_t gx = (int64_t)std::floor(ext[a0] / side) + 1, gy = (int64_t)std::floor(ext[a1] / side) + 1;
+  if (gx * gy > kMaxGridCells) return;
+  lv.gx = (int32_t)gx;
+  lv.gy = (int32_t)gy;
+  lv.bcolor = (int32_t*)dalloc(h, (size_t)n * 4);
+  lv.bcell = (int32_t*)talloc(s, (size_t)n * 4);
+  k_grid_cells<<<blocks_for(n), kBlock, 0, s>>>(lv.X, n, a0, a1, lo[a0], lo[a1], side, lv.gx, lv.bcolor, lv.bcell);
+}
+
+namespace {
+
+// The block sweep's layout of a level swept in block order (its solve
+// numbering already sorted by (block colour, colour, index)).  The level keeps
+// the launches per sweep class when a block does not fit the block kernel.
+void block_layout(Handle& h, Level& lv, int32_t C) {
+  hipStream_t s = h.stream;
+  const int64_t n = lv.n;
+  const int64_t ncell = (int64_t)lv.gx * lv.gy;
+  const int32_t hx = (lv.gx + 1) / 2, hy = (lv.gy + 1) / 2;
+  const int64_t H = (int64_t)hx * hy;
+  int32_t* cnt = (int32_t*)talloc(s, (size_t)ncell * 4);
+  fill_i32(cnt, 0, ncell, s);
+  k_count_cells<<<blocks_for(n), kBlock, 0, s>>>(lv.bcell, n, cnt);
+  int32_t* flag = (int32_t*)talloc(s, (size_t)(4 * H + 1) * 4);
+  int32_t* vid = (int32_t*)talloc(s, (size_t)(4 * H + 1) * 4);
+  k_cell_flags<<<blocks_for(4 * H), kBlock, 0, s>>>(cnt, H, hx, lv.gx, lv.gy, flag);
+  scan_i32(flag, vid, 4 * H, s);
+  int64_t bs[5];
+  {
+    ScalarRead rd[5];
+    for (int k = 0; k < 5; ++k) rd[k] = {vid + (int64_t)k * H, 4, &bs[k]};
+    read_scalars(h, rd, 5);
+  }
+  const int32_t nblk = (int32_t)bs[4];
+  tfree(s, cnt);
+  tfree(s, flag);
+  BlockView<double>& B = lv.view.B;
+  B = BlockView<double>();
+  if (nblk <= 0 || nblk > kMaxBlocks || C > kBlkMaxColors) {
+    tfree(s, vid);
+    return;
+  }
+  // rows of every block, ascending (a stable partition of the solve rows by block)
+  int32_t* blk = (int32_t*)talloc(s, (size_t)n * 4);
+  k_row_block<<<blocks_for(n), kBlock, 0, s>>>(lv.perm, lv.bcell, n, vid, H, hx, lv.gx, blk);
+  tfree(s, vid);
+  const int nb = blocks_for(n);
+  int32_t* hist = (int32_t*)talloc(s, ((size_t)nblk * nb + 1) * 4);
+  int32_t* hoffs = (int32_t*)talloc(s, ((size_t)nblk * nb + 1) * 4);
+  int32_t* boff = (int32_t*)dalloc(h, (size_t)(nblk + 1) * 4);
+  int32_t* brows = (int32_t*)dalloc(h, (size_t)n * 4);
+  int32_t* bpos = (int32_t*)talloc(s, (size_t)n * 4);
+  k_color_hist<<<nb, kBlock, (size_t)nblk * 4, s>>>(blk, n, nb, nblk, hist);
+  scan_i32(hist, hoffs, (int64_t)nblk * nb, s);
+  k_color_place<<<nb, kBlock, 0, s>>>(blk, n, nb, hoffs, brows, bpos);
+  k_color_ptr<<<blocks_for(nblk + 1), kBlock, 0, s>>>(hoffs, nb, nblk, boff);
+  tfree(s, hist);
+  tfree(s, hoffs);
+  // local row of every solve row; first local row of every colour
+  int32_t* lpos = (int32_t*)talloc(s, (size_t)n * 4);
+  k_local_rows<<<blocks_for(n), kBlock, 0, s>>>(bpos, blk, boff, n, lpos);
+  tfree(s, bpos);
+  int32_t* bcls = (int32_t*)dalloc(h, (size_t)nblk * (C + 1) * 4);
+  k_block_cls<<<blocks_for((int64_t)nblk * (C + 1)), kBlock, 0, s>>>(boff, brows, lv.perm, lv.color, nblk, C, bcls);
+  // halos (at most the blocks' entries each, compacted afterwards)
+  int32_t* bad = (int32_t*)talloc(s, 4);
+  fill_i32(bad, 0, 1, s);
+  int32_t* cap = (int32_t*)talloc(s, (size_t)(nblk + 1) * 4);
+  int32_t* tcap = (int32_t*)talloc(s, (size_t)(nblk + 1) * 4);
+  k_block_entries<<<blocks_for(nblk), kBlock, 0, s>>>(lv.arp, lv.perm, brows, boff, nblk, cap);
+  scan_i32(cap, tcap, nblk, s);
+  int32_t* tmp = (int32_t*)talloc(s, (size_t)std::max<int64_t>(lv.nnzA, 1) * 4);
+  int32_t* hcnt = cap;                       // reused: distinct halo rows per block
+  k_block_halo<<<nblk, kBlock, 0, s>>>(lv.arp, lv.acol, lv.perm, lv.iperm, blk, lv.bcolor, boff, brows, tmp, tcap,
+                                       hcnt, bad);
+  int32_t* hoff = (int32_t*)dalloc(h, (size_t)(nblk + 1) * 4);
+  scan_i32(hcnt, hoff, nblk, s);
+  int32_t* hlist = (int32_t*)dalloc(h, (size_t)std::max<int64_t>(lv.nnzA, 1) * 4);
+  compact_segments(tmp, tcap, hoff, hlist, nblk, s);
+  tfree(s, tmp);
+  tfree(s, tcap);
+  tfree(s, cap);
+  // widths and the ELL offsets
+  int32_t* bw = (int32_t*)dalloc(h, (size_t)(nblk + 1) * 4);
+  fill_i32(bw, 0, nblk, s);
+  k_block_width<<<blocks_for(n), kBlock, 0, s>>>(lv.arp, lv.perm, blk, n, bw);
+  int32_t* sz = (int32_t*)talloc(s, (size_t)(nblk + 1) * 4);
+  k_block_cells<<<blocks_for(nblk), kBlock, 0, s>>>(boff, bw, nblk, sz);
+  int32_t* beoff = (int32_t*)dalloc(h, (size_t)(nblk + 1) * 4);
+  scan_i32(sz, beoff, nblk, s);
+  tfree(s, sz);
+  int32_t* mx = (int32_t*)talloc(s, 3 * 4);
+  fill_i32(mx, 0, 3, s);
+  k_block_maxima<<<std::min(blocks_for(nblk), kReduceGrid), kBlock, 0, s>>>(boff, hoff, bw, nblk, mx);
+  int64_t v[5] = {0, 0, 0, 0, 0};
+  {
+    ScalarRead rd[5] = {{beoff + nblk, 4, &v[0]}, {mx, 4, &v[1]}, {mx + 1, 4, &v[2]}, {mx + 2, 4, &v[3]},
+                        {bad, 4, &v[4]}};
+    read_scalars(h, rd, 5);
+  }
+  tfree(s, mx);
+  tfree(s, bad);
+  const int64_t total = v[0], maxrows = v[1], maxhalo = v[2], maxw = v[3];
+  const int64_t lds = (maxrows + maxhalo + 1) * 8;
+  const bool fits = v[4] == 0 && maxrows <= 2 * kBlkThreads && maxw <= 64 && lds <= kBlkLdsMax;
+  if (fits) {
+    int32_t* elx = (int32_t*)dalloc(h, (size_t)std::max<int64_t>(total, 1) * 4);
+    double* elv = (double*)dalloc(h, (size_t)std::max<int64_t>(total, 1) * 8);
+    k_block_ell<<<nblk, kBlock, 0, s>>>(lv.arp, lv.acol, lv.aval, lv.perm, lv.iperm, blk, lpos, boff, brows, hoff,
+                                        hlist, bw, beoff, elx, elv);
+    B.nblk = nblk;
+    for (int k = 0; k < 5; ++k) B.bstart[k] = (int32_t)bs[k];
+    B.ncls = C;
+    B.rows_per_thread = maxrows <= kBlkThreads ? 1 : 2;
+    B.width = maxw <= 32 ? 32 : 64;
+    B.lds_bytes = (int32_t)lds;
+    B.boff = boff;
+    B.brows = brows;
+    B.bcls = bcls;
+    B.hoff = hoff;
+    B.hlist = hlist;
+    B.bw = bw;
+    B.beoff = beoff;
+    B.elx = elx;
+    B.elv = elv;
+    int32_t* rinfo = (int32_t*)dalloc(h, (size_t)n * 4);
+    uint64_t* bmask = (uint64_t*)dalloc(h, (size_t)nblk * 8);
+    k_block_rowinfo<<<blocks_for(n), kBlock, 0, s>>>(lv.arp, lv.perm, lv.color, brows, n, rinfo);
+    k_block_mask<<<blocks_for(nblk), kBlock, 0, s>>>(bcls, nblk, C, bmask);
+    B.rinfo = rinfo;
+    B.bmask = bmask;
+    lv.blk_entries = total;
+  }
+  tfree(s, blk);
+  tfree(s, lpos);
+}
+
+}  // namespace
+
+void block_values(Handle& h, Level& lv) {
+  const BlockView<double>& B = lv.view.B;
+  if (B.nblk == 0) return;
+  k_block_values<<<B.nblk, kBlock, 0, h.stream>>>(lv.arp, lv.acol, lv.aval, lv.perm, B.boff, B.brows, B.bw, B.beoff,
+                                                  B.nblk, (double*)B.elv);
+}
+
 namespace {
 
 // CSR (source rows perm[r], columns through cmap) -> SELL-64 owned by the
@@ -858,20 +1399,30 @@ void solve_layout(Handle& h, Level& lv, const Level* nx, const int32_t* t_rp, co
   hipStream_t s = h.stream;
   const int64_t n = lv.n;
   const int nb = blocks_for(n);
-  const int C = lv.color ? lv.ncolors : 1;
+  const int C0 = lv.color ? lv.ncolors : 1;
+  // sweep classes: the colours, or (block colour, colour) on a level swept in block order
+  const int C = lv.bcolor ? 4 * C0 : C0;
   lv.perm = (int32_t*)dalloc(h, (size_t)n * 4);
   lv.iperm = (int32_t*)dalloc(h, (size_t)n * 4);
   int32_t* cptr = (int32_t*)dalloc(h, (size_t)(C + 1) * 4);
   int32_t *hist = nullptr, *off = nullptr;
   int32_t* stage = (int32_t*)pinned_staging((size_t)(2 * C + 1) * 4);
   if (lv.color) {
-    // rows sorted by (colour, index)
+    // rows sorted by (sweep class, index)
+    const int32_t* key = lv.color;
+    int32_t* cls = nullptr;
+    if (lv.bcolor) {
+      cls = (int32_t*)talloc(s, (size_t)n * 4);
+      k_sweep_class<<<blocks_for(n), kBlock, 0, s>>>(lv.bcolor, lv.color, n, C0, cls);
+      key = cls;
+    }
     hist = (int32_t*)talloc(s, ((size_t)C * nb + 1) * 4);
     off = (int32_t*)talloc(s, ((size_t)C * nb + 1) * 4);
-    k_color_hist<<<nb, kBlock, (size_t)C * 4, s>>>(lv.color, n, nb, C, hist);
+    k_color_hist<<<nb, kBlock, (size_t)C * 4, s>>>(key, n, nb, C, hist);
     scan_i32(hist, off, (int64_t)C * nb, s);
-    k_color_place<<<nb, kBlock, 0, s>>>(lv.color, n, nb, off, lv.perm, lv.iperm);
+    k_color_place<<<nb, kBlock, 0, s>>>(key, n, nb, off, lv.perm, lv.iperm);
     k_color_ptr<<<blocks_for(C + 1), kBlock, 0, s>>>(off, nb, C, cptr);
+    if (cls) tfree(s, cls);
   } else {
     // the coarsest level keeps its numbering (it is solved directly)
     iota_i32(lv.perm, n, s);
@@ -894,6 +1445,11 @@ void solve_layout(Handle& h, Level& lv, const Level* nx, const int32_t* t_rp, co
   v.x = lv.x;
   v.b = lv.b;
   v.r = lv.r;
+  if (lv.bcolor) {
+    block_layout(h, lv, C0);
+    tfree(s, lv.bcell);
+    lv.bcell = nullptr;
+  }
   // algorithmic bytes: 12 per entry (column + value), 28 per row (b, diagonal, row length, x write)
   lv.residual_bytes = 12.0 * (double)lv.nnzA + 28.0 * (double)n;
   int32_t* pre = nullptr;

@@ -57,6 +57,101 @@ __global__ void __launch_bounds__(kBlock) k_gs_color(Sell<V> A, const V* __restr
   if (active && (threadIdx.x & (R - 1)) == 0) x[r] = (br - acc) / dr;
 }
 
+// One block colour of a Gauss-Seidel sweep in block order (levels swept by
+// blocks): one workgroup per block (grid cell) of that colour.  Rows of one
+// block colour in different blocks are never coupled, so the blocks run at
+// once; inside a block the colours run one after the other, separated by
+// workgroup barriers, with the block's iterates and the values of its halo
+// (the rows of other blocks its rows read, which this launch does not change)
+// in LDS.  Thread p holds local rows p and p + kBlkThreads (R of them) with
+// their entries in registers: the LDS slot of each column and its value, in
+// the row's entry order, the diagonal replaced by a zero term (slot `pad`
+// holds +0), so x_i <- (b_i - sum_{j != i} A_ij x_j) / A_ii is computed with
+// the terms added in entry order, as on the other paths.
+template <int R, int K, class V>
+__global__ void __launch_bounds__(kBlkThreads) k_gs_block(BlockView<V> B, const V* __restrict__ bvec,
+                                                          const V* __restrict__ diag, V* x, int32_t blk0,
+                                                          int32_t c_begin, int32_t descending) {
+  extern __shared__ double lds_raw[];
+  V* xl = reinterpret_cast<V*>(lds_raw);
+  const int32_t b = blk0 + (int32_t)blockIdx.x;
+  const int32_t r0 = B.boff[b], rows = B.boff[b + 1] - r0;
+  const int32_t h0 = B.hoff[b], nh = B.hoff[b + 1] - h0;
+  const int32_t w = B.bw[b];
+  const int32_t e0 = B.beoff[b];
+  const int C = B.ncls;
+  const int32_t pad = rows + nh;
+  const uint64_t present = B.bmask[b];       // colours with rows in the block
+  int32_t g[R], my_c[R], len[R];
+  V bv[R], dv[R];
+  int32_t lx[R][K];
+  V lv[R][K];
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int32_t p = (int32_t)threadIdx.x + q * kBlkThreads;
+    const bool own = p < rows;
+    g[q] = own ? B.brows[r0 + p] : 0;
+    const int32_t info = own ? B.rinfo[r0 + p] : -1;
+    my_c[q] = own ? (info & 0xFF) : -1;
+    len[q] = own ? (info >> 8) : 0;
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+      const bool e = own && t < w;
+      lx[q][t] = e ? B.elx[e0 + t * rows + p] : pad;
+      lv[q][t] = e ? B.elv[e0 + t * rows + p] : V(0);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int32_t p = (int32_t)threadIdx.x + q * kBlkThreads;
+    if (p < rows) {
+      bv[q] = bvec[g[q]];
+      dv[q] = diag[g[q]];
+      xl[p] = x[g[q]];
+    }
+  }
+  for (int32_t k = threadIdx.x; k < nh; k += kBlkThreads) xl[rows + k] = x[B.hlist[h0 + k]];
+  if (threadIdx.x == 0) xl[pad] = V(0);
+  __syncthreads();
+  for (int kk = c_begin; kk < C; ++kk) {
+    const int c = descending ? C - 1 - kk : kk;
+    if (!((present >> c) & 1)) continue;                // no row of this colour in the block
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      if (my_c[q] == c) {
+        // every gather of the row is issued at once, then the products are
+        // added in entry order, in chunks of 8 up to the row's length
+        // (terms past the row are +0); the largest shape works a chunk at a
+        // time, within its registers
+        constexpr int G = R * K <= 64 ? K : 8;
+        V s = V(0);
+#pragma unroll
+        for (int g0 = 0; g0 < K; g0 += G) {
+          if (g0 < w) {
+            V pr[G];
+#pragma unroll
+            for (int t = 0; t < G; ++t) pr[t] = lv[q][g0 + t] * xl[lx[q][g0 + t]];
+#pragma unroll
+            for (int t0 = 0; t0 < G; t0 += 8) {
+              if (g0 + t0 < len[q]) {
+#pragma unroll
+                for (int u = 0; u < 8; ++u) s = s + pr[t0 + u];
+              }
+            }
+          }
+        }
+        xl[(int32_t)threadIdx.x + q * kBlkThreads] = (bv[q] - s) / dv[q];
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int32_t p = (int32_t)threadIdx.x + q * kBlkThreads;
+    if (p < rows) x[g[q]] = xl[p];
+  }
+}
+
 // r = b - A x on level 0
 template <class V>
 __global__ void __launch_bounds__(kBlock) k_residual_fine(Sell<V> A, const V* __restrict__ b,
@@ -535,9 +630,40 @@ __global__ void k_check_finite(const double* v, int64_t n, int32_t* flag) {
 
 }  // namespace
 
+// One sweep in block order: the four block colours one launch each.  `skip`
+// (ascending sweeps only): the first colour of block colour 0 is already done.
+template <class V>
+void block_sweep(const LevelViewT<V>& v, const Level& lv, hipStream_t s, bool descending, bool timed, int skip) {
+  const BlockView<V>& B = v.B;
+  if (!B.boff || !B.brows || !B.hoff || !B.hlist || !B.bw || !B.beoff || !B.elx || !B.elv || !B.rinfo || !B.bmask)
+    throw Error{GMG_DEVICE_ERROR, "block sweep layout incomplete"};
+  for (int k = 0; k < 4; ++k) {
+    const int bc = descending ? 3 - k : k;
+    const int32_t nb = B.bstart[bc + 1] - B.bstart[bc];
+    if (nb <= 0) continue;
+    double bytes = 0.0;
+    for (int c = 0; c < B.ncls; ++c) bytes += lv.color_bytes[bc * B.ncls + c];
+    KernelTimer::Scope t(timed ? (int)KernelTimer::GS_GALERKIN : -1, bytes);
+    const int c_begin = !descending && k == 0 ? skip : 0;
+    auto go = [&](auto kern) {
+      hipExtLaunchKernelGGL(kern, dim3(nb), dim3(kBlkThreads), (size_t)B.lds_bytes, s, t.start, t.stop, 0, B,
+                            (const V*)v.b, (const V*)v.diag, v.x, B.bstart[bc], c_begin, descending ? 1 : 0);
+    };
+    if (B.rows_per_thread == 1) {
+      if (B.width <= 32) go(k_gs_block<1, 32, V>); else go(k_gs_block<1, 64, V>);
+    } else {
+      if (B.width <= 32) go(k_gs_block<2, 32, V>); else go(k_gs_block<2, 64, V>);
+    }
+  }
+}
+
 template <class V>
 void gs_sweep(const LevelViewT<V>& v, const Level& lv, hipStream_t s, bool finest, bool descending, bool timed,
               int skip) {
+  if (!finest && v.B.nblk > 0) {
+    block_sweep(v, lv, s, descending, timed, skip);
+    return;
+  }
   const int C = (int)lv.color_ptr.size() - 1;
   for (int k = skip; k < C; ++k) {
     const int c = descending ? C - 1 - k : k;

@@ -26,6 +26,8 @@ def problem(name):
             "ico5": lambda: synth.config_icosphere(5),
             "torus48": lambda: synth.small_torus(48, 40),
             "torus96": lambda: synth.small_torus(96, 80),
+            "torus256": lambda: synth.config_torus(256, 256),
+            "pc100k": lambda: synth.small_pointcloud(100000),
             "flat": lambda: synth.small_flat_grid(40, 36),
             "pc4k": lambda: synth.small_pointcloud(4000),
             "pc20k": lambda: synth.small_pointcloud(20000),

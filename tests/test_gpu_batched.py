@@ -32,7 +32,7 @@ def rhs_block(prob, nrhs, seed=3):
 
 @pytest.mark.parametrize("precision", ["f64", "f32"])
 @pytest.mark.parametrize("name,minc,nrhs", [("ico4", 100, 8), ("torus96", 200, 3), ("pc20k", 500, 11),
-                                            ("ico3", 100, 1), ("hubs_big", 1000, 8)])
+                                            ("ico3", 100, 1), ("hubs_big", 1000, 8), ("torus256", 1000, 8)])
 def test_batched_preconditioner_parity(name, minc, nrhs, precision):
     _say(f"[gpu] batched preconditioner {precision} {name} nrhs={nrhs}")
     prob = problem(name)

@@ -51,13 +51,13 @@ def both(prob, **opt):
 
 
 BITWISE = ["positions", "edge_rowptr", "edge_col", "edge_w", "scalars", "samples", "labels", "dist",
-           "p_col", "p_val", "p_cnt", "tri", "a_rowptr", "a_col", "a_val", "colors"]
+           "p_col", "p_val", "p_cnt", "tri", "a_rowptr", "a_col", "a_val", "colors", "block_colors"]
 ORC_CODE = {"positions": oracle.POSITIONS, "edge_rowptr": oracle.EDGE_ROWPTR, "edge_col": oracle.EDGE_COL,
             "edge_w": oracle.EDGE_W, "scalars": oracle.SCALARS, "samples": oracle.SAMPLES,
             "labels": oracle.LABELS, "dist": oracle.DIST, "p_col": oracle.P_COL, "p_val": oracle.P_VAL,
             "p_cnt": oracle.P_CNT, "tri": oracle.TRI, "a_rowptr": oracle.A_ROWPTR, "a_col": oracle.A_COL,
             "a_val": oracle.A_VAL, "colors": oracle.COLORS, "chol": oracle.CHOL,
-            "coarse_inverse": oracle.CINV}
+            "coarse_inverse": oracle.CINV, "block_colors": oracle.BLOCK_COLORS}
 
 
 def same_bits(a, b):
@@ -148,7 +148,7 @@ def compare_solves(orc, gpu, prob, tol=1e-8, max_iters=200, chunk=None):
 
 
 SMALL = [("ico3", 100), ("ico4", 100), ("ico5", 1000), ("torus48", 100), ("torus96", 200), ("flat", 100),
-         ("pc4k", 200), ("pc20k", 500)]
+         ("pc4k", 200), ("pc20k", 500), ("torus256", 1000), ("pc100k", 1000)]
 
 
 @pytest.mark.parametrize("name,minc", SMALL)
@@ -168,7 +168,8 @@ def test_solve_parity_small(name, minc):
 
 
 @pytest.mark.parametrize("opt", [dict(sample_order=1), dict(shift_coarse_points=0), dict(seed=12345),
-                                 dict(coarsening_ratio=0.25), dict(nu_pre=1, nu_post=3)])
+                                 dict(coarsening_ratio=0.25), dict(nu_pre=1, nu_post=3), dict(block_min_rows=300),
+                                 dict(block_min_rows=100, coarsening_ratio=0.25)])
 def test_option_variants(opt):
     _say(f"[gpu] options {opt}")
     prob = problem("torus96")

@@ -50,7 +50,7 @@ def both(prob, **opt):
 
 
 SMALL = [("ico3", 100), ("ico4", 100), ("ico5", 1000), ("torus48", 100), ("torus96", 200), ("flat", 100),
-         ("pc4k", 200), ("pc20k", 500), ("hubs_big", 1000)]
+         ("pc4k", 200), ("pc20k", 500), ("hubs_big", 1000), ("torus256", 1000), ("pc100k", 1000)]
 
 
 @pytest.mark.parametrize("precision", ["f64", "f32"])

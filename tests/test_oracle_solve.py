@@ -20,11 +20,20 @@ def dense_hierarchy(h):
     for l in range(h.num_levels):
         lv = h.level(l)
         n = lv["n"]
-        d = dict(A=brute.dense(lv["arp"], lv["acol"], lv["aval"], (n, n)), colors=lv["colors"])
+        d = dict(A=brute.dense(lv["arp"], lv["acol"], lv["aval"], (n, n)), colors=sweep_key(lv))
         if l + 1 < h.num_levels:
             d["P"] = brute.ell_to_dense(lv["pcol"], lv["pval"], lv["pcnt"], h.sizes(l + 1)["n"])
         levels.append(d)
     return levels
+
+
+def sweep_key(lv):
+    """Sweep class of each row: its colour, preceded by its block colour on
+    levels swept in block order."""
+    c = lv["colors"]
+    if len(lv["block_colors"]) == 0:
+        return c
+    return lv["block_colors"].astype(np.int64) * (int(c.max()) + 1) + c
 
 
 def gs_split(A, colors, mode):
@@ -52,14 +61,20 @@ def dense_vcycle(levels, l, x, b, nu=2, mode=0):
     return x
 
 
-CASES = [("torus48", 300), ("torus48", 100), ("ico4", 100), ("flat", 200), ("pc4k", 200)]
+CASES = [("torus48", 300, 4096), ("torus48", 100, 4096), ("ico4", 100, 4096), ("flat", 200, 4096),
+         ("pc4k", 200, 4096), ("torus48", 100, 50), ("pc4k", 100, 100)]
 
 
-@pytest.mark.parametrize("name,minc", CASES)
+@pytest.mark.parametrize("name,minc,bmin", CASES)
 @pytest.mark.parametrize("mode", [0, 1])
-def test_one_vcycle_matches_dense_restatement(name, minc, mode):
+def test_one_vcycle_matches_dense_restatement(name, minc, bmin, mode):
+    """One V-cycle equals the matrix-splitting form of Gauss-Seidel in the sweep
+    order (colours, or block colours then colours), with bmin lowered so that
+    the small meshes have levels swept in block order."""
     p = problem(name)
-    h = oracle.Hierarchy.from_problem(p, oracle.default_options(min_coarse_points=minc))
+    h = oracle.Hierarchy.from_problem(p, oracle.default_options(min_coarse_points=minc, block_min_rows=bmin))
+    if bmin < 4096 and mode == 0:
+        assert any(h.sizes(l)["blocks"] for l in range(h.num_levels))
     assert h.num_levels >= 2
     levels = dense_hierarchy(h)
     rng = np.random.default_rng(1)
