@@ -137,6 +137,11 @@ using SellView = Sell<double>;
 // (0 for the diagonal and padding).  rinfo packs each local row's length and
 // colour, bmask the colours present in each block.
 constexpr int kBlkThreads = 256;     // threads of a block-sweep workgroup
+constexpr int kBlkGather = 8;        // gather-list entries per thread (rows + halo of a block <= 2048)
+struct alignas(32) BlockHdr {
+  int32_t r0, rows, nh, w, e0, pad;    // first local row (boff), rows, halo rows, ELL width, first ELL element
+  uint64_t mask;                       // colours with rows in the block
+};
 constexpr int kBlkMaxColors = 64;    // colours a block sweep handles
 template <class V>
 struct BlockView {
@@ -156,6 +161,12 @@ struct BlockView {
   const V* elv = nullptr;
   const int32_t* rinfo = nullptr;       // per local row (boff order): row length << 8 | colour
   const uint64_t* bmask = nullptr;      // [nblk] colours with rows in the block
+  // What a block sweep reads first, at addresses known from the block index
+  // alone: its header and its gather list glist[b gstride + k] = the block's
+  // k-th row (k < rows), then its halo rows, padded with row 0.
+  const struct BlockHdr* hdr = nullptr;
+  const int32_t* glist = nullptr;
+  int32_t gstride = 0;
 
   // The same layout with values of another type (the float cycle's copy).
   template <class W>
@@ -178,6 +189,9 @@ struct BlockView {
     o.elv = values;
     o.rinfo = rinfo;
     o.bmask = bmask;
+    o.hdr = hdr;
+    o.glist = glist;
+    o.gstride = gstride;
     return o;
   }
 };

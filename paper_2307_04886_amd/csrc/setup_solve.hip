@@ -861,6 +861,27 @@ __global__ void k_block_rowinfo(const int32_t* rp, const int32_t* perm, const in
   rinfo[k] = ((rp[o + 1] - rp[o]) << 8) | color[o];
 }
 
+// Per block: its header and its gather list (own rows, then halo rows, padded with row 0).
+__global__ void k_block_gather(const int32_t* boff, const int32_t* brows, const int32_t* hoff, const int32_t* hlist,
+                               const int32_t* bw, const int32_t* beoff, const uint64_t* bmask, int32_t gstride,
+                               BlockHdr* hdr, int32_t* glist) {
+  const int32_t b = blockIdx.x;
+  const int32_t r0 = boff[b], rows = boff[b + 1] - r0, h0 = hoff[b], nh = hoff[b + 1] - h0;
+  if (threadIdx.x == 0) {
+    BlockHdr hd;
+    hd.r0 = r0;
+    hd.rows = rows;
+    hd.nh = nh;
+    hd.w = bw[b];
+    hd.e0 = beoff[b];
+    hd.pad = 0;
+    hd.mask = bmask[b];
+    hdr[b] = hd;
+  }
+  for (int32_t k = threadIdx.x; k < gstride; k += blockDim.x)
+    glist[(int64_t)b * gstride + k] = k < rows ? brows[r0 + k] : (k < rows + nh ? hlist[h0 + k - rows] : 0);
+}
+
 __global__ void k_block_mask(const int32_t* bcls, int32_t nblk, int32_t C, uint64_t* bmask) {
   const int32_t b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= nblk) return;
@@ -1303,7 +1324,8 @@ void block_layout(Handle& h, Level& lv, int32_t C) {
   tfree(s, bad);
   const int64_t total = v[0], maxrows = v[1], maxhalo = v[2], maxw = v[3];
   const int64_t lds = (maxrows + maxhalo + 1) * 8;
-  const bool fits = v[4] == 0 && maxrows <= 2 * kBlkThreads && maxw <= 64 && lds <= kBlkLdsMax;
+  const bool fits = v[4] == 0 && maxrows <= 2 * kBlkThreads && maxw <= 64 && lds <= kBlkLdsMax &&
+                    maxrows + maxhalo <= kBlkGather * kBlkThreads;
   if (fits) {
     int32_t* elx = (int32_t*)dalloc(h, (size_t)std::max<int64_t>(total, 1) * 4);
     double* elv = (double*)dalloc(h, (size_t)std::max<int64_t>(total, 1) * 8);
@@ -1330,6 +1352,14 @@ void block_layout(Handle& h, Level& lv, int32_t C) {
     k_block_mask<<<blocks_for(nblk), kBlock, 0, s>>>(bcls, nblk, C, bmask);
     B.rinfo = rinfo;
     B.bmask = bmask;
+    // headers and gather lists (stride: the largest block plus the largest halo, in wavefronts)
+    const int32_t gstride = (int32_t)((maxrows + maxhalo + kWave - 1) / kWave * kWave);
+    BlockHdr* hdr = (BlockHdr*)dalloc(h, (size_t)nblk * sizeof(BlockHdr));
+    int32_t* glist = (int32_t*)dalloc(h, (size_t)nblk * gstride * 4);
+    k_block_gather<<<nblk, kBlock, 0, s>>>(boff, brows, hoff, hlist, bw, beoff, bmask, gstride, hdr, glist);
+    B.hdr = hdr;
+    B.glist = glist;
+    B.gstride = gstride;
     lv.blk_entries = total;
   }
   tfree(s, blk);

@@ -75,14 +75,21 @@ __global__ void __launch_bounds__(kBlkThreads) k_gs_block(BlockView<V> B, const 
   extern __shared__ double lds_raw[];
   V* xl = reinterpret_cast<V*>(lds_raw);
   const int32_t b = blk0 + (int32_t)blockIdx.x;
-  const int32_t r0 = B.boff[b], rows = B.boff[b + 1] - r0;
-  const int32_t h0 = B.hoff[b], nh = B.hoff[b + 1] - h0;
-  const int32_t w = B.bw[b];
-  const int32_t e0 = B.beoff[b];
+  // first: the header and the gather list (addresses from the block index
+  // alone), then the entries, row data and iterates they point to
+  const BlockHdr hd = B.hdr[b];
+  const int32_t* gl = B.glist + (int64_t)b * B.gstride;
+  int32_t gi[kBlkGather];
+#pragma unroll
+  for (int j = 0; j < kBlkGather; ++j) {
+    const int32_t k = (int32_t)threadIdx.x + j * kBlkThreads;
+    gi[j] = k < B.gstride ? gl[k] : 0;
+  }
+  const int32_t r0 = hd.r0, rows = hd.rows, nh = hd.nh, w = hd.w, e0 = hd.e0;
   const int C = B.ncls;
   const int32_t pad = rows + nh;
-  const uint64_t present = B.bmask[b];       // colours with rows in the block
-  int32_t g[R], my_c[R], len[R];
+  const uint64_t present = hd.mask;          // colours with rows in the block
+  int32_t my_c[R], len[R];
   V bv[R], dv[R];
   int32_t lx[R][K];
   V lv[R][K];
@@ -90,7 +97,6 @@ __global__ void __launch_bounds__(kBlkThreads) k_gs_block(BlockView<V> B, const 
   for (int q = 0; q < R; ++q) {
     const int32_t p = (int32_t)threadIdx.x + q * kBlkThreads;
     const bool own = p < rows;
-    g[q] = own ? B.brows[r0 + p] : 0;
     const int32_t info = own ? B.rinfo[r0 + p] : -1;
     my_c[q] = own ? (info & 0xFF) : -1;
     len[q] = own ? (info >> 8) : 0;
@@ -101,16 +107,18 @@ __global__ void __launch_bounds__(kBlkThreads) k_gs_block(BlockView<V> B, const 
       lv[q][t] = e ? B.elv[e0 + t * rows + p] : V(0);
     }
   }
+  // the block's own rows (thread p holds rows p, p + kBlkThreads, ...) and its halo
 #pragma unroll
-  for (int q = 0; q < R; ++q) {
-    const int32_t p = (int32_t)threadIdx.x + q * kBlkThreads;
-    if (p < rows) {
-      bv[q] = bvec[g[q]];
-      dv[q] = diag[g[q]];
-      xl[p] = x[g[q]];
+  for (int j = 0; j < kBlkGather; ++j) {
+    const int32_t k = (int32_t)threadIdx.x + j * kBlkThreads;
+    if (k < pad) {
+      xl[k] = x[gi[j]];
+      if (j < R && k < rows) {
+        bv[j] = bvec[gi[j]];
+        dv[j] = diag[gi[j]];
+      }
     }
   }
-  for (int32_t k = threadIdx.x; k < nh; k += kBlkThreads) xl[rows + k] = x[B.hlist[h0 + k]];
   if (threadIdx.x == 0) xl[pad] = V(0);
   __syncthreads();
   for (int kk = c_begin; kk < C; ++kk) {
@@ -148,7 +156,7 @@ __global__ void __launch_bounds__(kBlkThreads) k_gs_block(BlockView<V> B, const 
 #pragma unroll
   for (int q = 0; q < R; ++q) {
     const int32_t p = (int32_t)threadIdx.x + q * kBlkThreads;
-    if (p < rows) x[g[q]] = xl[p];
+    if (p < rows) x[gi[q]] = xl[p];
   }
 }
 
@@ -635,7 +643,8 @@ __global__ void k_check_finite(const double* v, int64_t n, int32_t* flag) {
 template <class V>
 void block_sweep(const LevelViewT<V>& v, const Level& lv, hipStream_t s, bool descending, bool timed, int skip) {
   const BlockView<V>& B = v.B;
-  if (!B.boff || !B.brows || !B.hoff || !B.hlist || !B.bw || !B.beoff || !B.elx || !B.elv || !B.rinfo || !B.bmask)
+  if (!B.hdr || !B.glist || !B.elx || !B.elv || !B.rinfo || B.gstride <= 0 ||
+      B.gstride > kBlkGather * kBlkThreads)
     throw Error{GMG_DEVICE_ERROR, "block sweep layout incomplete"};
   for (int k = 0; k < 4; ++k) {
     const int bc = descending ? 3 - k : k;
