@@ -39,7 +39,8 @@ TRAFFIC = {"gs_finest": {"bytes_per_launch": 26822506, "src_sha256_16": "c193cd0
 
 KERNEL_NAMES = {"gs_finest": "k_gs_color_fine (one colour of a Gauss-Seidel sweep, level 0)",
                 "residual_finest": "k_residual_norm (residual + norm partials, level 0)",
-                "gs_galerkin": "k_gs_color<R> (one colour of a Gauss-Seidel sweep, Galerkin levels above the tail)"}
+                "gs_galerkin": "k_gs_block (one block colour of a block-ordered Gauss-Seidel sweep, Galerkin levels above "
+                               "the tail; k_gs_color<R> where a level has no block order)"}
 
 
 def kernel_src_sha():
@@ -103,7 +104,8 @@ def level_stats(h):
     L = h.num_levels
     for l in range(L):
         s = h.sizes(l)
-        row = {"n": s["n"], "edges": s["m"], "nnz_A": s["nnzA"], "colours": s["colors"]}
+        row = {"n": s["n"], "edges": s["m"], "nnz_A": s["nnzA"], "colours": s["colors"],
+               "block_order": s["blocks"], "kernel_shape": h.tuning(l)}
         if l + 1 < L:
             cnt = h.export(l, "p_cnt")
             row.update({"nnz_P": s["nnzP"], "coarse_points": s["samples"],
@@ -143,6 +145,47 @@ def progress(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def batched_leg(args, dev, opt, forms=("f32", "plain")):
+    """Many meshes of uneven size with 8 right-hand sides each: every hierarchy built and every
+    right-hand side solved to the same tolerance; batched float-preconditioned CG on concurrent
+    streams against the plain double V-cycle solve of each right-hand side in turn, on the same
+    streams."""
+    import torch
+    import synth
+    from paper_2307_04886_amd.batch import solve_many
+    batch = synth.config_batched()
+    systems = []
+    for bp, B in batch:
+        t = [torch.from_numpy(a).to(dev) for a in (bp.points, bp.edges, bp.indptr, bp.indices, bp.data)]
+        systems.append(tuple(t) + (torch.from_numpy(B).to(dev),))
+    nsolves = sum(B.shape[0] for _, B in batch)
+    progress("many-mesh workload generated")
+    res = {"workload": f"{len(batch)} jittered tori and icospheres, {min(b.n for b, _ in batch)}"
+                       f"-{max(b.n for b, _ in batch)} vertices ({sum(b.n for b, _ in batch)} in total),"
+                       f" 8 right-hand sides each, (M + 1e-3 L), tol {args.tol}", "solves": nsolves}
+    for form in forms:
+        kw = dict(precision="f32") if form == "f32" else dict(max_iters=200, form="plain")
+        solve_many(systems, streams=4, tol=args.tol, **kw)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        r = solve_many(systems, streams=4, tol=args.tol, **kw)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        if any(st != 0 for _, _, st in r):
+            raise RuntimeError(f"{form} many-mesh solve did not converge")
+        progress(f"many-mesh {form}: {1e3 * dt:.1f} ms")
+        if form == "f32":
+            res.update({"value": nsolves / dt, "unit": "solves/s", "ms": 1e3 * dt,
+                        "form": "setup + float-preconditioned double CG, 8 right-hand sides per launch, 4 streams"})
+        else:
+            res.update({"plain_fp64_form": "setup + plain double V-cycle solve of each right-hand side in turn, "
+                                           "the same 4 streams",
+                        "plain_fp64_value": nsolves / dt, "plain_fp64_ms": 1e3 * dt})
+    if "value" in res and "plain_fp64_ms" in res:
+        res["vs_plain_fp64"] = res["plain_fp64_ms"] / res["ms"]
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -152,6 +195,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the many-mesh batched measurement")
     ap.add_argument("--no-pointcloud", action="store_true", help="skip the 2M-point point-cloud measurement")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="only the many-mesh batched measurement (for profiler runs)")
     ap.add_argument("--headline-only", action="store_true",
                     help="only the plain steps (and roofline passes): for profiler runs")
     ap.add_argument("--size", type=int, default=1024, help="torus grid size (default 1024)")
@@ -177,6 +222,9 @@ def main():
     g.library()
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.batched_only:
+        print(json.dumps({"batched": batched_leg(args, dev, default_options(), forms=("f32",))}), flush=True)
+        return
     t0 = time.time()
     prob = synth.config_torus(args.size, args.size)
     gen_s = time.time() - t0
@@ -394,42 +442,7 @@ def main():
     # right-hand side solved to the same tolerance; batched float-preconditioned CG on concurrent
     # streams against the plain double V-cycle solve of each right-hand side in turn
     if not args.no_batched and not args.headline_only:
-        from paper_2307_04886_amd.batch import solve_many
-        batch = synth.config_batched()
-        systems = []
-        for bp, B in batch:
-            t = [torch.from_numpy(a).to(dev) for a in (bp.points, bp.edges, bp.indptr, bp.indices, bp.data)]
-            systems.append(tuple(t) + (torch.from_numpy(B).to(dev),))
-        nsolves = sum(B.shape[0] for _, B in batch)
-        progress("many-mesh workload generated")
-        solve_many(systems, streams=4, tol=args.tol, precision="f32")
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        res = solve_many(systems, streams=4, tol=args.tol, precision="f32")
-        torch.cuda.synchronize()
-        bdt = time.perf_counter() - t1
-        if any(st != 0 for _, _, st in res):
-            raise RuntimeError("batched solve did not converge")
-
-        # the plain double V-cycle solve of each right-hand side, on the same 4-stream pool
-        solve_many(systems, streams=4, tol=args.tol, max_iters=200, form="plain")
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        pres = solve_many(systems, streams=4, tol=args.tol, max_iters=200, form="plain")
-        torch.cuda.synchronize()
-        pdt = time.perf_counter() - t1
-        if any(st != 0 for _, _, st in pres):
-            raise RuntimeError("plain solve did not converge")
-        out["batched"] = {"workload": f"{len(batch)} jittered tori and icospheres, {min(b.n for b, _ in batch)}"
-                                      f"-{max(b.n for b, _ in batch)} vertices ({sum(b.n for b, _ in batch)} in total),"
-                                      f" 8 right-hand sides each, (M + 1e-3 L), tol {args.tol}",
-                          "value": nsolves / bdt, "unit": "solves/s", "ms": 1e3 * bdt, "solves": nsolves,
-                          "form": "setup + float-preconditioned double CG, 8 right-hand sides per launch, "
-                                  "4 streams",
-                          "plain_fp64_form": "setup + plain double V-cycle solve of each right-hand side in turn, "
-                                             "the same 4 streams",
-                          "plain_fp64_value": nsolves / pdt, "plain_fp64_ms": 1e3 * pdt,
-                          "vs_plain_fp64": pdt / bdt}
+        out["batched"] = batched_leg(args, dev, opt)
 
     if args.calibrate_copy:
         src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device=dev)   # 256 MiB

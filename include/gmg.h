@@ -67,6 +67,10 @@ typedef struct gmg_options {
                                     the cells are swept one after the other, and within a cell the
                                     colours in order.  A valid Gauss-Seidel order (the paper leaves the
                                     order open, Sec. 3) that needs four launches per sweep. */
+  int32_t autotune;              /* 1 (default): the lanes per row of the row kernels of every level solved by
+                                    separate launches, and the load chunk of level 0's, are picked by timing
+                                    the candidates on the level's data at the build (cached per shape class
+                                    for the process; a shape never changes a result bit); 0: fixed rules */
 } gmg_options;
 
 /* Values of gmg_options.weighting. */
@@ -279,6 +283,15 @@ int gmg_num_levels(gmg_handle h, int32_t* levels);
  *  Gauss-Seidel sweeps run in block order (see gmg_options.block_min_rows).
  */
 int gmg_level_sizes(gmg_handle h, int32_t level, int64_t* sizes_host);
+
+/*
+ * The row-kernel shapes level l's V-cycle uses, written to out_host[0..3]:
+ *  0 lanes per row of the row kernels of A_l (residual, colour sweeps; levels >= 1 solved by
+ *    separate launches, else 0), 1 lanes per row of the restriction by P_l^T (levels solved by
+ *    separate launches, else 0), 2 entries per load chunk of level 0's row kernels (level 0, else 0),
+ *  3 one if the level's sweeps run as block sweeps (one workgroup per grid cell, four launches).
+ */
+int gmg_level_tuning(gmg_handle h, int32_t level, int32_t* out_host);
 
 /* Export codes of gmg_export_level (element type and count for level l). */
 enum gmg_export_what {

@@ -39,13 +39,15 @@ class Options(ctypes.Structure):
                 ("nu_pre", ctypes.c_int32), ("nu_post", ctypes.c_int32),
                 ("shift_coarse_points", ctypes.c_int32), ("sample_order", ctypes.c_int32),
                 ("seed", ctypes.c_uint64), ("weighting", ctypes.c_int32), ("fallback_on_vertex", ctypes.c_int32),
-                ("color_passes", ctypes.c_int32), ("block_min_rows", ctypes.c_int32)]
+                ("color_passes", ctypes.c_int32), ("block_min_rows", ctypes.c_int32),
+                ("autotune", ctypes.c_int32)]
 
 
 def default_options(**kw):
     o = Options(ctypes.sizeof(Options), 1.0 / 8.0, 1000, 32, 2, 2, 1, 0, 0)
     o.color_passes = 3
     o.block_min_rows = 4096
+    o.autotune = 1
     for k, v in kw.items():
         setattr(o, k, v)
     return o

@@ -56,6 +56,7 @@ struct Options {                 // field order mirrors the public options struc
   int32_t fallback_on_vertex;    // 1: a best projection onto a triangle vertex uses the fallback
   int32_t color_passes;          // iterated-greedy passes after the first colouring (default 3)
   int32_t block_min_rows;        // levels 1.. above this many points sweep in block order (4096)
+  int32_t autotune;              // GPU kernel shapes only (mirrors the public struct; no effect here)
 };
 
 enum Status { OK = 0, NOT_CONVERGED = 1, INVALID_ARGUMENT = -1, NOT_SPD = -4, DEGENERATE = -5 };
@@ -883,7 +884,7 @@ int check_options(const Options& o) {
   if (o.min_coarse_points < 1 || o.max_levels < 1 || o.nu_pre < 0 || o.nu_post < 0) return INVALID_ARGUMENT;
   if (o.sample_order != 0 && o.sample_order != 1) return INVALID_ARGUMENT;
   if (o.weighting < 0 || o.weighting > 2 || (o.fallback_on_vertex != 0 && o.fallback_on_vertex != 1) ||
-      o.color_passes < 0 || o.color_passes > 64 || o.block_min_rows < 0)
+      o.color_passes < 0 || o.color_passes > 64 || o.block_min_rows < 0 || (o.autotune != 0 && o.autotune != 1))
     return INVALID_ARGUMENT;
   return OK;
 }

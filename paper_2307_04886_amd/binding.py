@@ -29,7 +29,7 @@ EXPORTS = {
 # Symbols the library exports (checked on load).
 SYMBOLS = ["gmg_default_options", "gmg_build_hierarchy", "gmg_solve", "gmg_solve_pcg", "gmg_precondition",
            "gmg_update_matrix", "gmg_pattern_outer", "gmg_solve_pcg_batched", "gmg_precondition_batched", "gmg_precondition_noalloc", "gmg_free", "gmg_status_string", "gmg_last_error",
-           "gmg_num_levels", "gmg_level_sizes", "gmg_export_level", "gmg_timer_start", "gmg_timer_stop"]
+           "gmg_num_levels", "gmg_level_sizes", "gmg_level_tuning", "gmg_export_level", "gmg_timer_start", "gmg_timer_stop"]
 
 # gmg_precision
 PRECISION = {"f64": 0, "f32": 1}
@@ -44,7 +44,8 @@ class Options(ctypes.Structure):
                 ("nu_pre", ctypes.c_int32), ("nu_post", ctypes.c_int32),
                 ("shift_coarse_points", ctypes.c_int32), ("sample_order", ctypes.c_int32),
                 ("seed", ctypes.c_uint64), ("weighting", ctypes.c_int32), ("fallback_on_vertex", ctypes.c_int32),
-                ("color_passes", ctypes.c_int32), ("block_min_rows", ctypes.c_int32)]
+                ("color_passes", ctypes.c_int32), ("block_min_rows", ctypes.c_int32),
+                ("autotune", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -90,6 +91,7 @@ def library():
     L.gmg_num_levels.argtypes = [P, ctypes.POINTER(I32)]
     L.gmg_level_sizes.argtypes = [P, I32, P]
     L.gmg_export_level.argtypes = [P, I32, I32, P, I64]
+    L.gmg_level_tuning.argtypes = [P, I32, P]
     L.gmg_timer_start.argtypes = [I32, I32]
     L.gmg_timer_stop.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64),
                                  ctypes.POINTER(ctypes.c_double)]
@@ -179,6 +181,14 @@ class Hierarchy:
             raise _err(st)
         return dict(n=int(s[0]), m=int(s[1]), nnzA=int(s[2]), nnzP=int(s[3]), colors=int(s[4]),
                     fallback=int(s[5]), samples=int(s[6]), nnzE=int(s[7]), blocks=int(s[8]))
+
+    def tuning(self, level):
+        """gmg_level_tuning: the row-kernel shapes of a level."""
+        t = np.zeros(4, dtype=np.int32)
+        st = library().gmg_level_tuning(self._h, level, t.ctypes.data_as(ctypes.c_void_p))
+        if st:
+            raise _err(st)
+        return dict(lanes_A=int(t[0]), lanes_PT=int(t[1]), chunk=int(t[2]), block_sweep=int(t[3]))
 
     def export(self, level, what):
         code, dt = EXPORTS[what]

@@ -9,7 +9,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgmg.so")
 SOURCES = ["prims.hip", "setup_graph.hip", "setup_prolong.hip", "setup_solve.hip", "solve.hip", "krylov.hip", "multi.hip",
-           "api.hip"]
+           "tune.hip", "api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # -ffp-contract=off: every floating-point operation is rounded on its own, so

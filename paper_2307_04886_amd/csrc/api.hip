@@ -305,7 +305,7 @@ bool options_ok(const gmg_options& o) {
          o.coarsening_ratio < 1.0 && o.min_coarse_points >= 1 && o.max_levels >= 1 && o.nu_pre >= 0 &&
          o.nu_post >= 0 && (o.sample_order == 0 || o.sample_order == 1) && o.weighting >= 0 && o.weighting <= 2 &&
          (o.fallback_on_vertex == 0 || o.fallback_on_vertex == 1) && o.color_passes >= 0 && o.color_passes <= 64 &&
-         o.block_min_rows >= 0;
+         o.block_min_rows >= 0 && (o.autotune == 0 || o.autotune == 1);
 }
 
 // The single-workgroup tail of a cycle: levels tail_start.. with their views
@@ -488,6 +488,7 @@ void build(Handle& h, int64_t n, const double* points, int64_t m, const int32_t*
     --h.tail_start;
   }
   for (int l = ell_first_level(h); l + 1 < nl; ++l) ell_layout(h, h.L[l], h.L[l + 1]);
+  autotune(h);
   h.plain.v.clear();
   for (int l = 0; l < nl; ++l) h.plain.v.push_back(h.L[l].view);
   h.plain.symmetric = false;
@@ -656,6 +657,7 @@ void kry_prepare(Handle& h, Cycle<float>& c) {
     f.cptr = d.cptr;
     f.ra = d.ra;
     f.rt = d.rt;
+    f.ch = d.ch;
     f.maxa = d.maxa;
     f.maxt = d.maxt;
     f.q_col = d.q_col;
@@ -1123,6 +1125,7 @@ int gmg_default_options(gmg_options* o) {
   o->seed = 0;
   o->color_passes = 3;
   o->block_min_rows = 4096;
+  o->autotune = 1;
   return GMG_OK;
 }
 
@@ -1557,6 +1560,17 @@ int gmg_level_sizes(gmg_handle h, int32_t l, int64_t* sz) {
   sz[6] = lv.nc;
   sz[7] = lv.nnzE;
   sz[8] = lv.bcolor ? 1 : 0;
+  return GMG_OK;
+}
+
+int gmg_level_tuning(gmg_handle h, int32_t l, int32_t* out) {
+  if (!h || !out || l < 0 || l >= (int32_t)h->L.size()) return GMG_INVALID_ARGUMENT;
+  const LevelView& v = h->L[l].view;
+  const bool multi = l < h->tail_start;
+  out[0] = multi && l > 0 ? v.ra : 0;
+  out[1] = multi ? v.rt : 0;
+  out[2] = multi && l == 0 ? v.ch : 0;
+  out[3] = multi && l > 0 && v.B.nblk > 0 ? 1 : 0;
   return GMG_OK;
 }
 

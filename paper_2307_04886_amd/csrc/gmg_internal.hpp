@@ -206,6 +206,7 @@ struct LevelViewT {
   Sell<V> A;                            // A_l
   Sell<V> T;                            // P_l^T (rows: coarse points)
   int32_t ra = 1, rt = 1;               // lanes per row for A_l / P_l^T (power of two)
+  int32_t ch = 8;                       // entries per load chunk of the one-lane-per-row kernels (level 0)
   int32_t maxa = 0, maxt = 0;           // longest row of A_l / P_l^T
   const V* diag = nullptr;
   const int32_t* q_col = nullptr;       // P_l, SoA ELL-3 [3][n]
@@ -487,6 +488,7 @@ void galerkin_values(Handle& h, Level& lv, Level& nx);     // same pattern, valu
 void colouring(Handle& h, Level& lv, int level);
 void block_order(Handle& h, Level& lv);                     // grid cells and block colours of a level
 void block_values(Handle& h, Level& lv);                    // block ELL values from the current A_l
+void autotune(Handle& h);                                   // row-kernel shapes of the multi-launch levels (tune.hip)
 void solve_layout(Handle& h, Level& lv, const Level* nx, const int32_t* t_rp, const int32_t* t_col,
                   const double* t_val);
 void coarse_factor(Handle& h, Level& lv);

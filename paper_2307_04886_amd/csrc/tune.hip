@@ -1,0 +1,126 @@
+// Autotuner of the row kernels' shapes: for every level solved by separate
+// launches, the lanes per row of the SELL row kernels of A_l (residual and
+// colour sweeps) and of P_l^T (restriction), and the load chunk of level 0's
+// one-lane-per-row kernels, are picked by timing the candidates on the
+// level's own data.  A shape only distributes a row's terms over lanes or
+// loads: every row is still summed in its entry order, so the choice never
+// changes a result bit.  Choices are cached per shape class (kind, rows,
+// mean and longest row), so later builds of similar levels reuse them; the
+// first build of a class pays for the measurement.
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <mutex>
+#include <tuple>
+
+#include "gmg_internal.hpp"
+
+namespace gmg {
+
+namespace {
+
+enum TuneKind : int32_t { TUNE_CHUNK0 = 0, TUNE_LANES_A = 1, TUNE_LANES_T = 2 };
+
+struct TuneKey {
+  int32_t kind, rows, mean, maxlen;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(kind, rows, mean, maxlen) < std::tie(o.kind, o.rows, o.mean, o.maxlen);
+  }
+};
+
+std::mutex g_tune_mutex;
+std::map<TuneKey, int32_t> g_tune;
+
+TuneKey key_of(int32_t kind, int64_t rows, int64_t entries, int32_t maxlen) {
+  const double r = (double)std::max<int64_t>(rows, 1);
+  return TuneKey{kind, (int32_t)std::floor(2.0 * std::log2(r)), (int32_t)std::lround((double)entries / r), maxlen};
+}
+
+// Smallest time of three launches after one warm-up, in milliseconds.
+template <class F>
+double time_launch(hipStream_t s, hipEvent_t e0, hipEvent_t e1, F launch) {
+  launch();
+  double best = 1e30;
+  for (int k = 0; k < 3; ++k) {
+    check_hip(hipEventRecord(e0, s), "tuning event");
+    launch();
+    check_hip(hipEventRecord(e1, s), "tuning event");
+    check_hip(hipEventSynchronize(e1), "tuning event");
+    float ms = 0.f;
+    check_hip(hipEventElapsedTime(&ms, e0, e1), "tuning event");
+    best = std::min(best, (double)ms);
+  }
+  return best;
+}
+
+// The cached choice for key, or the fastest candidate (then cached).
+template <class F>
+int32_t choose(const TuneKey& key, std::initializer_list<int32_t> cand, hipStream_t s, hipEvent_t e0, hipEvent_t e1,
+               F launch_with) {
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) return it->second;
+  }
+  int32_t best = *cand.begin();
+  double tbest = 1e30;
+  for (int32_t c : cand) {
+    const double t = time_launch(s, e0, e1, [&] { launch_with(c); });
+    if (t < tbest) {
+      tbest = t;
+      best = c;
+    }
+  }
+  std::lock_guard<std::mutex> lock(g_tune_mutex);
+  g_tune[key] = best;
+  return best;
+}
+
+}  // namespace
+
+void autotune(Handle& h) {
+  const int nl = (int)h.L.size();
+  if (!h.opt.autotune || nl < 2 || h.tail_start < 1) return;
+  hipStream_t s = h.stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  check_hip(hipEventCreate(&e0), "tuning event");
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    check_hip(hipErrorOutOfMemory, "tuning event");
+  }
+  try {
+    for (int l = 0; l < h.tail_start; ++l) {
+      Level& lv = h.L[l];
+      LevelView& v = lv.view;
+      const LevelView& cv = h.L[l + 1].view;
+      // the residual writes the level's residual vector and the restriction the next
+      // level's right-hand side and iterate: all of them are rewritten by every cycle
+      if (l == 0) {
+        v.ch = choose(key_of(TUNE_CHUNK0, v.n, lv.nnzA, v.maxa), {4, 8, 16}, s, e0, e1, [&](int32_t c) {
+          LevelView t = v;
+          t.ch = c;
+          residual(t, s, true);
+        });
+      } else {
+        v.ra = choose(key_of(TUNE_LANES_A, v.n, lv.nnzA, v.maxa), {4, 8, 16, 32, 64}, s, e0, e1, [&](int32_t c) {
+          LevelView t = v;
+          t.ra = c;
+          residual(t, s, false);
+        });
+      }
+      v.rt = choose(key_of(TUNE_LANES_T, cv.n, lv.nnzP, v.maxt), {4, 8, 16, 32, 64}, s, e0, e1, [&](int32_t c) {
+        LevelView t = v;
+        t.rt = c;
+        restrict_to(t, cv, s, 0);
+      });
+    }
+  } catch (...) {
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    throw;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+}
+
+}  // namespace gmg

@@ -378,3 +378,25 @@ def test_error_paths():
     with pytest.raises(g.GMGError) as e:
         h.solve(b)
     assert e.value.status == -1
+
+
+def test_autotuned_shapes_keep_the_bits():
+    """The autotuner only changes how rows are spread over lanes and loads:
+    hierarchies built with measured shapes and with the fixed rules give the
+    same bits, and the chosen shapes are among the candidates."""
+    _say("[gpu] autotuned row-kernel shapes")
+    prob = problem("torus256")
+    g = gmg()
+    from paper_2307_04886_amd.binding import from_problem
+    tuned, _ = from_problem(prob, g.default_options(min_coarse_points=1000, autotune=1))
+    fixed, _ = from_problem(prob, g.default_options(min_coarse_points=1000, autotune=0))
+    for l in range(tuned.num_levels):
+        t = tuned.tuning(l)
+        assert t["lanes_A"] in (0, 4, 8, 16, 32, 64) and t["lanes_PT"] in (0, 4, 8, 16, 32, 64)
+        assert t["chunk"] in (0, 4, 8, 16)
+        _say(f"[gpu]   level {l}: {t}")
+    assert tuned.tuning(0)["chunk"] > 0 and tuned.tuning(1)["block_sweep"] == 1
+    b = torch.from_numpy(prob.rhs).cuda()
+    assert torch.equal(tuned.solve(b)[0], fixed.solve(b)[0])
+    for precision in ("f64", "f32"):
+        assert torch.equal(tuned.solve_pcg(b, precision=precision)[0], fixed.solve_pcg(b, precision=precision)[0])
