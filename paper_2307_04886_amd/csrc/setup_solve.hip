@@ -861,7 +861,8 @@ __global__ void k_block_rowinfo(const int32_t* rp, const int32_t* perm, const in
   rinfo[k] = ((rp[o + 1] - rp[o]) << 8) | color[o];
 }
 
-// Per block: its header and its gather list (own rows, then halo rows, padded with row 0).
+// Per block: its header and its gather list (own rows, then halo rows, padded with the
+// block's first row, so that loads of padding slots share a line with a real load).
 __global__ void k_block_gather(const int32_t* boff, const int32_t* brows, const int32_t* hoff, const int32_t* hlist,
                                const int32_t* bw, const int32_t* beoff, const uint64_t* bmask, int32_t gstride,
                                BlockHdr* hdr, int32_t* glist) {
@@ -879,7 +880,7 @@ __global__ void k_block_gather(const int32_t* boff, const int32_t* brows, const 
     hdr[b] = hd;
   }
   for (int32_t k = threadIdx.x; k < gstride; k += blockDim.x)
-    glist[(int64_t)b * gstride + k] = k < rows ? brows[r0 + k] : (k < rows + nh ? hlist[h0 + k - rows] : 0);
+    glist[(int64_t)b * gstride + k] = k < rows ? brows[r0 + k] : (k < rows + nh ? hlist[h0 + k - rows] : brows[r0]);
 }
 
 __global__ void k_block_mask(const int32_t* bcls, int32_t nblk, int32_t C, uint64_t* bmask) {

@@ -66,8 +66,14 @@ __global__ void __launch_bounds__(kBlock) k_gs_color(Sell<V> A, const V* __restr
 // their entries in registers: the LDS slot of each column and its value, in
 // the row's entry order, the diagonal replaced by a zero term (slot `pad`
 // holds +0), so x_i <- (b_i - sum_{j != i} A_ij x_j) / A_ii is computed with
-// the terms added in entry order, as on the other paths.
-template <int R, int K, class V>
+// the terms added in entry order, as on the other paths.  NG gather slots per
+// thread cover the gather list (NG * kBlkThreads >= its stride); they are
+// read branch-free (slots past the stride re-read its last entry), so the
+// list's loads are in flight together.  The register budget sets how many
+// workgroups a compute unit holds at once (at 168 VGPRs, three: 768 on the
+// chip), and so whether a level's blocks of one colour run in a single round;
+// a variant that needs more registers must be measured for it.
+template <int R, int K, int NG, class V>
 __global__ void __launch_bounds__(kBlkThreads) k_gs_block(BlockView<V> B, const V* __restrict__ bvec,
                                                           const V* __restrict__ diag, V* x, int32_t blk0,
                                                           int32_t c_begin, int32_t descending) {
@@ -78,12 +84,9 @@ __global__ void __launch_bounds__(kBlkThreads) k_gs_block(BlockView<V> B, const 
   // alone), then the entries, row data and iterates they point to
   const BlockHdr hd = B.hdr[b];
   const int32_t* gl = B.glist + (int64_t)b * B.gstride;
-  int32_t gi[kBlkGather];
+  int32_t gi[NG];
 #pragma unroll
-  for (int j = 0; j < kBlkGather; ++j) {
-    const int32_t k = (int32_t)threadIdx.x + j * kBlkThreads;
-    gi[j] = k < B.gstride ? gl[k] : 0;
-  }
+  for (int j = 0; j < NG; ++j) gi[j] = gl[min((int32_t)threadIdx.x + j * kBlkThreads, B.gstride - 1)];
   const int32_t r0 = hd.r0, rows = hd.rows, nh = hd.nh, w = hd.w, e0 = hd.e0;
   const int C = B.ncls;
   const int32_t pad = rows + nh;
@@ -108,7 +111,7 @@ __global__ void __launch_bounds__(kBlkThreads) k_gs_block(BlockView<V> B, const 
   }
   // the block's own rows (thread p holds rows p, p + kBlkThreads, ...) and its halo
 #pragma unroll
-  for (int j = 0; j < kBlkGather; ++j) {
+  for (int j = 0; j < NG; ++j) {
     const int32_t k = (int32_t)threadIdx.x + j * kBlkThreads;
     if (k < pad) {
       xl[k] = x[gi[j]];
@@ -231,6 +234,19 @@ __global__ void __launch_bounds__(kBlock) k_restrict(Sell<V> T, const V* __restr
     bc[g] = acc;
     xc[g] = g < first ? (acc - V(0)) / diag_c[g] : V(0);
   }
+}
+
+// The same restriction with one lane per coarse row (its terms loaded CH at a
+// time and added in entry order, as by the R-lane form).
+template <int CH, class V>
+__global__ void __launch_bounds__(kBlock) k_restrict_seq(Sell<V> T, const V* __restrict__ r, V* __restrict__ bc,
+                                                         V* __restrict__ xc, int64_t nc,
+                                                         const V* __restrict__ diag_c, int32_t first) {
+  const int64_t g = (int64_t)xcd_block() * kBlock + threadIdx.x;
+  if (g >= nc) return;
+  const V acc = row_sum_seq<CH>(T, (int32_t)g, r, -1);
+  bc[g] = acc;
+  xc[g] = g < first ? (acc - V(0)) / diag_c[g] : V(0);
 }
 
 // x_i <- x_i + sum_t P[i, t] x_c[col_t]
@@ -668,10 +684,20 @@ void block_sweep(const LevelViewT<V>& v, const Level& lv, hipStream_t s, bool de
       hipExtLaunchKernelGGL(kern, dim3(nb), dim3(kBlkThreads), (size_t)B.lds_bytes, s, t.start, t.stop, 0, B,
                             (const V*)v.b, (const V*)v.diag, v.x, B.bstart[bc], c_begin, descending ? 1 : 0);
     };
+    // gather slots: 2 cover lists of up to 512 rows and halo, 8 the largest (2048)
+    const bool g2 = B.gstride <= 2 * kBlkThreads;
     if (B.rows_per_thread == 1) {
-      if (B.width <= 32) go(k_gs_block<1, 32, V>); else go(k_gs_block<1, 64, V>);
+      if (B.width <= 32) {
+        if (g2) go(k_gs_block<1, 32, 2, V>); else go(k_gs_block<1, 32, kBlkGather, V>);
+      } else {
+        if (g2) go(k_gs_block<1, 64, 2, V>); else go(k_gs_block<1, 64, kBlkGather, V>);
+      }
     } else {
-      if (B.width <= 32) go(k_gs_block<2, 32, V>); else go(k_gs_block<2, 64, V>);
+      if (B.width <= 32) {
+        if (g2) go(k_gs_block<2, 32, 2, V>); else go(k_gs_block<2, 32, kBlkGather, V>);
+      } else {
+        if (g2) go(k_gs_block<2, 64, 2, V>); else go(k_gs_block<2, 64, kBlkGather, V>);
+      }
     }
   }
 }
@@ -725,6 +751,10 @@ void residual(const LevelViewT<V>& v, hipStream_t s, bool finest) {
 
 template <class V>
 void restrict_to(const LevelViewT<V>& v, const LevelViewT<V>& c, hipStream_t s, int32_t first) {
+  if (v.rt == 1) {
+    k_restrict_seq<8, V><<<blocks_for(c.n), kBlock, 0, s>>>(v.T, v.r, c.b, c.x, c.n, (const V*)c.diag, first);
+    return;
+  }
   with_lanes(v.rt, [&](auto RC) {
     constexpr int R = decltype(RC)::value;
     k_restrict<R, V><<<blocks_for((int64_t)c.n * R), kBlock, 0, s>>>(v.T, v.r, c.b, c.x, c.n, v.maxt,

@@ -1,12 +1,13 @@
 // Autotuner of the row kernels' shapes: for every level solved by separate
 // launches, the lanes per row of the SELL row kernels of A_l (residual and
-// colour sweeps) and of P_l^T (restriction), and the load chunk of level 0's
-// one-lane-per-row kernels, are picked by timing the candidates on the
-// level's own data.  A shape only distributes a row's terms over lanes or
-// loads: every row is still summed in its entry order, so the choice never
-// changes a result bit.  Choices are cached per shape class (kind, rows,
-// mean and longest row), so later builds of similar levels reuse them; the
-// first build of a class pays for the measurement.
+// colour sweeps) and of P_l^T (restriction, where one lane per row is also a
+// candidate), and the load chunk of level 0's one-lane-per-row kernels, are
+// picked by timing the candidates on the level's own data.  A shape only
+// distributes a row's terms over lanes or loads: every row is still summed in
+// its entry order, so the choice never changes a result bit.  Choices are
+// cached per shape class (kind, rows, mean and longest row), so later builds
+// of similar levels reuse them; the first build of a class pays for the
+// measurement.
 #include <algorithm>
 #include <cmath>
 #include <map>
@@ -108,7 +109,7 @@ void autotune(Handle& h) {
           residual(t, s, false);
         });
       }
-      v.rt = choose(key_of(TUNE_LANES_T, cv.n, lv.nnzP, v.maxt), {4, 8, 16, 32, 64}, s, e0, e1, [&](int32_t c) {
+      v.rt = choose(key_of(TUNE_LANES_T, cv.n, lv.nnzP, v.maxt), {1, 4, 8, 16, 32, 64}, s, e0, e1, [&](int32_t c) {
         LevelView t = v;
         t.rt = c;
         restrict_to(t, cv, s, 0);
