@@ -382,8 +382,8 @@ def test_error_paths():
 
 def test_autotuned_shapes_keep_the_bits():
     """The autotuner only changes how rows are spread over lanes and loads:
-    hierarchies built with measured shapes and with the fixed rules give the
-    same bits, and the chosen shapes are among the candidates."""
+    solves on hierarchies with measured shapes and with the fixed rules give
+    the same bits, and the chosen shapes are among the candidates."""
     _say("[gpu] autotuned row-kernel shapes")
     prob = problem("torus256")
     g = gmg()
@@ -392,7 +392,7 @@ def test_autotuned_shapes_keep_the_bits():
     fixed, _ = from_problem(prob, g.default_options(min_coarse_points=1000, autotune=0))
     for l in range(tuned.num_levels):
         t = tuned.tuning(l)
-        assert t["lanes_A"] in (0, 4, 8, 16, 32, 64) and t["lanes_PT"] in (0, 4, 8, 16, 32, 64)
+        assert t["lanes_A"] in (0, 4, 8, 16, 32, 64) and t["lanes_PT"] in (0, 1, 4, 8, 16, 32, 64)
         assert t["chunk"] in (0, 4, 8, 16)
         _say(f"[gpu]   level {l}: {t}")
     assert tuned.tuning(0)["chunk"] > 0 and tuned.tuning(1)["block_sweep"] == 1
