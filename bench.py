@@ -145,11 +145,12 @@ def progress(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def batched_leg(args, dev, opt, forms=("f32", "plain")):
+def batched_leg(args, dev, opt, forms=("grouped", "f32", "plain")):
     """Many meshes of uneven size with 8 right-hand sides each: every hierarchy built and every
-    right-hand side solved to the same tolerance; batched float-preconditioned CG on concurrent
-    streams against the plain double V-cycle solve of each right-hand side in turn, on the same
-    streams."""
+    right-hand side solved to the same tolerance.  Forms: the grouped float-preconditioned CG
+    (builds on 4 streams, then one CG over all hierarchies, every step one launch for all meshes);
+    the same CG per mesh on the 4 streams; the plain double V-cycle solve of each right-hand side
+    in turn on the same 4 streams."""
     import torch
     import synth
     from paper_2307_04886_amd.batch import solve_many
@@ -163,26 +164,34 @@ def batched_leg(args, dev, opt, forms=("f32", "plain")):
     res = {"workload": f"{len(batch)} jittered tori and icospheres, {min(b.n for b, _ in batch)}"
                        f"-{max(b.n for b, _ in batch)} vertices ({sum(b.n for b, _ in batch)} in total),"
                        f" 8 right-hand sides each, (M + 1e-3 L), tol {args.tol}", "solves": nsolves}
+    names = {"grouped": "setup on 4 streams + one float-preconditioned double CG over all hierarchies "
+                        "(gmg_solve_pcg_grouped: each step one launch for all meshes, 8 right-hand sides each)",
+             "f32": "setup + float-preconditioned double CG per mesh (gmg_solve_pcg_batched), 8 right-hand "
+                    "sides per launch, 4 streams",
+             "plain": "setup + plain double V-cycle solve of each right-hand side in turn, the same 4 streams"}
     for form in forms:
-        kw = dict(precision="f32") if form == "f32" else dict(max_iters=200, form="plain")
+        kw = {"grouped": dict(precision="f32", form="grouped"), "f32": dict(precision="f32"),
+              "plain": dict(max_iters=200, form="plain")}[form]
         solve_many(systems, streams=4, tol=args.tol, **kw)
         torch.cuda.synchronize()
+        timing = {}
         t1 = time.perf_counter()
-        r = solve_many(systems, streams=4, tol=args.tol, **kw)
+        r = solve_many(systems, streams=4, tol=args.tol, timing=timing, **kw)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t1
         if any(st != 0 for _, _, st in r):
             raise RuntimeError(f"{form} many-mesh solve did not converge")
         progress(f"many-mesh {form}: {1e3 * dt:.1f} ms")
-        if form == "f32":
-            res.update({"value": nsolves / dt, "unit": "solves/s", "ms": 1e3 * dt,
-                        "form": "setup + float-preconditioned double CG, 8 right-hand sides per launch, 4 streams"})
-        else:
-            res.update({"plain_fp64_form": "setup + plain double V-cycle solve of each right-hand side in turn, "
-                                           "the same 4 streams",
-                        "plain_fp64_value": nsolves / dt, "plain_fp64_ms": 1e3 * dt})
-    if "value" in res and "plain_fp64_ms" in res:
-        res["vs_plain_fp64"] = res["plain_fp64_ms"] / res["ms"]
+        rec = {"form": names[form], "value": nsolves / dt, "unit": "solves/s", "ms": 1e3 * dt}
+        if timing:
+            rec.update({"build_ms": 1e3 * timing["build_s"], "solve_ms": 1e3 * timing["solve_s"]})
+        res[form] = rec
+    main = "grouped" if "grouped" in res else "f32"
+    if main in res:
+        res.update({"value": res[main]["value"], "unit": "solves/s", "ms": res[main]["ms"], "main_form": main})
+    for other in ("f32", "plain"):
+        if other in res and main in res and other != main:
+            res[f"vs_{other}"] = res[other]["ms"] / res[main]["ms"]
     return res
 
 
@@ -223,7 +232,7 @@ def main():
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     if args.batched_only:
-        print(json.dumps({"batched": batched_leg(args, dev, default_options(), forms=("f32",))}), flush=True)
+        print(json.dumps({"batched": batched_leg(args, dev, default_options(), forms=("grouped", "f32"))}), flush=True)
         return
     t0 = time.time()
     prob = synth.config_torus(args.size, args.size)

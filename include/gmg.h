@@ -151,6 +151,37 @@ int gmg_solve_pcg_batched(gmg_handle h, int32_t nrhs, const double* B_dev, doubl
                           int32_t max_iters, int32_t precision, void* stream, gmg_solve_info* infos);
 
 /*
+ * gmg_solve_pcg_batched for a group of hierarchies at once (many meshes, many
+ * right-hand sides; Sec. 2 and Sec. 5.5 motivate many solves per hierarchy):
+ * every step of a CG iteration is one launch for all members still
+ * iterating, so the launch latency is paid once per group instead of once per
+ * mesh, and the whole iteration is one replayed hipGraph.  Member m runs
+ * exactly the steps of gmg_solve_pcg_batched on its own hierarchy, so its
+ * solutions, iteration counts and residuals are bit-identical to a
+ * gmg_solve_pcg_batched call with the same arguments; members that have
+ * converged stop while the others go on.
+ *
+ *  count          number of members (>= 0)
+ *  handles        host array of count distinct handles on one device
+ *  nrhs           host array: member m's right-hand sides, 0..8 (0: member skipped)
+ *  B_dev, X_dev   host arrays of count device pointers, each laid out as in
+ *                 gmg_solve_pcg_batched for its member (X: initial guesses in, solutions out)
+ *  tol, max_iters, precision, stream: as for gmg_solve_pcg_batched (every member's
+ *                 work is queued on `stream`, which is synchronised on return)
+ *  infos          host array of count x 8 gmg_solve_info: member m's right-hand side q at
+ *                 m * 8 + q (entries q >= nrhs[m] untouched)
+ *  status_out     host array of count statuses (GMG_OK or GMG_NOT_CONVERGED per member)
+ * Returns GMG_OK if every member converged, GMG_NOT_CONVERGED if some did not,
+ * GMG_INVALID_ARGUMENT (repeated handle, handles on different devices, nrhs
+ * outside 0..8, null pointers, non-finite B or X), GMG_NOT_SPD,
+ * GMG_OUT_OF_MEMORY or GMG_DEVICE_ERROR.  A handle of the group must not be
+ * used by another call until this one returns.
+ */
+int gmg_solve_pcg_grouped(int32_t count, const gmg_handle* handles, const int32_t* nrhs, const double* const* B_dev,
+                          double* const* X_dev, double tol, int32_t max_iters, int32_t precision, void* stream,
+                          gmg_solve_info* infos, int32_t* status_out);
+
+/*
  * gmg_precondition for nrhs vectors (layout as in gmg_solve_pcg_batched):
  * Z_q = B R_q, one symmetric V-cycle from zero per vector.
  */

@@ -28,7 +28,7 @@ EXPORTS = {
 
 # Symbols the library exports (checked on load).
 SYMBOLS = ["gmg_default_options", "gmg_build_hierarchy", "gmg_solve", "gmg_solve_pcg", "gmg_precondition",
-           "gmg_update_matrix", "gmg_pattern_outer", "gmg_solve_pcg_batched", "gmg_precondition_batched", "gmg_precondition_noalloc", "gmg_free", "gmg_status_string", "gmg_last_error",
+           "gmg_update_matrix", "gmg_pattern_outer", "gmg_solve_pcg_batched", "gmg_solve_pcg_grouped", "gmg_precondition_batched", "gmg_precondition_noalloc", "gmg_free", "gmg_status_string", "gmg_last_error",
            "gmg_num_levels", "gmg_level_sizes", "gmg_level_tuning", "gmg_export_level", "gmg_timer_start", "gmg_timer_stop"]
 
 # gmg_precision
@@ -79,6 +79,9 @@ def library():
     L.gmg_precondition.argtypes = [P, P, P, I32, P]
     L.gmg_update_matrix.argtypes = [P, P, P]
     L.gmg_solve_pcg_batched.argtypes = [P, I32, P, P, ctypes.c_double, I32, I32, P, ctypes.POINTER(SolveInfo)]
+    L.gmg_solve_pcg_grouped.argtypes = [I32, ctypes.POINTER(P), ctypes.POINTER(I32), ctypes.POINTER(P),
+                                        ctypes.POINTER(P), ctypes.c_double, I32, I32, P, ctypes.POINTER(SolveInfo),
+                                        ctypes.POINTER(I32)]
     L.gmg_precondition_batched.argtypes = [P, I32, P, P, I32, P]
     L.gmg_precondition_noalloc.argtypes = [P, P, P, I32, P]
     L.gmg_pattern_outer.argtypes = [I64, P, P, P, P, ctypes.c_double, P, P]
@@ -305,6 +308,34 @@ class Hierarchy:
         st = library().gmg_update_matrix(self._h, pv, _stream_ptr(stream))
         if st:
             raise _err(st)
+
+
+def solve_pcg_grouped(hierarchies, Bs, Xs=None, tol=1e-8, max_iters=100, precision="f32", stream=None):
+    """gmg_solve_pcg_grouped: one CG over many hierarchies, B_m of shape (nrhs_m <= 8, n_m).
+    Returns ([X_m], [[SolveInfo]], [status_m], status)."""
+    import torch
+    count = len(hierarchies)
+    if len(Bs) != count or (Xs is not None and len(Xs) != count):
+        raise ValueError("one B (and X) per hierarchy")
+    Xs = [torch.zeros_like(B) for B in Bs] if Xs is None else list(Xs)
+    ph = (ctypes.c_void_p * max(count, 1))()
+    pn = (ctypes.c_int32 * max(count, 1))()
+    pb = (ctypes.c_void_p * max(count, 1))()
+    px = (ctypes.c_void_p * max(count, 1))()
+    for m, (h, B, X) in enumerate(zip(hierarchies, Bs, Xs)):
+        nrhs = int(B.shape[0])
+        ph[m] = h._h
+        pn[m] = nrhs
+        pb[m] = _dev(B, torch.float64, (nrhs, h.n), "B")
+        px[m] = _dev(X, torch.float64, (nrhs, h.n), "X")
+    infos = (SolveInfo * max(8 * count, 1))()
+    status = (ctypes.c_int32 * max(count, 1))()
+    st = library().gmg_solve_pcg_grouped(count, ph, pn, pb, px, float(tol), int(max_iters), PRECISION[precision],
+                                         _stream_ptr(stream), infos, status)
+    if st < 0:
+        raise _err(st)
+    out_infos = [list(infos[8 * m: 8 * m + int(B.shape[0])]) for m, B in enumerate(Bs)]
+    return Xs, out_infos, [int(status[m]) for m in range(count)], st
 
 
 def pattern_outer(rowptr, col, u, v, scale=1.0, out=None, stream=None):

@@ -2,6 +2,7 @@
 // the hierarchy construction (Sec. 4, Alg. 1), the V-cycle driver (Alg. 1,
 // Alg. 2) and the inspection exports.
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -311,11 +312,10 @@ bool options_ok(const gmg_options& o) {
 // The single-workgroup tail of a cycle: levels tail_start.. with their views
 // and the LDS offsets of their arrays (batched layout: make_tail_batched).
 template <class V>
-void make_tail(const Handle& h, Cycle<V>& c) {
+void make_tail_at(const Handle& h, const Cycle<V>& c, int start, TailDescT<V>& t) {
   const int nl = (int)h.L.size();
-  TailDescT<V>& t = c.tail;
   t = TailDescT<V>();
-  t.nlev = nl - h.tail_start;
+  t.nlev = nl - start;
   t.nu_pre = h.opt.nu_pre;
   t.nu_post = h.opt.nu_post;
   t.descending_post = c.symmetric ? 1 : 0;
@@ -326,9 +326,9 @@ void make_tail(const Handle& h, Cycle<V>& c) {
     off += (bytes + 15) & ~(int64_t)15;
     return o;
   };
-  for (int l = h.tail_start; l < nl; ++l) {
+  for (int l = start; l < nl; ++l) {
     const LevelViewT<V>& v = c.v[l];
-    const int i = l - h.tail_start;
+    const int i = l - start;
     t.lv[i] = v;
     const bool coarsest = l + 1 == nl;
     t.o_x[i] = take(((int64_t)v.n + (coarsest ? 0 : 1)) * sizeof(V));
@@ -340,6 +340,11 @@ void make_tail(const Handle& h, Cycle<V>& c) {
   }
   if (off > kTailLdsMax) throw Error{GMG_DEVICE_ERROR, "tail LDS layout exceeds its budget"};
   t.lds_bytes = (int32_t)off;
+}
+
+template <class V>
+void make_tail(const Handle& h, Cycle<V>& c) {
+  make_tail_at(h, c, h.tail_start, c.tail);
 }
 
 struct PT {
@@ -817,10 +822,9 @@ int pcg(Handle& h, double nb, double tol, int32_t max_iters, hipStream_t s, int3
 // ------------------------------------------------------------------ batched right-hand sides
 // The single-workgroup tail of a batched cycle: as make_tail, iterates of
 // n * kBatch elements.
+// LDS places of the batched tail's iterates, level by level while they fit.
 template <class V>
-void make_tail_batched(const Handle& h, Cycle<V>& c) {
-  make_tail(h, c);
-  TailDescT<V>& t = c.tail;
+void place_batched_tail(TailDescT<V>& t) {
   const int32_t cap = kTailLdsBytes / (int32_t)sizeof(V);
   t.lds_elems = 0;
   for (int l = 0; l < t.nlev; ++l) {
@@ -832,6 +836,12 @@ void make_tail_batched(const Handle& h, Cycle<V>& c) {
       t.lds_off[l] = -1;
     }
   }
+}
+
+template <class V>
+void make_tail_batched(const Handle& h, Cycle<V>& c) {
+  make_tail(h, c);
+  place_batched_tail(c.tail);
 }
 
 void bat_alloc(Handle& h) {
@@ -1086,6 +1096,394 @@ void precondition_noalloc(Handle& h, const double* r, double* z, int32_t precisi
     permute_out(l0.perm, (const double*)c.v[0].x, z, n, s);
   }
   check_hip(hipGetLastError(), "preconditioner launch");
+}
+
+// ------------------------------------------------------------------ grouped solve
+// The batched CG (pcg_batched) for a group of hierarchies at once, each member
+// with up to kBatch right-hand sides already in its h.bat.b / h.bat.x: every
+// step of a CG iteration is one grouped launch over all members still
+// iterating, and the iteration is one hipGraph for the whole group.  Each
+// member goes through exactly pcg_batched's steps in pcg_batched's order (its
+// true-residual checks included), so its results are bitwise those of a
+// pcg_batched call on it alone.
+
+// Device copies of host tables, returned to the block cache when the group ends.
+struct DeviceTables {
+  hipStream_t s;
+  std::vector<void*> blocks;
+  template <class T>
+  T* put(const std::vector<T>& v) {
+    if (v.empty()) return nullptr;
+    T* d = (T*)talloc(s, v.size() * sizeof(T));
+    blocks.push_back(d);
+    check_hip(hipMemcpyAsync(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s), "group tables");
+    return d;
+  }
+  ~DeviceTables() {
+    for (void* p : blocks) tfree(s, p);
+  }
+};
+
+// One row-parallel step: each listed member's job and the tiles covering it.
+template <class J>
+struct RowStep {
+  std::vector<J> jobs;
+  std::vector<GTile> tiles;
+  const J* djobs = nullptr;
+  const GTile* dtiles = nullptr;
+  void add(const J& j, int32_t member, int64_t elements) {
+    const int32_t job = (int32_t)jobs.size();
+    jobs.push_back(j);
+    const int64_t nt = (elements + kBlock - 1) / kBlock;
+    for (int64_t t = 0; t < nt; ++t) tiles.push_back(GTile{job, (int32_t)t, member, 0});
+  }
+  void upload(DeviceTables& d) {
+    djobs = d.put(jobs);
+    dtiles = d.put(tiles);
+  }
+  int32_t ntiles() const { return (int32_t)tiles.size(); }
+};
+
+template <class V>
+struct GroupPlan {
+  // the cycle as a sequence of steps, in launch order
+  enum Kind { SWEEP, RESIDUAL, RESTRICT, PROLONG, GEMV, TAIL };
+  struct Step {
+    Kind kind;
+    int32_t index;
+  };
+  std::vector<Step> order;
+  std::vector<RowStep<GSweepJob<V>>> sweeps;
+  std::vector<RowStep<GResJob<V>>> residuals;
+  std::vector<RowStep<GRestJob<V>>> restricts;
+  std::vector<RowStep<GProlJob<V>>> prolongs;
+  RowStep<GGemvJob<V>> gemv;
+  std::vector<TailDescT<V>> tails;
+  std::vector<int32_t> tail_members;
+  const TailDescT<V>* dtails = nullptr;
+  const int32_t* dtail_members = nullptr;
+  int32_t tail_lds = 0;
+  // CG: one job per member, tiles over each member's n * kBatch elements
+  RowStep<GKryJob<V>> kry;
+  int32_t count = 0;
+};
+
+template <class V>
+void build_group_plan(std::vector<Handle*>& H, GroupPlan<V>& P, DeviceTables& dt) {
+  const int M = (int)H.size();
+  P.count = M;
+  std::vector<Cycle<V>*> C(M);
+  // Each member's tail starts where all of its levels' iterates fit the
+  // batched tail's LDS (the levels above it run as grouped launches, with the
+  // same arithmetic as in the tail): one workgroup then carries only small
+  // levels, and the group waits for the slowest member's tail once per cycle.
+  std::vector<int> ts(M);
+  int Lmax = 0, pre = 0, post = 0;
+  for (int m = 0; m < M; ++m) {
+    const Handle& h = *H[m];
+    C[m] = &bat_ready<V>(*H[m]);
+    const int nl = (int)h.L.size();
+    int start = nl - 1;
+    int64_t elems = h.L[nl - 1].n * kBatch;
+    while (start > h.tail_start && elems + h.L[start - 1].n * kBatch <= kTailLdsBytes / (int64_t)sizeof(V)) {
+      elems += h.L[start - 1].n * kBatch;
+      --start;
+    }
+    ts[m] = start;
+    Lmax = std::max(Lmax, start);
+    pre = std::max(pre, h.opt.nu_pre);
+    post = std::max(post, h.opt.nu_post);
+  }
+  auto classes = [&](int m, int l) { return (int)H[m]->L[l].color_ptr.size() - 1; };
+  auto sweep_step = [&](int l, int sweep, bool descending) {
+    int kmax = 0;
+    for (int m = 0; m < M; ++m)
+      if (l < ts[m]) kmax = std::max(kmax, classes(m, l));
+    for (int k = 0; k < kmax; ++k) {
+      RowStep<GSweepJob<V>> st;
+      for (int m = 0; m < M; ++m) {
+        const Handle& h = *H[m];
+        const int nu = descending ? h.opt.nu_post : h.opt.nu_pre;
+        const int K = l < ts[m] ? classes(m, l) : 0;
+        if (sweep >= nu || k >= K) continue;
+        const int c = descending ? K - 1 - k : k;      // the batched cycle is symmetric
+        const int32_t r0 = h.L[l].color_ptr[c], r1 = h.L[l].color_ptr[c + 1];
+        if (r1 <= r0) continue;
+        const LevelViewT<V>& v = C[m]->v[l];
+        st.add(GSweepJob<V>{v.A, v.diag, v.b, v.x, r0, r1}, m, (int64_t)(r1 - r0) * kBatch);
+      }
+      if (st.ntiles() == 0) continue;
+      P.order.push_back({GroupPlan<V>::SWEEP, (int32_t)P.sweeps.size()});
+      P.sweeps.push_back(std::move(st));
+    }
+  };
+  for (int l = 0; l < Lmax; ++l) {
+    for (int sweep = 0; sweep < pre; ++sweep) sweep_step(l, sweep, false);
+    RowStep<GResJob<V>> rs;
+    RowStep<GRestJob<V>> rt;
+    for (int m = 0; m < M; ++m) {
+      if (l >= ts[m]) continue;
+      const LevelViewT<V>& v = C[m]->v[l];
+      const LevelViewT<V>& cv = C[m]->v[l + 1];
+      rs.add(GResJob<V>{v.A, v.b, v.x, v.r, v.n}, m, (int64_t)v.n * kBatch);
+      rt.add(GRestJob<V>{v.T, v.r, cv.b, cv.x, cv.n}, m, (int64_t)cv.n * kBatch);
+    }
+    P.order.push_back({GroupPlan<V>::RESIDUAL, (int32_t)P.residuals.size()});
+    P.residuals.push_back(std::move(rs));
+    P.order.push_back({GroupPlan<V>::RESTRICT, (int32_t)P.restricts.size()});
+    P.restricts.push_back(std::move(rt));
+  }
+  for (int m = 0; m < M; ++m) {
+    const Handle& h = *H[m];
+    const Cycle<V>& c = *C[m];
+    if (ts[m] + 1 == (int)h.L.size()) {
+      const LevelViewT<V>& v = c.v[ts[m]];
+      P.gemv.add(GGemvJob<V>{h.cinv, v.b, v.x, v.n}, m, (int64_t)v.n * kBatch);
+    } else {
+      TailDescT<V> t;
+      make_tail_at(h, c, ts[m], t);
+      place_batched_tail(t);
+      P.tails.push_back(t);
+      P.tail_members.push_back(m);
+      P.tail_lds = std::max(P.tail_lds, t.lds_elems * (int32_t)sizeof(V));
+    }
+  }
+  P.order.push_back({GroupPlan<V>::TAIL, 0});
+  P.order.push_back({GroupPlan<V>::GEMV, 0});
+  for (int l = Lmax - 1; l >= 0; --l) {
+    RowStep<GProlJob<V>> pr;
+    for (int m = 0; m < M; ++m) {
+      if (l >= ts[m]) continue;
+      const LevelViewT<V>& v = C[m]->v[l];
+      const LevelViewT<V>& cv = C[m]->v[l + 1];
+      pr.add(GProlJob<V>{v.q_col, v.q_val, v.q_cnt, cv.x, v.x, v.n}, m, (int64_t)v.n * kBatch);
+    }
+    P.order.push_back({GroupPlan<V>::PROLONG, (int32_t)P.prolongs.size()});
+    P.prolongs.push_back(std::move(pr));
+    for (int sweep = 0; sweep < post; ++sweep) sweep_step(l, sweep, true);
+  }
+  for (int m = 0; m < M; ++m) {
+    Handle& h = *H[m];
+    Batch& k = h.bat;
+    const int64_t n = h.L[0].n;
+    P.kry.add(GKryJob<V>{h.L[0].view.A, k.x, k.b, k.r, k.r_old, k.p, k.q, k.part, k.scal, C[m]->v[0].b,
+                         C[m]->v[0].x, h.flags, n},
+              m, n * kBatch);
+  }
+  for (auto& st : P.sweeps) st.upload(dt);
+  for (auto& st : P.residuals) st.upload(dt);
+  for (auto& st : P.restricts) st.upload(dt);
+  for (auto& st : P.prolongs) st.upload(dt);
+  P.gemv.upload(dt);
+  P.kry.upload(dt);
+  P.dtails = dt.put(P.tails);
+  P.dtail_members = dt.put(P.tail_members);
+}
+
+// One CG iteration of every member with active[m] != 0 (bat_iteration).
+template <class V>
+void group_iteration(const GroupPlan<V>& P, const int32_t* active, hipStream_t s) {
+  gcycle_start(P.kry.djobs, P.kry.dtiles, P.kry.ntiles(), active, s);
+  for (const auto& st : P.order) {
+    switch (st.kind) {
+      case GroupPlan<V>::SWEEP: {
+        const auto& r = P.sweeps[st.index];
+        gsweep(r.djobs, r.dtiles, r.ntiles(), active, s);
+        break;
+      }
+      case GroupPlan<V>::RESIDUAL: {
+        const auto& r = P.residuals[st.index];
+        gresidual(r.djobs, r.dtiles, r.ntiles(), active, s);
+        break;
+      }
+      case GroupPlan<V>::RESTRICT: {
+        const auto& r = P.restricts[st.index];
+        grestrict(r.djobs, r.dtiles, r.ntiles(), active, s);
+        break;
+      }
+      case GroupPlan<V>::PROLONG: {
+        const auto& r = P.prolongs[st.index];
+        gprolong(r.djobs, r.dtiles, r.ntiles(), active, s);
+        break;
+      }
+      case GroupPlan<V>::GEMV:
+        ggemv(P.gemv.djobs, P.gemv.dtiles, P.gemv.ntiles(), active, s);
+        break;
+      case GroupPlan<V>::TAIL:
+        gtail(P.dtails, P.dtail_members, (int32_t)P.tails.size(), P.tail_lds, active, s);
+        break;
+    }
+  }
+  gkry_direction(P.kry.djobs, P.count, P.kry.dtiles, P.kry.ntiles(), active, s);
+  gkry_step(P.kry.djobs, P.count, active, s);
+}
+
+// Pinned host memory for the group's masks and scalar reads.
+struct PinnedBuffer {
+  void* p = nullptr;
+  explicit PinnedBuffer(size_t bytes) {
+    check_hip(hipHostMalloc(&p, bytes, hipHostMallocDefault), "pinned host buffer");
+  }
+  ~PinnedBuffer() {
+    if (p) (void)hipHostFree(p);
+  }
+};
+
+struct GroupGraph {
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  ~GroupGraph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cap) (void)hipStreamDestroy(cap);
+  }
+};
+
+// nq[m] right-hand sides of member m (1..kBatch); infos[m * kBatch + q]; status[m].
+template <class V>
+void pcg_grouped(std::vector<Handle*>& H, const std::vector<int>& nq, double tol, int32_t max_iters, hipStream_t s,
+                 gmg_solve_info* infos, int32_t* status) {
+  const int M = (int)H.size();
+  DeviceTables dt{s, {}};
+  GroupPlan<V> P;
+  build_group_plan<V>(H, P, dt);
+  // masks (iterating, checking) and the gathered scalars, in pinned memory
+  const size_t mask_bytes = (size_t)M * 4, read_elems = (size_t)M * (kBatch + 1);
+  PinnedBuffer pin(2 * mask_bytes + read_elems * 8);
+  int32_t* h_iter = (int32_t*)pin.p;
+  int32_t* h_check = h_iter + M;
+  uint64_t* h_read = (uint64_t*)((char*)pin.p + 2 * mask_bytes);
+  uint64_t* d_read = nullptr;
+  check_hip(hipHostGetDevicePointer((void**)&d_read, h_read, 0), "pinned host buffer");
+  int32_t* d_masks = (int32_t*)talloc(s, 2 * mask_bytes);
+  dt.blocks.push_back(d_masks);
+  int32_t* d_iter = d_masks;
+  int32_t* d_check = d_masks + M;
+  auto set_mask = [&](int32_t* hm, int32_t* dm, const std::vector<char>& on) {
+    for (int m = 0; m < M; ++m) hm[m] = on[m] ? 1 : 0;
+    check_hip(hipMemcpyAsync(dm, hm, mask_bytes, hipMemcpyHostToDevice, s), "group mask");
+  };
+  // reads one kBatch-vector of scalars (and the flags) of every member
+  auto read_all = [&](int which, std::vector<std::array<double, kBatch>>& vals, std::vector<int32_t>& flags) {
+    ggather_scalars(P.kry.djobs, M, which, d_read, s);
+    check_hip(hipGetLastError(), "group read");
+    sync(s, "group read");
+    for (int m = 0; m < M; ++m) {
+      for (int q = 0; q < kBatch; ++q) std::memcpy(&vals[m][q], &h_read[m * (kBatch + 1) + q], 8);
+      flags[m] = (int32_t)h_read[m * (kBatch + 1) + kBatch];
+    }
+  };
+  std::vector<std::array<double, kBatch>> nb(M), norm(M), rel(M);
+  std::vector<int32_t> flags(M, 0);
+  std::vector<std::array<int32_t, kBatch>> first(M);
+  std::vector<unsigned> zero(M, 0);
+  std::vector<int32_t> it(M, 0);
+  std::vector<char> all_members(M, 1), iterating(M, 0), checking(M, 0);
+  // norms of b, zero right-hand sides (and padding columns) solved by x = 0
+  set_mask(h_check, d_check, all_members);
+  gnorms_b(P.kry.djobs, M, d_check, s);
+  read_all(KS_BNORM, nb, flags);
+  for (int m = 0; m < M; ++m) {
+    if (flags[m] & F_INVALID) throw Error{GMG_INVALID_ARGUMENT, "non-finite b or x"};
+    for (int q = 0; q < kBatch; ++q)
+      if (q >= nq[m] || nb[m][q] == 0.0) zero[m] |= 1u << q;
+    if (zero[m]) mzero_columns(H[m]->bat.x, H[m]->L[0].n, zero[m], s);
+    for (int q = 0; q < kBatch; ++q) first[m][q] = (zero[m] >> q) & 1u ? 0 : -1;
+  }
+  // true residuals of the members in `on`: rel, and whether all of a member's meet tol
+  std::vector<char> passed(M, 0);
+  auto true_residuals = [&](const std::vector<char>& on) {
+    set_mask(h_check, d_check, on);
+    gresidual_norms(P.kry.djobs, M, d_check, s);
+    read_all(KS_NORM, norm, flags);
+    for (int m = 0; m < M; ++m) {
+      if (!on[m]) continue;
+      bool all = true;
+      for (int q = 0; q < kBatch; ++q) {
+        rel[m][q] = (zero[m] >> q) & 1u ? 0.0 : norm[m][q] / nb[m][q];
+        all = all && rel[m][q] <= tol;
+      }
+      passed[m] = all;
+    }
+  };
+  true_residuals(all_members);
+  int remaining = 0;
+  for (int m = 0; m < M; ++m) {
+    status[m] = passed[m] ? GMG_OK : GMG_NOT_CONVERGED;
+    iterating[m] = !passed[m];
+    remaining += iterating[m];
+  }
+  if (remaining > 0) {
+    set_mask(h_iter, d_iter, iterating);
+    gkry_init(P.kry.djobs, P.kry.dtiles, P.kry.ntiles(), d_iter, s);
+    GroupGraph g;
+    bool graphs = !std::getenv("GMG_DISABLE_GRAPHS");
+    if (graphs) {
+      const int saved = KernelTimer::active;
+      KernelTimer::active = -1;
+      bool ok = hipStreamCreateWithFlags(&g.cap, hipStreamNonBlocking) == hipSuccess;
+      if (ok) ok = hipStreamBeginCapture(g.cap, hipStreamCaptureModeThreadLocal) == hipSuccess;
+      if (ok) {
+        group_iteration(P, d_iter, g.cap);
+        ok = hipStreamEndCapture(g.cap, &g.graph) == hipSuccess && g.graph;
+      }
+      KernelTimer::active = saved;
+      if (ok) ok = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0) == hipSuccess;
+      if (!ok) {
+        (void)hipGetLastError();
+        graphs = false;
+      }
+    }
+    int32_t done_iters = 0;
+    while (remaining > 0 && done_iters < max_iters) {
+      set_mask(h_iter, d_iter, iterating);
+      if (graphs) check_hip(hipGraphLaunch(g.exec, s), "graph launch");
+      else group_iteration(P, d_iter, s);
+      check_hip(hipGetLastError(), "group iteration");
+      read_all(KS_NORM, norm, flags);
+      ++done_iters;
+      std::fill(checking.begin(), checking.end(), 0);
+      bool any_check = false;
+      for (int m = 0; m < M; ++m) {
+        if (!iterating[m]) continue;
+        it[m] = done_iters;
+        if (flags[m] & F_NOT_SPD) throw Error{GMG_NOT_SPD, "CG: non-positive curvature (A or the cycle not SPD)"};
+        bool all = true;
+        for (int q = 0; q < kBatch; ++q) {
+          if ((zero[m] >> q) & 1u) continue;
+          const double r = norm[m][q] / nb[m][q];
+          if (r <= tol && first[m][q] < 0) first[m][q] = done_iters;
+          all = all && r <= tol;
+        }
+        checking[m] = all;
+        any_check = any_check || all;
+      }
+      if (any_check) {
+        true_residuals(checking);
+        for (int m = 0; m < M; ++m) {
+          if (!checking[m]) continue;
+          if (passed[m]) {
+            status[m] = GMG_OK;
+            iterating[m] = 0;
+            --remaining;
+          } else {
+            for (int q = 0; q < kBatch; ++q)
+              if (rel[m][q] > tol) first[m][q] = -1;
+          }
+        }
+      }
+    }
+    if (remaining > 0) true_residuals(iterating);
+  }
+  for (int m = 0; m < M; ++m)
+    for (int q = 0; q < nq[m]; ++q) {
+      gmg_solve_info& inf = infos[(int64_t)m * kBatch + q];
+      inf.iterations = first[m][q] >= 0 ? first[m][q] : it[m];
+      inf.converged = rel[m][q] <= tol;
+      inf.rel_residual = rel[m][q];
+    }
+  sync(s, "grouped solve");
 }
 
 const char* status_text(int st) {
@@ -1434,6 +1832,76 @@ int gmg_solve_pcg_batched(gmg_handle hh, int32_t nrhs, const double* B_dev, doub
     status = e.status;
   }
   h->stream = saved;
+  return status;
+}
+
+int gmg_solve_pcg_grouped(int32_t count, const gmg_handle* handles, const int32_t* nrhs, const double* const* B_dev,
+                          double* const* X_dev, double tol, int32_t max_iters, int32_t precision, void* stream,
+                          gmg_solve_info* infos, int32_t* status_out) {
+  set_error("");
+  bool ok = count >= 0 && (count == 0 || (handles && nrhs && B_dev && X_dev && infos && status_out)) &&
+            max_iters >= 1 && tol >= 0.0 &&
+            (precision == GMG_PRECISION_F64 || precision == GMG_PRECISION_F32);
+  std::vector<Handle*> H;
+  std::vector<int> nq, idx;
+  for (int32_t m = 0; ok && m < count; ++m) {
+    Handle* h = handles[m];
+    if (!h || nrhs[m] < 0 || nrhs[m] > kBatch || (nrhs[m] > 0 && (!B_dev[m] || !X_dev[m]))) {
+      ok = false;
+      break;
+    }
+    status_out[m] = GMG_OK;
+    if (nrhs[m] == 0) continue;
+    if (std::find(H.begin(), H.end(), h) != H.end() || (!H.empty() && h->device != H[0]->device)) {
+      ok = false;
+      break;
+    }
+    H.push_back(h);
+    nq.push_back(nrhs[m]);
+    idx.push_back(m);
+  }
+  if (!ok) {
+    set_error("invalid grouped solve arguments (handles distinct, on one device, 0..8 right-hand sides each)");
+    return GMG_INVALID_ARGUMENT;
+  }
+  if (H.empty()) return GMG_OK;
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<hipStream_t> saved;
+  for (Handle* h : H) {
+    saved.push_back(h->stream);
+    h->stream = s;
+  }
+  int status = GMG_OK;
+  try {
+    for (size_t m = 0; m < H.size(); ++m) {
+      Handle& h = *H[m];
+      const Level& l0 = h.L[0];
+      const int64_t n = l0.n;
+      const int32_t i = idx[m];
+      check_hip(hipMemsetAsync(h.flags, 0, 4, s), "memset");
+      check_finite(B_dev[i], n * nq[m], h.flags, s);
+      check_finite(X_dev[i], n * nq[m], h.flags, s);
+      bat_alloc(h);
+      mgather(l0.perm, B_dev[i], n, nq[m], h.bat.b, s);
+      mgather(l0.perm, X_dev[i], n, nq[m], h.bat.x, s);
+    }
+    std::vector<gmg_solve_info> inf(H.size() * kBatch);
+    std::vector<int32_t> st(H.size(), GMG_OK);
+    if (precision == GMG_PRECISION_F32) pcg_grouped<float>(H, nq, tol, max_iters, s, inf.data(), st.data());
+    else pcg_grouped<double>(H, nq, tol, max_iters, s, inf.data(), st.data());
+    for (size_t m = 0; m < H.size(); ++m) {
+      const int32_t i = idx[m];
+      mscatter(H[m]->L[0].perm, (const double*)H[m]->bat.x, H[m]->L[0].n, nq[m], X_dev[i], s);
+      for (int q = 0; q < nq[m]; ++q) infos[(int64_t)i * kBatch + q] = inf[m * kBatch + q];
+      status_out[i] = st[m];
+      if (st[m] != GMG_OK) status = st[m];
+    }
+    sync(s, "grouped solve");
+  } catch (const Error& e) {
+    set_error(e.msg);
+    status = e.status;
+  }
+  for (size_t m = 0; m < H.size(); ++m) H[m]->stream = saved[m];
   return status;
 }
 

@@ -554,6 +554,97 @@ void mgather(const int32_t* perm, const double* src, int64_t n, int nq, double* 
 template <class V>
 void mscatter(const int32_t* perm, const V* src, int64_t n, int nq, double* dst, hipStream_t s);
 void mzero_columns(double* x, int64_t n, unsigned mask, hipStream_t s);
+// Grouped launches (multi.hip): one launch runs one step of the batched cycle
+// or CG for a group of hierarchies.  A row-parallel step lists each member's
+// piece as a job and every workgroup's (job, tile of kBlock elements, member)
+// in a tile map; the CG steps index a job per member and run kNormBlocks
+// blocks per member where the single-hierarchy kernel does, so each member
+// gets that kernel's arithmetic, reductions included.  Workgroups of members
+// with active[member] == 0 return at once.
+struct GTile {
+  int32_t job, tile, member, pad;
+};
+template <class V>
+struct GSweepJob {                      // one colour class [r0, r1) of A_l
+  Sell<V> A;
+  const V* diag;
+  const V* b;
+  V* x;
+  int32_t r0, r1;
+};
+template <class V>
+struct GResJob {                        // r = b - A x on a level
+  Sell<V> A;
+  const V* b;
+  const V* x;
+  V* r;
+  int64_t n;
+};
+template <class V>
+struct GRestJob {                       // b_c = P^T r, x_c = 0
+  Sell<V> T;
+  const V* r;
+  V* bc;
+  V* xc;
+  int64_t nc;
+};
+template <class V>
+struct GProlJob {                       // x += P x_c
+  const int32_t* q_col;
+  const V* q_val;
+  const int32_t* q_cnt;
+  const V* xc;
+  V* x;
+  int64_t n;
+};
+template <class V>
+struct GGemvJob {                       // x = A_c^-1 b
+  const double* M;
+  const V* b;
+  V* x;
+  int64_t n;
+};
+template <class V>
+struct GKryJob {                        // a member's CG state (level 0, double) and cycle ends
+  SellView A0;
+  double *x, *b, *r, *r_old, *p, *q, *part, *scal;
+  V* cb;                                // the cycle's level-0 right-hand side (float copy of r, or r)
+  V* cx;                                // the cycle's level-0 output z
+  int32_t* flags;
+  int64_t n;
+};
+template <class V>
+void gsweep(const GSweepJob<V>* jobs, const GTile* tiles, int32_t ntiles, const int32_t* active, hipStream_t s);
+template <class V>
+void gresidual(const GResJob<V>* jobs, const GTile* tiles, int32_t ntiles, const int32_t* active, hipStream_t s);
+template <class V>
+void grestrict(const GRestJob<V>* jobs, const GTile* tiles, int32_t ntiles, const int32_t* active, hipStream_t s);
+template <class V>
+void gprolong(const GProlJob<V>* jobs, const GTile* tiles, int32_t ntiles, const int32_t* active, hipStream_t s);
+template <class V>
+void ggemv(const GGemvJob<V>* jobs, const GTile* tiles, int32_t ntiles, const int32_t* active, hipStream_t s);
+// one workgroup per listed member: descs[i] is member members[i]'s tail
+template <class V>
+void gtail(const TailDescT<V>* descs, const int32_t* members, int32_t count, int32_t lds_bytes, const int32_t* active,
+           hipStream_t s);
+// CG steps over the members' jobs (count of them); `tiles` cover each member's n * kBatch elements
+template <class V>
+void gkry_init(const GKryJob<V>* jobs, const GTile* tiles, int32_t ntiles, const int32_t* active, hipStream_t s);
+template <class V>
+void gcycle_start(const GKryJob<V>* jobs, const GTile* tiles, int32_t ntiles, const int32_t* active, hipStream_t s);
+template <class V>
+void gkry_direction(const GKryJob<V>* jobs, int32_t count, const GTile* tiles, int32_t ntiles, const int32_t* active,
+                    hipStream_t s);
+template <class V>
+void gkry_step(const GKryJob<V>* jobs, int32_t count, const int32_t* active, hipStream_t s);
+// norms of b (into KS_BNORM) or true residuals r = b - A x (into KS_NORM, r replaced)
+template <class V>
+void gnorms_b(const GKryJob<V>* jobs, int32_t count, const int32_t* active, hipStream_t s);
+template <class V>
+void gresidual_norms(const GKryJob<V>* jobs, int32_t count, const int32_t* active, hipStream_t s);
+// out[m * (kBatch + 1) + q] = scal_m[which * kBatch + q], out[m * (kBatch + 1) + kBatch] = *flags_m
+template <class V>
+void ggather_scalars(const GKryJob<V>* jobs, int32_t count, int which, uint64_t* out, hipStream_t s);
 // preconditioned CG steps (level 0, double; z in V)
 void kry_init(Krylov& k, int64_t n, hipStream_t s);
 template <class V>

@@ -268,7 +268,19 @@ __global__ void __launch_bounds__(kBlock) k_dense_gemv(const double* __restrict_
   if (i >= n) return;
   double acc = 0.0;
   const int64_t ld = inv_ld(n);
-  for (int64_t k = 0; k < n; ++k) acc = acc + M[k * ld + i] * (double)b[k];
+  // the loads of eight terms are issued before they are added (in ascending k)
+  int64_t k = 0;
+  for (; k + 8 <= n; k += 8) {
+    double m[8], v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      m[u] = M[(k + u) * ld + i];
+      v[u] = (double)b[k + u];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc = acc + m[u] * v[u];
+  }
+  for (; k < n; ++k) acc = acc + M[k * ld + i] * (double)b[k];
   x[i] = (V)acc;
 }
 

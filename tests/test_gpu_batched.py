@@ -151,3 +151,102 @@ def test_many_meshes_on_concurrent_streams():
         X = xb.cpu().numpy()
         for q in range(B.shape[0]):
             assert np.linalg.norm(B[q] - A @ X[q]) <= 1e-8 * (1 + 1e-9) * np.linalg.norm(B[q])
+
+
+GROUP = [("ico4", 100, 8), ("torus96", 200, 5), ("pc20k", 500, 3), ("hubs_big", 1000, 8), ("ico3", 100, 1),
+         ("torus256", 1000, 8), ("flat", 100, 0), ("pc4k", 200, 7)]
+
+
+def _group(seed=5):
+    import paper_2307_04886_amd as g
+    from paper_2307_04886_amd.binding import from_problem
+    g.library()
+    hs, Bs = [], []
+    for i, (name, minc, nrhs) in enumerate(GROUP):
+        prob = problem(name)
+        h, _ = from_problem(prob, g.default_options(min_coarse_points=minc))
+        B = rhs_block(prob, nrhs, seed=seed + i) if nrhs else np.zeros((0, prob.n))
+        if name == "pc4k":
+            B[2] = 0.0                                   # a zero right-hand side inside a member
+        hs.append(h)
+        Bs.append(torch.from_numpy(np.ascontiguousarray(B)).cuda())
+    return hs, Bs
+
+
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+def test_grouped_solve_equals_batched_solves(precision):
+    """One grouped CG over 8 hierarchies (block-ordered levels, hubs, point clouds,
+    1 to 8 right-hand sides, a member without any, a zero right-hand side): every
+    member's solutions, iteration counts and residuals equal gmg_solve_pcg_batched
+    on that hierarchy alone, bit for bit."""
+    _say(f"[gpu] grouped CG {precision} over {len(GROUP)} hierarchies")
+    from paper_2307_04886_amd.binding import solve_pcg_grouped
+    hs, Bs = _group()
+    Xs, infos, sts, st = solve_pcg_grouped(hs, Bs, tol=1e-8, precision=precision)
+    assert st == 0 and all(v == 0 for v in sts)
+    for h, B, X, inf, (name, _, nrhs) in zip(hs, Bs, Xs, infos, GROUP):
+        if nrhs == 0:
+            assert X.shape[0] == 0 and inf == []
+            continue
+        Xr, infr, str_ = h.solve_pcg_batched(B, tol=1e-8, precision=precision)
+        assert str_ == 0
+        assert torch.equal(X, Xr), name
+        for a, b in zip(inf, infr):
+            assert (a.iterations, a.converged, a.rel_residual) == (b.iterations, b.converged, b.rel_residual), name
+        _say(f"[gpu]   {name}: {nrhs} rhs, iterations {[a.iterations for a in inf]}")
+
+
+def test_grouped_solve_cap_and_guesses():
+    """Iteration cap: members that stop unconverged report it and match the
+    per-hierarchy call with the same cap; initial guesses are honoured."""
+    _say("[gpu] grouped CG with a cap and initial guesses")
+    from paper_2307_04886_amd.binding import solve_pcg_grouped
+    hs, Bs = _group(seed=9)
+    X0 = [torch.from_numpy(np.random.default_rng(i).uniform(-1, 1, tuple(B.shape))).cuda() for i, B in enumerate(Bs)]
+    Xs, infos, sts, st = solve_pcg_grouped(hs, Bs, [x.clone() for x in X0], tol=1e-12, max_iters=3, precision="f32")
+    assert st == 1
+    for h, B, x0, X, inf, s_m, (name, _, nrhs) in zip(hs, Bs, X0, Xs, infos, sts, GROUP):
+        if nrhs == 0:
+            continue
+        Xr, infr, str_ = h.solve_pcg_batched(B, x0.clone(), tol=1e-12, max_iters=3, precision="f32")
+        assert s_m == str_ and torch.equal(X, Xr), name
+        assert [a.iterations for a in inf] == [b.iterations for b in infr]
+
+
+def test_grouped_solve_errors():
+    _say("[gpu] grouped CG errors")
+    import paper_2307_04886_amd as g
+    from paper_2307_04886_amd.binding import solve_pcg_grouped
+    hs, Bs = _group()
+    with pytest.raises(g.GMGError) as e:                  # the same hierarchy twice
+        solve_pcg_grouped([hs[0], hs[0]], [Bs[0], Bs[0]])
+    assert e.value.status == -1
+    with pytest.raises(g.GMGError) as e:                  # more than 8 right-hand sides
+        solve_pcg_grouped([hs[0]], [torch.cat([Bs[0], Bs[0]])])
+    assert e.value.status == -1
+    bad = Bs[1].clone()
+    bad[0, 3] = float("nan")
+    with pytest.raises(g.GMGError) as e:
+        solve_pcg_grouped(hs[:2], [Bs[0], bad])
+    assert e.value.status == -1
+    assert solve_pcg_grouped([], [])[3] == 0
+
+
+def test_many_meshes_grouped_form():
+    """The many-mesh driver's grouped form gives the bits of its per-mesh form."""
+    _say("[gpu] many meshes, grouped form")
+    import paper_2307_04886_amd as g
+    from paper_2307_04886_amd.batch import solve_many
+    g.library()
+    batch = synth.config_batched(count=6, hi=40_000)
+    systems = []
+    for prob, B in batch:
+        t = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in
+             (prob.points, prob.edges, prob.indptr, prob.indices, prob.data)]
+        systems.append(tuple(t) + (torch.from_numpy(B).cuda(),))
+    per = solve_many(systems, streams=4)
+    grp = solve_many(systems, streams=4, form="grouped")
+    for (xa, ia, sa), (xb, ib, sb) in zip(per, grp):
+        assert sa == sb == 0
+        assert torch.equal(xa, xb)
+        assert [i.iterations for i in ia] == [i.iterations for i in ib]
