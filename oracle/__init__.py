@@ -75,6 +75,7 @@ def lib():
         L.orc_solve_pcg.argtypes = [P, P, P, ctypes.c_double, ctypes.c_int32, ctypes.c_int32, P, P, P]
         L.orc_closest_point.argtypes = [P, P, P, P, P]
         L.orc_degenerate.argtypes = [P, P, P]
+        L.orc_dsatur.argtypes = [ctypes.c_int32, P, P, P]
         L.orc_mix64.argtypes = [ctypes.c_uint64]
         L.orc_mix64.restype = ctypes.c_uint64
         if L.orc_options_size() != ctypes.sizeof(Options):
@@ -232,6 +233,18 @@ def closest_point(p, a, b, c):
     arr = [np.ascontiguousarray(v, dtype=np.float64) for v in (p, a, b, c)]
     region = lib().orc_closest_point(*[_ptr(v) for v in arr], _ptr(w))
     return w, region
+
+
+def dsatur(rowptr, col):
+    """DSATUR colouring of a graph in CSR form (the colouring of each cell of a
+    level swept in block order): (colours per vertex, number of colours), or
+    (None, -1) if a vertex would need 64 colours or more."""
+    rp = np.ascontiguousarray(rowptr, dtype=np.int32)
+    cl = np.ascontiguousarray(col, dtype=np.int32)
+    m = len(rp) - 1
+    out = np.zeros(max(m, 1), dtype=np.int32)
+    nc = lib().orc_dsatur(m, _ptr(rp), _ptr(cl), _ptr(out))
+    return (out[:m], nc) if nc >= 0 else (None, -1)
 
 
 def degenerate(a, b, c):

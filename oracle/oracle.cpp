@@ -89,6 +89,8 @@ constexpr int64_t kMaxDenseCoarse = 4096;  // largest coarsest level factored de
 constexpr uint64_t kColorSalt = 0xC2B2AE3D27D4EB4FULL;
 constexpr double kBlockMargin = 1.0 + 1.0 / (1 << 20);   // cell side over the largest coupling distance
 constexpr int64_t kMaxGridCells = int64_t(1) << 22;       // grids with more cells keep the colour order
+constexpr int32_t kMaxCellRows = 512;                      // cells with more rows keep the level in colour order
+constexpr int32_t kMaxCellColors = 64;                     // likewise a cell that needs this many colours
 
 // SplitMix64 finaliser (Steele, Lea & Flood 2014): a bijective 64-bit mixer.
 uint64_t mix64(uint64_t z) {
@@ -611,9 +613,12 @@ void colouring(Level& lv, int level, const Options& o) {
 // colours, are swept one after the other, all cells of a class at once and
 // within a cell the colours in ascending order.  Without couplings (w = 0),
 // or with more than kMaxGridCells cells, the level keeps the colour order.
-void block_order(Level& lv) {
+// cell[i] receives row i's cell (cy * ncx + cx); returns whether the level
+// has a grid.
+bool block_order(Level& lv, std::vector<int64_t>& cell) {
   const int64_t n = lv.n;
   lv.block_color.clear();
+  cell.clear();
   double lo[3], hi[3], ext[3];
   for (int a = 0; a < 3; ++a) {
     lo[a] = lv.X[a];
@@ -636,16 +641,90 @@ void block_order(Level& lv) {
       w = std::max(w, std::fabs(lv.X[3 * j + a0] - lv.X[3 * i + a0]));
       w = std::max(w, std::fabs(lv.X[3 * j + a1] - lv.X[3 * i + a1]));
     }
-  if (!(w > 0.0)) return;
+  if (!(w > 0.0)) return false;
   const double side = w * kBlockMargin;
   const int64_t ncx = (int64_t)std::floor(ext[a0] / side) + 1, ncy = (int64_t)std::floor(ext[a1] / side) + 1;
-  if (ncx * ncy > kMaxGridCells) return;
+  if (ncx * ncy > kMaxGridCells) return false;
   lv.block_color.assign(n, 0);
+  cell.assign(n, 0);
   for (int64_t i = 0; i < n; ++i) {
     const int64_t cx = (int64_t)std::floor((lv.X[3 * i + a0] - lo[a0]) / side);
     const int64_t cy = (int64_t)std::floor((lv.X[3 * i + a1] - lo[a1]) / side);
     lv.block_color[i] = (int32_t)((cx & 1) + 2 * (cy & 1));
+    cell[i] = cy * ncx + cx;
   }
+  return true;
+}
+
+// DSATUR colouring (Brelaz) of a graph on m vertices given by adjacency
+// lists: repeatedly the uncoloured vertex with the most distinct colours
+// among its coloured neighbours (its saturation) is coloured, ties going to
+// the larger degree and then to the smaller vertex number, with the smallest
+// colour none of its neighbours has.  Returns the number of colours, or -1 if
+// a vertex would need colour kMaxCellColors or more.
+int32_t dsatur(int32_t m, const std::vector<std::vector<int32_t>>& adj, std::vector<int32_t>& col) {
+  col.assign(m, -1);
+  std::vector<std::vector<char>> seen(m, std::vector<char>(kMaxCellColors, 0));
+  std::vector<int32_t> sat(m, 0);
+  int32_t ncol = 0;
+  for (int32_t step = 0; step < m; ++step) {
+    int32_t v = -1;
+    for (int32_t u = 0; u < m; ++u) {
+      if (col[u] >= 0) continue;
+      if (v < 0 || sat[u] > sat[v] || (sat[u] == sat[v] && adj[u].size() > adj[v].size())) v = u;
+    }
+    int32_t c = 0;
+    while (c < kMaxCellColors && seen[v][c]) ++c;
+    if (c == kMaxCellColors) return -1;
+    col[v] = c;
+    ncol = std::max(ncol, c + 1);
+    for (int32_t u : adj[v])
+      if (!seen[u][c]) {
+        seen[u][c] = 1;
+        ++sat[u];
+      }
+  }
+  return ncol;
+}
+
+// The colouring of a level swept in block order (a reading, like the block
+// order itself): each cell's rows are coloured on their own, by DSATUR on the
+// couplings of A_l between rows of that cell (rows numbered by ascending
+// index within the cell), since rows of different cells of one block colour
+// are never coupled.  A cell with more than kMaxCellRows rows, or one that
+// needs kMaxCellColors colours or more, sends the level back to the colour
+// order (returns false).
+bool cell_colouring(Level& lv, const std::vector<int64_t>& cell) {
+  const int64_t n = lv.n;
+  std::vector<int64_t> order(n);
+  for (int64_t i = 0; i < n; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return cell[a] < cell[b]; });
+  std::vector<int32_t> local(n, -1), color(n, -1);
+  int32_t ncolors = 0;
+  for (int64_t a = 0; a < n;) {
+    int64_t b = a;
+    while (b < n && cell[order[b]] == cell[order[a]]) ++b;
+    const int32_t m = (int32_t)(b - a);
+    if (m > kMaxCellRows) return false;
+    for (int32_t p = 0; p < m; ++p) local[order[a + p]] = p;
+    std::vector<std::vector<int32_t>> adj(m);
+    for (int32_t p = 0; p < m; ++p) {
+      const int64_t i = order[a + p];
+      for (int32_t e = lv.arp[i]; e < lv.arp[i + 1]; ++e) {
+        const int64_t j = lv.acol[e];
+        if (j != i && cell[j] == cell[i]) adj[p].push_back(local[j]);
+      }
+    }
+    std::vector<int32_t> col;
+    const int32_t nc = dsatur(m, adj, col);
+    if (nc < 0) return false;
+    for (int32_t p = 0; p < m; ++p) color[order[a + p]] = col[p];
+    ncolors = std::max(ncolors, nc);
+    a = b;
+  }
+  lv.color.swap(color);
+  lv.ncolors = ncolors;
+  return true;
 }
 
 // The rows in sweep order, sorted by (block colour, colour, index); rows of
@@ -935,9 +1014,15 @@ int orc_build(int64_t n, const double* pts, int64_t m, const int32_t* edges, con
   last.dist.clear();
   if (last.n > kMaxDenseCoarse) { delete h; return DEGENERATE; }
   for (size_t l = 0; l + 1 < h->L.size(); ++l) {
-    colouring(h->L[l], (int)l, o);
-    if (l >= 1 && h->L[l].n > o.block_min_rows) block_order(h->L[l]);
-    sweep_order(h->L[l]);
+    Level& lv = h->L[l];
+    bool blocked = false;
+    if (l >= 1 && lv.n > o.block_min_rows) {
+      std::vector<int64_t> cell;
+      blocked = block_order(lv, cell) && cell_colouring(lv, cell);
+      if (!blocked) lv.block_color.clear();
+    }
+    if (!blocked) colouring(lv, (int)l, o);
+    sweep_order(lv);
   }
   st = cholesky(last, h->chol);
   if (st != OK) { delete h; return st; }
@@ -1110,6 +1195,18 @@ int orc_solve_pcg(void* hp, const double* b, double* x, double tol, int32_t max_
 }
 
 // Single-step entry points, exposed so that tests can pin them in isolation.
+// DSATUR on a graph given as CSR (rows 0..m-1, neighbour lists, no loops):
+// writes every vertex's colour, returns the number of colours or -1.
+int orc_dsatur(int32_t m, const int32_t* rp, const int32_t* col, int32_t* out) {
+  if (m < 0) return -1;
+  std::vector<std::vector<int32_t>> adj(m);
+  for (int32_t v = 0; v < m; ++v) adj[v].assign(col + rp[v], col + rp[v + 1]);
+  std::vector<int32_t> c;
+  const int32_t nc = dsatur(m, adj, c);
+  if (nc >= 0) std::copy(c.begin(), c.end(), out);
+  return nc;
+}
+
 int orc_closest_point(const double* p, const double* a, const double* b, const double* c, double* w) {
   return closest_point({p[0], p[1], p[2]}, {a[0], a[1], a[2]}, {b[0], b[1], b[2]}, {c[0], c[1], c[2]}, w);
 }

@@ -451,8 +451,14 @@ void build(Handle& h, int64_t n, const double* points, int64_t m, const int32_t*
   if (last.n > kMaxDenseCoarse) throw Error{GMG_DEGENERATE, "coarsening stalled above the dense-solve limit"};
   const int nl = (int)h.L.size();
   for (int l = 0; l + 1 < nl; ++l) {
-    colouring(h, h.L[l], l);
-    if (l >= 1 && h.L[l].n > o.block_min_rows) block_order(h, h.L[l]);
+    // block-ordered levels are coloured cell by cell; the others (and a level
+    // whose cells do not allow it) take the colouring of the whole level
+    bool blocked = false;
+    if (l >= 1 && h.L[l].n > o.block_min_rows) {
+      block_order(h, h.L[l]);
+      if (h.L[l].bcolor) blocked = block_colouring(h, h.L[l]);
+    }
+    if (!blocked) colouring(h, h.L[l], l);
     mark("colouring", l);
   }
   solve_layout(h, h.L[nl - 1], nullptr, nullptr, nullptr, nullptr);

@@ -487,6 +487,9 @@ void galerkin_values(Handle& h, Level& lv, Level& nx);     // same pattern, valu
 // ------------------------------------------------------------------ launchers (setup_solve.hip)
 void colouring(Handle& h, Level& lv, int level);
 void block_order(Handle& h, Level& lv);                     // grid cells and block colours of a level
+// DSATUR colouring in every cell of a level with a grid; false (grid dropped)
+// when a cell has more than 512 rows or needs 64 colours
+bool block_colouring(Handle& h, Level& lv);
 void block_values(Handle& h, Level& lv);                    // block ELL values from the current A_l
 void autotune(Handle& h);                                   // row-kernel shapes of the multi-launch levels (tune.hip)
 void solve_layout(Handle& h, Level& lv, const Level* nx, const int32_t* t_rp, const int32_t* t_col,

@@ -807,6 +807,143 @@ __global__ void k_count_cells(const int32_t* bcell, int64_t n, int32_t* cnt) {
   if (i < n) atomicAdd(&cnt[bcell[i]], 1);
 }
 
+// ---- per-cell colouring of a level swept in block order (DSATUR in each cell)
+constexpr int32_t kMaxCellRows = 512;     // larger cells send the level back to the colour order
+constexpr int32_t kMaxCellColors = 64;    // likewise a cell that needs this many colours
+constexpr int32_t kCellAdjLds = 4096;     // in-cell couplings of a cell kept in LDS (else in HBM)
+
+__global__ void k_cell_slots(const int32_t* bcell, int64_t n, int32_t* cnt, int32_t* slot) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) slot[i] = atomicAdd(&cnt[bcell[i]], 1);
+}
+
+__global__ void k_cell_scatter(const int32_t* __restrict__ bcell, int64_t n, const int32_t* __restrict__ cptr,
+                               const int32_t* __restrict__ slot, int32_t* __restrict__ rows) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) rows[cptr[bcell[i]] + slot[i]] = (int32_t)i;
+}
+
+// In-cell degree of row i (couplings to other rows of its cell), and the
+// cell's total.
+__global__ void k_incell_degree(const int32_t* __restrict__ arp, const int32_t* __restrict__ acol,
+                                const int32_t* __restrict__ bcell, int64_t n, int32_t* __restrict__ deg,
+                                int32_t* __restrict__ cell_deg) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int32_t c = bcell[i];
+  int32_t d = 0;
+  for (int32_t e = arp[i]; e < arp[i + 1]; ++e) {
+    const int32_t j = acol[e];
+    d += (j != (int32_t)i && bcell[j] == c) ? 1 : 0;
+  }
+  deg[i] = d;
+  atomicAdd(&cell_deg[c], d);
+}
+
+// DSATUR in one cell, one wavefront per cell.  The cell's rows are sorted
+// ascending in LDS (bitonic), so a row's position is its rank by index; its
+// in-cell neighbours become positions (binary search), kept in LDS when they
+// fit and otherwise in the cell's segment of adj.  Each step colours the
+// uncoloured row of largest saturation (distinct colours among its coloured
+// in-cell neighbours), then largest in-cell degree, then smallest position,
+// with the smallest colour none of its neighbours has.  A row that would need
+// colour kMaxCellColors sets *overflow.
+__global__ void __launch_bounds__(kWave) k_cell_dsatur(const int32_t* __restrict__ cptr,
+                                                      const int32_t* __restrict__ rows,
+                                                      const int32_t* __restrict__ deg_of,
+                                                      const int32_t* __restrict__ cadj,
+                                                      const int32_t* __restrict__ arp,
+                                                      const int32_t* __restrict__ acol,
+                                                      const int32_t* __restrict__ bcell, int32_t* __restrict__ adj,
+                                                      int32_t* __restrict__ color, int32_t* __restrict__ maxcol,
+                                                      int32_t* __restrict__ overflow) {
+  __shared__ uint64_t mask[kMaxCellRows];
+  __shared__ int32_t r[kMaxCellRows], col[kMaxCellRows], deg[kMaxCellRows], off[kMaxCellRows + 1];
+  __shared__ int32_t ladj[kCellAdjLds];
+  const int32_t c = blockIdx.x;
+  const int32_t base = cptr[c], m = cptr[c + 1] - base;
+  if (m <= 0 || m > kMaxCellRows) return;
+  const int lane = threadIdx.x;
+  int32_t M = 1;
+  while (M < m) M <<= 1;
+  for (int32_t p = lane; p < M; p += kWave) r[p] = p < m ? rows[base + p] : INT32_MAX;
+  __syncthreads();
+  for (int32_t k = 2; k <= M; k <<= 1)
+    for (int32_t j = k >> 1; j > 0; j >>= 1) {
+      for (int32_t p = lane; p < M; p += kWave) {
+        const int32_t q = p ^ j;
+        if (q > p) {
+          const int32_t x = r[p], y = r[q];
+          if ((x > y) == ((p & k) == 0)) {
+            r[p] = y;
+            r[q] = x;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  for (int32_t p = lane; p < m; p += kWave) {
+    mask[p] = 0;
+    col[p] = -1;
+    deg[p] = deg_of[r[p]];
+  }
+  __syncthreads();
+  if (lane == 0) {
+    int32_t acc = 0;
+    for (int32_t p = 0; p < m; ++p) {
+      off[p] = acc;
+      acc += deg[p];
+    }
+    off[m] = acc;
+  }
+  __syncthreads();
+  int32_t* A = off[m] <= kCellAdjLds ? ladj : adj + cadj[c];
+  for (int32_t p = lane; p < m; p += kWave) {
+    const int32_t i = r[p];
+    int32_t t = off[p];
+    for (int32_t e = arp[i]; e < arp[i + 1]; ++e) {
+      const int32_t j = acol[e];
+      if (j == i || bcell[j] != c) continue;
+      int32_t lo = 0, hi = m;
+      while (lo < hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (r[mid] < j) lo = mid + 1;
+        else hi = mid;
+      }
+      A[t++] = lo;
+    }
+  }
+  __threadfence_block();
+  __syncthreads();
+  int32_t used = 0;
+  for (int32_t step = 0; step < m; ++step) {
+    uint32_t best = 0;
+    for (int32_t p = lane; p < m; p += kWave)
+      if (col[p] < 0) {
+        const uint32_t key = ((uint32_t)__popcll(mask[p]) << 20) | ((uint32_t)deg[p] << 10) | (uint32_t)(1023 - p);
+        best = best > key ? best : key;
+      }
+    for (int o = kWave / 2; o >= 1; o >>= 1) {
+      const uint32_t other = (uint32_t)__shfl_xor((int)best, o, kWave);
+      best = best > other ? best : other;
+    }
+    const int32_t v = 1023 - (int32_t)(best & 1023u);
+    const uint64_t free_colours = ~mask[v];
+    if (free_colours == 0) {                // every colour below kMaxCellColors is taken
+      if (lane == 0) atomicOr(overflow, 1);
+      return;
+    }
+    const int32_t k = __builtin_ctzll(free_colours);
+    used = used > k ? used : k;
+    __syncthreads();
+    if (lane == 0) col[v] = k;
+    for (int32_t t = lane; t < deg[v]; t += kWave) mask[A[off[v] + t]] |= uint64_t(1) << k;
+    __syncthreads();
+  }
+  for (int32_t p = lane; p < m; p += kWave) color[r[p]] = col[p];
+  if (lane == 0) atomicMax(maxcol, used);
+}
+
 // Occupied cells enumerated block colour by block colour: slot v of
 // [0, 4 H), H = hx hy, is cell (2 (v mod H mod hx) + (k & 1), 2 (v mod H div hx) + (k >> 1))
 // of block colour k = v div H.
@@ -1228,6 +1365,63 @@ void block_order(Handle& h, Level& lv) {
   lv.bcolor = (int32_t*)dalloc(h, (size_t)n * 4);
   lv.bcell = (int32_t*)talloc(s, (size_t)n * 4);
   k_grid_cells<<<blocks_for(n), kBlock, 0, s>>>(lv.X, n, a0, a1, lo[a0], lo[a1], side, lv.gx, lv.bcolor, lv.bcell);
+}
+
+// The colouring of a level swept in block order: DSATUR in every cell (the
+// rows of a cell numbered by ascending index).  Returns false, with the level's
+// grid dropped, when a cell has more than kMaxCellRows rows or needs
+// kMaxCellColors colours; the level then takes the colour order.
+bool block_colouring(Handle& h, Level& lv) {
+  hipStream_t s = h.stream;
+  const int64_t n = lv.n;
+  const int64_t ncell = (int64_t)lv.gx * lv.gy;
+  int32_t* cnt = (int32_t*)talloc(s, (size_t)(ncell + 1) * 4);
+  int32_t* slot = (int32_t*)talloc(s, (size_t)n * 4);
+  int32_t* mx = (int32_t*)talloc(s, 3 * 4);
+  fill_i32(cnt, 0, ncell + 1, s);
+  fill_i32(mx, 0, 3, s);
+  k_cell_slots<<<blocks_for(n), kBlock, 0, s>>>(lv.bcell, n, cnt, slot);
+  max_i32(cnt, ncell, 0, mx, s);
+  int64_t biggest = 0;
+  {
+    ScalarRead rd[1] = {{mx, 4, &biggest}};
+    read_scalars(h, rd, 1);
+  }
+  bool ok = biggest <= kMaxCellRows;
+  if (ok) {
+    int32_t* cptr = (int32_t*)talloc(s, (size_t)(ncell + 1) * 4);
+    int32_t* rows = (int32_t*)talloc(s, (size_t)n * 4);
+    scan_i32(cnt, cptr, ncell, s);
+    k_cell_scatter<<<blocks_for(n), kBlock, 0, s>>>(lv.bcell, n, cptr, slot, rows);
+    int32_t* deg = slot;                               // reused: in-cell degree of every row
+    fill_i32(cnt, 0, ncell + 1, s);                    // reused: in-cell couplings of every cell
+    k_incell_degree<<<blocks_for(n), kBlock, 0, s>>>(lv.arp, lv.acol, lv.bcell, n, deg, cnt);
+    int32_t* cadj = (int32_t*)talloc(s, (size_t)(ncell + 1) * 4);
+    scan_i32(cnt, cadj, ncell, s);
+    int32_t* adj = (int32_t*)talloc(s, (size_t)std::max<int64_t>(lv.nnzA, 1) * 4);
+    lv.color = (int32_t*)dalloc(h, (size_t)n * 4);
+    k_cell_dsatur<<<(unsigned)ncell, kWave, 0, s>>>(cptr, rows, deg, cadj, lv.arp, lv.acol, lv.bcell, adj, lv.color,
+                                                   mx + 1, mx + 2);
+    int64_t top = 0, over = 0;
+    ScalarRead rd[2] = {{mx + 1, 4, &top}, {mx + 2, 4, &over}};
+    read_scalars(h, rd, 2);
+    ok = over == 0;
+    lv.ncolors = (int32_t)top + 1;
+    tfree(s, cptr);
+    tfree(s, rows);
+    tfree(s, cadj);
+    tfree(s, adj);
+  }
+  tfree(s, cnt);
+  tfree(s, slot);
+  tfree(s, mx);
+  if (!ok) {                                           // the level takes the colour order
+    tfree(s, lv.bcell);
+    lv.bcell = nullptr;
+    lv.bcolor = nullptr;
+    lv.color = nullptr;
+  }
+  return ok;
 }
 
 namespace {
