@@ -823,6 +823,21 @@ __global__ void k_cell_scatter(const int32_t* __restrict__ bcell, int64_t n, con
   if (i < n) rows[cptr[bcell[i]] + slot[i]] = (int32_t)i;
 }
 
+// The largest value over the wavefront, in every lane: running maxima within
+// each row of 16 lanes (DPP row shifts by 1, 2, 4, 8; lanes shifted in from
+// outside the row contribute 0), the row maxima carried across rows (DPP row
+// broadcasts of lanes 15 and 31), then lane 63's value read back.
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+  auto mx = [](uint32_t a, uint32_t b) { return a > b ? a : b; };
+  v = mx(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false));   // row_shr:1
+  v = mx(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false));   // row_shr:2
+  v = mx(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false));   // row_shr:4
+  v = mx(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false));   // row_shr:8
+  v = mx(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false));   // row_bcast:15
+  v = mx(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false));   // row_bcast:31
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, kWave - 1);
+}
+
 // In-cell degree of row i (couplings to other rows of its cell), and the
 // cell's total.
 __global__ void k_incell_degree(const int32_t* __restrict__ arp, const int32_t* __restrict__ acol,
@@ -923,10 +938,7 @@ __global__ void __launch_bounds__(kWave) k_cell_dsatur(const int32_t* __restrict
         const uint32_t key = ((uint32_t)__popcll(mask[p]) << 20) | ((uint32_t)deg[p] << 10) | (uint32_t)(1023 - p);
         best = best > key ? best : key;
       }
-    for (int o = kWave / 2; o >= 1; o >>= 1) {
-      const uint32_t other = (uint32_t)__shfl_xor((int)best, o, kWave);
-      best = best > other ? best : other;
-    }
+    best = wave_max_u32(best);
     const int32_t v = 1023 - (int32_t)(best & 1023u);
     const uint64_t free_colours = ~mask[v];
     if (free_colours == 0) {                // every colour below kMaxCellColors is taken
