@@ -316,11 +316,13 @@ int gmg_num_levels(gmg_handle h, int32_t* levels);
 int gmg_level_sizes(gmg_handle h, int32_t level, int64_t* sizes_host);
 
 /*
- * The row-kernel shapes level l's V-cycle uses, written to out_host[0..3]:
+ * The row-kernel shapes level l's V-cycle uses, written to out_host[0..4]:
  *  0 lanes per row of the row kernels of A_l (residual, colour sweeps; levels >= 1 solved by
  *    separate launches, else 0), 1 lanes per row of the restriction by P_l^T (1: one lane per row;
  *    levels solved by separate launches, else 0), 2 entries per load chunk of level 0's row kernels (level 0, else 0),
- *  3 one if the level's sweeps run as block sweeps (one workgroup per grid cell, four launches).
+ *  3 one if the level's sweeps run as block sweeps (one workgroup per grid cell, four launches),
+ *  4 the uniform slice width level 0's row kernels use (its SELL padded to the longest row, chosen
+ *    where that stores at most 1.15 times the entries and measures faster; else 0).
  */
 int gmg_level_tuning(gmg_handle h, int32_t level, int32_t* out_host);
 

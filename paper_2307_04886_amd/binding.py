@@ -187,11 +187,12 @@ class Hierarchy:
 
     def tuning(self, level):
         """gmg_level_tuning: the row-kernel shapes of a level."""
-        t = np.zeros(4, dtype=np.int32)
+        t = np.zeros(5, dtype=np.int32)
         st = library().gmg_level_tuning(self._h, level, t.ctypes.data_as(ctypes.c_void_p))
         if st:
             raise _err(st)
-        return dict(lanes_A=int(t[0]), lanes_PT=int(t[1]), chunk=int(t[2]), block_sweep=int(t[3]))
+        return dict(lanes_A=int(t[0]), lanes_PT=int(t[1]), chunk=int(t[2]), block_sweep=int(t[3]),
+                    uniform_width=int(t[4]))
 
     def export(self, level, what):
         code, dt = EXPORTS[what]

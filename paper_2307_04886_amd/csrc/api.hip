@@ -669,6 +669,7 @@ void kry_prepare(Handle& h, Cycle<float>& c) {
     f.ra = d.ra;
     f.rt = d.rt;
     f.ch = d.ch;
+    f.uni = d.uni;
     f.maxa = d.maxa;
     f.maxt = d.maxt;
     f.q_col = d.q_col;
@@ -677,7 +678,7 @@ void kry_prepare(Handle& h, Cycle<float>& c) {
     f.b = (float*)dalloc(h, (size_t)d.n * 4);
     f.r = (float*)dalloc(h, (size_t)d.n * 4);
     if (l + 1 < nl) {                        // the coarsest level only uses b and x
-      f.A = {d.A.ptr, d.A.col, to_f32_copy(h, d.A.val, lv.a_slots, s), d.A.len};
+      f.A = {d.A.ptr, d.A.col, to_f32_copy(h, d.A.val, lv.a_slots, s), d.A.len, d.A.uw};
       f.T = {d.T.ptr, d.T.col, to_f32_copy(h, d.T.val, lv.t_slots, s), d.T.len};
       f.diag = to_f32_copy(h, d.diag, d.n, s);
       f.q_val = to_f32_copy(h, d.q_val, (int64_t)3 * d.n, s);
@@ -2045,6 +2046,7 @@ int gmg_level_tuning(gmg_handle h, int32_t l, int32_t* out) {
   out[1] = multi ? v.rt : 0;
   out[2] = multi && l == 0 ? v.ch : 0;
   out[3] = multi && l > 0 && v.B.nblk > 0 ? 1 : 0;
+  out[4] = multi && l == 0 && v.uni && v.A.uw > 0 ? v.A.uw : 0;
   return GMG_OK;
 }
 

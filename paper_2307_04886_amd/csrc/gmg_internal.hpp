@@ -122,6 +122,9 @@ struct Sell {
   const int32_t* col = nullptr;
   const V* val = nullptr;
   const int32_t* len = nullptr;
+  // > 0: every slice has this width (rows padded with column 0, value 0), so
+  // entry t of row r sits at (r / 64) * 64 * uw + 64 t + r % 64
+  int32_t uw = 0;
 };
 using SellView = Sell<double>;
 
@@ -207,6 +210,7 @@ struct LevelViewT {
   Sell<V> T;                            // P_l^T (rows: coarse points)
   int32_t ra = 1, rt = 1;               // lanes per row for A_l / P_l^T (power of two)
   int32_t ch = 8;                       // entries per load chunk of the one-lane-per-row kernels (level 0)
+  int32_t uni = 0;                      // 1: level 0's one-lane kernels use the uniform slice width A.uw
   int32_t maxa = 0, maxt = 0;           // longest row of A_l / P_l^T
   const V* diag = nullptr;
   const int32_t* q_col = nullptr;       // P_l, SoA ELL-3 [3][n]

@@ -52,6 +52,34 @@ __device__ __forceinline__ V row_sum_seq(const Sell<V>& A, int32_t r, const V* x
   return acc;
 }
 
+// The same sum over a SELL of uniform slice width A.uw: the row's entries sit
+// at addresses known from r alone, so they load with x's first gathers' index
+// loads and without the row length.  Slots past the row's end hold column 0
+// and value 0; their products are +-0 and leave the sum unchanged (a sum that
+// starts at +0 is never -0), so the bits equal row_sum_seq's.
+template <int CH, class V>
+__device__ __forceinline__ V row_sum_uni(const Sell<V>& A, int32_t r, const V* x, int32_t skip) {
+  const int32_t w = A.uw;
+  const int64_t base = (int64_t)(r >> 6) * (kSlice * (int64_t)w) + (r & (kSlice - 1));
+  V acc = V(0);
+  for (int32_t t0 = 0; t0 < w; t0 += CH) {
+    int32_t j[CH];
+    V v[CH], xv[CH];
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      const int64_t o = base + (int64_t)min(t0 + u, w - 1) * kSlice;
+      j[u] = A.col[o];
+      v[u] = A.val[o];
+    }
+#pragma unroll
+    for (int u = 0; u < CH; ++u) xv[u] = x[j[u]];
+#pragma unroll
+    for (int u = 0; u < CH; ++u)
+      if (t0 + u < w && j[u] != skip) acc = acc + v[u] * xv[u];
+  }
+  return acc;
+}
+
 // Calls f(std::integral_constant<int, S>) for S = 0 .. N-1 in order.
 template <int N, class F, int S = 0>
 __device__ __forceinline__ void static_for(F&& f) {

@@ -1586,8 +1586,13 @@ namespace {
 
 // CSR (source rows perm[r], columns through cmap) -> SELL-64 owned by the
 // handle; *maxlen receives the longest row, *slots the allocated entry slots.
+// uniform_nnz > 0 (the matrix's entries): every slice gets the width of the
+// longest row when that stores at most kUniformSlack times the entries.
+constexpr double kUniformSlack = 1.15;
+
 SellView make_sell(Handle& h, const int32_t* perm, const int32_t* cmap, const int32_t* rp, const int32_t* col,
-                   const double* val, int64_t n, double* diag, int32_t* maxlen, int64_t* slots) {
+                   const double* val, int64_t n, double* diag, int32_t* maxlen, int64_t* slots,
+                   int64_t uniform_nnz = 0) {
   hipStream_t s = h.stream;
   const int64_t ns = (n + kSlice - 1) / kSlice;
   int32_t* len = (int32_t*)dalloc(h, (size_t)(n + 1) * 4);
@@ -1600,6 +1605,13 @@ SellView make_sell(Handle& h, const int32_t* perm, const int32_t* cmap, const in
   int64_t tot = 0, ml = 0;
   ScalarRead rd[2] = {{ptr + ns, 4, &tot}, {mx, 4, &ml}};
   read_scalars(h, rd, 2);
+  int32_t uw = 0;
+  if (uniform_nnz > 0 && ml > 0 && (double)(ns * kSlice * ml) <= kUniformSlack * (double)uniform_nnz) {
+    fill_i32(wsz, (int32_t)(ml * kSlice), ns, s);
+    scan_i32(wsz, ptr, ns, s);
+    tot = ns * kSlice * ml;
+    uw = (int32_t)ml;
+  }
   *maxlen = (int32_t)ml;
   *slots = tot + 1;
   int32_t* scol = (int32_t*)dalloc(h, (size_t)(tot + 1) * 4);
@@ -1618,6 +1630,7 @@ SellView make_sell(Handle& h, const int32_t* perm, const int32_t* cmap, const in
   v.col = scol;
   v.val = sval;
   v.len = len;
+  v.uw = uw;
   return v;
 }
 
@@ -1673,7 +1686,8 @@ void solve_layout(Handle& h, Level& lv, const Level* nx, const int32_t* t_rp, co
   v.n = (int32_t)n;
   v.ncolors = C;
   v.cptr = cptr;
-  v.A = make_sell(h, lv.perm, lv.iperm, lv.arp, lv.acol, lv.aval, n, lv.diag, &v.maxa, &lv.a_slots);
+  v.A = make_sell(h, lv.perm, lv.iperm, lv.arp, lv.acol, lv.aval, n, lv.diag, &v.maxa, &lv.a_slots,
+                  &lv == &h.L[0] ? lv.nnzA : 0);
   v.ra = lanes_for(v.maxa);
   v.diag = lv.diag;
   lv.x = (double*)dalloc(h, (size_t)n * 8);

@@ -29,16 +29,24 @@ __device__ __forceinline__ void prolong_row(const LevelViewT<V>& L, const V* __r
   x[i] = x[i] + acc;
 }
 
+// Level 0's one-lane row sum: per-slice widths (row lengths read), or the
+// uniform slice width (U) when the level's SELL has one.
+template <int CH, bool U, class V>
+__device__ __forceinline__ V row_sum_fine(const Sell<V>& A, int32_t r, const V* x, int32_t skip) {
+  if constexpr (U) return row_sum_uni<CH>(A, r, x, skip);
+  else return row_sum_seq<CH>(A, r, x, skip);
+}
+
 // One colour of a Gauss-Seidel sweep on level 0, rows [r0, r1):
 //   x_r <- (b_r - sum_{j != r} A_rj x_j) / A_rr.
 // Rows of one colour are not coupled, so they update in parallel.
-template <int CH, class V>
+template <int CH, bool U, class V>
 __global__ void __launch_bounds__(kBlock) k_gs_color_fine(Sell<V> A, const V* __restrict__ diag,
                                                           const V* __restrict__ b, V* x, int32_t r0, int32_t r1) {
   const int32_t r = (r0 & ~(kSlice - 1)) + (int32_t)(xcd_block() * kBlock + threadIdx.x);
   if (r < r0 || r >= r1) return;
   const V br = b[r], dr = diag[r];        // issued with the row's loads
-  const V acc = row_sum_seq<CH>(A, r, x, r);
+  const V acc = row_sum_fine<CH, U>(A, r, x, r);
   x[r] = (br - acc) / dr;
 }
 
@@ -163,13 +171,13 @@ __global__ void __launch_bounds__(kBlkThreads) k_gs_block(BlockView<V> B, const 
 }
 
 // r = b - A x on level 0
-template <int CH, class V>
+template <int CH, bool U, class V>
 __global__ void __launch_bounds__(kBlock) k_residual_fine(Sell<V> A, const V* __restrict__ b,
                                                           const V* __restrict__ x, V* __restrict__ res,
                                                           int64_t n) {
   const int64_t r = (int64_t)xcd_block() * kBlock + threadIdx.x;
   if (r >= n) return;
-  res[r] = b[r] - row_sum_seq<CH>(A, (int32_t)r, x, -1);
+  res[r] = b[r] - row_sum_fine<CH, U>(A, (int32_t)r, x, -1);
 }
 
 // r = b - A x on a Galerkin level, R lanes per row
@@ -184,7 +192,7 @@ __global__ void __launch_bounds__(kBlock) k_residual(Sell<V> A, const V* __restr
 
 // r = b - A x on level 0 (double), plus per-block partial sums of r^2 (fixed
 // grid: deterministic).
-template <int CH>
+template <int CH, bool U>
 __global__ void __launch_bounds__(kBlock) k_residual_norm(SellView A, const double* __restrict__ b,
                                                           const double* __restrict__ x,
                                                           double* __restrict__ res, int64_t n,
@@ -194,7 +202,7 @@ __global__ void __launch_bounds__(kBlock) k_residual_norm(SellView A, const doub
   const uint32_t lb = xcd_block();
   double sq = 0.0;
   for (int64_t r = (int64_t)lb * kBlock + threadIdx.x; r < n; r += (int64_t)gridDim.x * kBlock) {
-    const double v = b[r] - row_sum_seq<CH>(A, (int32_t)r, x, -1);
+    const double v = b[r] - row_sum_fine<CH, U>(A, (int32_t)r, x, -1);
     res[r] = v;
     sq += v * v;
   }
@@ -666,14 +674,20 @@ __global__ void k_check_finite(const double* v, int64_t n, int32_t* flag) {
 
 }  // namespace
 
-// Calls f(std::integral_constant<int, CH>) for the load chunk CH of the level-0 row kernels.
-template <class F>
-void with_chunk(int ch, F&& f) {
-  switch (ch) {
-    case 4: f(std::integral_constant<int, 4>{}); break;
-    case 16: f(std::integral_constant<int, 16>{}); break;
-    default: f(std::integral_constant<int, 8>{}); break;
-  }
+// Calls f(std::integral_constant<int, CH>, std::integral_constant<bool, U>) for
+// the load chunk CH of the level-0 row kernels and their slice form U (uniform
+// width; only where the level's SELL has one).
+template <class V, class F>
+void with_chunk(const LevelViewT<V>& v, F&& f) {
+  auto go = [&](auto UC) {
+    switch (v.ch) {
+      case 4: f(std::integral_constant<int, 4>{}, UC); break;
+      case 16: f(std::integral_constant<int, 16>{}, UC); break;
+      default: f(std::integral_constant<int, 8>{}, UC); break;
+    }
+  };
+  if (v.uni && v.A.uw > 0) go(std::integral_constant<bool, true>{});
+  else go(std::integral_constant<bool, false>{});
 }
 
 // One sweep in block order: the four block colours one launch each.  `skip`
@@ -729,10 +743,11 @@ void gs_sweep(const LevelViewT<V>& v, const Level& lv, hipStream_t s, bool fines
     if (finest) {
       KernelTimer::Scope t(timed ? (int)KernelTimer::GS_FINEST : -1, lv.color_bytes[c]);
       const int32_t span = r1 - (r0 & ~(kSlice - 1));
-      with_chunk(v.ch, [&](auto CC) {
+      with_chunk(v, [&](auto CC, auto UC) {
         constexpr int CH = decltype(CC)::value;
-        hipExtLaunchKernelGGL(k_gs_color_fine<CH, V>, dim3(blocks_for(span)), dim3(kBlock), 0, s, t.start, t.stop,
-                              0, v.A, (const V*)v.diag, (const V*)v.b, v.x, r0, r1);
+        constexpr bool U = decltype(UC)::value;
+        hipExtLaunchKernelGGL(k_gs_color_fine<CH, U, V>, dim3(blocks_for(span)), dim3(kBlock), 0, s, t.start,
+                              t.stop, 0, v.A, (const V*)v.diag, (const V*)v.b, v.x, r0, r1);
       });
     } else {
       KernelTimer::Scope t(timed ? (int)KernelTimer::GS_GALERKIN : -1, lv.color_bytes[c]);
@@ -749,9 +764,10 @@ void gs_sweep(const LevelViewT<V>& v, const Level& lv, hipStream_t s, bool fines
 template <class V>
 void residual(const LevelViewT<V>& v, hipStream_t s, bool finest) {
   if (finest) {
-    with_chunk(v.ch, [&](auto CC) {
+    with_chunk(v, [&](auto CC, auto UC) {
       constexpr int CH = decltype(CC)::value;
-      k_residual_fine<CH, V><<<blocks_for(v.n), kBlock, 0, s>>>(v.A, v.b, v.x, v.r, v.n);
+      constexpr bool U = decltype(UC)::value;
+      k_residual_fine<CH, U, V><<<blocks_for(v.n), kBlock, 0, s>>>(v.A, v.b, v.x, v.r, v.n);
     });
   } else {
     with_lanes(v.ra, [&](auto RC) {
@@ -814,9 +830,10 @@ void norm2_partials(const double* v, int64_t n, double* partials, hipStream_t s)
 void residual_norm(const Level& lv, const double* b, const double* x, double* res, double* partials,
                    hipStream_t s) {
   KernelTimer::Scope t(KernelTimer::RESIDUAL_FINEST, lv.residual_bytes);
-  with_chunk(lv.view.ch, [&](auto CC) {
+  with_chunk(lv.view, [&](auto CC, auto UC) {
     constexpr int CH = decltype(CC)::value;
-    hipExtLaunchKernelGGL(k_residual_norm<CH>, dim3(kNormBlocks), dim3(kBlock), 0, s, t.start, t.stop, 0,
+    constexpr bool U = decltype(UC)::value;
+    hipExtLaunchKernelGGL(k_residual_norm<CH, U>, dim3(kNormBlocks), dim3(kBlock), 0, s, t.start, t.stop, 0,
                           lv.view.A, b, x, res, (int64_t)lv.n, partials);
   });
 }

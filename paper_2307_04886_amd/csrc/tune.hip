@@ -1,10 +1,13 @@
 // Autotuner of the row kernels' shapes: for every level solved by separate
 // launches, the lanes per row of the SELL row kernels of A_l (residual and
 // colour sweeps) and of P_l^T (restriction, where one lane per row is also a
-// candidate), and the load chunk of level 0's one-lane-per-row kernels, are
+// candidate), and the load chunk of level 0's one-lane-per-row kernels (with
+// the uniform slice width as a candidate where level 0's SELL has one), are
 // picked by timing the candidates on the level's own data.  A shape only
 // distributes a row's terms over lanes or loads: every row is still summed in
-// its entry order, so the choice never changes a result bit.  Choices are
+// its entry order (uniform slices add their padding's +-0 products after the
+// row's own, which leaves the sum unchanged), so the choice never changes a
+// result bit.  Choices are
 // cached per shape class (kind, rows, mean and longest row), so later builds
 // of similar levels reuse them; the first build of a class pays for the
 // measurement.
@@ -20,7 +23,7 @@ namespace gmg {
 
 namespace {
 
-enum TuneKind : int32_t { TUNE_CHUNK0 = 0, TUNE_LANES_A = 1, TUNE_LANES_T = 2 };
+enum TuneKind : int32_t { TUNE_CHUNK0 = 0, TUNE_LANES_A = 1, TUNE_LANES_T = 2, TUNE_CHUNK0_UNIFORM = 3 };
 
 struct TuneKey {
   int32_t kind, rows, mean, maxlen;
@@ -97,11 +100,17 @@ void autotune(Handle& h) {
       // the residual writes the level's residual vector and the restriction the next
       // level's right-hand side and iterate: all of them are rewritten by every cycle
       if (l == 0) {
-        v.ch = choose(key_of(TUNE_CHUNK0, v.n, lv.nnzA, v.maxa), {4, 8, 16}, s, e0, e1, [&](int32_t c) {
-          LevelView t = v;
-          t.ch = c;
-          residual(t, s, true);
-        });
+        // chunk c % 100; c >= 100: the uniform slice width (where the layout has one)
+        const std::initializer_list<int32_t> sell = {4, 8, 16}, both = {4, 8, 16, 104, 108, 116};
+        const int32_t c = choose(key_of(v.A.uw > 0 ? TUNE_CHUNK0_UNIFORM : TUNE_CHUNK0, v.n, lv.nnzA, v.maxa),
+                                 v.A.uw > 0 ? both : sell, s, e0, e1, [&](int32_t c) {
+                                   LevelView t = v;
+                                   t.ch = c % 100;
+                                   t.uni = c >= 100 ? 1 : 0;
+                                   residual(t, s, true);
+                                 });
+        v.ch = c % 100;
+        v.uni = c >= 100 ? 1 : 0;
       } else {
         v.ra = choose(key_of(TUNE_LANES_A, v.n, lv.nnzA, v.maxa), {4, 8, 16, 32, 64}, s, e0, e1, [&](int32_t c) {
           LevelView t = v;

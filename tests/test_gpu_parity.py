@@ -393,7 +393,7 @@ def test_autotuned_shapes_keep_the_bits():
     for l in range(tuned.num_levels):
         t = tuned.tuning(l)
         assert t["lanes_A"] in (0, 4, 8, 16, 32, 64) and t["lanes_PT"] in (0, 1, 4, 8, 16, 32, 64)
-        assert t["chunk"] in (0, 4, 8, 16)
+        assert t["chunk"] in (0, 4, 8, 16) and (t["uniform_width"] == 0 or (l == 0 and t["uniform_width"] >= 1))
         _say(f"[gpu]   level {l}: {t}")
     assert tuned.tuning(0)["chunk"] > 0 and tuned.tuning(1)["block_sweep"] == 1
     b = torch.from_numpy(prob.rhs).cuda()
