@@ -32,10 +32,10 @@ sys.path.insert(0, ROOT)
 
 
 # HBM bytes per launch from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE, scaled by what the counters read
-# for a plain device copy (profiles/k_gs_color_*_torus1024.md); valid only for the kernel sources
-# they were taken on (sha256 prefix of solve.hip + rows.hpp).
-TRAFFIC = {"gs_finest": {"bytes_per_launch": 26822506, "src_sha256_16": "c193cd04f86734a6"},
-           "gs_galerkin": {"bytes_per_launch": 2557707, "src_sha256_16": "c193cd04f86734a6"}}
+# for a plain device copy (profiles/k_gs_block_torus1024.md, profiles/k_gs_color_fine_torus1024.md);
+# valid only for the kernel sources they were taken on (sha256 prefix of solve.hip + rows.hpp).
+TRAFFIC = {"gs_finest": {"bytes_per_launch": 26101198, "src_sha256_16": "b7efa72a99bdd190"},
+           "gs_galerkin": {"bytes_per_launch": 11060104, "src_sha256_16": "b7efa72a99bdd190"}}
 
 KERNEL_NAMES = {"gs_finest": "k_gs_color_fine (one colour of a Gauss-Seidel sweep, level 0)",
                 "residual_finest": "k_residual_norm (residual + norm partials, level 0)",
@@ -145,7 +145,7 @@ def progress(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def batched_leg(args, dev, opt, forms=("grouped", "f32", "plain")):
+def batched_leg(args, dev, opt, forms=("f32", "grouped", "plain")):
     """Many meshes of uneven size with 8 right-hand sides each: every hierarchy built and every
     right-hand side solved to the same tolerance.  Forms: the grouped float-preconditioned CG
     (builds on 4 streams, then one CG over all hierarchies, every step one launch for all meshes);
@@ -161,22 +161,24 @@ def batched_leg(args, dev, opt, forms=("grouped", "f32", "plain")):
         systems.append(tuple(t) + (torch.from_numpy(B).to(dev),))
     nsolves = sum(B.shape[0] for _, B in batch)
     progress("many-mesh workload generated")
-    res = {"workload": f"{len(batch)} jittered tori and icospheres, {min(b.n for b, _ in batch)}"
+    res = {"streams": args.batched_streams,
+           "workload": f"{len(batch)} jittered tori and icospheres, {min(b.n for b, _ in batch)}"
                        f"-{max(b.n for b, _ in batch)} vertices ({sum(b.n for b, _ in batch)} in total),"
                        f" 8 right-hand sides each, (M + 1e-3 L), tol {args.tol}", "solves": nsolves}
-    names = {"grouped": "setup on 4 streams + one float-preconditioned double CG over all hierarchies "
+    ns = args.batched_streams
+    names = {"grouped": f"setup on {ns} streams + one float-preconditioned double CG over all hierarchies "
                         "(gmg_solve_pcg_grouped: each step one launch for all meshes, 8 right-hand sides each)",
              "f32": "setup + float-preconditioned double CG per mesh (gmg_solve_pcg_batched), 8 right-hand "
-                    "sides per launch, 4 streams",
-             "plain": "setup + plain double V-cycle solve of each right-hand side in turn, the same 4 streams"}
+                    f"sides per launch, {ns} streams",
+             "plain": f"setup + plain double V-cycle solve of each right-hand side in turn, the same {ns} streams"}
     for form in forms:
         kw = {"grouped": dict(precision="f32", form="grouped"), "f32": dict(precision="f32"),
               "plain": dict(max_iters=200, form="plain")}[form]
-        solve_many(systems, streams=4, tol=args.tol, **kw)
+        solve_many(systems, streams=args.batched_streams, tol=args.tol, **kw)
         torch.cuda.synchronize()
         timing = {}
         t1 = time.perf_counter()
-        r = solve_many(systems, streams=4, tol=args.tol, timing=timing, **kw)
+        r = solve_many(systems, streams=args.batched_streams, tol=args.tol, timing=timing, **kw)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t1
         if any(st != 0 for _, _, st in r):
@@ -206,6 +208,9 @@ def main():
     ap.add_argument("--no-pointcloud", action="store_true", help="skip the 2M-point point-cloud measurement")
     ap.add_argument("--batched-only", action="store_true",
                     help="only the many-mesh batched measurement (for profiler runs)")
+    ap.add_argument("--batched-streams", type=int, default=4,
+                    help="streams (host threads) of the many-mesh builds and per-mesh solves (1: one thread, "
+                         "for profiler runs)")
     ap.add_argument("--headline-only", action="store_true",
                     help="only the plain steps (and roofline passes): for profiler runs")
     ap.add_argument("--size", type=int, default=1024, help="torus grid size (default 1024)")
@@ -232,7 +237,7 @@ def main():
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     if args.batched_only:
-        print(json.dumps({"batched": batched_leg(args, dev, default_options(), forms=("grouped", "f32"))}), flush=True)
+        print(json.dumps({"batched": batched_leg(args, dev, default_options(), forms=("f32", "grouped"))}), flush=True)
         return
     t0 = time.time()
     prob = synth.config_torus(args.size, args.size)

@@ -99,22 +99,44 @@ __global__ void __launch_bounds__(kBlkThreads) k_gs_block(BlockView<V> B, const 
   const int C = B.ncls;
   const int32_t pad = rows + nh;
   const uint64_t present = hd.mask;          // colours with rows in the block
-  int32_t my_c[R], len[R];
+  // Row data and entries.  Two forms with the same values in every slot that
+  // is used.  Double: per-lane conditional loads (lanes past the block's rows
+  // and slots past its width take the zero term), which fit 168 VGPRs.  Float:
+  // no branch inside a wavefront (with per-lane conditions the compiler waited
+  // for each load before issuing the next): a wavefront without rows of the
+  // block skips them (its registers are never read), lanes past the block's
+  // rows re-read its last row (masked where the rows are swept) and slots
+  // past the width re-read its last slot (their products are replaced by zero
+  // where the row is summed).
+  constexpr bool kClamp = sizeof(V) == 4;
+  const int32_t wbase = __builtin_amdgcn_readfirstlane((int32_t)threadIdx.x & ~(kWave - 1));
+  int32_t info[R];
   V bv[R], dv[R];
   int32_t lx[R][K];
   V lv[R][K];
 #pragma unroll
   for (int q = 0; q < R; ++q) {
     const int32_t p = (int32_t)threadIdx.x + q * kBlkThreads;
-    const bool own = p < rows;
-    const int32_t info = own ? B.rinfo[r0 + p] : -1;
-    my_c[q] = own ? (info & 0xFF) : -1;
-    len[q] = own ? (info >> 8) : 0;
+    if constexpr (kClamp) {
+      const int32_t pc = min(p, rows - 1);
+      if (wbase + q * kBlkThreads < rows) {
+        info[q] = B.rinfo[r0 + pc];
 #pragma unroll
-    for (int t = 0; t < K; ++t) {
-      const bool e = own && t < w;
-      lx[q][t] = e ? B.elx[e0 + t * rows + p] : pad;
-      lv[q][t] = e ? B.elv[e0 + t * rows + p] : V(0);
+        for (int t = 0; t < K; ++t) {
+          const int32_t o = e0 + min(t, w - 1) * rows + pc;
+          lx[q][t] = B.elx[o];
+          lv[q][t] = B.elv[o];
+        }
+      }
+    } else {
+      const bool own = p < rows;
+      info[q] = own ? B.rinfo[r0 + p] : 0;
+#pragma unroll
+      for (int t = 0; t < K; ++t) {
+        const bool e = own && t < w;
+        lx[q][t] = e ? B.elx[e0 + t * rows + p] : pad;
+        lv[q][t] = e ? B.elv[e0 + t * rows + p] : V(0);
+      }
     }
   }
   // the block's own rows (thread p holds rows p, p + kBlkThreads, ...) and its halo
@@ -136,7 +158,8 @@ __global__ void __launch_bounds__(kBlkThreads) k_gs_block(BlockView<V> B, const 
     if (!((present >> c) & 1)) continue;                // no row of this colour in the block
 #pragma unroll
     for (int q = 0; q < R; ++q) {
-      if (my_c[q] == c) {
+      if ((int32_t)threadIdx.x + q * kBlkThreads < rows && (info[q] & 0xFF) == c) {
+        const int32_t len = info[q] >> 8;
         // every gather of the row is issued at once, then the products are
         // added in entry order, in chunks of 8 up to the row's length
         // (terms past the row are +0); the largest shape works a chunk at a
@@ -148,10 +171,11 @@ __global__ void __launch_bounds__(kBlkThreads) k_gs_block(BlockView<V> B, const 
           if (g0 < w) {
             V pr[G];
 #pragma unroll
-            for (int t = 0; t < G; ++t) pr[t] = lv[q][g0 + t] * xl[lx[q][g0 + t]];
+            for (int t = 0; t < G; ++t)
+              pr[t] = (!kClamp || g0 + t < w ? lv[q][g0 + t] : V(0)) * xl[lx[q][g0 + t]];
 #pragma unroll
             for (int t0 = 0; t0 < G; t0 += 8) {
-              if (g0 + t0 < len[q]) {
+              if (g0 + t0 < len) {
 #pragma unroll
                 for (int u = 0; u < 8; ++u) s = s + pr[t0 + u];
               }
