@@ -336,6 +336,7 @@ void make_tail_at(const Handle& h, const Cycle<V>& c, int start, TailDescT<V>& t
     if (!coarsest) {
       t.o_r[i] = take(((int64_t)v.n + 1) * sizeof(V));
       t.o_c[i] = take((int64_t)v.ncolors * 16);
+      t.o_w[i] = take((int64_t)v.n * 2);
     }
   }
   if (off > kTailLdsMax) throw Error{GMG_DEVICE_ERROR, "tail LDS layout exceeds its budget"};
@@ -686,6 +687,7 @@ void kry_prepare(Handle& h, Cycle<float>& c) {
         f.B = d.B.with_values(to_f32_copy(h, d.B.elv, lv.blk_entries, s));
       if (d.e_cinfo) {                       // a tail level
         f.e_cinfo = d.e_cinfo;
+        f.e_ww = d.e_ww;
         f.e_col_gs = d.e_col_gs;
         f.e_col = d.e_col;
         f.e_tcol = d.e_tcol;

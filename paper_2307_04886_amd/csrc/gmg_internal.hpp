@@ -228,7 +228,12 @@ struct LevelViewT {
   // and width e_wt.  Padding entries have column n and value 0: the tail keeps
   // a zero at x[n] and r[n], so that every padded term is +0 and leaves the sum
   // unchanged.
+  // A tail level's rows are sorted within each colour by length, longest
+  // first, and e_ww[r] is the width (entries, a multiple of 4) of the longest
+  // row among the 64 rows of r's wavefront (64-row chunks from the colour's
+  // first row): a wavefront loads only that many entries of its rows.
   const int32_t* e_cinfo = nullptr;     // [ncolors][4]: lo, hi, w, off
+  const uint16_t* e_ww = nullptr;
   const int32_t* e_col_gs = nullptr;
   const V* e_val_gs = nullptr;
   const int32_t* e_col = nullptr;
@@ -249,7 +254,7 @@ struct TailDescT {
   // single-vector tail: byte offsets in LDS of every tail level's x (n + 1),
   // b (n), r (n + 1) and colour table (the coarsest level: x and b)
   int32_t lds_bytes = 0;
-  int32_t o_x[kMaxTail] = {}, o_b[kMaxTail] = {}, o_r[kMaxTail] = {}, o_c[kMaxTail] = {};
+  int32_t o_x[kMaxTail] = {}, o_b[kMaxTail] = {}, o_r[kMaxTail] = {}, o_c[kMaxTail] = {}, o_w[kMaxTail] = {};
   // batched tail: LDS (elements of V) holding the tail levels' iterates
   int32_t lds_elems = 0;
   int32_t lds_off[kMaxTail] = {};       // offset of level l's x in LDS, or -1 (global)
@@ -275,13 +280,18 @@ inline __host__ __device__ int64_t ell_val_index(int64_t off, int64_t cnt, int64
 }
 
 // LDS bytes of one level in the single-vector tail (value type V): x and r with
-// their zero, b, the colour table; the coarsest level keeps x and b only.
-// Arrays start on 16-byte boundaries.
+// their zero, b, the colour table and the rows' wavefront widths; the coarsest
+// level keeps x and b only.  Arrays start on 16-byte boundaries.
 inline int64_t tail_lds_bytes(int64_t n, int64_t ncolors, bool coarsest, int64_t vbytes) {
   auto up = [](int64_t b) { return (b + 15) & ~(int64_t)15; };
   if (coarsest) return 2 * up(n * vbytes);
-  return 2 * up((n + 1) * vbytes) + up(n * vbytes) + up(ncolors * 16);
+  return 2 * up((n + 1) * vbytes) + up(n * vbytes) + up(ncolors * 16) + up(n * 2);
 }
+
+// Rows of a level with at most kTailRows rows are sorted within each colour by
+// their width in 4-entry quads (longest first; kLenKeys classes, longer rows
+// share the last), then by index.
+constexpr int kLenKeys = 32;
 
 // One variant of the V-cycle: its per-level views and its tail descriptor.
 // symmetric: post-smoothing runs the colours in descending order, so that the

@@ -247,9 +247,19 @@ __global__ void __launch_bounds__(kBlock) k_color_place(const int32_t* color, in
   iperm[v] = nw;
 }
 
-__global__ void k_color_ptr(const int32_t* off, int nb, int nc, int32_t* cptr) {
+// cptr[c] = first new index of colour c (keys of stride classes per colour).
+__global__ void k_color_ptr(const int32_t* off, int nb, int nc, int stride, int32_t* cptr) {
   int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c <= nc) cptr[c] = off[(int64_t)c * nb];
+  if (c <= nc) cptr[c] = off[(int64_t)c * stride * nb];
+}
+
+// key = colour * kLenKeys + class, the class counting down from the widest
+// rows (in 4-entry quads), so that a colour's rows come longest first.
+__global__ void k_len_class(const int32_t* color, const int32_t* rp, int64_t n, int32_t* key) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const int32_t quads = (rp[v + 1] - rp[v] + 3) / 4;
+  key[v] = color[v] * kLenKeys + (kLenKeys - 1 - min(max(quads - 1, 0), kLenKeys - 1));
 }
 
 // ------------------------------------------------------------------ SELL-64 matrices
@@ -686,15 +696,24 @@ __global__ void k_color_width(const int32_t* len, const int32_t* cptr, int32_t* 
   }
 }
 
-// A_l (SELL) into the tail's per-colour ELL, with and without the diagonal.
+// A_l (SELL) into the tail's per-colour ELL, with and without the diagonal,
+// and every row's wavefront width: the longest row of its 64-row chunk of the
+// colour, rounded up to 4 entries.
 __global__ void k_tail_ell(SellView A, const int32_t* cinfo, int nc, int64_t n, int32_t* col_gs, double* val_gs,
-                           int32_t* col, double* val) {
+                           int32_t* col, double* val, uint16_t* ww) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n) return;
   int c = 0;
   while (c + 1 < nc && cinfo[4 * (c + 1)] <= r) ++c;
   const int32_t lo = cinfo[4 * c], hi = cinfo[4 * c + 1], w = cinfo[4 * c + 2], off = cinfo[4 * c + 3];
   const int32_t len = A.len[r];
+  {
+    const int32_t c0 = lo + (int32_t)((r - lo) & ~(int64_t)(kWave - 1));
+    const int32_t c1 = min(c0 + kWave, hi);
+    int32_t m = 0;
+    for (int32_t q = c0; q < c1; ++q) m = max(m, A.len[q]);
+    ww[r] = (uint16_t)min((m + 3) & ~3, w);
+  }
   const int64_t base = A.ptr[r / kSlice] + (r & (kSlice - 1));
   for (int32_t t = 0; t < w; ++t) {
     const int64_t oc = ell_col_index(off, hi - lo, lo, r, t), ov = ell_val_index(off, hi - lo, lo, r, t);
@@ -1482,7 +1501,7 @@ void block_layout(Handle& h, Level& lv, int32_t C) {
   k_color_hist<<<nb, kBlock, (size_t)nblk * 4, s>>>(blk, n, nb, nblk, hist);
   scan_i32(hist, hoffs, (int64_t)nblk * nb, s);
   k_color_place<<<nb, kBlock, 0, s>>>(blk, n, nb, hoffs, brows, bpos);
-  k_color_ptr<<<blocks_for(nblk + 1), kBlock, 0, s>>>(hoffs, nb, nblk, boff);
+  k_color_ptr<<<blocks_for(nblk + 1), kBlock, 0, s>>>(hoffs, nb, nblk, 1, boff);
   tfree(s, hist);
   tfree(s, hoffs);
   // local row of every solve row; first local row of every colour
@@ -1658,20 +1677,28 @@ void solve_layout(Handle& h, Level& lv, const Level* nx, const int32_t* t_rp, co
   int32_t *hist = nullptr, *off = nullptr;
   int32_t* stage = (int32_t*)pinned_staging((size_t)(2 * C + 1) * 4);
   if (lv.color) {
-    // rows sorted by (sweep class, index)
+    // rows sorted by (sweep class, index); on levels small enough for the
+    // single-workgroup tail by (colour, width class, index)
     const int32_t* key = lv.color;
     int32_t* cls = nullptr;
+    int K = 1;
     if (lv.bcolor) {
       cls = (int32_t*)talloc(s, (size_t)n * 4);
       k_sweep_class<<<blocks_for(n), kBlock, 0, s>>>(lv.bcolor, lv.color, n, C0, cls);
       key = cls;
+    } else if (n <= kTailRows && (int64_t)C * kLenKeys * 4 <= 48 * 1024) {
+      K = kLenKeys;
+      cls = (int32_t*)talloc(s, (size_t)n * 4);
+      k_len_class<<<blocks_for(n), kBlock, 0, s>>>(lv.color, lv.arp, n, cls);
+      key = cls;
     }
-    hist = (int32_t*)talloc(s, ((size_t)C * nb + 1) * 4);
-    off = (int32_t*)talloc(s, ((size_t)C * nb + 1) * 4);
-    k_color_hist<<<nb, kBlock, (size_t)C * 4, s>>>(key, n, nb, C, hist);
-    scan_i32(hist, off, (int64_t)C * nb, s);
+    const int64_t classes = (int64_t)C * K;
+    hist = (int32_t*)talloc(s, ((size_t)classes * nb + 1) * 4);
+    off = (int32_t*)talloc(s, ((size_t)classes * nb + 1) * 4);
+    k_color_hist<<<nb, kBlock, (size_t)classes * 4, s>>>(key, n, nb, (int)classes, hist);
+    scan_i32(hist, off, classes * nb, s);
     k_color_place<<<nb, kBlock, 0, s>>>(key, n, nb, off, lv.perm, lv.iperm);
-    k_color_ptr<<<blocks_for(C + 1), kBlock, 0, s>>>(off, nb, C, cptr);
+    k_color_ptr<<<blocks_for(C + 1), kBlock, 0, s>>>(off, nb, C, K, cptr);
     if (cls) tfree(s, cls);
   } else {
     // the coarsest level keeps its numbering (it is solved directly)
@@ -1839,6 +1866,7 @@ void ell_layout(Handle& h, Level& lv, const Level& nx) {
   v.e_col = (int32_t*)dalloc(h, e * 4);
   v.e_val_gs = (double*)dalloc(h, e * 8);
   v.e_val = (double*)dalloc(h, e * 8);
+  v.e_ww = (uint16_t*)dalloc(h, (size_t)lv.n * 2);
   ell_values(h, lv);
   v.e_wt = (v.maxt + kTailGroup - 1) / kTailGroup * kTailGroup;
   lv.e_tslots = (int64_t)v.e_wt * nx.n;
@@ -1855,7 +1883,8 @@ void ell_layout(Handle& h, Level& lv, const Level& nx) {
 void ell_values(Handle& h, Level& lv) {
   const LevelView& v = lv.view;
   k_tail_ell<<<blocks_for(lv.n), kBlock, 0, h.stream>>>(v.A, v.e_cinfo, v.ncolors, lv.n, (int32_t*)v.e_col_gs,
-                                                        (double*)v.e_val_gs, (int32_t*)v.e_col, (double*)v.e_val);
+                                                        (double*)v.e_val_gs, (int32_t*)v.e_col, (double*)v.e_val,
+                                                        (uint16_t*)v.e_ww);
 }
 
 }  // namespace gmg

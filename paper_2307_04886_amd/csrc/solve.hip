@@ -331,9 +331,9 @@ __global__ void __launch_bounds__(kBlock) k_dense_gemv(const double* __restrict_
 // are exactly +0.
 constexpr int kTailThreads1 = 256;
 constexpr int kTailW = 32;                 // entries of a row held in registers; the rest load on demand
-constexpr int kTailGroups = kTailW / kTailGroup;
 constexpr int kTailProlong = 4;            // prolongation rows per thread whose loads are issued together
 constexpr int kTailGemv = 16;              // columns of the coarsest inverse per prefetched chunk
+constexpr int kTailLoad = 16;              // elements per thread of the first tail level's loads into LDS
 
 struct TailSeg {
   int32_t lo, hi, w, off;                  // rows [lo, hi), ELL width, offset of entry (0, lo)
@@ -344,6 +344,7 @@ struct TailRow {
   int32_t j[kTailW];
   V v[kTailW];
   V d;
+  int32_t w;                               // entries loaded for the wavefront's rows (uniform)
 };
 
 __device__ __forceinline__ int32_t uniform(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -393,81 +394,94 @@ __device__ __forceinline__ TailMat<V> tail_mat(const int32_t* col, const V* val,
   return TailMat<V>{make_rsrc(col, slots * 4), make_rsrc(val, slots * (int64_t)sizeof(V))};
 }
 
-// Entries t0..t0+7 of the lane's row (row offset lo in a segment of cnt rows
-// at element offset off): two 4-entry column blocks, four 2-entry value blocks.
+// Entries t0..t0+3 of the lane's row (row offset lo in a segment of cnt rows
+// at element offset off): one 4-entry column block, two 2-entry value blocks.
 template <class V>
-__device__ __forceinline__ void tail_group(const TailMat<V>& M, uint32_t off, uint32_t cnt, uint32_t lo,
-                                           uint32_t t0, int32_t* j, V* v) {
+__device__ __forceinline__ void tail_quad(const TailMat<V>& M, uint32_t off, uint32_t cnt, uint32_t lo,
+                                          uint32_t t0, int32_t* j, V* v) {
+  const u32x4 c = bload16(M.col, lo * 16u, (off + (t0 >> 2) * cnt * 4u) * 4u);
+  j[0] = (int32_t)c.x;
+  j[1] = (int32_t)c.y;
+  j[2] = (int32_t)c.z;
+  j[3] = (int32_t)c.w;
 #pragma unroll
-  for (int b = 0; b < 2; ++b) {
-    const u32x4 c = bload16(M.col, lo * 16u, (off + ((t0 >> 2) + b) * cnt * 4u) * 4u);
-    j[4 * b] = (int32_t)c.x;
-    j[4 * b + 1] = (int32_t)c.y;
-    j[4 * b + 2] = (int32_t)c.z;
-    j[4 * b + 3] = (int32_t)c.w;
-  }
-#pragma unroll
-  for (int b = 0; b < 4; ++b) val_pair<V>(M.val, lo, off + ((t0 >> 1) + b) * cnt * 2u, v[2 * b], v[2 * b + 1]);
+  for (int b = 0; b < 2; ++b) val_pair<V>(M.val, lo, off + ((t0 >> 1) + b) * cnt * 2u, v[2 * b], v[2 * b + 1]);
 }
 
-// Entries 0..kTailW-1 (up to the segment's width) of row r (clamped into the
-// segment by the caller), and its diagonal when D.
+// A row offset whose lane offsets (16 or 8 bytes per row) lie past every tail
+// array: such a buffer load reads no memory and returns zeros.
+constexpr uint32_t kTailNoRow = 0x08000000u;
+
+// Entries 0..kTailW-1 of row r (clamped into the segment by the caller), up to
+// w (uniform over the wavefront, a multiple of 4 within the segment's width),
+// and its diagonal when D.  The quads past w are loads out of the buffer's
+// range (no memory traffic), so that every round issues the same number of
+// loads and the consumer of a round waits only for that round's loads, not
+// for the next round's already in flight.
 template <bool D, class V>
 __device__ __forceinline__ void tail_fetch(const TailMat<V>& M, const V* diag, const TailSeg& sg, int32_t r,
-                                           TailRow<V>& q) {
+                                           int32_t w, TailRow<V>& q) {
   const uint32_t cnt = (uint32_t)(sg.hi - sg.lo);
   const uint32_t lo = (uint32_t)(r - sg.lo);
+  q.w = w;
 #pragma unroll
-  for (int g = 0; g < kTailGroups; ++g)
-    if (g * kTailGroup < sg.w)
-      tail_group(M, (uint32_t)sg.off, cnt, lo, (uint32_t)(g * kTailGroup), q.j + g * kTailGroup,
-                 q.v + g * kTailGroup);
+  for (int g = 0; g < kTailW / 4; ++g)
+    tail_quad(M, (uint32_t)sg.off, cnt, 4 * g < w ? lo : kTailNoRow, (uint32_t)(4 * g), q.j + 4 * g, q.v + 4 * g);
   if (D) q.d = diag[r];
 }
 
-// sum over the row's entries in entry order of val * X[col] (padding adds +0)
+// sum over the row's entries in entry order of val * X[col]; the entries past
+// the row's end up to the wavefront's width are padding (+0 terms)
 template <class V>
 __device__ __forceinline__ V tail_sum(const TailMat<V>& M, const TailSeg& sg, int32_t r, const TailRow<V>& q,
                                       const V* X) {
-  V p[kTailW];
+  const int32_t w = q.w;
+  // all gathers first, so that they are in flight together
+  V xv[kTailW];
 #pragma unroll
-  for (int g = 0; g < kTailGroups; ++g)
-    if (g * kTailGroup < sg.w) {
+  for (int g = 0; g < kTailW / 4; ++g)
+    if (4 * g < w) {
 #pragma unroll
-      for (int u = 0; u < kTailGroup; ++u) p[g * kTailGroup + u] = q.v[g * kTailGroup + u] * X[q.j[g * kTailGroup + u]];
+      for (int u = 0; u < 4; ++u) xv[4 * g + u] = X[q.j[4 * g + u]];
     }
   V acc = V(0);
 #pragma unroll
-  for (int g = 0; g < kTailGroups; ++g)
-    if (g * kTailGroup < sg.w) {
+  for (int g = 0; g < kTailW / 4; ++g)
+    if (4 * g < w) {
 #pragma unroll
-      for (int u = 0; u < kTailGroup; ++u) acc = acc + p[g * kTailGroup + u];
+      for (int u = 0; u < 4; ++u) acc = acc + q.v[4 * g + u] * xv[4 * g + u];
     }
   const uint32_t cnt = (uint32_t)(sg.hi - sg.lo);
   const uint32_t lo = (uint32_t)(r - sg.lo);
-  for (int32_t t0 = kTailW; t0 < sg.w; t0 += kTailGroup) {
-    int32_t j[kTailGroup];
-    V v[kTailGroup];
-    tail_group(M, (uint32_t)sg.off, cnt, lo, (uint32_t)t0, j, v);
+  for (int32_t t0 = kTailW; t0 < w; t0 += 4) {
+    int32_t j[4];
+    V v[4];
+    tail_quad(M, (uint32_t)sg.off, cnt, lo, (uint32_t)t0, j, v);
 #pragma unroll
-    for (int u = 0; u < kTailGroup; ++u) acc = acc + v[u] * X[j[u]];
+    for (int u = 0; u < 4; ++u) acc = acc + v[u] * X[j[u]];
   }
   return acc;
 }
 
 // Runs the rows of segments 0..nseg-1 (seg(s) -> TailSeg) through the
-// pipeline; out(r, acc, diag) consumes each row's sum.  A workgroup barrier
+// pipeline; out(r, acc, diag) consumes each row's sum.  A wavefront loads the
+// entries up to WW[r] of its rows (WW in LDS, the same for the wavefront's 64
+// rows), or up to the segment's width when WW is null.  A workgroup barrier
 // follows every segment when `barrier_each` (colours of a sweep), else only
 // the last.  Two row buffers alternate (no copies between rounds).
 template <bool D, class V, class Seg, class Out>
-__device__ __forceinline__ void tail_rows(const TailMat<V>& M, const V* diag, int nseg, Seg seg, const V* X,
-                                          bool barrier_each, Out out) {
+__device__ __forceinline__ void tail_rows(const TailMat<V>& M, const V* diag, const uint16_t* WW, int nseg, Seg seg,
+                                          const V* X, bool barrier_each, Out out) {
   const int32_t tid = threadIdx.x;
+  auto width = [&](const TailSeg& g, int32_t r) { return WW ? uniform((int32_t)WW[r]) : g.w; };
   TailSeg sg = seg(0);
   int s = 0;
   int32_t r0 = sg.lo;
   TailRow<V> ra, rb;
-  tail_fetch<D>(M, diag, sg, max(min(r0 + tid, sg.hi - 1), 0), ra);
+  {
+    const int32_t r = max(min(r0 + tid, sg.hi - 1), 0);
+    tail_fetch<D>(M, diag, sg, r, width(sg, r), ra);
+  }
   // one round: loads the next round into nxt, then computes cur; false after the last
   auto round = [&](TailRow<V>& cur, TailRow<V>& nxt) {
     TailSeg sg2 = sg;
@@ -486,7 +500,10 @@ __device__ __forceinline__ void tail_rows(const TailMat<V>& M, const V* diag, in
       sg2 = sg;
       r2 = r0;
     }
-    tail_fetch<D>(M, diag, sg2, max(min(r2 + tid, sg2.hi - 1), 0), nxt);
+    {
+      const int32_t rn = max(min(r2 + tid, sg2.hi - 1), 0);
+      tail_fetch<D>(M, diag, sg2, rn, width(sg2, rn), nxt);
+    }
     const int32_t r = r0 + tid;
     const V acc = tail_sum(M, sg, max(min(r, sg.hi - 1), 0), cur, X);
     if (r < sg.hi) out(r, acc, cur.d);
@@ -504,6 +521,7 @@ template <class V>
 struct TailLds {
   V *x, *b, *r;
   const int4* c;                           // colour table (lo, hi, w, off)
+  const uint16_t* w;                       // rows' wavefront widths
 };
 
 template <class V>
@@ -513,6 +531,7 @@ __device__ __forceinline__ TailLds<V> tail_lds(const TailDescT<V>& d, char* lds,
   t.b = reinterpret_cast<V*>(lds + d.o_b[l]);
   t.r = reinterpret_cast<V*>(lds + d.o_r[l]);
   t.c = reinterpret_cast<const int4*>(lds + d.o_c[l]);
+  t.w = reinterpret_cast<const uint16_t*>(lds + d.o_w[l]);
   return t;
 }
 
@@ -527,7 +546,7 @@ __device__ __forceinline__ void tail_gs(const LevelViewT<V>& L, const TailLds<V>
   const int nc = L.ncolors;
   if (nsweeps <= 0) return;
   tail_rows<true>(
-      tail_mat(L.e_col_gs, L.e_val_gs, L.e_slots), L.diag, nsweeps * nc,
+      tail_mat(L.e_col_gs, L.e_val_gs, L.e_slots), L.diag, t.w, nsweeps * nc,
       [&](int s) {
         const int i = s % nc;
         return colour_seg(t.c, descending ? nc - 1 - i : i);
@@ -541,36 +560,53 @@ __global__ void __launch_bounds__(kTailThreads1) k_tail_vcycle(TailDescT<V> d) {
   char* lds = reinterpret_cast<char*>(lds_raw);
   const int tid = threadIdx.x;
   const int lc = d.nlev - 1;   // the coarsest level
-  // colour tables and the zeros behind x and r; the first tail level's x and b
-  for (int l = 0; l < lc; ++l) {
-    const LevelViewT<V>& L = d.lv[l];
-    const TailLds<V> t = tail_lds(d, lds, l);
-    int32_t* ct = reinterpret_cast<int32_t*>(lds + d.o_c[l]);
-    for (int i = tid; i < 4 * L.ncolors; i += kTailThreads1) ct[i] = L.e_cinfo[i];
-    if (tid == 0) {
-      t.x[L.n] = V(0);
-      t.r[L.n] = V(0);
-    }
-  }
+  // the first tail level's x and b (and, when it is not the coarsest, its
+  // rows' widths) with its colour table: each chunk's loads are all issued
+  // before its LDS writes, so that they wait on one memory latency
   {
+    const LevelViewT<V>& L = d.lv[0];
     const TailLds<V> t = tail_lds(d, lds, 0);
-    const int32_t n = d.lv[0].n;
-    for (int32_t i0 = 0; i0 < n; i0 += 8 * kTailThreads1) {
-      V xv[8], bv[8];
+    const int32_t n = L.n;
+    const bool smoothed = lc > 0;
+    uint16_t* ww = reinterpret_cast<uint16_t*>(lds + d.o_w[0]);
+    for (int32_t i0 = 0; i0 < n; i0 += kTailLoad * kTailThreads1) {
+      V xv[kTailLoad], bv[kTailLoad];
+      uint16_t wv[kTailLoad];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
+      for (int u = 0; u < kTailLoad; ++u) {
         const int32_t i = min(i0 + u * kTailThreads1 + tid, n - 1);
-        xv[u] = d.lv[0].x[i];
-        bv[u] = d.lv[0].b[i];
+        xv[u] = L.x[i];
+        bv[u] = L.b[i];
+        wv[u] = smoothed ? L.e_ww[i] : (uint16_t)0;
+      }
+      if (i0 == 0 && smoothed) {
+        int32_t* ct = reinterpret_cast<int32_t*>(lds + d.o_c[0]);
+        for (int i = tid; i < 4 * L.ncolors; i += kTailThreads1) ct[i] = L.e_cinfo[i];
       }
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
+      for (int u = 0; u < kTailLoad; ++u) {
         const int32_t i = i0 + u * kTailThreads1 + tid;
         if (i < n) {
           t.x[i] = xv[u];
           t.b[i] = bv[u];
+          if (smoothed) ww[i] = wv[u];
         }
       }
+    }
+  }
+  // the other smoothed tail levels' colour tables and widths; the zeros behind x and r
+  for (int l = 0; l < lc; ++l) {
+    const LevelViewT<V>& L = d.lv[l];
+    const TailLds<V> t = tail_lds(d, lds, l);
+    if (l > 0) {
+      int32_t* ct = reinterpret_cast<int32_t*>(lds + d.o_c[l]);
+      for (int i = tid; i < 4 * L.ncolors; i += kTailThreads1) ct[i] = L.e_cinfo[i];
+      uint16_t* ww = reinterpret_cast<uint16_t*>(lds + d.o_w[l]);
+      for (int i = tid; i < L.n; i += kTailThreads1) ww[i] = L.e_ww[i];
+    }
+    if (tid == 0) {
+      t.x[L.n] = V(0);
+      t.r[L.n] = V(0);
     }
   }
   __syncthreads();
@@ -580,14 +616,15 @@ __global__ void __launch_bounds__(kTailThreads1) k_tail_vcycle(TailDescT<V> d) {
     tail_gs(L, t, d.nu_pre, false);
     // r = b - A x, colour by colour
     tail_rows<false>(
-        tail_mat(L.e_col, L.e_val, L.e_slots), L.diag, L.ncolors, [&](int s) { return colour_seg(t.c, s); }, t.x,
-        false,
+        tail_mat(L.e_col, L.e_val, L.e_slots), L.diag, t.w, L.ncolors, [&](int s) { return colour_seg(t.c, s); },
+        t.x, false,
         [&](int32_t r, V acc, V) { t.r[r] = t.b[r] - acc; });
     // b_c = P^T r, x_c = 0
     const TailLds<V> tc = tail_lds(d, lds, l + 1);
     const int32_t nc = d.lv[l + 1].n;
     tail_rows<false>(
-        tail_mat(L.e_tcol, L.e_tval, L.e_tslots), L.diag, 1, [&](int) { return TailSeg{0, nc, uniform(L.e_wt), 0}; },
+        tail_mat(L.e_tcol, L.e_tval, L.e_tslots), L.diag, nullptr, 1,
+        [&](int) { return TailSeg{0, nc, uniform(L.e_wt), 0}; },
         t.r, false,
         [&](int32_t r, V acc, V) {
           tc.b[r] = acc;
