@@ -128,10 +128,14 @@ void cache_settle(hipStream_t s) {
 }
 
 constexpr size_t kStaging = 1 << 16;
+constexpr int kNormSpins = 1 << 22;   // host polls of a V-cycle's norm (tens of ms) before a blocking wait
 
 double* pinned_scratch() {
   static thread_local double* p = nullptr;
-  if (!p) check_hip(hipHostMalloc((void**)&p, kStaging, hipHostMallocDefault), "pinned host buffer");
+  if (!p) {
+    check_hip(hipHostMalloc((void**)&p, kStaging, hipHostMallocDefault), "pinned host buffer");
+    std::memset(p, 0, kStaging);
+  }
   return p;
 }
 }  // namespace
@@ -144,12 +148,15 @@ void* pinned_staging(size_t bytes) {
 // Up to kScalarGather device scalars copied by one launch into 8-byte slots
 // of the pinned buffer (lane k takes item k; a 4-byte item fills the low half).
 constexpr int kScalarGather = 8;
+constexpr int kScalarMark = 256;      // 8-byte slot of the pinned buffer that marks a finished read
 struct ScalarGather {
   const void* src[kScalarGather];
   int32_t bytes[kScalarGather];
 };
 
-__global__ void k_read_scalars(ScalarGather g, int count, uint64_t* out) {
+// The last launch of a read also stores seq at mark (after the values), which
+// the host polls for.
+__global__ void k_read_scalars(ScalarGather g, int count, uint64_t* out, uint64_t* mark, uint64_t seq) {
   const int k = (int)threadIdx.x;
   if (k >= count) return;
   const void* src = g.src[0];
@@ -161,12 +168,28 @@ __global__ void k_read_scalars(ScalarGather g, int count, uint64_t* out) {
       bytes = g.bytes[j];
     }
   out[k] = bytes == 4 ? (uint64_t)*(const uint32_t*)src : *(const uint64_t*)src;
+  if (mark && k == 0) __hip_atomic_store(mark, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// Waits until the stream's last kernel has stored seq at *mark (pinned host
+// memory); after kNormSpins polls, for the stream itself (which also reports
+// any device error).
+void wait_mark(hipStream_t s, volatile uint64_t* mark, uint64_t seq, const char* what) {
+  check_hip(hipGetLastError(), what);
+  for (int spin = 0; spin < kNormSpins; ++spin) {
+    if (*mark == seq) return;
+    __builtin_ia32_pause();
+  }
+  sync(s, what);
 }
 
 void read_scalars(Handle& h, const ScalarRead* items, int count) {
   char* buf = (char*)pinned_scratch();
   static thread_local uint64_t* dbuf = nullptr;      // the buffer's device address
+  static thread_local uint64_t seq = 0;
   if (!dbuf) check_hip(hipHostGetDevicePointer((void**)&dbuf, buf, 0), "pinned host buffer");
+  if (count > kScalarMark) throw Error{GMG_DEVICE_ERROR, "too many scalars in one read"};
+  ++seq;
   for (int k0 = 0; k0 < count; k0 += kScalarGather) {
     ScalarGather g{};
     const int c = std::min(count - k0, kScalarGather);
@@ -174,10 +197,10 @@ void read_scalars(Handle& h, const ScalarRead* items, int count) {
       g.src[k] = items[k0 + k].src;
       g.bytes[k] = items[k0 + k].bytes;
     }
-    k_read_scalars<<<1, kWave, 0, h.stream>>>(g, c, dbuf + k0);
+    const bool last = k0 + kScalarGather >= count;
+    k_read_scalars<<<1, kWave, 0, h.stream>>>(g, c, dbuf + k0, last ? dbuf + kScalarMark : nullptr, seq);
   }
-  check_hip(hipGetLastError(), "scalar read");
-  sync(h.stream, "device-to-host copy");
+  wait_mark(h.stream, reinterpret_cast<volatile uint64_t*>(buf) + kScalarMark, seq, "device-to-host copy");
   for (int k = 0; k < count; ++k) {
     if (items[k].bytes == 4) {
       int32_t v;
@@ -221,16 +244,9 @@ void sync(hipStream_t s, const char* what) {
 }
 
 int64_t read_i64(Handle& h, const void* dev_ptr, int bytes) {
-  double* buf = pinned_scratch();
-  check_hip(hipMemcpyAsync(buf, dev_ptr, bytes, hipMemcpyDeviceToHost, h.stream), "device-to-host copy");
-  sync(h.stream, "device-to-host copy");
-  if (bytes == 4) {
-    int32_t v;
-    std::memcpy(&v, buf, 4);
-    return v;
-  }
-  int64_t v;
-  std::memcpy(&v, buf, 8);
+  int64_t v = 0;
+  ScalarRead rd{dev_ptr, bytes, &v};
+  read_scalars(h, &rd, 1);
   return v;
 }
 
@@ -290,6 +306,8 @@ void release(H* h) {
   }
   mark("release: graphs");
   if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+  (void)hipStreamSynchronize(h->stream);
+  if (h->norm_host) (void)hipHostFree(h->norm_host);
   mark("release: capture stream");
   (void)hipStreamSynchronize(h->stream);
   try {
@@ -571,7 +589,7 @@ void run_iteration(Handle& h, hipStream_t s) {
     vcycle(h, h.plain, 0, s);
   }
   residual_norm(l0, l0.b, l0.x, l0.r, h.red, s);
-  finish_norm(h.red, h.red + kNormBlocks, s);
+  finish_norm(h.red, h.red + kNormBlocks, s, h.norm_dev);
 }
 
 // Captures the iteration into a graph (one launch instead of ~100) on a
@@ -605,7 +623,7 @@ void capture_cycle(Handle& h) {
       vcycle(h, h.plain, 0, h.cap_stream);
       if (h.graph_mode == 0) {
         residual_norm(l0, l0.b, l0.x, l0.r, h.red, h.cap_stream);
-        finish_norm(h.red, h.red + kNormBlocks, h.cap_stream);
+        finish_norm(h.red, h.red + kNormBlocks, h.cap_stream, h.norm_dev);
       }
     }
     ok = hipStreamEndCapture(h.cap_stream, &h.graph) == hipSuccess && h.graph;
@@ -1615,13 +1633,27 @@ int gmg_solve(gmg_handle hh, const double* b_dev, double* x_dev, double tol, int
     status = GMG_NOT_CONVERGED;
     double rel = 0.0;
     int32_t it = 0;
+    if (!h->norm_host) {
+      check_hip(hipHostMalloc((void**)&h->norm_host, 64, hipHostMallocDefault), "pinned host buffer");
+      check_hip(hipHostGetDevicePointer((void**)&h->norm_dev, h->norm_host, 0), "pinned host buffer");
+    }
     capture_cycle(*h);
+    volatile uint64_t* nh = reinterpret_cast<volatile uint64_t*>(h->norm_host);
     while (it < max_iters) {
+      // the cycle's last kernel stores the norm in pinned memory: the host
+      // waits for that store (a norm is never the all-ones pattern) rather
+      // than for a copy and the stream, then for the stream's completion only
+      // when the solve ends or the wait runs long
+      *nh = ~0ull;
       run_iteration(*h, s);
-      check_hip(hipMemcpyAsync(hs, red + kNormBlocks, 8, hipMemcpyDeviceToHost, s), "copy");
-      sync(s, "V-cycle");
+      uint64_t u = ~0ull;
+      for (int spin = 0; spin < kNormSpins && (u = *nh) == ~0ull; ++spin) __builtin_ia32_pause();
+      if (u == ~0ull) {
+        sync(s, "V-cycle");
+        u = *nh;
+      }
       ++it;
-      rel = hs[0] / nb;
+      rel = __builtin_bit_cast(double, u) / nb;
       if (residual_history) residual_history[it - 1] = rel;
       if (rel <= tol) {
         status = GMG_OK;

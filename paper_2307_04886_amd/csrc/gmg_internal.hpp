@@ -415,6 +415,8 @@ struct Handle {
   int32_t* flags = nullptr;             // device error flags and counters
   int32_t* rounds = nullptr;            // device per-round counters of frontier loops
   double* red = nullptr;                // reduction partials
+  double* norm_host = nullptr;          // pinned: the solve's residual norm, written by the cycle's last kernel
+  double* norm_dev = nullptr;           // its device address
   int tail_start = -1;                  // first level solved by the single-workgroup tail kernel
   Cycle<double> plain;                  // the V-cycle of the solve (Alg. 2)
   Cycle<double> noalloc64;              // the symmetric double cycle on the no-allocation scratch
@@ -544,7 +546,7 @@ void permute_out(const int32_t* perm, const V* src, double* dst, int64_t n, hipS
 void norm2_partials(const double* v, int64_t n, double* partials, hipStream_t s);
 void residual_norm(const Level& lv, const double* b, const double* x, double* res, double* partials,
                    hipStream_t s);
-void finish_norm(const double* partials, double* out, hipStream_t s);
+void finish_norm(const double* partials, double* out, hipStream_t s, double* host_out = nullptr);
 void check_finite(const double* v, int64_t n, int32_t* flag, hipStream_t s);
 void pattern_outer(int64_t n, const int32_t* rp, const int32_t* col, const double* u, const double* v,
                    double scale, double* out, hipStream_t s);

@@ -242,11 +242,19 @@ __global__ void __launch_bounds__(kBlock) k_norm_partials(const double* v, int64
   if (threadIdx.x == 0) partials[blockIdx.x] = t;
 }
 
-__global__ void __launch_bounds__(kBlock) k_finish_norm(const double* partials, double* out) {
+// The norm into out and, when host_out is set (pinned host memory), there too,
+// so that the host sees it without a copy.
+__global__ void __launch_bounds__(kBlock) k_finish_norm(const double* partials, double* out, double* host_out) {
   double s = 0.0;
   for (int i = threadIdx.x; i < kNormBlocks; i += kBlock) s += partials[i];
   double t = block_sum(s);
-  if (threadIdx.x == 0) *out = sqrt(t);
+  if (threadIdx.x == 0) {
+    const double v = sqrt(t);
+    *out = v;
+    if (host_out)
+      __hip_atomic_store(reinterpret_cast<uint64_t*>(host_out), __builtin_bit_cast(uint64_t, v), __ATOMIC_RELEASE,
+                         __HIP_MEMORY_SCOPE_SYSTEM);
+  }
 }
 
 // b_c[I] = sum over row I of P^T (ascending original fine index) of P[i,I] r_i,
@@ -899,8 +907,8 @@ void residual_norm(const Level& lv, const double* b, const double* x, double* re
   });
 }
 
-void finish_norm(const double* partials, double* out, hipStream_t s) {
-  k_finish_norm<<<1, kBlock, 0, s>>>(partials, out);
+void finish_norm(const double* partials, double* out, hipStream_t s, double* host_out) {
+  k_finish_norm<<<1, kBlock, 0, s>>>(partials, out, host_out);
 }
 
 void check_finite(const double* v, int64_t n, int32_t* flag, hipStream_t s) {
