@@ -192,6 +192,213 @@ __global__ void __launch_bounds__(kBlock) k_ig_class(const int32_t* rp, const in
   }
 }
 
+// A whole small level in one workgroup of kDrainItems threads, its row
+// offsets, 16-bit columns and colours in LDS: the Jones-Plassmann rounds (the
+// same first-fit decisions in key order as the multi-launch rounds), then
+// `passes` iterated-greedy passes (the classes of the first colouring from the
+// highest down, as k_ig_class).  Each row is first partitioned in place, its
+// lower-key neighbours first, so that the rounds compute no keys; the rounds
+// visit a worklist of the rows still waiting, and each pass lists the rows of
+// every class, so that a thread holds at most a few rows of a round or class.
+// Writes the colours and their count.
+constexpr int kSmallColorRows = 4096;
+constexpr int kSmallColorPer = kSmallColorRows / kDrainItems;
+constexpr int kSmallColorMax = 256;               // classes a pass can list
+constexpr int64_t kSmallColorLds = 150 * 1024;
+inline int64_t small_color_lds(int64_t n, int64_t nnz) {
+  auto up = [](int64_t b) { return (b + 15) & ~(int64_t)15; };
+  return up((n + 1) * 4) + up(nnz * 2) + 5 * up(n * 2);
+}
+
+// Smallest colour from the neighbours' mask, or, when every colour below 64
+// is taken, the smallest colour no entry of scol[lo, hi) other than v has.
+__device__ inline int32_t small_first_fit(const uint16_t* scol, int32_t lo, int32_t hi, const int16_t* c,
+                                          int32_t v, uint64_t mask, bool high) {
+  int32_t k = (~mask) ? __builtin_ctzll(~mask) : 64;
+  if (k < 64 || !high) return k;
+  for (;; ++k) {                                // rare: every colour below 64 is taken
+    bool used = false;
+    for (int32_t e = lo; e < hi && !used; ++e) used = scol[e] != v && c[scol[e]] == k;
+    if (!used) return k;
+  }
+}
+
+__global__ void __launch_bounds__(kDrainItems) k_color_small(const int32_t* rp, const int32_t* col, int32_t n,
+                                                             ColorKey key, int32_t passes, int32_t* color,
+                                                             int32_t* ncolors, int32_t* flags) {
+  extern __shared__ int32_t lds_small[];
+  auto up = [](int64_t b) { return (int32_t)((b + 15) & ~(int64_t)15); };
+  char* base = reinterpret_cast<char*>(lds_small);
+  int32_t* srp = reinterpret_cast<int32_t*>(base);
+  const int32_t nnz = rp[n];
+  uint16_t* scol = reinterpret_cast<uint16_t*>(base + up((int64_t)(n + 1) * 4));
+  const int32_t na = up((int64_t)n * 2) / 2;       // int16 elements per n-array
+  int16_t* ca = reinterpret_cast<int16_t*>(base + up((int64_t)(n + 1) * 4) + up((int64_t)nnz * 2));
+  int16_t* cb = ca + na;
+  int16_t* lowc = cb + na;                       // lower-key neighbours of each row
+  int16_t* wa = lowc + na;                       // worklists / class lists
+  int16_t* wb = wa + na;
+  __shared__ int32_t s_cnt[3];
+  __shared__ int32_t s_cls[kSmallColorMax + 1];
+  const int tid = (int)threadIdx.x;
+  for (int32_t i = tid; i <= n; i += kDrainItems) srp[i] = rp[i];
+  for (int32_t i = tid; i < n; i += kDrainItems) ca[i] = -1;
+  if (tid < 3) s_cnt[tid] = 0;
+  // columns: 16 loads in flight per thread before their stores
+  for (int32_t e0 = 0; e0 < nnz; e0 += 16 * kDrainItems) {
+    int32_t cv[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) cv[u] = col[min(e0 + u * kDrainItems + tid, nnz - 1)];
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+      if (e0 + u * kDrainItems + tid < nnz) scol[e0 + u * kDrainItems + tid] = (uint16_t)cv[u];
+  }
+  __syncthreads();
+  // each thread partitions its own rows
+#pragma unroll
+  for (int q = 0; q < kSmallColorPer; ++q) {
+    const int32_t v = tid + q * kDrainItems;
+    if (v >= n) continue;
+    const uint64_t kv = key(v);
+    const int32_t b = srp[v], e = srp[v + 1];
+    int32_t w = b;
+    for (int32_t t = b; t < e; ++t) {
+      const int32_t u = scol[t];
+      if (u == v) continue;
+      const uint64_t ku = key(u);
+      if (ku < kv || (ku == kv && u < v)) {
+        scol[t] = scol[w];
+        scol[w] = (uint16_t)u;
+        ++w;
+      }
+    }
+    lowc[v] = (int16_t)(w - b);
+  }
+  __syncthreads();
+  // Rounds: round r reads the rows of round r - 1 still waiting and appends
+  // its own to the other list, counted in s_cnt[r % 3] (reset at the start of
+  // round r - 1, after every thread read the count it held before).
+  int32_t count = n;
+  bool done = false;
+  for (int round = 0; round < kMaxRounds && !done; ++round) {
+    const int16_t* src = (round & 1) ? wa : wb;
+    int16_t* dst = (round & 1) ? wb : wa;
+    if (tid == 0) s_cnt[(round + 1) % 3] = 0;
+#pragma unroll
+    for (int q = 0; q < kSmallColorPer; ++q) {
+      const int32_t i = tid + q * kDrainItems;
+      if (i >= count) continue;
+      const int32_t v = round == 0 ? i : src[i];
+      const int32_t b = srp[v], e = b + lowc[v];
+      uint64_t mask = 0;
+      bool high = false, wait = false;
+      // eight neighbours at a time, their reads in flight together; colours of
+      // this round may land while they are read: relaxed atomic reads (a row
+      // still shown as waiting is visited again next round)
+      for (int32_t t0 = b; t0 < e; t0 += 8) {
+        int32_t u[8], cu[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) u[k] = scol[min(t0 + k, e - 1)];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) cu[k] = __hip_atomic_load(&ca[u[k]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          if (t0 + k >= e) continue;
+          if (cu[k] < 0) wait = true;
+          else if (cu[k] < 64) mask |= 1ull << cu[k];
+          else high = true;
+        }
+      }
+      if (wait)
+        dst[atomicAdd(&s_cnt[round % 3], 1)] = (int16_t)v;
+      else
+        __hip_atomic_store(&ca[v], (int16_t)small_first_fit(scol, b, e, ca, v, mask, high), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+    __syncthreads();
+    count = s_cnt[round % 3];
+    done = count == 0;
+  }
+  if (!done) {
+    if (tid == 0) atomicOr(flags, F_TIMEOUT);
+    return;
+  }
+  // the count of colours
+  if (tid == 0) s_cnt[0] = 0;
+  __syncthreads();
+  {
+    int32_t m = 0;
+    for (int32_t v = tid; v < n; v += kDrainItems) m = max(m, (int32_t)ca[v] + 1);
+    atomicMax(&s_cnt[0], m);
+  }
+  __syncthreads();
+  const int32_t nc0 = s_cnt[0];
+  if (nc0 > kSmallColorMax) {
+    if (tid == 0) atomicOr(flags, F_OVERFLOW);
+    return;
+  }
+  int16_t* cur = ca;
+  int16_t* nxt = cb;
+  if (nc0 > 1) {
+    for (int p = 0; p < passes; ++p) {
+      // the rows of every class of cur, listed in wa (any order within a class)
+      for (int32_t c = tid; c <= nc0; c += kDrainItems) s_cls[c] = 0;
+      __syncthreads();
+      for (int32_t v = tid; v < n; v += kDrainItems) {
+        atomicAdd(&s_cls[cur[v] + 1], 1);
+        nxt[v] = -1;
+      }
+      __syncthreads();
+      if (tid == 0)
+        for (int32_t c = 1; c <= nc0; ++c) s_cls[c] += s_cls[c - 1];
+      __syncthreads();
+      for (int32_t v = tid; v < n; v += kDrainItems) wa[atomicAdd(&s_cls[cur[v]], 1)] = (int16_t)v;
+      __syncthreads();
+      // after the placement s_cls[c] is the end of class c (its start: s_cls[c - 1], or 0)
+      for (int32_t c = nc0 - 1; c >= 0; --c) {
+        const int32_t lo = c > 0 ? s_cls[c - 1] : 0, hi = s_cls[c];
+#pragma unroll
+        for (int q = 0; q < kSmallColorPer; ++q) {
+          const int32_t i = lo + tid + q * kDrainItems;
+          if (i >= hi) continue;
+          const int32_t v = wa[i];
+          const int32_t b = srp[v], e = srp[v + 1];
+          uint64_t mask = 0;
+          bool high = false;
+          for (int32_t t0 = b; t0 < e; t0 += 8) {           // eight neighbours at a time
+            int32_t u[8], cu[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) u[k] = scol[min(t0 + k, e - 1)];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) cu[k] = nxt[u[k]];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+              if (t0 + k >= e || u[k] == v || cu[k] < 0) continue;
+              if (cu[k] < 64) mask |= 1ull << cu[k];
+              else high = true;
+            }
+          }
+          nxt[v] = (int16_t)small_first_fit(scol, b, e, nxt, v, mask, high);
+        }
+        __syncthreads();
+      }
+      int16_t* t = cur;
+      cur = nxt;
+      nxt = t;
+    }
+  }
+  if (tid == 0) s_cnt[0] = 0;
+  __syncthreads();
+  int32_t m = 0;
+  for (int32_t v = tid; v < n; v += kDrainItems) {
+    color[v] = cur[v];
+    m = max(m, (int32_t)cur[v] + 1);
+  }
+  atomicMax(&s_cnt[0], m);
+  __syncthreads();
+  if (tid == 0) *ncolors = s_cnt[0];
+}
+
 // The remaining Jones-Plassmann rounds in one workgroup, once at most
 // kDrainItems rows wait: count_in rows in wl_in (or, if wl_in is null, all
 // rows 0 .. n - 1).
@@ -1290,6 +1497,26 @@ void colouring(Handle& h, Level& lv, int level) {
   }
   const int grid = std::min(blocks_for(n), 4 * kRoundGrid);
   int k = 0;
+  const int64_t lds_small = small_color_lds(n, lv.nnzA);
+  if (n <= kSmallColorRows && lds_small <= kSmallColorLds) {
+    // the whole level, passes included, in one workgroup
+    k_color_small<<<1, kDrainItems, (size_t)lds_small, s>>>(lv.arp, lv.acol, (int32_t)n, key, h.opt.color_passes,
+                                                            lv.color, ncol, h.flags);
+    int64_t nco = 0, fl = 0;
+    ScalarRead rd[2] = {{ncol, 4, &nco}, {h.flags, 4, &fl}};
+    read_scalars(h, rd, 2);
+    if (fl & F_TIMEOUT) throw Error{GMG_DEVICE_ERROR, "colouring did not terminate"};
+    if (fl & F_OVERFLOW) throw Error{GMG_DEVICE_ERROR, "colouring: too many colours"};
+    lv.ncolors = (int32_t)nco;
+    tfree(s, wl);
+    if (L.list) {
+      tfree(s, L.list);
+      tfree(s, L.mask);
+      tfree(s, L.cnt);
+    }
+    tfree(s, ncol);
+    return;
+  }
   if (n <= kDrainItems) {
     k_color_drain<<<1, kDrainItems, 0, s>>>(lv.arp, lv.acol, n, key, lv.color, nullptr, nullptr, L, h.flags);
   } else {
