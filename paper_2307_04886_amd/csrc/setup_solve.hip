@@ -207,7 +207,7 @@ constexpr int kSmallColorMax = 256;               // classes a pass can list
 constexpr int64_t kSmallColorLds = 150 * 1024;
 inline int64_t small_color_lds(int64_t n, int64_t nnz) {
   auto up = [](int64_t b) { return (b + 15) & ~(int64_t)15; };
-  return up((n + 1) * 4) + up(nnz * 2) + 5 * up(n * 2);
+  return up((n + 1) * 4) + up(nnz * 2) + 5 * up(n * 2) + up(n * 4);
 }
 
 // Smallest colour from the neighbours' mask, or, when every colour below 64
@@ -238,6 +238,7 @@ __global__ void __launch_bounds__(kDrainItems) k_color_small(const int32_t* rp, 
   int16_t* lowc = cb + na;                       // lower-key neighbours of each row
   int16_t* wa = lowc + na;                       // worklists / class lists
   int16_t* wb = wa + na;
+  int32_t* waitc = reinterpret_cast<int32_t*>(wb + na);   // uncoloured lower-key neighbours of each row
   __shared__ int32_t s_cnt[3];
   __shared__ int32_t s_cls[kSmallColorMax + 1];
   const int tid = (int)threadIdx.x;
@@ -275,50 +276,86 @@ __global__ void __launch_bounds__(kDrainItems) k_color_small(const int32_t* rp, 
     lowc[v] = (int16_t)(w - b);
   }
   __syncthreads();
-  // Rounds: round r reads the rows of round r - 1 still waiting and appends
-  // its own to the other list, counted in s_cnt[r % 3] (reset at the start of
-  // round r - 1, after every thread read the count it held before).
-  int32_t count = n;
-  bool done = false;
+  // Rounds in dependency order: a row is ready once all its lower-key
+  // neighbours are coloured (its count of uncoloured ones, held in wait[],
+  // reaches zero); round r colours the rows that became ready in round r - 1
+  // (round 0: the rows without lower-key neighbours) and counts down their
+  // higher-key neighbours, appending those that become ready, counted in
+  // s_cnt[r % 3] (reset at the start of round r - 1, after every thread read
+  // the count it held before).  Each coupling is visited twice in all.
+  const int lane = tid & (kWave - 1);
+  int32_t count = 0;
+  if (tid == 0) s_cnt[0] = 0;
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < kSmallColorPer; ++q) {
+    const int32_t v = tid + q * kDrainItems;
+    const bool ready = v < n && lowc[v] == 0;
+    if (v < n) waitc[v] = lowc[v];
+    const unsigned long long m = __ballot(ready);
+    if (m) {
+      int32_t o = 0;
+      if (lane == 0) o = atomicAdd(&s_cnt[0], (int32_t)__popcll(m));
+      o = __shfl(o, 0, kWave);
+      if (ready) wb[o + __popcll(m & ((1ull << lane) - 1ull))] = (int16_t)v;
+    }
+  }
+  __syncthreads();
+  count = s_cnt[0];
+  int32_t coloured = 0;
+  bool done = count == 0;
   for (int round = 0; round < kMaxRounds && !done; ++round) {
     const int16_t* src = (round & 1) ? wa : wb;
     int16_t* dst = (round & 1) ? wb : wa;
-    if (tid == 0) s_cnt[(round + 1) % 3] = 0;
+    if (tid == 0) s_cnt[(round + 2) % 3] = 0;
 #pragma unroll
     for (int q = 0; q < kSmallColorPer; ++q) {
       const int32_t i = tid + q * kDrainItems;
       if (i >= count) continue;
-      const int32_t v = round == 0 ? i : src[i];
-      const int32_t b = srp[v], e = b + lowc[v];
+      const int32_t v = src[i];
+      const int32_t b = srp[v], l = b + lowc[v], e = srp[v + 1];
       uint64_t mask = 0;
-      bool high = false, wait = false;
-      // eight neighbours at a time, their reads in flight together; colours of
-      // this round may land while they are read: relaxed atomic reads (a row
-      // still shown as waiting is visited again next round)
-      for (int32_t t0 = b; t0 < e; t0 += 8) {
+      bool high = false;
+      for (int32_t t0 = b; t0 < l; t0 += 8) {          // the lower-key neighbours, all coloured
         int32_t u[8], cu[8];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) u[k] = scol[min(t0 + k, e - 1)];
+        for (int k = 0; k < 8; ++k) u[k] = scol[min(t0 + k, l - 1)];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) cu[k] = __hip_atomic_load(&ca[u[k]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        for (int k = 0; k < 8; ++k) cu[k] = ca[u[k]];
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
-          if (t0 + k >= e) continue;
-          if (cu[k] < 0) wait = true;
-          else if (cu[k] < 64) mask |= 1ull << cu[k];
+          if (t0 + k >= l) continue;
+          if (cu[k] < 64) mask |= 1ull << cu[k];
           else high = true;
         }
       }
-      if (wait)
-        dst[atomicAdd(&s_cnt[round % 3], 1)] = (int16_t)v;
-      else
-        __hip_atomic_store(&ca[v], (int16_t)small_first_fit(scol, b, e, ca, v, mask, high), __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_WORKGROUP);
+      ca[v] = (int16_t)small_first_fit(scol, b, l, ca, v, mask, high);
     }
+    __syncthreads();                              // the round's colours are written
+    // count down the higher-key neighbours of the round's rows
+#pragma unroll
+    for (int q = 0; q < kSmallColorPer; ++q) {
+      const int32_t i = tid + q * kDrainItems;
+      const bool act = i < count;
+      const int32_t v = act ? src[i] : 0;
+      const int32_t l = act ? srp[v] + lowc[v] : 0, e = act ? srp[v + 1] : 0;
+      for (int32_t t0 = l; t0 < e; t0 += 8) {          // eight at a time, the atomics in flight together
+        int32_t u[8], old[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) u[k] = t0 + k < e ? (int32_t)scol[t0 + k] : v;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) old[k] = atomicSub(&waitc[u[k]], u[k] != v ? 1 : 0);   // v itself: minus 0
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+          if (u[k] != v && old[k] == 1) dst[atomicAdd(&s_cnt[(round + 1) % 3], 1)] = (int16_t)u[k];
+      }
+    }
+    coloured += count;
     __syncthreads();
-    count = s_cnt[round % 3];
+    count = s_cnt[(round + 1) % 3];
     done = count == 0;
   }
+  done = coloured == n;
   if (!done) {
     if (tid == 0) atomicOr(flags, F_TIMEOUT);
     return;
