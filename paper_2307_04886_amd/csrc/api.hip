@@ -699,6 +699,10 @@ void kry_prepare(Handle& h, Cycle<float>& c) {
     if (l + 1 < nl) {                        // the coarsest level only uses b and x
       f.A = {d.A.ptr, d.A.col, to_f32_copy(h, d.A.val, lv.a_slots, s), d.A.len, d.A.uw};
       f.T = {d.T.ptr, d.T.col, to_f32_copy(h, d.T.val, lv.t_slots, s), d.T.len};
+      if (d.to_row) {
+        f.To = {d.To.ptr, d.To.col, to_f32_copy(h, d.To.val, lv.to_slots, s), d.To.len};
+        f.to_row = d.to_row;
+      }
       f.diag = to_f32_copy(h, d.diag, d.n, s);
       f.q_val = to_f32_copy(h, d.q_val, (int64_t)3 * d.n, s);
       if (d.B.nblk > 0)                      // block sweep: same layout, float values

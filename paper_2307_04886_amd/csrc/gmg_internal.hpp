@@ -208,6 +208,12 @@ struct LevelViewT {
   const int32_t* cptr = nullptr;        // device colour ranges [ncolors + 1]
   Sell<V> A;                            // A_l
   Sell<V> T;                            // P_l^T (rows: coarse points)
+  // On large levels, also P_l^T with its rows in the coarse level's original
+  // numbering (row k is coarse row to_row[k] of the solve numbering), which
+  // is spatially ordered: the restriction takes it, so that the fine-level
+  // residuals each XCD gathers form a compact band (read once, not by all).
+  Sell<V> To;
+  const int32_t* to_row = nullptr;
   int32_t ra = 1, rt = 1;               // lanes per row for A_l / P_l^T (power of two)
   int32_t ch = 8;                       // entries per load chunk of the one-lane-per-row kernels (level 0)
   int32_t uni = 0;                      // 1: level 0's one-lane kernels use the uniform slice width A.uw
@@ -352,6 +358,7 @@ struct Level {
   double* b = nullptr;
   double* r = nullptr;
   int64_t a_slots = 0, t_slots = 0;     // SELL entry slots of A_l and P_l^T (with padding)
+  int64_t to_slots = 0;                 // the same for the original-order copy of P_l^T
   LevelView view;
   // P_l^T in the original numbering (rows: coarse points, entries in ascending
   // fine index), kept for recomputing A_{l+1} when A changes

@@ -1873,6 +1873,9 @@ namespace {
 // longest row when that stores at most kUniformSlack times the entries.
 constexpr double kUniformSlack = 1.15;
 
+// Coarse levels of at least this many rows also get P_l^T in original row order.
+constexpr int64_t kRestrictOrigRows = 65536;
+
 SellView make_sell(Handle& h, const int32_t* perm, const int32_t* cmap, const int32_t* rp, const int32_t* col,
                    const double* val, int64_t n, double* diag, int32_t* maxlen, int64_t* slots,
                    int64_t uniform_nnz = 0) {
@@ -2014,6 +2017,11 @@ void solve_layout(Handle& h, Level& lv, const Level* nx, const int32_t* t_rp, co
     v.q_cnt = qcnt;
     // P^T: row I' = coarse row perm_c[I'], entries in ascending original fine index
     v.T = make_sell(h, nx->perm, lv.iperm, t_rp, t_col, t_val, nx->n, nullptr, &v.maxt, &lv.t_slots);
+    if (nx->n >= kRestrictOrigRows) {
+      int32_t mt = 0;
+      v.To = make_sell(h, nullptr, lv.iperm, t_rp, t_col, t_val, nx->n, nullptr, &mt, &lv.to_slots);
+      v.to_row = nx->iperm;
+    }
     v.rt = lanes_for(v.maxt);
   }
   // colour ranges and per-colour entry counts (staging is reused by make_sell's reads, so copy last)

@@ -266,13 +266,15 @@ __global__ void __launch_bounds__(kBlock) k_finish_norm(const double* partials, 
 template <int R, class V>
 __global__ void __launch_bounds__(kBlock) k_restrict(Sell<V> T, const V* __restrict__ r, V* __restrict__ bc,
                                                      V* __restrict__ xc, int64_t nc, int32_t maxlen,
-                                                     const V* __restrict__ diag_c, int32_t first) {
+                                                     const V* __restrict__ diag_c, int32_t first,
+                                                     const int32_t* __restrict__ orow) {
   const int64_t g = ((int64_t)xcd_block() * kBlock + threadIdx.x) / R;
   const bool active = g < nc;
   const V acc = row_sumR<R>(T, (int32_t)g, active, r, -1, maxlen);
   if (active && (threadIdx.x & (R - 1)) == 0) {
-    bc[g] = acc;
-    xc[g] = g < first ? (acc - V(0)) / diag_c[g] : V(0);
+    const int64_t o = orow ? orow[g] : g;        // T's row g is coarse row o
+    bc[o] = acc;
+    xc[o] = o < first ? (acc - V(0)) / diag_c[o] : V(0);
   }
 }
 
@@ -281,12 +283,14 @@ __global__ void __launch_bounds__(kBlock) k_restrict(Sell<V> T, const V* __restr
 template <int CH, class V>
 __global__ void __launch_bounds__(kBlock) k_restrict_seq(Sell<V> T, const V* __restrict__ r, V* __restrict__ bc,
                                                          V* __restrict__ xc, int64_t nc,
-                                                         const V* __restrict__ diag_c, int32_t first) {
+                                                         const V* __restrict__ diag_c, int32_t first,
+                                                         const int32_t* __restrict__ orow) {
   const int64_t g = (int64_t)xcd_block() * kBlock + threadIdx.x;
   if (g >= nc) return;
   const V acc = row_sum_seq<CH>(T, (int32_t)g, r, -1);
-  bc[g] = acc;
-  xc[g] = g < first ? (acc - V(0)) / diag_c[g] : V(0);
+  const int64_t o = orow ? orow[g] : g;          // T's row g is coarse row o
+  bc[o] = acc;
+  xc[o] = o < first ? (acc - V(0)) / diag_c[o] : V(0);
 }
 
 // x_i <- x_i + sum_t P[i, t] x_c[col_t]
@@ -848,14 +852,17 @@ void residual(const LevelViewT<V>& v, hipStream_t s, bool finest) {
 
 template <class V>
 void restrict_to(const LevelViewT<V>& v, const LevelViewT<V>& c, hipStream_t s, int32_t first) {
+  // the original-order copy of P^T where the level has one (row map to_row)
+  const Sell<V>& T = v.to_row ? v.To : v.T;
   if (v.rt == 1) {
-    k_restrict_seq<8, V><<<blocks_for(c.n), kBlock, 0, s>>>(v.T, v.r, c.b, c.x, c.n, (const V*)c.diag, first);
+    k_restrict_seq<8, V><<<blocks_for(c.n), kBlock, 0, s>>>(T, v.r, c.b, c.x, c.n, (const V*)c.diag, first,
+                                                            v.to_row);
     return;
   }
   with_lanes(v.rt, [&](auto RC) {
     constexpr int R = decltype(RC)::value;
-    k_restrict<R, V><<<blocks_for((int64_t)c.n * R), kBlock, 0, s>>>(v.T, v.r, c.b, c.x, c.n, v.maxt,
-                                                                      (const V*)c.diag, first);
+    k_restrict<R, V><<<blocks_for((int64_t)c.n * R), kBlock, 0, s>>>(T, v.r, c.b, c.x, c.n, v.maxt,
+                                                                      (const V*)c.diag, first, v.to_row);
   });
 }
 

@@ -16,6 +16,7 @@
 #include <map>
 #include <mutex>
 #include <tuple>
+#include <vector>
 
 #include "gmg_internal.hpp"
 
@@ -40,12 +41,13 @@ TuneKey key_of(int32_t kind, int64_t rows, int64_t entries, int32_t maxlen) {
   return TuneKey{kind, (int32_t)std::floor(2.0 * std::log2(r)), (int32_t)std::lround((double)entries / r), maxlen};
 }
 
-// Smallest time of three launches after one warm-up, in milliseconds.
+// Smallest time of kTuneReps launches after one warm-up, in milliseconds.
+constexpr int kTuneReps = 5;
 template <class F>
 double time_launch(hipStream_t s, hipEvent_t e0, hipEvent_t e1, F launch) {
   launch();
   double best = 1e30;
-  for (int k = 0; k < 3; ++k) {
+  for (int k = 0; k < kTuneReps; ++k) {
     check_hip(hipEventRecord(e0, s), "tuning event");
     launch();
     check_hip(hipEventRecord(e1, s), "tuning event");
@@ -66,14 +68,25 @@ int32_t choose(const TuneKey& key, std::initializer_list<int32_t> cand, hipStrea
     auto it = g_tune.find(key);
     if (it != g_tune.end()) return it->second;
   }
+  // two sweeps over the candidates, each candidate's smallest time (a
+  // candidate's launches are not all timed in one stretch of the box's state)
+  std::vector<double> tmin(cand.size(), 1e30);
+  for (int sweep = 0; sweep < 2; ++sweep) {
+    int i = 0;
+    for (int32_t c : cand) {
+      tmin[i] = std::min(tmin[i], time_launch(s, e0, e1, [&] { launch_with(c); }));
+      ++i;
+    }
+  }
   int32_t best = *cand.begin();
   double tbest = 1e30;
+  int i = 0;
   for (int32_t c : cand) {
-    const double t = time_launch(s, e0, e1, [&] { launch_with(c); });
-    if (t < tbest) {
-      tbest = t;
+    if (tmin[i] < tbest) {
+      tbest = tmin[i];
       best = c;
     }
+    ++i;
   }
   std::lock_guard<std::mutex> lock(g_tune_mutex);
   g_tune[key] = best;
@@ -118,9 +131,13 @@ void autotune(Handle& h) {
           residual(t, s, false);
         });
       }
+      // each restriction candidate is timed after the residual it reads, as in
+      // the cycle (the residual just written, not yet in this compute unit's
+      // cache): the pair's time ranks the candidates
       v.rt = choose(key_of(TUNE_LANES_T, cv.n, lv.nnzP, v.maxt), {1, 4, 8, 16, 32, 64}, s, e0, e1, [&](int32_t c) {
         LevelView t = v;
         t.rt = c;
+        residual(t, s, l == 0);
         restrict_to(t, cv, s, 0);
       });
     }
