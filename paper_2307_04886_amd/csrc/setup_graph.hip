@@ -461,7 +461,7 @@ __global__ void __launch_bounds__(kBlock) k_voronoi_round(const int32_t* rp, con
                                                           int64_t n, const double* dA, const int32_t* lA,
                                                           double* dB, int32_t* lB, int32_t* rounds, int k) {
   if (k > 0 && rounds[k - 1] == 0) return;
-  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t v = (int64_t)xcd_block() * blockDim.x + threadIdx.x;
   bool changed = false;
   if (v < n) {
     double bd = dA[v];
@@ -600,7 +600,7 @@ __global__ void __launch_bounds__(kBlock) k_cell_neighbours(const int32_t* ptr, 
   __shared__ int32_t cand[kCellsPerBlock][kCellCand];
   __shared__ uint8_t first[kCellsPerBlock][kCellCand];
   const int g = threadIdx.x / kCellLanes, sub = threadIdx.x & (kCellLanes - 1);
-  const int64_t I = (int64_t)blockIdx.x * kCellsPerBlock + g;
+  const int64_t I = (int64_t)xcd_block() * kCellsPerBlock + g;
   const bool act = I < nc;
   const int32_t slots = act ? cptr[I + 1] - cptr[I] : 0;   // the members' degree sum
   const bool group = act && slots <= kCellCand;

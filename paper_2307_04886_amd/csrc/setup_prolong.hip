@@ -432,7 +432,7 @@ __global__ void __launch_bounds__(kWave) k_galerkin_count(const int32_t* trp, co
                                                           int32_t* flags) {
   __shared__ int32_t keys[HS];
   __shared__ PairChunk pc;
-  const int32_t I = blockIdx.x;
+  const int32_t I = (int32_t)xcd_block();        // neighbouring rows share an XCD
   if (I >= nc) return;
   const int lane = threadIdx.x;
   for (int s = lane; s < HS; s += kWave) keys[s] = -1;
@@ -512,7 +512,7 @@ __global__ void __launch_bounds__(kWave) k_galerkin_fill(const int32_t* trp, con
   __shared__ double tV[3 * kWave];     // and its value
   __shared__ PairChunk pc;
   __shared__ int32_t nlist;
-  const int32_t I = blockIdx.x;
+  const int32_t I = (int32_t)xcd_block();        // neighbouring rows share an XCD
   if (I >= nc) return;
   const int lane = threadIdx.x;
   // distinct columns (the symbolic pass guaranteed they fit)

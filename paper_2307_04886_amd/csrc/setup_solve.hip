@@ -162,7 +162,7 @@ __global__ void __launch_bounds__(kBlock) k_color_round(const int32_t* rp, const
 // not adjacent, so they are recoloured in parallel.
 __global__ void __launch_bounds__(kBlock) k_ig_class(const int32_t* rp, const int32_t* col, int64_t n,
                                                      const int32_t* old, int32_t* neu, int32_t c) {
-  for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < n; v += (int64_t)gridDim.x * kBlock) {
+  for (int64_t v = (int64_t)xcd_block() * kBlock + threadIdx.x; v < n; v += (int64_t)gridDim.x * kBlock) {
     if (old[v] != c) continue;
     const int32_t b = rp[v], e = rp[v + 1];
     uint64_t mask = 0;
@@ -595,7 +595,7 @@ __global__ void __launch_bounds__(kBlock) k_sell_fill_slice(const int32_t* __res
   double* lv = fill_lds;                                   // [kSlice][pitch]
   int32_t* lc = (int32_t*)(fill_lds + kSlice * pitch);     // [kSlice][pitch]
   __shared__ int32_t rb[kSlice], rl[kSlice], rs[kSlice];
-  const int64_t s = blockIdx.x;
+  const int64_t s = xcd_block();
   const int64_t r0 = s * kSlice;
   const int tid = threadIdx.x;
   if (tid < kSlice) {
@@ -1427,7 +1427,7 @@ __global__ void __launch_bounds__(kBlock) k_block_ell(const int32_t* __restrict_
                                                       const int32_t* __restrict__ bw,
                                                       const int32_t* __restrict__ beoff, int32_t* elx, double* elv) {
   __shared__ int32_t hl[kHaloSort];
-  const int32_t b = blockIdx.x;
+  const int32_t b = (int32_t)xcd_block();
   const int32_t r0 = boff[b], rows = boff[b + 1] - r0;
   const int32_t h0 = hoff[b], nh = hoff[b + 1] - h0;
   for (int32_t k = threadIdx.x; k < nh; k += kBlock) hl[k] = hlist[h0 + k];
