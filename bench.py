@@ -34,8 +34,8 @@ sys.path.insert(0, ROOT)
 # HBM bytes per launch from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE, scaled by what the counters read
 # for a plain device copy (profiles/k_gs_block_torus1024.md, profiles/k_gs_color_fine_torus1024.md);
 # valid only for the kernel sources they were taken on (sha256 prefix of solve.hip + rows.hpp).
-TRAFFIC = {"gs_finest": {"bytes_per_launch": 26104951, "src_sha256_16": "d46293d01a96911c"},
-           "gs_galerkin": {"bytes_per_launch": 11056002, "src_sha256_16": "d46293d01a96911c"}}
+TRAFFIC = {"gs_finest": {"bytes_per_launch": 26836582, "src_sha256_16": "f82e40132e218e6d"},
+           "gs_galerkin": {"bytes_per_launch": 11061122, "src_sha256_16": "f82e40132e218e6d"}}
 
 KERNEL_NAMES = {"gs_finest": "k_gs_color_fine (one colour of a Gauss-Seidel sweep, level 0)",
                 "residual_finest": "k_residual_norm (residual + norm partials, level 0)",

@@ -7,10 +7,11 @@
 // distributes a row's terms over lanes or loads: every row is still summed in
 // its entry order (uniform slices add their padding's +-0 products after the
 // row's own, which leaves the sum unchanged), so the choice never changes a
-// result bit.  Choices are
-// cached per shape class (kind, rows, mean and longest row), so later builds
-// of similar levels reuse them; the first build of a class pays for the
-// measurement.
+// result bit.  Choices are cached per shape class (kind, rows to a factor of
+// sqrt 2, mean row, longest row to a power of two), so later builds of
+// similar levels reuse them; the first build of a class pays for the
+// measurement.  Lane counts wider than half the longest row are not timed,
+// and a restriction is timed right after the residual it reads.
 #include <algorithm>
 #include <cmath>
 #include <map>
@@ -38,11 +39,13 @@ std::map<TuneKey, int32_t> g_tune;
 
 TuneKey key_of(int32_t kind, int64_t rows, int64_t entries, int32_t maxlen) {
   const double r = (double)std::max<int64_t>(rows, 1);
-  return TuneKey{kind, (int32_t)std::floor(2.0 * std::log2(r)), (int32_t)std::lround((double)entries / r), maxlen};
+  int32_t m = 1;                                  // the longest row, rounded up to a power of two
+  while (m < maxlen) m *= 2;
+  return TuneKey{kind, (int32_t)std::floor(2.0 * std::log2(r)), (int32_t)std::lround((double)entries / r), m};
 }
 
 // Smallest time of kTuneReps launches after one warm-up, in milliseconds.
-constexpr int kTuneReps = 5;
+constexpr int kTuneReps = 3;
 template <class F>
 double time_launch(hipStream_t s, hipEvent_t e0, hipEvent_t e1, F launch) {
   launch();
@@ -59,9 +62,20 @@ double time_launch(hipStream_t s, hipEvent_t e0, hipEvent_t e1, F launch) {
   return best;
 }
 
+// Lane counts worth timing for rows of at most maxlen entries: one lane (when
+// allowed) and the powers of two from 4 up to half the longest row (at least
+// 4); wider groups leave most of their lanes idle.
+std::vector<int32_t> lane_candidates(int32_t maxlen, bool one) {
+  std::vector<int32_t> c;
+  if (one) c.push_back(1);
+  for (int32_t r = 4; r <= 64; r *= 2)
+    if (r == 4 || 2 * r <= maxlen) c.push_back(r);
+  return c;
+}
+
 // The cached choice for key, or the fastest candidate (then cached).
 template <class F>
-int32_t choose(const TuneKey& key, std::initializer_list<int32_t> cand, hipStream_t s, hipEvent_t e0, hipEvent_t e1,
+int32_t choose(const TuneKey& key, const std::vector<int32_t>& cand, hipStream_t s, hipEvent_t e0, hipEvent_t e1,
                F launch_with) {
   {
     std::lock_guard<std::mutex> lock(g_tune_mutex);
@@ -114,7 +128,7 @@ void autotune(Handle& h) {
       // level's right-hand side and iterate: all of them are rewritten by every cycle
       if (l == 0) {
         // chunk c % 100; c >= 100: the uniform slice width (where the layout has one)
-        const std::initializer_list<int32_t> sell = {4, 8, 16}, both = {4, 8, 16, 104, 108, 116};
+        const std::vector<int32_t> sell = {4, 8, 16}, both = {4, 8, 16, 104, 108, 116};
         const int32_t c = choose(key_of(v.A.uw > 0 ? TUNE_CHUNK0_UNIFORM : TUNE_CHUNK0, v.n, lv.nnzA, v.maxa),
                                  v.A.uw > 0 ? both : sell, s, e0, e1, [&](int32_t c) {
                                    LevelView t = v;
@@ -125,7 +139,8 @@ void autotune(Handle& h) {
         v.ch = c % 100;
         v.uni = c >= 100 ? 1 : 0;
       } else {
-        v.ra = choose(key_of(TUNE_LANES_A, v.n, lv.nnzA, v.maxa), {4, 8, 16, 32, 64}, s, e0, e1, [&](int32_t c) {
+        v.ra = choose(key_of(TUNE_LANES_A, v.n, lv.nnzA, v.maxa), lane_candidates(v.maxa, false), s, e0, e1,
+                      [&](int32_t c) {
           LevelView t = v;
           t.ra = c;
           residual(t, s, false);
@@ -134,7 +149,8 @@ void autotune(Handle& h) {
       // each restriction candidate is timed after the residual it reads, as in
       // the cycle (the residual just written, not yet in this compute unit's
       // cache): the pair's time ranks the candidates
-      v.rt = choose(key_of(TUNE_LANES_T, cv.n, lv.nnzP, v.maxt), {1, 4, 8, 16, 32, 64}, s, e0, e1, [&](int32_t c) {
+      v.rt = choose(key_of(TUNE_LANES_T, cv.n, lv.nnzP, v.maxt), lane_candidates(v.maxt, true), s, e0, e1,
+                    [&](int32_t c) {
         LevelView t = v;
         t.rt = c;
         residual(t, s, l == 0);
