@@ -243,6 +243,15 @@ void sync(hipStream_t s, const char* what) {
   check_hip(hipStreamSynchronize(s), what);
 }
 
+// The next unused slice of the build's rounds arena (zeroed with the arena),
+// or, once all are used, the last slice zeroed again.
+int32_t* fresh_rounds(Handle& h) {
+  if (h.rounds_next < kRoundsSlices) return h.rounds + (size_t)(h.rounds_next++) * kMaxRounds;
+  int32_t* r = h.rounds + (size_t)(kRoundsSlices - 1) * kMaxRounds;
+  check_hip(hipMemsetAsync(r, 0, (size_t)kMaxRounds * 4, h.stream), "memset");
+  return r;
+}
+
 int64_t read_i64(Handle& h, const void* dev_ptr, int bytes) {
   int64_t v = 0;
   ScalarRead rd{dev_ptr, bytes, &v};
@@ -389,9 +398,11 @@ void build(Handle& h, int64_t n, const double* points, int64_t m, const int32_t*
     t_last = t;
   };
   h.flags = (int32_t*)dalloc(h, 64 * 4);
-  h.rounds = (int32_t*)dalloc(h, kMaxRounds * 4);
+  h.rounds = (int32_t*)dalloc(h, (size_t)kMaxRounds * kRoundsSlices * 4);
+  h.rounds_next = 0;
   h.red = (double*)dalloc(h, (kNormBlocks + 8) * 8);
   check_hip(hipMemsetAsync(h.flags, 0, 64 * 4, s), "memset");
+  check_hip(hipMemsetAsync(h.rounds, 0, (size_t)kMaxRounds * kRoundsSlices * 4, s), "memset");
 
   h.L.emplace_back();
   {

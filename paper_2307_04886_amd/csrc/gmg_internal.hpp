@@ -25,6 +25,7 @@ constexpr int kRoundBatch = 8;       // rounds launched between host checks of a
 // separated by barriers, worklists in LDS).
 constexpr int kDrainItems = 1024;
 constexpr int kMaxRounds = 4096;
+constexpr int kRoundsSlices = 32;
 
 // Device error flags (bit set in Handle::flags[0]).
 enum : int { F_INVALID = 1, F_NOT_SPD = 2, F_OVERFLOW = 4, F_TIMEOUT = 8 };
@@ -420,7 +421,9 @@ struct Handle {
   double* chol = nullptr;               // dense lower factor of the coarsest A
   double* cinv = nullptr;               // dense inverse of the coarsest A: inv[k inv_ld(n) + i] = (A^-1 e_k)_i
   int32_t* flags = nullptr;             // device error flags and counters
-  int32_t* rounds = nullptr;            // device per-round counters of frontier loops
+  int32_t* rounds = nullptr;            // device per-round counters of frontier loops: kRoundsSlices
+                                        // slices of kMaxRounds, zeroed once per build (fresh_rounds)
+  int32_t rounds_next = 0;              // slices handed out
   double* red = nullptr;                // reduction partials
   double* norm_host = nullptr;          // pinned: the solve's residual norm, written by the cycle's last kernel
   double* norm_dev = nullptr;           // its device address
@@ -474,6 +477,7 @@ struct ScalarRead {
   int64_t* dst;
 };
 void read_scalars(Handle& h, const ScalarRead* items, int count);
+int32_t* fresh_rounds(Handle& h);                           // zeroed per-round counters for one frontier loop
 void* pinned_staging(size_t bytes);                         // per-thread pinned host buffer
 
 // ------------------------------------------------------------------ launchers (prims.hip)

@@ -723,7 +723,7 @@ int64_t sample_lfmis(Handle& h, Level& lv, int level) {
   int64_t n = lv.n;
   uint8_t* status = (uint8_t*)talloc(s, (size_t)n);
   check_hip(hipMemsetAsync(status, 0, (size_t)n, s), "memset");
-  check_hip(hipMemsetAsync(h.rounds, 0, kMaxRounds * 4, s), "memset");
+  int32_t* rounds = fresh_rounds(h);
   SweepKey key{h.opt.seed ^ ((uint64_t)level << 32), h.opt.sample_order == 1};
   int32_t* wl = (int32_t*)talloc(s, (size_t)2 * n * 4);
   const int grid = std::min(blocks_for(n), kRoundGrid);
@@ -744,18 +744,18 @@ int64_t sample_lfmis(Handle& h, Level& lv, int level) {
     if (!drained)
       for (int t = 0; t < kRoundBatch; ++t, ++k)
         k_lfmis_round<<<grid, kBlock, 0, s>>>(lv.erp, lv.ecol, lv.ew, n, lv.scal, key, status,
-                                              wl + ((k + 1) % 2) * n, wl + (k % 2) * n, h.rounds, k, list, cnt);
+                                              wl + ((k + 1) % 2) * n, wl + (k % 2) * n, rounds, k, list, cnt);
     // coarse ids, valid if the sweep has finished (read together with the round count)
     k_seed_flags<<<blocks_for(n), kBlock, 0, s>>>(status, n, f);
     scan_i32(f, ids, n, s);
     int64_t left = 0, fl = 0;
-    ScalarRead rd[3] = {{h.rounds + (drained ? 0 : k - 1), 4, &left}, {ids + n, 4, &nc}, {h.flags, 4, &fl}};
+    ScalarRead rd[3] = {{rounds + (drained ? 0 : k - 1), 4, &left}, {ids + n, 4, &nc}, {h.flags, 4, &fl}};
     read_scalars(h, rd, 3);
     if (fl & F_TIMEOUT) throw Error{GMG_DEVICE_ERROR, "sampling did not terminate"};
     if (drained || left == 0) break;
     if (left <= kDrainItems) {
       k_lfmis_drain<<<1, kDrainItems, 0, s>>>(lv.erp, lv.ecol, lv.ew, lv.scal, key, status, wl + ((k - 1) % 2) * n,
-                                             h.rounds + (k - 1), n, list, cnt, h.flags);
+                                             rounds + (k - 1), n, list, cnt, h.flags);
       drained = true;
       continue;
     }
@@ -785,7 +785,7 @@ void voronoi(Handle& h, Level& lv) {
   lv.status = nullptr;
   double* dB = (double*)talloc(s, (size_t)n * 8);
   int32_t* lB = (int32_t*)talloc(s, (size_t)n * 4);
-  check_hip(hipMemsetAsync(h.rounds, 0, kMaxRounds * 4, s), "memset");
+  int32_t* rounds = fresh_rounds(h);
   int k = 0;
   for (;;) {
     for (int t = 0; t < kRoundBatch; ++t, ++k) {
@@ -794,9 +794,9 @@ void voronoi(Handle& h, Level& lv) {
       double* dO = (k % 2 == 0) ? dB : lv.dist;
       int32_t* lO = (k % 2 == 0) ? lB : lv.label;
       k_voronoi_round<<<blocks_for(n), kBlock, 0, s>>>(lv.erp, lv.ecol, lv.ew, status, n, dA, lA, dO, lO,
-                                                       h.rounds, k);
+                                                       rounds, k);
     }
-    if (read_i64(h, h.rounds + (k - 1), 4) == 0) break;
+    if (read_i64(h, rounds + (k - 1), 4) == 0) break;
     if (k + kRoundBatch > kMaxRounds) throw Error{GMG_DEVICE_ERROR, "Voronoi rounds did not terminate"};
   }
   // The first round without changes copied its input unchanged, so both

@@ -1522,8 +1522,6 @@ void colouring(Handle& h, Level& lv, int level) {
   lv.color = (int32_t*)dalloc(h, (size_t)n * 4);
   fill_i32(lv.color, -1, n, s);
   int32_t* ncol = (int32_t*)talloc(s, 4);
-  check_hip(hipMemsetAsync(ncol, 0, 4, s), "memset");
-  check_hip(hipMemsetAsync(h.rounds, 0, kMaxRounds * 4, s), "memset");
   ColorKey key{(h.opt.seed ^ kColorSalt) ^ ((uint64_t)level << 32)};
   int32_t* wl = (int32_t*)talloc(s, (size_t)2 * n * 4);
   ColorLists L;
@@ -1554,20 +1552,22 @@ void colouring(Handle& h, Level& lv, int level) {
     tfree(s, ncol);
     return;
   }
+  check_hip(hipMemsetAsync(ncol, 0, 4, s), "memset");
+  int32_t* rounds = fresh_rounds(h);
   if (n <= kDrainItems) {
     k_color_drain<<<1, kDrainItems, 0, s>>>(lv.arp, lv.acol, n, key, lv.color, nullptr, nullptr, L, h.flags);
   } else {
     for (;;) {
       for (int t = 0; t < kColorBatch; ++t, ++k)
         k_color_round<<<grid, kBlock, 0, s>>>(lv.arp, lv.acol, n, key, lv.color, wl + ((k + 1) % 2) * n,
-                                              wl + (k % 2) * n, h.rounds, k, L);
+                                              wl + (k % 2) * n, rounds, k, L);
       int64_t left = 0;
-      ScalarRead rd[1] = {{h.rounds + (k - 1), 4, &left}};
+      ScalarRead rd[1] = {{rounds + (k - 1), 4, &left}};
       read_scalars(h, rd, 1);
       if (left == 0) break;
       if (left <= kDrainItems) {
         k_color_drain<<<1, kDrainItems, 0, s>>>(lv.arp, lv.acol, n, key, lv.color, wl + ((k - 1) % 2) * n,
-                                               h.rounds + (k - 1), L, h.flags);
+                                               rounds + (k - 1), L, h.flags);
         break;
       }
       if (k + kColorBatch > kMaxRounds) throw Error{GMG_DEVICE_ERROR, "colouring did not terminate"};
