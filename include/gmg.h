@@ -348,8 +348,8 @@ enum gmg_export_what {
   GMG_EXPORT_COARSE_INVERSE = 17, /* double[n*n] inverse of the coarsest A by columns: element k*n + i is
                                     (A^-1 e_k)_i (coarsest level only; the direct solve of Alg. 2 is the
                                     product with it, summed over k ascending) */
-  GMG_EXPORT_BLOCK_COLORS = 18 /* int32[n] block colour 0..3 (parity class of the grid cell) of each point,
-                                  on levels swept in block order; size 0 elsewhere */
+  GMG_EXPORT_BLOCK_COLORS = 18 /* int32[n] block colour of each point (0..2 for bricks of two grid cells,
+                                  0..3 for single cells), on levels swept in block order; size 0 elsewhere */
 };
 
 /*

@@ -89,8 +89,9 @@ constexpr int64_t kMaxDenseCoarse = 4096;  // largest coarsest level factored de
 constexpr uint64_t kColorSalt = 0xC2B2AE3D27D4EB4FULL;
 constexpr double kBlockMargin = 1.0 + 1.0 / (1 << 20);   // cell side over the largest coupling distance
 constexpr int64_t kMaxGridCells = int64_t(1) << 22;       // grids with more cells keep the colour order
-constexpr int32_t kMaxCellRows = 512;                      // cells with more rows keep the level in colour order
-constexpr int32_t kMaxCellColors = 64;                     // likewise a cell that needs this many colours
+constexpr int32_t kMaxCellRows = 512;                      // blocks with more rows keep the level in colour order
+constexpr int32_t kMaxBrickRows = 256;                     // bricks with more rows: single cells are the blocks
+constexpr int32_t kMaxCellColors = 64;                     // likewise a block that needs this many colours
 
 // SplitMix64 finaliser (Steele, Lea & Flood 2014): a bijective 64-bit mixer.
 uint64_t mix64(uint64_t z) {
@@ -122,7 +123,7 @@ struct Level {
   std::vector<double> aval, adiag;
   std::vector<int32_t> color;
   int32_t ncolors = 0;
-  std::vector<int32_t> block_color;             // grid-cell parity class 0..3 per row (block order), or empty
+  std::vector<int32_t> block_color;             // block colour 0..3 per row (block order), or empty
   std::vector<int32_t> color_rows;              // rows in sweep order: (block colour, colour, index)
   std::vector<int32_t> color_ptr;               // colour c rows: color_rows[color_ptr[c] .. color_ptr[c+1])
 };
@@ -608,13 +609,20 @@ void colouring(Level& lv, int level, const Options& o) {
 // the first on ties) and binned into square cells whose side is slightly more
 // than w, the largest distance along either kept axis between two points
 // coupled by A_l.  Two coupled points then lie in the same cell or in
-// neighbouring ones (sharing a side or a corner), so cells of equal parity
-// (cx mod 2, cy mod 2) are never coupled: the four parity classes, the block
-// colours, are swept one after the other, all cells of a class at once and
-// within a cell the colours in ascending order.  Without couplings (w = 0),
+// neighbouring ones (sharing a side or a corner).  The blocks are bricks of
+// two cells side by side, shifted by one cell on every odd row of cells:
+// brick bx of row cy holds cells cx with (cx + (cy mod 2)) div 2 = bx.  A
+// brick then touches exactly six others (two in its row, two in each
+// neighbouring row), the pattern of a triangular lattice, and with
+// a = bx - (cy + 1) div 2 the brick colour (a - cy) mod 3 differs between
+// any two touching bricks.  A level with a brick of more than kMaxBrickRows
+// rows takes single cells as blocks instead, coloured by the parity pair
+// (cx mod 2) + 2 (cy mod 2), which differs between touching cells.  The block
+// colours are swept one after the other, all blocks of a colour at once and
+// within a block the colours in ascending order.  Without couplings (w = 0),
 // or with more than kMaxGridCells cells, the level keeps the colour order.
-// cell[i] receives row i's cell (cy * ncx + cx); returns whether the level
-// has a grid.
+// cell[i] receives row i's block (bricks: cy * nbx + bx, nbx = ncx div 2 + 1
+// bricks per row; cells: cy * ncx + cx); returns whether the level has a grid.
 bool block_order(Level& lv, std::vector<int64_t>& cell) {
   const int64_t n = lv.n;
   lv.block_color.clear();
@@ -645,13 +653,27 @@ bool block_order(Level& lv, std::vector<int64_t>& cell) {
   const double side = w * kBlockMargin;
   const int64_t ncx = (int64_t)std::floor(ext[a0] / side) + 1, ncy = (int64_t)std::floor(ext[a1] / side) + 1;
   if (ncx * ncy > kMaxGridCells) return false;
+  const int64_t nbx = ncx / 2 + 1;
+  std::vector<int64_t> cx(n), cy(n);
+  std::vector<int64_t> brick_rows((size_t)(nbx * ncy), 0);
+  for (int64_t i = 0; i < n; ++i) {
+    cx[i] = (int64_t)std::floor((lv.X[3 * i + a0] - lo[a0]) / side);
+    cy[i] = (int64_t)std::floor((lv.X[3 * i + a1] - lo[a1]) / side);
+    brick_rows[cy[i] * nbx + (cx[i] + cy[i] % 2) / 2] += 1;
+  }
+  const bool bricks = *std::max_element(brick_rows.begin(), brick_rows.end()) <= kMaxBrickRows;
   lv.block_color.assign(n, 0);
   cell.assign(n, 0);
   for (int64_t i = 0; i < n; ++i) {
-    const int64_t cx = (int64_t)std::floor((lv.X[3 * i + a0] - lo[a0]) / side);
-    const int64_t cy = (int64_t)std::floor((lv.X[3 * i + a1] - lo[a1]) / side);
-    lv.block_color[i] = (int32_t)((cx & 1) + 2 * (cy & 1));
-    cell[i] = cy * ncx + cx;
+    if (bricks) {
+      const int64_t bx = (cx[i] + cy[i] % 2) / 2;
+      const int64_t a = bx - (cy[i] + 1) / 2;
+      lv.block_color[i] = (int32_t)(((a - cy[i]) % 3 + 3) % 3);
+      cell[i] = cy[i] * nbx + bx;
+    } else {
+      lv.block_color[i] = (int32_t)((cx[i] & 1) + 2 * (cy[i] & 1));
+      cell[i] = cy[i] * ncx + cx[i];
+    }
   }
   return true;
 }
@@ -688,12 +710,12 @@ int32_t dsatur(int32_t m, const std::vector<std::vector<int32_t>>& adj, std::vec
 }
 
 // The colouring of a level swept in block order (a reading, like the block
-// order itself): each cell's rows are coloured on their own, by DSATUR on the
-// couplings of A_l between rows of that cell (rows numbered by ascending
-// index within the cell), since rows of different cells of one block colour
-// are never coupled.  A cell with more than kMaxCellRows rows, or one that
+// order itself): each block's rows are coloured on their own, by DSATUR on
+// the couplings of A_l between rows of that block (rows numbered by ascending
+// index within the block), since rows of different blocks of one block colour
+// are never coupled.  A block with more than kMaxCellRows rows, or one that
 // needs kMaxCellColors colours or more, sends the level back to the colour
-// order (returns false).
+// order (returns false).  cell[i] is row i's block.
 bool cell_colouring(Level& lv, const std::vector<int64_t>& cell) {
   const int64_t n = lv.n;
   std::vector<int64_t> order(n);

@@ -346,7 +346,9 @@ struct Level {
   // block order (levels swept in block order): grid cell and its parity class per row
   int32_t* bcolor = nullptr;            // [n] block colour 0..3, original numbering
   int32_t* bcell = nullptr;             // [n] cell cy * gx + cx (until the solve layout is built)
-  int32_t gx = 0, gy = 0;               // grid cells along the two kept axes
+  int32_t gx = 0, gy = 0;               // grid cells along the two kept axes (block order)
+  int32_t bricks = 0;                   // 1: the blocks are bricks of two cells (three colours), else cells
+  int32_t* ccell = nullptr;             // cell of every point, until the blocks are chosen
   int64_t blk_entries = 0;              // elements of the block ELL
   std::vector<int32_t> color_ptr;       // host: rows [color_ptr[c], color_ptr[c+1]) in new numbering
   std::vector<double> color_bytes;      // algorithmic bytes of one colour's sweep

@@ -1048,15 +1048,45 @@ __global__ void __launch_bounds__(kBlock) k_grid_extents(const double* __restric
   }
 }
 
-// Grid cell (cy gx + cx) and block colour (cx mod 2) + 2 (cy mod 2) of every point.
+// Colour of brick bx of cell row cy: with a = bx - (cy + 1) div 2, (a - cy)
+// mod 3.  A brick holds the cells cx of its row with (cx + cy mod 2) div 2 =
+// bx (two cells side by side, shifted by one cell on odd rows); it touches
+// two bricks in its row and two in each neighbouring row, and these six
+// colours all differ from its own.
+__host__ __device__ inline int32_t brick_color(int64_t bx, int64_t cy) {
+  const int64_t a = bx - (cy + 1) / 2;
+  return (int32_t)(((a - cy) % 3 + 3) % 3);
+}
+
+// Block colour of block id c (bricks: cy nbx + bx with nbx = gx div 2 + 1;
+// single cells: cy gx + cx, coloured by their parity pair).
+__host__ __device__ inline int32_t block_color_of(int32_t c, int32_t gx, bool bricks) {
+  if (bricks) {
+    const int32_t nbx = gx / 2 + 1;
+    return brick_color(c % nbx, c / nbx);
+  }
+  return (c % gx & 1) + 2 * (c / gx & 1);
+}
+
+// Brick (cy nbx + bx) and cell (cy gx + cx) of every point.
 __global__ void k_grid_cells(const double* __restrict__ X, int64_t n, int a0, int a1, double lo0, double lo1,
-                             double side, int32_t gx, int32_t* bcolor, int32_t* bcell) {
+                             double side, int32_t gx, int32_t* brick, int32_t* cell) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int64_t cx = (int64_t)floor((X[3 * i + a0] - lo0) / side);
   const int64_t cy = (int64_t)floor((X[3 * i + a1] - lo1) / side);
-  bcolor[i] = (int32_t)((cx & 1) + 2 * (cy & 1));
-  bcell[i] = (int32_t)(cy * gx + cx);
+  brick[i] = (int32_t)(cy * (gx / 2 + 1) + (cx + (cy & 1)) / 2);
+  cell[i] = (int32_t)(cy * gx + cx);
+}
+
+// The chosen blocks of every point and their colours.
+__global__ void k_block_ids(const int32_t* brick, const int32_t* cell, int64_t n, int32_t gx, int32_t bricks,
+                            int32_t* bcell, int32_t* bcolor) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int32_t c = bricks ? brick[i] : cell[i];
+  bcell[i] = c;
+  bcolor[i] = block_color_of(c, gx, bricks != 0);
 }
 
 // Sweep class of a row: block colour, then colour.
@@ -1070,8 +1100,17 @@ __global__ void k_count_cells(const int32_t* bcell, int64_t n, int32_t* cnt) {
   if (i < n) atomicAdd(&cnt[bcell[i]], 1);
 }
 
+// Rows per brick and rows per cell, in one pass.
+__global__ void k_count_cells2(const int32_t* brick, const int32_t* cell, int64_t n, int32_t* cntb, int32_t* cntc) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  atomicAdd(&cntb[brick[i]], 1);
+  atomicAdd(&cntc[cell[i]], 1);
+}
+
 // ---- per-cell colouring of a level swept in block order (DSATUR in each cell)
-constexpr int32_t kMaxCellRows = 512;     // larger cells send the level back to the colour order
+constexpr int32_t kMaxCellRows = 512;     // larger blocks send the level back to the colour order
+constexpr int32_t kMaxBrickRows = 256;    // a larger brick makes single cells the level's blocks
 constexpr int32_t kMaxCellColors = 64;    // likewise a cell that needs this many colours
 constexpr int32_t kCellAdjLds = 4096;     // in-cell couplings of a cell kept in LDS (else in HBM)
 
@@ -1219,32 +1258,28 @@ __global__ void __launch_bounds__(kWave) k_cell_dsatur(const int32_t* __restrict
   if (lane == 0) atomicMax(maxcol, used);
 }
 
-// Occupied cells enumerated block colour by block colour: slot v of
-// [0, 4 H), H = hx hy, is cell (2 (v mod H mod hx) + (k & 1), 2 (v mod H div hx) + (k >> 1))
-// of block colour k = v div H.
-__device__ __forceinline__ int32_t grid_cell_of(int64_t v, int64_t H, int32_t hx, int32_t gx, int32_t gy) {
+// Slot v of the block numbering, [0, 4 H) with H block ids: id v mod H if its
+// colour is k = v div H (else -1); blocks are numbered by colour, then id.
+__device__ __forceinline__ int32_t grid_cell_of(int64_t v, int64_t H, int32_t gx, bool bricks) {
   const int32_t k = (int32_t)(v / H);
-  const int64_t u = v % H;
-  const int32_t cx = 2 * (int32_t)(u % hx) + (k & 1), cy = 2 * (int32_t)(u / hx) + (k >> 1);
-  return cx < gx && cy < gy ? cy * gx + cx : -1;
+  const int32_t b = (int32_t)(v % H);
+  return block_color_of(b, gx, bricks) == k ? b : -1;
 }
 
-__global__ void k_cell_flags(const int32_t* cnt, int64_t H, int32_t hx, int32_t gx, int32_t gy, int32_t* flag) {
+__global__ void k_cell_flags(const int32_t* cnt, int64_t H, int32_t gx, int32_t bricks, int32_t* flag) {
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= 4 * H) return;
-  const int32_t c = grid_cell_of(v, H, hx, gx, gy);
+  const int32_t c = grid_cell_of(v, H, gx, bricks != 0);
   flag[v] = c >= 0 && cnt[c] > 0 ? 1 : 0;
 }
 
 // Block (compact id) of every solve row.
 __global__ void k_row_block(const int32_t* perm, const int32_t* bcell, int64_t n, const int32_t* vid, int64_t H,
-                            int32_t hx, int32_t gx, int32_t* blk) {
+                            int32_t gx, int32_t bricks, int32_t* blk) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= n) return;
   const int32_t c = bcell[perm[g]];
-  const int32_t cx = c % gx, cy = c / gx;
-  const int32_t k = (cx & 1) + 2 * (cy & 1);
-  blk[g] = vid[(int64_t)k * H + (int64_t)(cy >> 1) * hx + (cx >> 1)];
+  blk[g] = vid[(int64_t)block_color_of(c, gx, bricks != 0) * H + c];
 }
 
 // First local row of every colour c = 0..C in every block (rows of a block are
@@ -1617,8 +1652,9 @@ void colouring(Handle& h, Level& lv, int level) {
 // two coordinate axes of largest extent (the first smallest one dropped),
 // cells of side w (1 + 2^-20), w the longest coupling of A_l along those axes.
 // The host reads the extents and w, decides the grid, and the device assigns
-// every point its cell and block colour.  The level keeps the colour order
-// when it has no couplings or more than kMaxGridCells cells.
+// every point its brick (two cells of a row, shifted by one cell on odd rows)
+// and its cell; block_colouring chooses between them.  The level keeps the
+// colour order when it has no couplings or more than kMaxGridCells cells.
 constexpr double kBlockMargin = 1.0 + 1.0 / (1 << 20);
 constexpr int64_t kMaxGridCells = int64_t(1) << 22;
 
@@ -1659,29 +1695,47 @@ void block_order(Handle& h, Level& lv) {
   lv.gy = (int32_t)gy;
   lv.bcolor = (int32_t*)dalloc(h, (size_t)n * 4);
   lv.bcell = (int32_t*)talloc(s, (size_t)n * 4);
-  k_grid_cells<<<blocks_for(n), kBlock, 0, s>>>(lv.X, n, a0, a1, lo[a0], lo[a1], side, lv.gx, lv.bcolor, lv.bcell);
+  lv.ccell = (int32_t*)talloc(s, (size_t)n * 4);
+  k_grid_cells<<<blocks_for(n), kBlock, 0, s>>>(lv.X, n, a0, a1, lo[a0], lo[a1], side, lv.gx, lv.bcell, lv.ccell);
 }
 
-// The colouring of a level swept in block order: DSATUR in every cell (the
-// rows of a cell numbered by ascending index).  Returns false, with the level's
-// grid dropped, when a cell has more than kMaxCellRows rows or needs
-// kMaxCellColors colours; the level then takes the colour order.
+// The blocks and colouring of a level swept in block order: bricks of two
+// cells, or single cells where a brick would hold more than kMaxBrickRows rows
+// (lv.bcell receives the block of every row, lv.bcolor its colour), then
+// DSATUR in every block (its rows numbered by ascending index).  Returns false,
+// with the level's grid dropped, when a block has more than kMaxCellRows rows
+// or needs kMaxCellColors colours; the level then takes the colour order.
 bool block_colouring(Handle& h, Level& lv) {
   hipStream_t s = h.stream;
   const int64_t n = lv.n;
-  const int64_t ncell = (int64_t)lv.gx * lv.gy;
-  int32_t* cnt = (int32_t*)talloc(s, (size_t)(ncell + 1) * 4);
+  // rows per brick and per cell: bricks are the blocks unless one of them
+  // holds more than kMaxBrickRows rows
+  const int64_t nbrick = (int64_t)(lv.gx / 2 + 1) * lv.gy, ncells = (int64_t)lv.gx * lv.gy;
+  const int64_t cap = std::max(nbrick, ncells);
+  int32_t* cnt = (int32_t*)talloc(s, (size_t)(cap + 1) * 4);
+  int32_t* cnt2 = (int32_t*)talloc(s, (size_t)(ncells + 1) * 4);
   int32_t* slot = (int32_t*)talloc(s, (size_t)n * 4);
-  int32_t* mx = (int32_t*)talloc(s, 3 * 4);
-  fill_i32(cnt, 0, ncell + 1, s);
-  fill_i32(mx, 0, 3, s);
-  k_cell_slots<<<blocks_for(n), kBlock, 0, s>>>(lv.bcell, n, cnt, slot);
-  max_i32(cnt, ncell, 0, mx, s);
-  int64_t biggest = 0;
+  int32_t* mx = (int32_t*)talloc(s, 4 * 4);
+  fill_i32(cnt, 0, nbrick, s);
+  fill_i32(cnt2, 0, ncells, s);
+  fill_i32(mx, 0, 4, s);
+  k_count_cells2<<<blocks_for(n), kBlock, 0, s>>>(lv.bcell, lv.ccell, n, cnt, cnt2);
+  max_i32(cnt, nbrick, 0, mx, s);
+  max_i32(cnt2, ncells, 0, mx + 3, s);
+  int64_t mb = 0, mc = 0;
   {
-    ScalarRead rd[1] = {{mx, 4, &biggest}};
-    read_scalars(h, rd, 1);
+    ScalarRead rd[2] = {{mx, 4, &mb}, {mx + 3, 4, &mc}};
+    read_scalars(h, rd, 2);
   }
+  tfree(s, cnt2);
+  lv.bricks = mb <= kMaxBrickRows ? 1 : 0;
+  const int64_t ncell = lv.bricks ? nbrick : ncells;
+  const int64_t biggest = lv.bricks ? mb : mc;
+  k_block_ids<<<blocks_for(n), kBlock, 0, s>>>(lv.bcell, lv.ccell, n, lv.gx, lv.bricks, lv.bcell, lv.bcolor);
+  tfree(s, lv.ccell);
+  lv.ccell = nullptr;
+  fill_i32(cnt, 0, ncell + 1, s);
+  k_cell_slots<<<blocks_for(n), kBlock, 0, s>>>(lv.bcell, n, cnt, slot);
   bool ok = biggest <= kMaxCellRows;
   if (ok) {
     int32_t* cptr = (int32_t*)talloc(s, (size_t)(ncell + 1) * 4);
@@ -1727,15 +1781,14 @@ namespace {
 void block_layout(Handle& h, Level& lv, int32_t C) {
   hipStream_t s = h.stream;
   const int64_t n = lv.n;
-  const int64_t ncell = (int64_t)lv.gx * lv.gy;
-  const int32_t hx = (lv.gx + 1) / 2, hy = (lv.gy + 1) / 2;
-  const int64_t H = (int64_t)hx * hy;
+  const int64_t ncell = lv.bricks ? (int64_t)(lv.gx / 2 + 1) * lv.gy : (int64_t)lv.gx * lv.gy;   // block ids
+  const int64_t H = ncell;
   int32_t* cnt = (int32_t*)talloc(s, (size_t)ncell * 4);
   fill_i32(cnt, 0, ncell, s);
   k_count_cells<<<blocks_for(n), kBlock, 0, s>>>(lv.bcell, n, cnt);
   int32_t* flag = (int32_t*)talloc(s, (size_t)(4 * H + 1) * 4);
   int32_t* vid = (int32_t*)talloc(s, (size_t)(4 * H + 1) * 4);
-  k_cell_flags<<<blocks_for(4 * H), kBlock, 0, s>>>(cnt, H, hx, lv.gx, lv.gy, flag);
+  k_cell_flags<<<blocks_for(4 * H), kBlock, 0, s>>>(cnt, H, lv.gx, lv.bricks, flag);
   scan_i32(flag, vid, 4 * H, s);
   int64_t bs[5];
   {
@@ -1754,7 +1807,7 @@ void block_layout(Handle& h, Level& lv, int32_t C) {
   }
   // rows of every block, ascending (a stable partition of the solve rows by block)
   int32_t* blk = (int32_t*)talloc(s, (size_t)n * 4);
-  k_row_block<<<blocks_for(n), kBlock, 0, s>>>(lv.perm, lv.bcell, n, vid, H, hx, lv.gx, blk);
+  k_row_block<<<blocks_for(n), kBlock, 0, s>>>(lv.perm, lv.bcell, n, vid, H, lv.gx, lv.bricks, blk);
   tfree(s, vid);
   const int nb = blocks_for(n);
   int32_t* hist = (int32_t*)talloc(s, ((size_t)nblk * nb + 1) * 4);

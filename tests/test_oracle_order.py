@@ -2,10 +2,12 @@
 
 The block colours are recomputed here with NumPy from their definition (the
 two coordinate axes of largest extent, square cells of side slightly more
-than the largest coupling distance along them, the parity pair of the cell),
-and the property the block sweep relies on is checked directly on A_l: two
-coupled rows lie in the same or in neighbouring cells, so coupled rows of
-equal block colour share a cell.
+than the largest coupling distance along them, bricks of two cells side by
+side shifted by one cell on odd rows with three brick colours, or single cells
+with their parity pair where a brick would hold more than 256 rows), and the
+property the block sweep relies on is checked directly on A_l: two coupled
+rows lie in the same or in neighbouring cells, so coupled rows of equal block
+colour share a block.
 """
 import numpy as np
 import pytest
@@ -29,10 +31,54 @@ def grid_cells(lv):
     return cells, rows[off], lv["acol"][off]
 
 
+def bricks(cells):
+    """Brick key and brick colour of every cell (x, y): brick bx = (x + y mod 2) div 2
+    of row y, colour (bx - (y + 1) div 2 - y) mod 3."""
+    x, y = cells[:, 0], cells[:, 1]
+    bx = (x + (y & 1)) // 2
+    return y * ((x.max() + 1) // 2 + 1) + bx, (bx - (y + 1) // 2 - y) % 3
+
+
+def test_brick_colours_differ_between_touching_bricks():
+    """Brute force over a 13 x 11 grid of cells: two cells that share a side or a
+    corner lie in one brick or in bricks of different colours; every brick holds
+    at most two cells, side by side, and touches exactly six others away from
+    the grid's edge."""
+    gx, gy = 13, 11
+    cells = np.array([(x, y) for y in range(gy) for x in range(gx)], np.int64)
+    key, col = bricks(cells)
+    at = {(int(x), int(y)): t for t, (x, y) in enumerate(cells)}
+    touch = {}
+    for t, (x, y) in enumerate(cells):
+        for dx in (-1, 0, 1):
+            for dy in (-1, 0, 1):
+                u = at.get((int(x) + dx, int(y) + dy))
+                if u is None or key[u] == key[t]:
+                    continue
+                assert col[u] != col[t]
+                touch.setdefault(int(key[t]), set()).add(int(key[u]))
+    for k in np.unique(key):
+        mem = cells[key == k]
+        assert len(mem) <= 2 and (len(mem) == 1 or (mem[1, 0] - mem[0, 0] == 1 and mem[1, 1] == mem[0, 1]))
+        x0, y0 = mem[0]
+        if 2 <= x0 <= gx - 4 and 1 <= y0 <= gy - 2:
+            assert len(touch[int(k)]) == 6
+
+
+def blocks(cells):
+    """Block key and block colour of every cell: bricks when no brick holds more
+    than 256 rows, else single cells coloured by their parity pair."""
+    key, col = bricks(cells)
+    if np.bincount(key).max() <= 256:
+        return key, col
+    x, y = cells[:, 0], cells[:, 1]
+    return y * (x.max() + 1) + x, (x & 1) + 2 * (y & 1)
+
+
 def cell_colouring_fits(lv, cells):
-    """Whether every cell has at most 512 rows and its couplings can be coloured
+    """Whether every block has at most 512 rows and its couplings can be coloured
     by DSATUR with fewer than 64 colours."""
-    key = cells[:, 1] * (cells[:, 0].max() + 1) + cells[:, 0]
+    key, _ = blocks(cells)
     rp, ci = lv["arp"], lv["acol"]
     for k in np.unique(key):
         rows = np.flatnonzero(key == k)
@@ -65,11 +111,36 @@ def test_block_colours_from_the_grid(name, minc, bmin):
             assert not cell_colouring_fits(lv, cells), (name, l)
             continue
         seen += 1
-        assert np.array_equal(bc, (cells[:, 0] & 1) + 2 * (cells[:, 1] & 1))
+        key, col = blocks(cells)
+        assert np.array_equal(bc, col)
         assert np.abs(cells[i] - cells[j]).max() <= 1
         same = bc[i] == bc[j]
-        assert np.array_equal(cells[i][same], cells[j][same])
+        assert np.array_equal(key[i][same], key[j][same])
     assert seen >= 1 or name == "hubs"
+
+
+def test_bricks_or_cells_on_the_torus():
+    """1024 x 1024 torus, default options: level 1 has bricks of more than 256
+    rows, so its blocks are single cells with the four parity colours; level 2's
+    bricks all fit, so it takes bricks and three colours."""
+    import synth
+    h = oracle.Hierarchy.from_problem(synth.config_torus(1024, 1024))
+    forms = []
+    for l in (1, 2):
+        lv = h.level(l)
+        cells, i, j = grid_cells(lv)
+        bkey, bcol = bricks(cells)
+        x, y = cells[:, 0], cells[:, 1]
+        if np.bincount(bkey).max() > 256:
+            assert np.array_equal(lv["block_colors"], (x & 1) + 2 * (y & 1))
+            forms.append("cells")
+        else:
+            assert np.array_equal(lv["block_colors"], bcol)
+            forms.append("bricks")
+        same = lv["block_colors"][i] == lv["block_colors"][j]
+        key, _ = blocks(cells)
+        assert np.array_equal(key[i][same], key[j][same])
+    assert forms == ["cells", "bricks"]
 
 
 def test_block_order_on_the_default_levels():
@@ -146,9 +217,9 @@ def test_dsatur_colour_limit():
 @pytest.mark.parametrize("name,minc,bmin", [("torus96", 200, 1000), ("pc20k", 500, 1000), ("ico5", 100, 500)])
 def test_cell_colouring_of_block_levels(name, minc, bmin):
     """On every level swept in block order, the colours are a proper colouring
-    of each cell's couplings, and every row of colour c has a neighbour in its
-    cell of every colour below c (the property of any greedy colouring, which
-    DSATUR is); rows of different cells may share colours freely."""
+    of each brick's couplings, and every row of colour c has a neighbour in its
+    brick of every colour below c (the property of any greedy colouring, which
+    DSATUR is); rows of different bricks may share colours freely."""
     p = problem(name)
     h = oracle.Hierarchy.from_problem(p, oracle.default_options(min_coarse_points=minc, block_min_rows=bmin))
     seen = 0
@@ -158,7 +229,7 @@ def test_cell_colouring_of_block_levels(name, minc, bmin):
             continue
         seen += 1
         cells, _, _ = grid_cells(lv)
-        key = cells[:, 1] * (cells[:, 0].max() + 1) + cells[:, 0]
+        key, _ = blocks(cells)
         col = lv["colors"]
         rp, ci = lv["arp"], lv["acol"]
         for i in range(lv["n"]):
