@@ -64,6 +64,30 @@ __device__ inline T wave_sum(T v) {
   return v;
 }
 
+// Adds one to cnt[key] for every lane with `on` set, with one atomic per run
+// of equal keys in consecutive lanes with `on` set (rows of one cell, edges of
+// one vertex, are mostly consecutive), and returns the lane's slot: the count
+// before its own increment.  Every lane of the wavefront calls it.
+__device__ inline int32_t run_add(int32_t* cnt, int32_t key, bool on) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int32_t prev = __shfl_up(key, 1, kWave);
+  const int prev_on = __shfl_up((int)on, 1, kWave);
+  const bool head = on && (lane == 0 || !prev_on || prev != key);
+  const uint64_t heads = __ballot(head);
+  const uint64_t offs = ~__ballot(on);
+  const uint64_t upto = lane == kWave - 1 ? ~0ull : (2ull << lane) - 1;   // lanes 0..lane
+  int32_t base = 0;
+  if (head) {
+    const uint64_t after = (heads | offs) & ~upto;     // the run ends before the next head or idle lane
+    const int next = after ? __builtin_ctzll(after) : kWave;
+    base = atomicAdd(&cnt[key], next - lane);
+  }
+  const uint64_t mine = heads & upto;
+  const int h = mine ? 63 - __builtin_clzll(mine) : lane;
+  base = __shfl(base, h, kWave);
+  return base + (lane - h);
+}
+
 // Reduction of one value per thread over a block of kBlock threads (every
 // thread calls it); the result is valid on thread 0.  Reductions into one
 // global counter combine a block first: atomics on one address from every

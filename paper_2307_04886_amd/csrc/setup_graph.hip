@@ -26,16 +26,19 @@ __global__ void k_validate_points(const double* X, int64_t n3, int32_t* flags) {
 // this edge is the edge's slot in that end point's row (slot[2e], slot[2e+1]).
 __global__ void k_edge_degree(const int32_t* edges, int64_t m, int64_t n, int32_t* deg, int32_t* slot,
                               int32_t* flags) {
-  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= m) return;
-  int32_t u = edges[2 * e], v = edges[2 * e + 1];
-  if (u < 0 || v < 0 || u >= n || v >= n) {
-    atomicOr(flags, F_INVALID);
-    return;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool in = e < m;
+  const int32_t u = in ? edges[2 * e] : 0, v = in ? edges[2 * e + 1] : 0;
+  const bool bad = in && (u < 0 || v < 0 || u >= n || v >= n);
+  if (bad) atomicOr(flags, F_INVALID);
+  const bool on = in && !bad && u != v;
+  // one atomic per run of equal endpoints (edges are often listed vertex by vertex)
+  const int32_t su = run_add(deg, on ? u : -1, on);
+  const int32_t sv = run_add(deg, on ? v : -1, on);
+  if (on) {
+    slot[2 * e] = su;
+    slot[2 * e + 1] = sv;
   }
-  if (u == v) return;
-  slot[2 * e] = atomicAdd(&deg[u], 1);
-  slot[2 * e + 1] = atomicAdd(&deg[v], 1);
 }
 
 // Row entries at the slots the degree count handed out (rows are sorted

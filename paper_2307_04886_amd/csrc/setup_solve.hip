@@ -1095,30 +1095,6 @@ __global__ void k_sweep_class(const int32_t* bcolor, const int32_t* color, int64
   if (i < n) cls[i] = bcolor[i] * C + color[i];
 }
 
-// Adds one to cnt[key] for every lane with `on` set, with one atomic per run
-// of equal keys in consecutive lanes (rows of one cell are mostly
-// consecutive), and returns the lane's slot: the count before its own
-// increment.  The lanes with `on` set form a prefix of the wavefront; every
-// lane calls it.
-__device__ inline int32_t run_add(int32_t* cnt, int32_t key, bool on) {
-  const int lane = threadIdx.x & (kWave - 1);
-  const int32_t prev = __shfl_up(key, 1, kWave);
-  const bool head = on && (lane == 0 || prev != key);
-  const uint64_t heads = __ballot(head);
-  const int nactive = __popcll(__ballot(on));
-  const uint64_t upto = lane == kWave - 1 ? ~0ull : (2ull << lane) - 1;   // lanes 0..lane
-  int32_t base = 0;
-  if (head) {
-    const uint64_t after = heads & ~upto;
-    const int next = after ? __builtin_ctzll(after) : nactive;
-    base = atomicAdd(&cnt[key], next - lane);
-  }
-  const uint64_t mine = heads & upto;
-  const int h = mine ? 63 - __builtin_clzll(mine) : lane;
-  base = __shfl(base, h, kWave);
-  return base + (lane - h);
-}
-
 __global__ void k_count_cells(const int32_t* bcell, int64_t n, int32_t* cnt) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool on = i < n;
