@@ -516,6 +516,8 @@ void segment_sort_unique(int32_t* keys, const int32_t* ptr, int32_t* cnt_out, in
                          hipStream_t s);
 void compact_segments(const int32_t* src, const int32_t* src_ptr, const int32_t* dst_ptr,
                       int32_t* dst, int64_t nseg, hipStream_t s);
+void compact_long_segments(const int32_t* src, const int32_t* src_ptr, const int32_t* dst_ptr,
+                           int32_t* dst, int64_t nseg, hipStream_t s);  // a wavefront per segment
 
 // ------------------------------------------------------------------ launchers (setup_graph.hip)
 void validate_points(const double* X, int64_t n, int32_t* flags, hipStream_t s);

@@ -108,6 +108,15 @@ __global__ void k_compact_segments(const int32_t* src, const int32_t* src_ptr, c
   for (int32_t t = 0; t < len; ++t) dst[d + t] = src[b + t];
 }
 
+// Wavefront per segment (segments of many entries: block halo lists).
+__global__ void k_compact_segments_wave(const int32_t* src, const int32_t* src_ptr, const int32_t* dst_ptr,
+                                        int32_t* dst, int64_t nseg) {
+  const int64_t sg = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  if (sg >= nseg) return;
+  const int32_t b = src_ptr[sg], d = dst_ptr[sg], len = dst_ptr[sg + 1] - d;
+  for (int32_t t = threadIdx.x & (kWave - 1); t < len; t += kWave) dst[d + t] = src[b + t];
+}
+
 }  // namespace
 
 void scan_i32(const int32_t* in, int32_t* out, int64_t n, hipStream_t s) {
@@ -149,6 +158,12 @@ void segment_sort_unique(int32_t* keys, const int32_t* ptr, int32_t* cnt_out, in
 void compact_segments(const int32_t* src, const int32_t* src_ptr, const int32_t* dst_ptr,
                       int32_t* dst, int64_t nseg, hipStream_t s) {
   if (nseg > 0) k_compact_segments<<<blocks_for(nseg), kBlock, 0, s>>>(src, src_ptr, dst_ptr, dst, nseg);
+}
+
+void compact_long_segments(const int32_t* src, const int32_t* src_ptr, const int32_t* dst_ptr,
+                           int32_t* dst, int64_t nseg, hipStream_t s) {
+  if (nseg > 0)
+    k_compact_segments_wave<<<blocks_for(nseg, kBlock / kWave), kBlock, 0, s>>>(src, src_ptr, dst_ptr, dst, nseg);
 }
 
 }  // namespace gmg

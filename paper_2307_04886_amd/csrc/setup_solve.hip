@@ -1342,13 +1342,6 @@ __global__ void k_block_mask(const int32_t* bcls, int32_t nblk, int32_t C, uint6
   bmask[b] = m;
 }
 
-// Largest row (entries of A_l, diagonal included) of every block.
-__global__ void k_block_width(const int32_t* rp, const int32_t* perm, const int32_t* blk, int64_t n, int32_t* bw) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= n) return;
-  const int32_t o = perm[g];
-  atomicMax(&bw[blk[g]], rp[o + 1] - rp[o]);
-}
 
 __global__ void k_block_cells(const int32_t* boff, const int32_t* bw, int32_t nblk, int32_t* sz) {
   const int32_t b = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1436,16 +1429,24 @@ __global__ void __launch_bounds__(kBlock) k_block_halo(const int32_t* __restrict
 }
 
 // Entries of A_l (diagonal included) in the rows of every block: the halo's capacity.
+// Entries (cap) and longest row (bw) of every block, a wavefront per block.
 __global__ void k_block_entries(const int32_t* rp, const int32_t* perm, const int32_t* brows, const int32_t* boff,
-                                int32_t nblk, int32_t* cap) {
-  const int32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+                                int32_t nblk, int32_t* cap, int32_t* bw) {
+  const int32_t b = (int32_t)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave);
   if (b >= nblk) return;
-  int32_t s = 0;
-  for (int32_t k = boff[b]; k < boff[b + 1]; ++k) {
+  int32_t s = 0, w = 0;
+  for (int32_t k = boff[b] + (int32_t)(threadIdx.x & (kWave - 1)); k < boff[b + 1]; k += kWave) {
     const int32_t o = perm[brows[k]];
-    s += rp[o + 1] - rp[o];
+    const int32_t len = rp[o + 1] - rp[o];
+    s += len;
+    w = max(w, len);
   }
-  cap[b] = s;
+  s = wave_sum(s);
+  for (int o = kWave / 2; o > 0; o >>= 1) w = max(w, __shfl_xor(w, o, kWave));
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+    cap[b] = s;
+    bw[b] = w;
+  }
 }
 
 // The block ELL, one workgroup per block (its halo in LDS): entry t of local
@@ -1835,7 +1836,8 @@ void block_layout(Handle& h, Level& lv, int32_t C) {
   fill_i32(bad, 0, 1, s);
   int32_t* cap = (int32_t*)talloc(s, (size_t)(nblk + 1) * 4);
   int32_t* tcap = (int32_t*)talloc(s, (size_t)(nblk + 1) * 4);
-  k_block_entries<<<blocks_for(nblk), kBlock, 0, s>>>(lv.arp, lv.perm, brows, boff, nblk, cap);
+  int32_t* bw = (int32_t*)dalloc(h, (size_t)(nblk + 1) * 4);   // longest row of every block
+  k_block_entries<<<blocks_for(nblk, kBlock / kWave), kBlock, 0, s>>>(lv.arp, lv.perm, brows, boff, nblk, cap, bw);
   scan_i32(cap, tcap, nblk, s);
   int32_t* tmp = (int32_t*)talloc(s, (size_t)std::max<int64_t>(lv.nnzA, 1) * 4);
   int32_t* hcnt = cap;                       // reused: distinct halo rows per block
@@ -1844,14 +1846,11 @@ void block_layout(Handle& h, Level& lv, int32_t C) {
   int32_t* hoff = (int32_t*)dalloc(h, (size_t)(nblk + 1) * 4);
   scan_i32(hcnt, hoff, nblk, s);
   int32_t* hlist = (int32_t*)dalloc(h, (size_t)std::max<int64_t>(lv.nnzA, 1) * 4);
-  compact_segments(tmp, tcap, hoff, hlist, nblk, s);
+  compact_long_segments(tmp, tcap, hoff, hlist, nblk, s);
   tfree(s, tmp);
   tfree(s, tcap);
   tfree(s, cap);
   // widths and the ELL offsets
-  int32_t* bw = (int32_t*)dalloc(h, (size_t)(nblk + 1) * 4);
-  fill_i32(bw, 0, nblk, s);
-  k_block_width<<<blocks_for(n), kBlock, 0, s>>>(lv.arp, lv.perm, blk, n, bw);
   int32_t* sz = (int32_t*)talloc(s, (size_t)(nblk + 1) * 4);
   k_block_cells<<<blocks_for(nblk), kBlock, 0, s>>>(boff, bw, nblk, sz);
   int32_t* beoff = (int32_t*)dalloc(h, (size_t)(nblk + 1) * 4);
