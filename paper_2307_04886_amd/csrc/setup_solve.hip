@@ -1178,7 +1178,7 @@ __global__ void __launch_bounds__(kWave) k_cell_dsatur(const int32_t* __restrict
                                                       int32_t* __restrict__ color, int32_t* __restrict__ maxcol,
                                                       int32_t* __restrict__ overflow) {
   __shared__ uint64_t mask[kMaxCellRows];
-  __shared__ int32_t r[kMaxCellRows], col[kMaxCellRows], deg[kMaxCellRows], off[kMaxCellRows + 1];
+  __shared__ int32_t r[kMaxCellRows], deg[kMaxCellRows], off[kMaxCellRows + 1];
   __shared__ int32_t ladj[kCellAdjLds];
   const int32_t c = blockIdx.x;
   const int32_t base = cptr[c], m = cptr[c + 1] - base;
@@ -1204,7 +1204,6 @@ __global__ void __launch_bounds__(kWave) k_cell_dsatur(const int32_t* __restrict
     }
   for (int32_t p = lane; p < m; p += kWave) {
     mask[p] = 0;
-    col[p] = -1;
     deg[p] = deg_of[r[p]];
   }
   __syncthreads();
@@ -1235,14 +1234,29 @@ __global__ void __launch_bounds__(kWave) k_cell_dsatur(const int32_t* __restrict
   }
   __threadfence_block();
   __syncthreads();
+  // Lane l holds rows l + 64 q: their colour (-1: not yet coloured; rows past
+  // m count as coloured) and degree in registers, so a step reads only the
+  // rows' masks from LDS, all of them at once.
+  constexpr int kQ = kMaxCellRows / kWave;
+  int32_t cq[kQ], dq[kQ];
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) {
+    const int32_t p = lane + q * kWave;
+    cq[q] = p < m ? -1 : 0;
+    dq[q] = p < m ? deg[p] : 0;
+  }
   int32_t used = 0;
   for (int32_t step = 0; step < m; ++step) {
+    uint64_t mk[kQ];
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) mk[q] = mask[lane + q * kWave];
     uint32_t best = 0;
-    for (int32_t p = lane; p < m; p += kWave)
-      if (col[p] < 0) {
-        const uint32_t key = ((uint32_t)__popcll(mask[p]) << 20) | ((uint32_t)deg[p] << 10) | (uint32_t)(1023 - p);
-        best = best > key ? best : key;
-      }
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+      const int32_t p = lane + q * kWave;
+      const uint32_t key = ((uint32_t)__popcll(mk[q]) << 20) | ((uint32_t)dq[q] << 10) | (uint32_t)(1023 - p);
+      best = cq[q] < 0 && key > best ? key : best;
+    }
     best = wave_max_u32(best);
     const int32_t v = 1023 - (int32_t)(best & 1023u);
     const uint64_t free_colours = ~mask[v];
@@ -1252,12 +1266,18 @@ __global__ void __launch_bounds__(kWave) k_cell_dsatur(const int32_t* __restrict
     }
     const int32_t k = __builtin_ctzll(free_colours);
     used = used > k ? used : k;
+#pragma unroll
+    for (int q = 0; q < kQ; ++q)
+      if (lane + q * kWave == v) cq[q] = k;
     __syncthreads();
-    if (lane == 0) col[v] = k;
     for (int32_t t = lane; t < deg[v]; t += kWave) mask[A[off[v] + t]] |= uint64_t(1) << k;
     __syncthreads();
   }
-  for (int32_t p = lane; p < m; p += kWave) color[r[p]] = col[p];
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) {
+    const int32_t p = lane + q * kWave;
+    if (p < m) color[r[p]] = cq[q];
+  }
   if (lane == 0) atomicMax(maxcol, used);
 }
 
