@@ -290,10 +290,18 @@ __global__ void k_store_total(const int32_t* total, unsigned long long* out) { *
 
 // Entries per column of P; the count a column had before entry (i, t) is that
 // entry's slot in row I of P^T (slot[3 i + t]).
+// Entries of every column of P, with a slot for each entry (one atomic per run
+// of equal columns over consecutive rows: neighbouring fine points mostly
+// share their triangle).
 __global__ void k_count_cols(const int32_t* pcol, const int32_t* pcnt, int64_t n, int32_t* cnt, int32_t* slot) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  for (int t = 0; t < pcnt[i]; ++t) slot[3 * i + t] = atomicAdd(&cnt[pcol[3 * i + t]], 1);
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = i < n ? pcnt[i] : 0;
+#pragma unroll
+  for (int t = 0; t < 3; ++t) {
+    const bool on = t < c;
+    const int32_t k = run_add(cnt, on ? pcol[3 * i + t] : -1, on);
+    if (on) slot[3 * i + t] = k;
+  }
 }
 
 // P^T entries at the slots the count handed out (each row is sorted by fine
