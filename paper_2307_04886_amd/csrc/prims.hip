@@ -5,7 +5,7 @@ namespace gmg {
 
 namespace {
 
-constexpr int kScanItems = 8;                          // items per thread
+constexpr int kScanItems = 16;                         // items per thread
 constexpr int kScanTile = kBlock * kScanItems;         // items per block
 
 // Exclusive scan of one value per thread over a 256-thread block.

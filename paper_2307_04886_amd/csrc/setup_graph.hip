@@ -508,10 +508,13 @@ __global__ void __launch_bounds__(kBlock) k_voronoi_round(const int32_t* rp, con
 }
 
 // ------------------------------------------------------------------ cells, shift (Sec. 4.4)
-// Cell sizes; the count a cell had before point v is v's slot in the cell.
+// Cell sizes; the count a cell had before point v is v's slot in the cell
+// (one atomic per run of equal labels: neighbouring points mostly share a cell).
 __global__ void k_count_labels(const int32_t* lab, int64_t n, int32_t* cnt, int32_t* slot) {
-  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v < n) slot[v] = atomicAdd(&cnt[lab[v]], 1);
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool on = v < n;
+  const int32_t k = run_add(cnt, on ? lab[v] : -1, on);
+  if (on) slot[v] = k;
 }
 
 // Cell members at their slots (sorted afterwards).
