@@ -507,8 +507,12 @@ __global__ void __launch_bounds__(kWave) k_galerkin_fill(const int32_t* trp, con
                                                          const int32_t* acol, const double* aval,
                                                          const int32_t* pcol, const double* pval,
                                                          const int32_t* pcnt, int64_t nc, const int32_t* crp,
-                                                         int32_t* ccol, double* cval, int32_t* flags) {
-  constexpr int kOut = HS * 3 / 4;     // distinct columns of a row (the symbolic pass checked the bound)
+                                                         int32_t* ccol, double* cval, int32_t* flags,
+                                                         int32_t* rowcnt, int32_t* unfit) {
+  // Row I goes to crp[I] (the symbolic pass counted it and checked the bound),
+  // or, with crp null, to I * kOut of padded rows with its length in rowcnt[I];
+  // a row with more than kOut columns then sets *unfit and is left out.
+  constexpr int kOut = HS * 3 / 4;     // distinct columns of a row
   constexpr int kFastSub = 4;          // pairs per lane of the one-chunk form
   constexpr int kPer = (kOut + kWave - 1) / kWave;   // output columns per lane
   __shared__ int32_t keys[HS];
@@ -574,9 +578,19 @@ __global__ void __launch_bounds__(kWave) k_galerkin_fill(const int32_t* trp, con
     }
   }
   for (int s = lane; s < HS; s += kWave)
-    if (keys[s] >= 0) sorted[atomicAdd(&nlist, 1)] = s;            // slots, in any order
+    if (keys[s] >= 0) {                                             // slots, in any order
+      const int a = atomicAdd(&nlist, 1);
+      if (a < kOut) sorted[a] = s;
+    }
   __syncthreads();
   const int k = nlist;
+  if (k > kOut) {                                                   // uniform over the wavefront
+    if (lane == 0) {
+      if (unfit) atomicOr(unfit, 1);
+      if (rowcnt) rowcnt[I] = 0;
+    }
+    return;
+  }
   int32_t myslot[kPer], mykey[kPer];
 #pragma unroll
   for (int g = 0; g < kPer; ++g) {
@@ -709,7 +723,8 @@ __global__ void __launch_bounds__(kWave) k_galerkin_fill(const int32_t* trp, con
       }
     }
   }
-  const int32_t out = crp[I];
+  const int64_t out = crp ? (int64_t)crp[I] : (int64_t)I * kOut;
+  if (rowcnt && lane == 0) rowcnt[I] = k;
   bool diag_ok = false;
   for (int o = lane; o < k; o += kWave) {
     ccol[out + o] = sorted[o];
@@ -719,6 +734,22 @@ __global__ void __launch_bounds__(kWave) k_galerkin_fill(const int32_t* trp, con
   // a missing or non-positive diagonal makes Gauss-Seidel divide by zero
   unsigned long long bal = __ballot(diag_ok);
   if (lane == 0 && bal == 0) atomicOr(flags, F_NOT_SPD);
+}
+
+// Padded rows (stride W) of the first numeric pass into their CSR place, a
+// wavefront per row.
+__global__ void __launch_bounds__(kBlock) k_galerkin_compact(const int32_t* __restrict__ rowcnt,
+                                                             const int32_t* __restrict__ rp,
+                                                             const int32_t* __restrict__ pcol,
+                                                             const double* __restrict__ pval, int64_t nc, int32_t W,
+                                                             int32_t* __restrict__ col, double* __restrict__ val) {
+  const int64_t I = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  if (I >= nc) return;
+  const int32_t n = rowcnt[I], o = rp[I];
+  for (int32_t t = threadIdx.x & (kWave - 1); t < n; t += kWave) {
+    col[o + t] = pcol[I * W + t];
+    val[o + t] = pval[I * W + t];
+  }
 }
 
 __global__ void __launch_bounds__(kBlock) k_max_i32(const int32_t* v, int64_t n, int32_t* out) {
@@ -774,10 +805,43 @@ void galerkin(Handle& h, Level& lv, Level& nx, const int32_t* t_rp, const int32_
               const double* t_val) {
   hipStream_t s = h.stream;
   int64_t nc = nx.n;
+  lv.t_rp = (int32_t*)t_rp;
+  lv.t_col = (int32_t*)t_col;
+  lv.t_val = (double*)t_val;
+  // First the numeric pass into padded rows of up to 48 columns (the smallest
+  // hash table); its rows then only move into place.  If a row has more
+  // columns, the symbolic pass sizes the rows and the numeric pass runs again.
+  {
+    constexpr int32_t W = 64 * 3 / 4;
+    int32_t* cnt = (int32_t*)talloc(s, (size_t)(nc + 1) * 4);
+    int32_t* unfit = (int32_t*)talloc(s, 4);
+    int32_t* pcol = (int32_t*)talloc(s, (size_t)nc * W * 4);
+    double* pval = (double*)talloc(s, (size_t)nc * W * 8);
+    fill_i32(unfit, 0, 1, s);
+    nx.arp = (int32_t*)dalloc(h, (size_t)(nc + 1) * 4);
+    k_galerkin_fill<64><<<(int)nc, kWave, 0, s>>>(t_rp, t_col, t_val, lv.arp, lv.acol, lv.aval, lv.pcol, lv.pval,
+                                                  lv.pcnt, nc, nullptr, pcol, pval, h.flags, cnt, unfit);
+    scan_i32(cnt, nx.arp, nc, s);
+    int64_t bad = 0, f = 0;
+    ScalarRead rd[3] = {{nx.arp + nc, 4, &nx.nnzA}, {unfit, 4, &bad}, {h.flags, 4, &f}};
+    read_scalars(h, rd, 3);
+    if (bad == 0) {
+      throw_flags((int32_t)f, "Galerkin operator");
+      nx.acol = (int32_t*)dalloc(h, (size_t)(nx.nnzA + 1) * 4);
+      nx.aval = (double*)dalloc(h, (size_t)(nx.nnzA + 1) * 8);
+      k_galerkin_compact<<<blocks_for(nc, kBlock / kWave), kBlock, 0, s>>>(cnt, nx.arp, pcol, pval, nc, W, nx.acol,
+                                                                          nx.aval);
+      lv.galerkin_hs = 64;
+    }
+    tfree(s, pcol);
+    tfree(s, pval);
+    tfree(s, unfit);
+    tfree(s, cnt);
+    if (bad == 0) return;
+  }
   int32_t* cnt = (int32_t*)talloc(s, (size_t)(nc + 1) * 4);
   int32_t* mx = (int32_t*)talloc(s, 4);
   check_hip(hipMemsetAsync(mx, 0, 4, s), "memset");
-  nx.arp = (int32_t*)dalloc(h, (size_t)(nc + 1) * 4);
   k_galerkin_count<1024><<<(int)nc, kWave, 0, s>>>(t_rp, t_col, t_val, lv.arp, lv.acol, lv.pcol, lv.pcnt, nc,
                                                   cnt, h.flags);
   k_max_i32<<<std::min(blocks_for(nc), kReduceGrid), kBlock, 0, s>>>(cnt, nc, mx);
@@ -791,9 +855,6 @@ void galerkin(Handle& h, Level& lv, Level& nx, const int32_t* t_rp, const int32_
   // the smallest hash table that holds every row (3/4 full at most): a
   // smaller LDS footprint keeps more rows in flight per CU
   lv.galerkin_hs = maxrow <= 64 * 3 / 4 ? 64 : (maxrow <= 256 * 3 / 4 ? 256 : 1024);
-  lv.t_rp = (int32_t*)t_rp;
-  lv.t_col = (int32_t*)t_col;
-  lv.t_val = (double*)t_val;
   galerkin_values(h, lv, nx);
   tfree(s, cnt);
   tfree(s, mx);
@@ -805,7 +866,7 @@ void galerkin_values(Handle& h, Level& lv, Level& nx) {
   const int64_t nc = nx.n;
   auto fill = [&](auto kern) {
     kern<<<(int)nc, kWave, 0, s>>>(lv.t_rp, lv.t_col, lv.t_val, lv.arp, lv.acol, lv.aval, lv.pcol, lv.pval, lv.pcnt,
-                                   nc, nx.arp, nx.acol, nx.aval, h.flags);
+                                   nc, nx.arp, nx.acol, nx.aval, h.flags, nullptr, nullptr);
   };
   if (lv.galerkin_hs == 64) fill(k_galerkin_fill<64>);
   else if (lv.galerkin_hs == 256) fill(k_galerkin_fill<256>);
