@@ -33,9 +33,10 @@ sys.path.insert(0, ROOT)
 
 # HBM bytes per launch from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE, scaled by what the counters read
 # for a plain device copy (profiles/k_gs_block_torus1024.md, profiles/k_gs_color_fine_torus1024.md);
-# valid only for the kernel sources they were taken on (sha256 prefix of solve.hip + rows.hpp).
-TRAFFIC = {"gs_finest": {"bytes_per_launch": 26836582, "src_sha256_16": "f82e40132e218e6d"},
-           "gs_galerkin": {"bytes_per_launch": 11061122, "src_sha256_16": "f82e40132e218e6d"}}
+# valid only for the kernel and layout sources they were taken on (sha256 prefix of solve.hip +
+# rows.hpp + setup_solve.hip, which lays out the matrices and blocks the kernels read).
+TRAFFIC = {"gs_finest": {"bytes_per_launch": 26110584, "src_sha256_16": "31b51fa393f97f9e"},
+           "gs_galerkin": {"bytes_per_launch": 12451111, "src_sha256_16": "31b51fa393f97f9e"}}
 
 KERNEL_NAMES = {"gs_finest": "k_gs_color_fine (one colour of a Gauss-Seidel sweep, level 0)",
                 "residual_finest": "k_residual_norm (residual + norm partials, level 0)",
@@ -46,7 +47,7 @@ KERNEL_NAMES = {"gs_finest": "k_gs_color_fine (one colour of a Gauss-Seidel swee
 def kernel_src_sha():
     import hashlib
     h = hashlib.sha256()
-    for f in ("solve.hip", "rows.hpp"):
+    for f in ("solve.hip", "rows.hpp", "setup_solve.hip"):
         h.update(open(os.path.join(ROOT, "paper_2307_04886_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
