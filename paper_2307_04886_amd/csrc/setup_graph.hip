@@ -567,6 +567,15 @@ __global__ void k_cell_degree(const int32_t* ptr, const int32_t* mem, const int3
 //
 // Cells with more than kCellCand edges: one lane, insertion into the sorted
 // range.
+// Orders the LDS accesses of a lane group inside one wavefront (its lanes
+// run in lockstep and its LDS operations complete in issue order, so only the
+// compiler must be kept from moving accesses across).
+__device__ __forceinline__ void group_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __device__ inline void cell_neighbours_serial(const int32_t* ptr, const int32_t* mem, const int32_t* rp,
                                               const int32_t* col, const int32_t* lab, int32_t I, int32_t* out,
                                               int32_t* ucnt) {
@@ -604,7 +613,6 @@ __global__ void __launch_bounds__(kBlock) k_cell_neighbours(const int32_t* ptr, 
                                                             const int32_t* lab, const int32_t* cptr, int64_t nc,
                                                             int32_t* tmp, int32_t* ucnt) {
   __shared__ int32_t cand[kCellsPerBlock][kCellCand];
-  __shared__ uint8_t first[kCellsPerBlock][kCellCand];
   const int g = threadIdx.x / kCellLanes, sub = threadIdx.x & (kCellLanes - 1);
   const int64_t I = (int64_t)xcd_block() * kCellsPerBlock + g;
   const bool act = I < nc;
@@ -644,26 +652,43 @@ __global__ void __launch_bounds__(kBlock) k_cell_neighbours(const int32_t* ptr, 
     }
   }
   __syncthreads();
-  if (group)
-    for (int32_t q = sub; q < total; q += kCellLanes) {
-      const int32_t key = cand[g][q];
-      bool f = key != INT32_MIN;
-      for (int32_t q2 = 0; q2 < q && f; ++q2) f = cand[g][q2] != key;
-      first[g][q] = f;
-    }
-  __syncthreads();
   if (group) {
+    // the group's candidates sorted (bitonic, padded with INT32_MAX to a power
+    // of two; the group's 16 lanes are in one wavefront, whose LDS accesses
+    // complete in order), then every distinct label other than the cell's own
+    // (INT32_MIN) at the count of distinct labels before it
+    int32_t* cg = cand[g];
+    int32_t P = 1;
+    while (P < total) P <<= 1;
+    for (int32_t q = total + sub; q < P; q += kCellLanes) cg[q] = INT32_MAX;
+    group_sync();
+    for (int32_t k = 2; k <= P; k <<= 1)
+      for (int32_t j = k >> 1; j > 0; j >>= 1) {
+        for (int32_t q = sub; q < P; q += kCellLanes) {
+          const int32_t l = q ^ j;
+          if (l > q) {
+            const int32_t x = cg[q], y = cg[l];
+            if ((x > y) == ((q & k) == 0)) {
+              cg[q] = y;
+              cg[l] = x;
+            }
+          }
+        }
+        group_sync();
+      }
+    const int32_t per = (total + kCellLanes - 1) / kCellLanes;
+    const int32_t q0 = min(total, sub * per), q1 = min(total, q0 + per);
     int32_t u = 0;
-    for (int32_t q = sub; q < total; q += kCellLanes) {
-      if (!first[g][q]) continue;
-      const int32_t key = cand[g][q];
-      int32_t rank = 0;
-      for (int32_t q2 = 0; q2 < total; ++q2) rank += first[g][q2] && cand[g][q2] < key;
-      out[rank] = key;
-      ++u;
+    for (int32_t q = q0; q < q1; ++q) u += cg[q] != INT32_MIN && (q == 0 || cg[q - 1] != cg[q]);
+    int32_t incl = u;
+    for (int o = 1; o < kCellLanes; o <<= 1) {
+      const int32_t t = __shfl_up(incl, o, kCellLanes);
+      if (sub >= o) incl += t;
     }
-    for (int o = kCellLanes / 2; o > 0; o >>= 1) u += __shfl_xor(u, o, kCellLanes);
-    if (sub == 0) ucnt[I] = u;
+    int32_t at = incl - u;
+    for (int32_t q = q0; q < q1; ++q)
+      if (cg[q] != INT32_MIN && (q == 0 || cg[q - 1] != cg[q])) out[at++] = cg[q];
+    if (sub == kCellLanes - 1) ucnt[I] = incl;
   }
 }
 
