@@ -35,8 +35,8 @@ sys.path.insert(0, ROOT)
 # for a plain device copy (profiles/k_gs_block_torus1024.md, profiles/k_gs_color_fine_torus1024.md);
 # valid only for the kernel and layout sources they were taken on (sha256 prefix of solve.hip +
 # rows.hpp + setup_solve.hip, which lays out the matrices and blocks the kernels read).
-TRAFFIC = {"gs_finest": {"bytes_per_launch": 26110584, "src_sha256_16": "31b51fa393f97f9e"},
-           "gs_galerkin": {"bytes_per_launch": 12451111, "src_sha256_16": "31b51fa393f97f9e"}}
+TRAFFIC = {"gs_finest": {"bytes_per_launch": 26110584, "src_sha256_16": "b297e82abd4cef97"},
+           "gs_galerkin": {"bytes_per_launch": 12451111, "src_sha256_16": "b297e82abd4cef97"}}
 
 KERNEL_NAMES = {"gs_finest": "k_gs_color_fine (one colour of a Gauss-Seidel sweep, level 0)",
                 "residual_finest": "k_residual_norm (residual + norm partials, level 0)",

@@ -88,6 +88,29 @@ __device__ inline int32_t run_add(int32_t* cnt, int32_t key, bool on) {
   return base + (lane - h);
 }
 
+// Adds val to cnt[key] for every lane with `on` set, with one atomic per run of
+// equal keys in consecutive lanes with `on` set (the run's values summed in
+// the wavefront first).  Every lane of the wavefront calls it.
+__device__ inline void run_sum(int32_t* cnt, int32_t key, int32_t val, bool on) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int32_t v = on ? val : 0;
+  int32_t incl = v;
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int32_t t = __shfl_up(incl, o, kWave);
+    if (lane >= o) incl += t;
+  }
+  const int32_t prev = __shfl_up(key, 1, kWave);
+  const int prev_on = __shfl_up((int)on, 1, kWave);
+  const bool head = on && (lane == 0 || !prev_on || prev != key);
+  const uint64_t heads = __ballot(head);
+  const uint64_t offs = ~__ballot(on);
+  const uint64_t upto = lane == kWave - 1 ? ~0ull : (2ull << lane) - 1;   // lanes 0..lane
+  const uint64_t after = (heads | offs) & ~upto;
+  const int end = head ? (after ? __builtin_ctzll(after) : kWave) - 1 : lane;   // the run's last lane
+  const int32_t upto_end = __shfl(incl, end, kWave);
+  if (head) atomicAdd(&cnt[key], upto_end - (incl - v));
+}
+
 // Reduction of one value per thread over a block of kBlock threads (every
 // thread calls it); the result is valid on thread 0.  Reductions into one
 // global counter combine a block first: atomics on one address from every

@@ -1149,15 +1149,17 @@ __global__ void k_incell_degree(const int32_t* __restrict__ arp, const int32_t* 
                                 const int32_t* __restrict__ bcell, int64_t n, int32_t* __restrict__ deg,
                                 int32_t* __restrict__ cell_deg) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int32_t c = bcell[i];
+  const bool on = i < n;
+  const int32_t c = on ? bcell[i] : -1;
   int32_t d = 0;
-  for (int32_t e = arp[i]; e < arp[i + 1]; ++e) {
-    const int32_t j = acol[e];
-    d += (j != (int32_t)i && bcell[j] == c) ? 1 : 0;
+  if (on) {
+    for (int32_t e = arp[i]; e < arp[i + 1]; ++e) {
+      const int32_t j = acol[e];
+      d += (j != (int32_t)i && bcell[j] == c) ? 1 : 0;
+    }
+    deg[i] = d;
   }
-  deg[i] = d;
-  atomicAdd(&cell_deg[c], d);
+  run_sum(cell_deg, c, d, on);                 // one atomic per run of rows of one block
 }
 
 // DSATUR in one cell, one wavefront per cell.  The cell's rows are sorted
